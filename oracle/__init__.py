@@ -1,0 +1,341 @@
+"""CPU oracle for the analytic-BOP energy path — TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package.  The HIP product path never imports,
+links or calls it, and this package imports nothing from the product.
+
+The numerics live in ``bop_oracle.c`` (plain FP64 C, OpenMP over atoms), each
+function citing the passage of arXiv:1803.07491 it follows; this module only
+marshals NumPy arrays into it.  The MLP reference (forward, backward, Adam)
+is written here in NumPy FP64.
+
+Functions whose results have no independent pin are marked "parity unpinned"
+in their docstring.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "bop_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+MAXSP = 4
+NCH = 14
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (FP contraction off, OpenMP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class _Model(C.Structure):
+    _fields_ = [
+        ("n_species", C.c_int),
+        ("n_orb", C.c_int),
+        ("r_cut", C.c_double),
+        ("d_cut", C.c_double),
+        ("onsite", (C.c_double * 3) * MAXSP),
+        ("form", (C.c_int * NCH) * (MAXSP * MAXSP)),
+        ("beta0", (C.c_double * NCH) * (MAXSP * MAXSP)),
+        ("r0", (C.c_double * NCH) * (MAXSP * MAXSP)),
+        ("q", (C.c_double * NCH) * (MAXSP * MAXSP)),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = C.CDLL(build())
+        P = C.c_void_p
+        _lib.or_neighbours.restype = C.c_long
+        _lib.or_neighbours.argtypes = [C.c_int, P, P, C.c_double, C.c_int, C.c_long, P, P, P, P]
+        _lib.or_build_H.argtypes = [P, C.c_int, P, P, P, P, P, P, P]
+        _lib.or_moments.argtypes = [C.c_int, C.c_int, C.c_int, P, P, P, P, C.c_int, P, P]
+        _lib.or_recursion.argtypes = [C.c_int, C.c_int, P, C.c_int, C.c_double, C.c_double, P, P, P, P, P]
+        _lib.or_jackson.argtypes = [C.c_int, P]
+        _lib.or_dos_coeffs.argtypes = [C.c_int, C.c_int, C.c_int, P, P, P, P, P, P, P]
+        _lib.or_orbital_NU.argtypes = [C.c_int, P, C.c_double, C.c_double, C.c_double, C.c_double, P, P, P]
+        _lib.or_count.restype = C.c_double
+        _lib.or_count.argtypes = [C.c_int, C.c_int, P, P, P, C.c_double]
+        _lib.or_fermi.restype = C.c_double
+        _lib.or_fermi.argtypes = [C.c_int, C.c_int, P, P, P, C.c_double]
+        _lib.or_energy.restype = C.c_double
+        _lib.or_energy.argtypes = [C.c_int, C.c_int, C.c_int, P, P, P, P, C.c_double, P, P, P]
+        _lib.or_scf_step.restype = C.c_double
+        _lib.or_scf_step.argtypes = [C.c_int, P, P, P, C.c_double, C.c_double, C.c_double, P, P, P]
+        _lib.or_rotation.argtypes = [P, P, P]
+        _lib.or_n_a.argtypes = [C.c_int]
+        _lib.or_n_b.argtypes = [C.c_int]
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(C.c_void_p) if a is not None else None
+
+
+def _c(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+def num_threads() -> int:
+    return int(lib().or_num_threads())
+
+
+def model_struct(model: dict) -> _Model:
+    """Fill the oracle's own model struct from a plain model dict
+    (``workloads`` format)."""
+    from workloads import CHANNELS  # plain data names only
+    m = _Model()
+    ns = model["n_species"]
+    assert ns <= MAXSP
+    m.n_species = ns
+    m.n_orb = model["n_orb"]
+    m.r_cut = model["r_cut"]
+    m.d_cut = model.get("d_cut", 0.0)
+    for s in range(ns):
+        for l in range(3):
+            m.onsite[s][l] = model["onsite"][s][l]
+    for pr in range(MAXSP * MAXSP):
+        for c in range(NCH):
+            m.r0[pr][c] = 1.0
+    for (si, sj), chans in model["bonds"].items():
+        pr = si * ns + sj
+        for name, (f, b0, r0, q) in chans.items():
+            c = CHANNELS.index(name)
+            m.form[pr][c] = f
+            m.beta0[pr][c] = b0
+            m.r0[pr][c] = r0
+            m.q[pr][c] = q
+    return m
+
+
+# --------------------------------------------------------------------------
+def neighbours(pos, cell, r_cut, brute=False):
+    """Periodic neighbour list (CSR).  Returns dict(row_ptr, nbr_j, nbr_shift,
+    nbr_d)."""
+    pos = _c(pos, np.float64)
+    cell = _c(cell, np.float64)
+    n = pos.shape[0]
+    rp = np.zeros(n + 1, np.int32)
+    need = lib().or_neighbours(n, _p(pos), _p(cell), r_cut, int(brute), 0, _p(rp), None, None, None)
+    nj = np.zeros(need, np.int32)
+    ns = np.zeros((need, 3), np.int32)
+    nd = np.zeros((need, 3), np.float64)
+    got = lib().or_neighbours(n, _p(pos), _p(cell), r_cut, int(brute), need, _p(rp), _p(nj), _p(ns), _p(nd))
+    assert got == need
+    return {"row_ptr": rp, "nbr_j": nj, "nbr_shift": ns, "nbr_d": nd}
+
+
+def build_H(model, species, nl, shift=None):
+    """Onsite levels [N, n_orb] and bond blocks [P, n_orb, n_orb] (FP64)."""
+    m = model_struct(model)
+    species = _c(species, np.int32)
+    n = species.shape[0]
+    no = model["n_orb"]
+    P = nl["nbr_j"].shape[0]
+    H_on = np.zeros((n, no))
+    H_bond = np.zeros((P, no, no))
+    sh = None if shift is None else _c(shift, np.float64)
+    lib().or_build_H(C.byref(m), n, _p(species), _p(sh), _p(nl["row_ptr"]), _p(nl["nbr_j"]),
+                     _p(nl["nbr_d"]), _p(H_on), _p(H_bond))
+    return H_on, H_bond
+
+
+def moments(nl, H_on, H_bond, n_max, sel=None):
+    """Orbital moments mu[s, a, n] = <i a|H^n|i a> for i = sel[s]."""
+    n, no = H_on.shape
+    sel = np.arange(n, dtype=np.int32) if sel is None else _c(sel, np.int32)
+    mu = np.zeros((sel.shape[0], no, n_max + 1))
+    lib().or_moments(n, no, n_max, _p(nl["row_ptr"]), _p(nl["nbr_j"]), _p(_c(H_on, np.float64)),
+                     _p(_c(H_bond, np.float64)), sel.shape[0], _p(sel), _p(mu))
+    return mu
+
+
+def n_a(n_max):
+    return int(lib().or_n_a(n_max))
+
+
+def n_b(n_max):
+    return int(lib().or_n_b(n_max))
+
+
+def recursion(mu_rows, n_max, global_ab=None):
+    """Recursion coefficients and Gershgorin terminator per row (orbital).
+    ``mu_rows`` [R, n_max+1].  Returns dict(a, b, a_inf, b_inf, flags)."""
+    mu_rows = _c(mu_rows, np.float64).reshape(-1, n_max + 1)
+    R = mu_rows.shape[0]
+    a = np.zeros((R, n_a(n_max)))
+    b = np.zeros((R, n_b(n_max) + 1))
+    ai = np.zeros(R)
+    bi = np.zeros(R)
+    fl = np.zeros(R, np.int32)
+    mode, ag, bg = (0, 0.0, 0.0) if global_ab is None else (1, global_ab[0], global_ab[1])
+    lib().or_recursion(R, n_max, _p(mu_rows), mode, ag, bg, _p(a), _p(b), _p(ai), _p(bi), _p(fl))
+    return {"a": a, "b": b, "a_inf": ai, "b_inf": bi, "flags": fl}
+
+
+def jackson(n_exp):
+    g = np.zeros(n_exp + 1)
+    lib().or_jackson(n_exp, _p(g))
+    return g
+
+
+def dos_coeffs(mu_rows, rec, n_max, n_exp, with_chain=False):
+    """g_m sigma_m [R, n_exp+1]; with ``with_chain`` also the chain route's
+    sigma_m for m <= n_max [R, n_max+1]."""
+    mu_rows = _c(mu_rows, np.float64).reshape(-1, n_max + 1)
+    R = mu_rows.shape[0]
+    gs = np.zeros((R, n_exp + 1))
+    sc = np.zeros((R, n_max + 1)) if with_chain else None
+    lib().or_dos_coeffs(R, n_max, n_exp, _p(mu_rows), _p(rec["a"]), _p(rec["b"]), _p(rec["a_inf"]),
+                        _p(rec["b_inf"]), _p(gs), _p(sc))
+    return (gs, sc) if with_chain else gs
+
+
+def orbital_NU(gsig_row, a_inf, b_inf, e_on, E):
+    n_exp = gsig_row.shape[0] - 1
+    N, U, D = C.c_double(), C.c_double(), C.c_double()
+    lib().or_orbital_NU(n_exp, _p(_c(gsig_row, np.float64)), a_inf, b_inf, e_on, E,
+                        C.byref(N), C.byref(U), C.byref(D))
+    return N.value, U.value, D.value
+
+
+def count(gsig, a_inf, b_inf, E):
+    R, ne1 = gsig.shape
+    return lib().or_count(R, ne1 - 1, _p(gsig), _p(a_inf), _p(b_inf), E)
+
+
+def fermi(gsig, a_inf, b_inf, n_elec):
+    R, ne1 = gsig.shape
+    return lib().or_fermi(R, ne1 - 1, _p(_c(gsig, np.float64)), _p(_c(a_inf, np.float64)),
+                          _p(_c(b_inf, np.float64)), float(n_elec))
+
+
+def energy(gsig, a_inf, b_inf, H_on, E_F):
+    """Per-atom N_i, U_i, n_i(E_F) (both spins) and U_total."""
+    n, no = H_on.shape
+    Na = np.zeros(n)
+    Ua = np.zeros(n)
+    Da = np.zeros(n)
+    tot = lib().or_energy(n, no, gsig.shape[1] - 1, _p(_c(gsig, np.float64)), _p(_c(a_inf, np.float64)),
+                          _p(_c(b_inf, np.float64)), _p(_c(H_on, np.float64)), E_F, _p(Na), _p(Ua), _p(Da))
+    return {"N_atom": Na, "U_atom": Ua, "dos_atom": Da, "U_total": tot}
+
+
+def scf_step(N_atom, dos_atom, n0, shift, mix=0.5, n_floor=1e-3, tol=1e-4):
+    shift = np.array(shift, dtype=np.float64, copy=True)
+    q = np.zeros_like(shift)
+    conv = C.c_int()
+    mq = lib().or_scf_step(shift.shape[0], _p(_c(N_atom, np.float64)), _p(_c(dos_atom, np.float64)),
+                           _p(_c(n0, np.float64)), mix, n_floor, tol, _p(shift), _p(q), C.byref(conv))
+    return shift, q, mq, bool(conv.value)
+
+
+def rotation(u):
+    Rp = np.zeros((3, 3))
+    Rd = np.zeros((5, 5))
+    lib().or_rotation(_p(_c(u, np.float64)), _p(Rp), _p(Rd))
+    return Rp, Rd
+
+
+# --------------------------------------------------------------------------
+def energy_pipeline(wl, shift=None, sel=None, n_max=None, n_exp=None, E_F=None, nl=None):
+    """Whole path for a workload: neighbours -> H -> moments -> recursion ->
+    DOS coefficients -> Fermi level (unless given) -> energies.  With ``sel``
+    only those atoms' moments and energies are computed and ``E_F`` must be
+    given."""
+    n_max = wl.n_max if n_max is None else n_max
+    n_exp = wl.n_exp if n_exp is None else n_exp
+    if nl is None:
+        nl = neighbours(wl.pos, wl.cell, wl.model["r_cut"])
+    H_on, H_bond = build_H(wl.model, wl.species, nl, shift)
+    mu = moments(nl, H_on, H_bond, n_max, sel)
+    no = H_on.shape[1]
+    rows = mu.reshape(-1, n_max + 1)
+    rec = recursion(rows, n_max)
+    gs = dos_coeffs(rows, rec, n_max, n_exp)
+    Hs = H_on if sel is None else H_on[np.asarray(sel)]
+    if E_F is None:
+        assert sel is None
+        E_F = fermi(gs, rec["a_inf"], rec["b_inf"], float(np.sum(wl.n_elec)))
+    en = energy(gs, rec["a_inf"], rec["b_inf"], Hs, E_F)
+    return {"nl": nl, "H_on": H_on, "H_bond": H_bond, "mu": mu, "rec": rec, "gsig": gs,
+            "E_F": E_F, **en}
+
+
+def scf(wl, shift0=None, mix=0.5, tol=1e-4, max_iter=200, n_floor=1e-3, n_max=None):
+    """Plain local-charge-neutrality cycle; returns (shift, history)."""
+    n = wl.n_atoms
+    shift = np.zeros(n) if shift0 is None else np.array(shift0, float)
+    nl = neighbours(wl.pos, wl.cell, wl.model["r_cut"])
+    hist = []
+    for it in range(max_iter):
+        r = energy_pipeline(wl, shift=shift, nl=nl, n_max=n_max)
+        shift_new, q, mq, conv = scf_step(r["N_atom"], r["dos_atom"], wl.n_elec, shift, mix, n_floor, tol)
+        hist.append({"it": it, "max_dq": mq, "U_total": r["U_total"], "E_F": r["E_F"]})
+        if conv:
+            return shift, hist, r
+        shift = shift_new
+    return shift, hist, r
+
+
+# --------------------------------------------------------------------------
+# MLP reference (NumPy FP64).  Network: x (6) -> tanh(W1 x + b1) (64)
+# -> tanh(W2 h1 + b2) (64) -> W3 h2 + b3 (1); loss = mean squared error.
+# Not from the paper (its warm start of onsite levels, Sec. III "Speed-ups"
+# (ii), is the idea this replaces); parity unpinned beyond finite differences.
+# --------------------------------------------------------------------------
+def mlp_forward(params, x):
+    W1, b1, W2, b2, W3, b3 = params
+    z1 = x @ W1.T + b1
+    h1 = np.tanh(z1)
+    z2 = h1 @ W2.T + b2
+    h2 = np.tanh(z2)
+    y = h2 @ W3.T + b3
+    return y[:, 0], (x, h1, h2)
+
+
+def mlp_loss_grad(params, x, t):
+    W1, b1, W2, b2, W3, b3 = params
+    y, (x, h1, h2) = mlp_forward(params, x)
+    B = x.shape[0]
+    r = y - t
+    loss = np.mean(r * r)
+    gy = (2.0 / B) * r[:, None]            # dL/dy
+    gW3 = gy.T @ h2
+    gb3 = gy.sum(0)
+    gh2 = gy @ W3
+    gz2 = gh2 * (1.0 - h2 * h2)
+    gW2 = gz2.T @ h1
+    gb2 = gz2.sum(0)
+    gh1 = gz2 @ W2
+    gz1 = gh1 * (1.0 - h1 * h1)
+    gW1 = gz1.T @ x
+    gb1 = gz1.sum(0)
+    return loss, [gW1, gb1, gW2, gb2, gW3, gb3]
+
+
+def adam_step(params, grads, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    out_p, out_m, out_v = [], [], []
+    for p, g, mm, vv in zip(params, grads, m, v):
+        mm = b1 * mm + (1 - b1) * g
+        vv = b2 * vv + (1 - b2) * g * g
+        mh = mm / (1 - b1 ** t)
+        vh = vv / (1 - b2 ** t)
+        out_p.append(p - lr * mh / (np.sqrt(vh) + eps))
+        out_m.append(mm)
+        out_v.append(vv)
+    return out_p, out_m, out_v

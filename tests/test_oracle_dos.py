@@ -1,0 +1,247 @@
+"""Pins for the oracle's recursion coefficients, band edges, expansion
+coefficients, electron counts, bond energies and Fermi level (CPU only).
+References: direct Lanczos on the dense Hamiltonian, the closed forms of the
+lowest moments, the semicircle (constant chain) special case, direct kernel
+polynomial expansion, numerical quadrature of the expanded DOS, and the exact
+tight-binding energy of the same periodic cell."""
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate, special
+
+import oracle as O
+import workloads as W
+
+GOLDEN = __import__("os").path.join(__import__("os").path.dirname(__file__), "golden")
+
+
+def _dense(nl, H_on, H_b):
+    n, no = H_on.shape
+    H = np.zeros((n * no, n * no))
+    for i in range(n):
+        H[i * no:(i + 1) * no, i * no:(i + 1) * no] += np.diag(H_on[i])
+        for p in range(nl["row_ptr"][i], nl["row_ptr"][i + 1]):
+            j = nl["nbr_j"][p]
+            H[i * no:(i + 1) * no, j * no:(j + 1) * no] += H_b[p]
+    return H
+
+
+def _lanczos(H, start, steps):
+    """Lanczos with full reorthogonalisation from the unit vector e_start."""
+    D = H.shape[0]
+    V = np.zeros((steps + 2, D))
+    V[0, start] = 1.0
+    a, b = [], [0.0]
+    for n in range(steps + 1):
+        w = H @ V[n] - b[-1] * (V[n - 1] if n > 0 else 0.0)
+        a.append(V[n] @ w)
+        w -= a[-1] * V[n]
+        for _ in range(2):
+            w -= V[: n + 1].T @ (V[: n + 1] @ w)
+        b.append(np.linalg.norm(w))
+        V[n + 1] = w / b[-1]
+    return np.array(a), np.array(b)
+
+
+@pytest.fixture(scope="module")
+def bcc432():
+    rng = np.random.default_rng(9)
+    pos, cell = W.cubic_lattice("bcc", 3.16, 6)
+    pos = W.displace(pos, cell, 0.08, rng)
+    model = W.canonical_d_model(3.8)
+    nl = O.neighbours(pos, cell, 3.8)
+    H_on, H_b = O.build_H(model, np.zeros(432, np.int32), nl)
+    return pos, cell, model, nl, H_on, H_b, _dense(nl, H_on, H_b)
+
+
+@pytest.mark.parametrize("n_max", [9, 18])
+def test_recursion_vs_direct_lanczos(bcc432, n_max):
+    pos, cell, model, nl, H_on, H_b, H = bcc432
+    sel = np.array([0, 17, 230], np.int32)
+    mu = O.moments(nl, H_on, H_b, n_max, sel).reshape(-1, n_max + 1)
+    rec = O.recursion(mu, n_max)
+    na, nb = O.n_a(n_max), O.n_b(n_max)
+    tol = 1e-12 if n_max <= 9 else 1e-9
+    for r in range(mu.shape[0]):
+        i, al = sel[r // 5], r % 5
+        a, b = _lanczos(H, 5 * i + al, na)
+        np.testing.assert_allclose(rec["a"][r], a[:na], atol=tol)
+        np.testing.assert_allclose(rec["b"][r, 1:nb + 1], b[1:nb + 1], atol=tol)
+    # closed forms of App. B.3 for the lowest moments
+    a0, a1, b1 = rec["a"][:, 0], rec["a"][:, 1], rec["b"][:, 1]
+    np.testing.assert_allclose(mu[:, 1], a0, atol=1e-13)
+    np.testing.assert_allclose(mu[:, 2], a0 ** 2 + b1 ** 2, atol=1e-13)
+    np.testing.assert_allclose(mu[:, 3], a0 ** 3 + 2 * a0 * b1 ** 2 + a1 * b1 ** 2, atol=1e-13)
+
+
+def _semicircle_moments(bb, n_max, centre=0.0):
+    """Moments of a semicircle of half-width 2b about ``centre``:
+    mu_2k = Catalan(k) b^2k (centred), shifted binomially."""
+    c = [math.comb(2 * k, k) // (k + 1) for k in range(n_max + 1)]
+    cen = np.array([c[n // 2] * bb ** n if n % 2 == 0 else 0.0 for n in range(n_max + 1)])
+    return np.array([sum(math.comb(n, l) * centre ** (n - l) * cen[l] for l in range(n + 1))
+                     for n in range(n_max + 1)])
+
+
+def test_semicircle_special_case():
+    """Constant chain a_n = c, b_n = b: its moments give back the constants,
+    the Gershgorin terminator equals the chain, sigma_m = delta_m0, and at
+    E_F = c the orbital is half filled with U = -4b/(3 pi)."""
+    gold = dict(l.split() for l in open(f"{GOLDEN}/semicircle.txt") if l.strip() and not l.startswith("#"))
+    bb, c, n_max, n_exp = 0.8, 0.3, 12, 200
+    mu = _semicircle_moments(bb, n_max, centre=c)[None]
+    rec = O.recursion(mu, n_max)
+    np.testing.assert_allclose(rec["a"], c, atol=1e-12)
+    np.testing.assert_allclose(rec["b"][0, 1:], bb, atol=1e-12)
+    assert abs(rec["a_inf"][0] - c) < 1e-12 and abs(rec["b_inf"][0] - bb) < 1e-12
+    gs = O.dos_coeffs(mu, rec, n_max, n_exp)
+    assert abs(gs[0, 0] - 1.0) < 1e-12 and np.max(np.abs(gs[0, 1:])) < 1e-10
+    N, U, D = O.orbital_NU(gs[0], rec["a_inf"][0], rec["b_inf"][0], c, c)
+    assert abs(N - float(gold["N_half"])) < 1e-12
+    assert abs(U - float(gold["U_half_per_b"]) * bb) < 1e-12
+    assert abs(D - 1.0 / (math.pi * bb)) < 1e-10
+
+
+def test_gershgorin_contains_chain_spectrum(bcc432):
+    pos, cell, model, nl, H_on, H_b, H = bcc432
+    n_max = 18
+    mu = O.moments(nl, H_on, H_b, n_max, np.arange(0, 432, 37, dtype=np.int32)).reshape(-1, n_max + 1)
+    rec = O.recursion(mu, n_max)
+    na, nb = O.n_a(n_max), O.n_b(n_max)
+    for r in range(mu.shape[0]):
+        T = np.diag(rec["a"][r]) + np.diag(rec["b"][r, 1:na], 1) + np.diag(rec["b"][r, 1:na], -1)
+        ev = np.linalg.eigvalsh(T)
+        lo = rec["a_inf"][r] - 2 * rec["b_inf"][r]
+        hi = rec["a_inf"][r] + 2 * rec["b_inf"][r]
+        assert ev.min() >= lo - 1e-12 and ev.max() <= hi + 1e-12
+
+
+def test_expansion_coefficients_vs_direct_kpm_and_chain(bcc432):
+    """sigma_m for m <= n_max by the moment route equals <e|U_m(H^)|e> from a
+    direct Chebyshev vector recursion on the dense Hamiltonian, and equals the
+    chain route; the Jackson factors run from 1 to 0."""
+    pos, cell, model, nl, H_on, H_b, H = bcc432
+    n_max, n_exp = 9, 200
+    sel = np.array([3, 100], np.int32)
+    mu = O.moments(nl, H_on, H_b, n_max, sel).reshape(-1, n_max + 1)
+    rec = O.recursion(mu, n_max)
+    gs, sc = O.dos_coeffs(mu, rec, n_max, n_exp, with_chain=True)
+    g = O.jackson(n_exp)
+    assert g[0] == 1.0 and abs(g[-1]) < 1e-15 and np.all(np.diff(g) <= 1e-15)
+    sig = gs[:, : n_max + 1] / g[: n_max + 1]
+    np.testing.assert_allclose(sc, sig, atol=1e-11)
+    for r in range(mu.shape[0]):
+        i, al = sel[r // 5], r % 5
+        Hh = (H - rec["a_inf"][r] * np.eye(H.shape[0])) / (2 * rec["b_inf"][r])
+        u0 = np.zeros(H.shape[0]); u0[5 * i + al] = 1.0
+        um1, u = np.zeros_like(u0), u0.copy()
+        for m in range(n_max + 1):
+            assert abs(u0 @ u - sig[r, m]) < 1e-11
+            um1, u = u, 2 * Hh @ u - um1
+
+
+def test_counts_and_energies_vs_quadrature(bcc432):
+    """N and U per orbital equal the numerical integral of the expanded DOS
+    n(eps) = (2/pi) sqrt(1 - eps^2) sum_m g_m sigma_m U_m(eps) (Eq. nialpha),
+    and the DOS is non-negative."""
+    pos, cell, model, nl, H_on, H_b, H = bcc432
+    n_max, n_exp = 9, 200
+    mu = O.moments(nl, H_on, H_b, n_max, np.array([11], np.int32)).reshape(-1, n_max + 1)
+    rec = O.recursion(mu, n_max)
+    gs = O.dos_coeffs(mu, rec, n_max, n_exp)
+    ai, bi = rec["a_inf"][0], rec["b_inf"][0]
+    m = np.arange(n_exp + 1)
+
+    def n_eps(e):
+        return 2 / np.pi * np.sqrt(max(0.0, 1 - e * e)) * np.sum(gs[0] * special.eval_chebyu(m, e))
+
+    grid = np.linspace(-0.999, 0.999, 801)
+    assert min(n_eps(e) for e in grid) > -1e-10
+    for E in (ai - 1.5 * bi, ai + 0.3 * bi, ai + 1.9 * bi):
+        ef = (E - ai) / (2 * bi)
+        N_q = integrate.quad(n_eps, -1, ef, limit=400, epsabs=1e-13)[0]
+        U_q = integrate.quad(lambda e: (ai + 2 * bi * e - H_on[0, 0]) * n_eps(e), -1, ef,
+                             limit=400, epsabs=1e-13)[0] * 1.0
+        N, U, D = O.orbital_NU(gs[0], ai, bi, H_on[0, 0], E)
+        assert abs(N - N_q) < 1e-9
+        assert abs(U - U_q) < 1e-9
+        assert abs(D - n_eps(ef) / (2 * bi)) < 1e-9
+    # outside the band: empty / full, U over the whole band
+    N, U, _ = O.orbital_NU(gs[0], ai, bi, 0.0, ai - 3 * bi)
+    assert abs(N) < 1e-14 and abs(U) < 1e-14
+    N, U, _ = O.orbital_NU(gs[0], ai, bi, 0.0, ai + 3 * bi)
+    U_q = integrate.quad(lambda e: (ai + 2 * bi * e) * n_eps(e), -1, 1, limit=400, epsabs=1e-13)[0]
+    assert abs(N - 1.0) < 1e-12 and abs(U - U_q) < 1e-9
+
+
+def test_fermi_level_and_gauge():
+    wl = W.bcc_small()
+    r = O.energy_pipeline(wl)
+    ne = float(np.sum(wl.n_elec))
+    assert abs(O.count(r["gsig"], r["rec"]["a_inf"], r["rec"]["b_inf"], r["E_F"]) - ne) < 1e-10 * ne
+    assert abs(r["N_atom"].sum() - ne) < 1e-10 * ne
+    # monotone electron count
+    Es = np.linspace(r["E_F"] - 1, r["E_F"] + 1, 21)
+    cnt = [O.count(r["gsig"], r["rec"]["a_inf"], r["rec"]["b_inf"], E) for E in Es]
+    assert np.all(np.diff(cnt) >= 0)
+    # a uniform onsite shift c moves E_F by c and leaves N_i and U_i unchanged
+    r2 = O.energy_pipeline(wl, shift=np.full(wl.n_atoms, 0.37))
+    assert abs(r2["E_F"] - r["E_F"] - 0.37) < 1e-9
+    np.testing.assert_allclose(r2["U_atom"], r["U_atom"], atol=1e-8)
+    np.testing.assert_allclose(r2["N_atom"], r["N_atom"], atol=1e-8)
+
+
+def test_bond_energy_converges_to_exact_tight_binding(bcc432):
+    """As the number of moments grows, the BOP bond energy of a displaced
+    432-atom bcc cell approaches the exact Gamma-point tight-binding energy
+    2 sum_occ e_k (zero onsite levels; fractional filling at E_F)."""
+    pos, cell, model, nl, H_on, H_b, H = bcc432
+    ne = 4.5 * 432
+    w = np.linalg.eigvalsh(H)
+    nocc = ne / 2.0
+    full = int(math.floor(nocc))
+    U_tb = 2 * (np.sum(w[:full]) + (nocc - full) * w[full])
+    errs = []
+    for n_max in (5, 9, 13, 17):
+        wl = W.Workload("c", pos, cell, np.zeros(432, np.int32), model, n_max, 200, np.full(432, 4.5))
+        r = O.energy_pipeline(wl, nl=nl)
+        errs.append(abs(r["U_total"] - U_tb) / 432)
+    assert errs[-1] < errs[0]
+    assert errs[-1] < 0.02          # eV / atom
+
+
+def test_scf_fixed_point_and_invariants():
+    rng = np.random.default_rng(5)
+    pos, cell = W.cubic_lattice("bcc", 2.87, 3)
+    spc = W.random_species(54, [27, 27], rng)
+    wl = W.Workload("a", W.wrap(pos, cell), cell, spc, W.canonical_d_model(3.5, onsite_d=(0.0, 0.8)),
+                    8, 200, np.where(spc == 0, 6.0, 5.0))
+    shift, hist, r = O.scf(wl, mix=0.5, tol=1e-4, max_iter=100)
+    assert hist[-1]["max_dq"] < 1e-4 and len(hist) < 100
+    assert abs(np.mean(shift)) < 1e-12
+    assert abs(r["N_atom"].sum() - wl.n_elec.sum()) < 1e-8
+    # the B atoms (higher bare level, fewer electrons wanted) end up lower
+    assert np.mean(shift[spc == 1]) < np.mean(shift[spc == 0])
+
+
+def test_mlp_gradients_vs_finite_differences():
+    rng = np.random.default_rng(0)
+    sizes = [(64, 6), (64,), (64, 64), (64,), (1, 64), (1,)]
+    params = [rng.normal(scale=0.3, size=s) for s in sizes]
+    x = rng.normal(size=(37, 6))
+    t = rng.normal(size=37)
+    loss, grads = O.mlp_loss_grad(params, x, t)
+    h = 1e-6
+    for k, p in enumerate(params):
+        flat = p.reshape(-1)
+        for idx in rng.choice(flat.size, size=min(6, flat.size), replace=False):
+            old = flat[idx]
+            flat[idx] = old + h
+            lp, _ = O.mlp_loss_grad(params, x, t)
+            flat[idx] = old - h
+            lm, _ = O.mlp_loss_grad(params, x, t)
+            flat[idx] = old
+            fd = (lp - lm) / (2 * h)
+            g = grads[k].reshape(-1)[idx]
+            assert abs(fd - g) <= 1e-7 * max(1.0, abs(g))
