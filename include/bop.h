@@ -1,0 +1,262 @@
+/*
+ * bop.h — C ABI of the MI355X (gfx950) analytic-BOP energy path.
+ *
+ * The path follows Hammerschmidt et al., "BOPfox program for tight-binding
+ * and analytic bond-order potential calculations" (arXiv:1803.07491):
+ *
+ *   bop_build_neighbours   periodic neighbour list          (Sec. II "Initialisation")
+ *   bop_build_H            two-centre Slater-Koster blocks  (App. A.2.1, App. D)
+ *   bop_moments_plan / bop_moments
+ *                          orbital moments <ia|H^n|ia>      (App. B.3, Eqs. momDOS,
+ *                                                            xi_rec, xi_invert, xi_merge)
+ *   bop_recursion          recursion coefficients + band    (App. B.3 Eqs. momtoa,
+ *                          edges (Gershgorin terminator)     momtob; App. B.5)
+ *   bop_energy             expansion coefficients, Jackson  (App. B.2-B.4, App. A.1
+ *                          damping, Fermi level, N and U     Eq. TB-Ubond, Sec. II)
+ *   bop_scf_step           one local-charge-neutrality step (App. A.3 Eq. BOP_LCN)
+ *
+ * Conventions (all calls):
+ *  - Array arguments are device pointers to caller-owned, contiguous, row-major
+ *    memory unless marked [host].  The library allocates no device memory; any
+ *    scratch comes from a caller buffer whose size a *_workspace_size /
+ *    *_plan call reports.
+ *  - Every call takes the HIP stream last, only enqueues work on it and returns;
+ *    exceptions (documented per call) read a count back to the host.
+ *    Buffers must stay alive until the stream's work has completed.
+ *  - Return value: BOP_OK or a negative BOP_E_* code; bop_last_error() gives a
+ *    thread-local message for the last failure.  Device-side conditions never
+ *    abort: they set bits in per-row `flags` words (see BOP_FLAG_*).
+ *  - Energies in eV, lengths in Angstrom.  Orbital order per atom: d-only
+ *    (n_orb = 5): 3z^2-r^2, zx, yz, x^2-y^2, xy; s,p,d (n_orb = 9): s, p_z, p_x,
+ *    p_y, then the five d orbitals (Eq. Hij).
+ */
+#ifndef BOP_H
+#define BOP_H
+
+#include <stddef.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes -------------------------------------------------------- */
+#define BOP_OK                0
+#define BOP_E_ARG            -1   /* null pointer, negative or inconsistent size */
+#define BOP_E_CAPACITY       -2   /* output too small; the required size is reported */
+#define BOP_E_HIP            -3   /* a HIP runtime call failed */
+#define BOP_E_UNSUPPORTED    -4   /* n_orb, n_max, n_exp or dtype outside the supported set */
+#define BOP_E_NOT_CONVERGED  -5
+
+/* ---- per-row flags (int, set on the device) ------------------------------- */
+#define BOP_FLAG_BREAKDOWN   1    /* recursion chain ended early; level in bits 8.. */
+#define BOP_FLAG_NONFINITE   2    /* a non-finite moment was seen */
+#define BOP_FLAG_OUTSIDE     4    /* E_F lies outside this orbital's band */
+#define BOP_FLAG_NARROW      8    /* band width raised to its floor (1e-6 eV) */
+
+/* ---- compute types for H and the H.X products ----------------------------- */
+#define BOP_F64   0
+#define BOP_F32   1
+#define BOP_BF16  2
+
+/* ---- tight-binding model (host struct, passed by value to kernels) -------- */
+#define BOP_MAX_SPECIES 3
+#define BOP_N_CHANNELS 14
+/* channel order; first letter = orbital on the atom the bond starts from,
+ * second = orbital on the atom it points to; last letter = sigma/pi/delta */
+enum { BOP_SSS, BOP_SPS, BOP_PSS, BOP_SDS, BOP_DSS, BOP_PPS, BOP_PPP,
+       BOP_PDS, BOP_DPS, BOP_PDP, BOP_DPP, BOP_DDS, BOP_DDP, BOP_DDD };
+#define BOP_FORM_POWER 0          /* beta(r) = beta0 (r0 / r)^q          */
+#define BOP_FORM_EXP   1          /* beta(r) = beta0 exp(-q (r - r0))    */
+
+typedef struct bop_model {
+    int n_species;                /* 1 .. BOP_MAX_SPECIES */
+    int n_orb;                    /* 5 (d) or 9 (s, p, d) */
+    double r_cut;                 /* bond cutoff */
+    double d_cut;                 /* width of the cosine taper Eq. (cutoff); 0 = hard */
+    double onsite[BOP_MAX_SPECIES][3];              /* s, p, d levels */
+    unsigned char form[BOP_MAX_SPECIES * BOP_MAX_SPECIES][BOP_N_CHANNELS];
+    double beta0[BOP_MAX_SPECIES * BOP_MAX_SPECIES][BOP_N_CHANNELS];
+    double r0[BOP_MAX_SPECIES * BOP_MAX_SPECIES][BOP_N_CHANNELS];
+    double q[BOP_MAX_SPECIES * BOP_MAX_SPECIES][BOP_N_CHANNELS];
+} bop_model;                      /* index [si * n_species + sj][channel] */
+
+/* ---- messages ------------------------------------------------------------ */
+/* Copies the calling thread's last error message into buf (NUL-terminated,
+ * truncated to n bytes); returns its full length. */
+int bop_last_error(char *buf, size_t n);
+
+/* =========================================================================
+ * Neighbour list (Sec. II "Initialisation": pairs within the cutoff via cell
+ * lists; the paper's ghost cells appear here as explicit image shifts).
+ *
+ * All (j, S) with 0 < |d|^2 < r_cut^2, d = (r_j - r_i) + S.A evaluated in FP64
+ * in the fixed order (r_j - r_i) + ((s1 a1 + s2 a2) + s3 a3), |d|^2 =
+ * (dx dx + dy dy) + dz dz, without contraction: the list is bit-exact and
+ * deterministic.  The cell is periodic along all three vectors.  Rows are
+ * atoms in input order; entries are sorted by (j, s1, s2, s3).  (i, i, 0) is
+ * excluded; other images of i and repeated j with different S are included.
+ *
+ *  pos        [N][3]  positions (fractional coordinates need not be wrapped)
+ *  cell       [host] [3][3], rows = a1, a2, a3
+ *  capacity   entries the output arrays can hold
+ *  row_ptr    [N+1], nbr_j [cap], nbr_shift [cap][3], nbr_d [cap][3]
+ *  order      [N] or NULL: atoms in spatial (blocked cell-list) order, used
+ *             to form compact moment tiles
+ *  n_pairs    [host] out: number of entries.  This call waits for the count
+ *             (one device-to-host copy).  If it exceeds `capacity` nothing is
+ *             written and BOP_E_CAPACITY is returned.
+ *  ws         scratch of bop_neighbours_workspace_size() bytes
+ * ========================================================================= */
+size_t bop_neighbours_workspace_size(int n_atoms, const double *cell, double r_cut);
+int bop_build_neighbours(int n_atoms, const double *pos, const double *cell, double r_cut,
+                         long capacity, int *row_ptr, int *nbr_j, int *nbr_shift,
+                         double *nbr_d, int *order, long *n_pairs,
+                         void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* =========================================================================
+ * Hamiltonian (App. A.2.1 Eqs. Hij, cutoff, Hij_rot; App. D rotations).
+ *
+ *  H_on   [N][n_orb] FP64: onsite level of the atom's species for the
+ *         orbital's l, plus shift[i] (shift may be NULL).
+ *  H_bond [P][n_orb][n_orb] in `dtype` (BOP_F64, BOP_F32 or BOP_BF16):
+ *         block p = <i a|H|j b> for pair p = (i -> j), built in the bond frame
+ *         (z' along d) and rotated as R^T H^(b) R, where R[a][b] is App. D's
+ *         matrix with a = bond-frame orbital, b = global orbital, theta the
+ *         polar angle and phi the azimuth of d (taken from direction cosines).
+ *         H_bond = NULL updates H_on only (self-consistency steps).
+ * ========================================================================= */
+int bop_build_H(const bop_model *model /*[host]*/, int n_atoms, const int *species,
+                const double *shift, const int *row_ptr, const int *nbr_j,
+                const double *nbr_d, long n_pairs, int dtype,
+                double *H_on, void *H_bond, hipStream_t stream);
+
+/* =========================================================================
+ * Moments (App. B.3).  mu[i][a][n] = <i a|H^n|i a>, n = 0..n_max, where H is
+ * the folded periodic (Gamma-point) Hamiltonian: H[i][j] = sum over the
+ * list's images of H_bond, plus diag(H_on).
+ *
+ * Interference paths are built iteratively, X^k = H X^(k-1) (Eq. xi_rec), for
+ * tiles of `tile_atoms` atoms whose unit start vectors form the columns of X;
+ * moments follow from merging path halves (Eqs. xi_invert, xi_merge):
+ * mu_2k = <X^k, X^k>, mu_2k-1 = <X^(k-1), X^k>, and mu_2K+1 = <X^K, H X^K>.
+ * X is stored and multiplied in `dtype`; mu is accumulated and returned in FP64.
+ *
+ * bop_moments_plan: walks the neighbour graph once (device breadth-first
+ * search per tile), waits for it, and fills `plan` with the sizes the moment
+ * kernel needs, including plan->ws_bytes.  It uses `scratch`
+ * (bop_moments_plan_scratch_size bytes) and must be redone when the
+ * neighbour list changes (not when only H_on or H_bond change).
+ * `order` (may be NULL = input order) groups atoms into tiles.
+ * ========================================================================= */
+typedef struct bop_tuning {
+    int tile_atoms;      /* atoms per tile; 0 = as many as fit one wavefront */
+    int block_threads;   /* 256, 512 or 1024; 0 = default */
+    int n_blocks;        /* persistent workgroups; 0 = default (2 per CU) */
+} bop_tuning;
+
+typedef struct bop_plan {
+    int n_atoms, n_orb, n_max, dtype;
+    int tile_atoms, n_tiles, block_threads, n_blocks;
+    int deg_max;         /* longest neighbour row */
+    int rows_cap;        /* largest tile support (rows of X) */
+    size_t ws_bytes;     /* workspace bop_moments needs */
+} bop_plan;
+
+size_t bop_moments_plan_scratch_size(int n_atoms);
+int bop_moments_plan(int n_atoms, int n_orb, int n_max, int dtype,
+                     const int *row_ptr, const int *nbr_j, const int *order,
+                     const bop_tuning *tuning /*[host] or NULL*/,
+                     void *scratch, size_t scratch_bytes,
+                     bop_plan *plan /*[host] out*/, hipStream_t stream);
+int bop_moments(const bop_plan *plan /*[host]*/, const int *row_ptr,
+                const int *nbr_j, const int *order, const double *H_on,
+                const void *H_bond, double *mu, void *ws, size_t ws_bytes,
+                hipStream_t stream);
+
+/* =========================================================================
+ * Recursion coefficients and terminator (App. B.3, App. B.5), FP64.
+ *
+ * Per row (one orbital; mu normalised by its mu_0): a_n for n < n_a =
+ * (n_max-1)/2 + 1 and b_n for 1 <= n <= n_b = n_max/2 (b[.][0] = 0), from the
+ * moments via the c_j^n recursion, with b_(n+1) taken as the norm of the next
+ * unnormalised Lanczos vector (the printed Eq. momtob needs c^n before b_n
+ * is known).  Breakdown (b_(n+1)^2 <= 1e-14 (mu_2 - mu_1^2)) sets b_(n+1) = 0,
+ * repeats a_n, and flags BOP_FLAG_BREAKDOWN | level << 8.
+ * bw_mode 0: Gershgorin band edges Eq. (gershogorin) over rows n < n_a (b_0 = 0,
+ * b_(n_a) used only if computed); a_inf = (top + bottom)/2, b_inf =
+ * (top - bottom)/4.  bw_mode 1: the given global a_glob, b_glob (option viii).
+ *
+ *  mu [n_rows][n_max+1] -> a [n_rows][n_a], b [n_rows][n_b+1],
+ *  a_inf, b_inf, flags [n_rows].   n_max <= 40.
+ * ========================================================================= */
+int bop_recursion(int n_rows, int n_max, const double *mu, int bw_mode,
+                  double a_glob, double b_glob, double *a, double *b,
+                  double *a_inf, double *b_inf, int *flags, hipStream_t stream);
+
+/* =========================================================================
+ * Bond energy (App. B.2-B.4, App. A.1 Eq. TB-Ubond; Fermi level Sec. II), FP64.
+ *
+ * Per orbital: sigma_m = sum_n p_mn mu^_n for m <= n_max (Eq. sigma_i) and, for
+ * n_max < m <= n_exp, the chain recursion of App. B.4 with the constant
+ * terminator (evaluated exactly on the computed levels plus one delay level,
+ * since the free terminator tail only delays its input); damping g_m =
+ * g^J_(m+1)/g^J_1 with the Jackson kernel of length n_exp.  Then with
+ * cos(phi) = clamp((E - a_inf)/(2 b_inf), -1, 1):
+ *   N_ia = sum_m g sigma_m chi^_(m+1)(phi),
+ *   U_ia = b_inf sum_m g sigma_m [chi^_(m+2) + chi^_m](phi) + (a_inf - E_ia) N_ia
+ *          (= integral up to E of (E' - E_ia) n_ia(E') dE'),
+ *   n_ia(E) = sum_m g sigma_m sin((m+1) phi) / (pi b_inf).
+ * Per atom, both spins: N_atom = 2 sum_a N_ia, U_atom = 2 sum_a U_ia,
+ * dos_atom = 2 sum_a n_ia(E_F); U_total = sum_i U_atom.
+ *
+ *  ef_mode 0: E_F [device, 1 double] out: bisection on 2 sum N_ia(E) = n_elec
+ *             over [min(a_inf - 2 b_inf), max(a_inf + 2 b_inf)], halving while
+ *             the midpoint differs from both ends (at most 64 times).
+ *  ef_mode 1: E_F [device] in: energies at the given level.
+ *  ws: bop_energy_workspace_size(n_atoms, n_orb, n_exp) bytes.
+ *  n_exp <= 1024 (default used by the paper's example: 200).
+ * ========================================================================= */
+size_t bop_energy_workspace_size(int n_atoms, int n_orb, int n_exp);
+int bop_energy(int n_atoms, int n_orb, int n_max, int n_exp, const double *mu,
+               const double *a, const double *b, const double *a_inf,
+               const double *b_inf, const double *H_on, double n_elec /*[host]*/,
+               int ef_mode, double *E_F, double *N_atom, double *U_atom,
+               double *dos_atom, double *U_total, int *flags,
+               void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* =========================================================================
+ * One local-charge-neutrality step (App. A.3 Eq. BOP_LCN with the linear
+ * input/output mixing of Sec. II "Self-consistency").  One onsite shift per
+ * atom: rebuild H_on from `shift`, then moments, recursion and energy as
+ * above, then q_i = N_i - n0_i; if max|q_i| < tol: *converged = 1 and shift is
+ * unchanged; else shift_i += mix q_i / max(n_i(E_F), n_floor) followed by
+ * removal of the mean shift (shift + c with E_F + c is the same state).
+ * Everything stays on the device; the host loops until *converged.
+ * ========================================================================= */
+typedef struct bop_system {
+    bop_model model;
+    int n_atoms, n_max, n_exp, dtype;
+    const int *species;            /* [N] */
+    const double *n0;              /* [N] reference electrons per atom */
+    const int *row_ptr, *nbr_j, *order;
+    long n_pairs;
+    double *H_on;                  /* [N][n_orb] (rebuilt each step) */
+    const void *H_bond;            /* [P][n_orb][n_orb] in dtype */
+    bop_plan plan;
+    void *moments_ws; size_t moments_ws_bytes;
+    double *mu, *a, *b, *a_inf, *b_inf;
+    int *flags;
+    void *energy_ws; size_t energy_ws_bytes;
+    double n_elec;                 /* total electrons, both spins */
+    double *E_F, *N_atom, *U_atom, *dos_atom, *U_total;   /* outputs */
+} bop_system;
+
+int bop_scf_step(const bop_system *sys /*[host]*/, double mix, double n_floor,
+                 double tol, double *shift, double *q, double *max_dq,
+                 int *converged, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BOP_H */

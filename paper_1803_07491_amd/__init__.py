@@ -1,0 +1,388 @@
+"""MI355X (gfx950) analytic-BOP energy path — Python binding.
+
+Thin ctypes layer over ``libbop.so`` (C ABI in ``include/bop.h``): it checks
+tensor dtypes, devices and contiguity, passes device pointers and the current
+HIP stream, and allocates the caller-side buffers the ABI asks for.  Every
+step of the computation runs in the library's HIP kernels; if the library is
+not built this module raises instead of computing anything itself.
+
+Entry points mirror the ABI: ``build_neighbours``, ``build_H``,
+``moments_plan`` / ``moments``, ``recursion``, ``energy``, ``scf_step``;
+``EnergyPath`` strings them together for a structure.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbop.so")
+
+BOP_OK, BOP_E_ARG, BOP_E_CAPACITY, BOP_E_HIP, BOP_E_UNSUPPORTED, BOP_E_NOT_CONVERGED = 0, -1, -2, -3, -4, -5
+F64, F32, BF16 = 0, 1, 2
+DTYPES = {"f64": F64, "f32": F32, "bf16": BF16}
+MAX_SPECIES = 3
+N_CHANNELS = 14
+CHANNELS = ("sss", "sps", "pss", "sds", "dss", "pps", "ppp",
+            "pds", "dps", "pdp", "dpp", "dds", "ddp", "ddd")
+
+FLAG_BREAKDOWN, FLAG_NONFINITE, FLAG_OUTSIDE, FLAG_NARROW = 1, 2, 4, 8
+
+
+class BopError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"bop error {code}: {msg}")
+        self.code = code
+
+
+class Model(C.Structure):
+    _fields_ = [
+        ("n_species", C.c_int),
+        ("n_orb", C.c_int),
+        ("r_cut", C.c_double),
+        ("d_cut", C.c_double),
+        ("onsite", (C.c_double * 3) * MAX_SPECIES),
+        ("form", (C.c_ubyte * N_CHANNELS) * (MAX_SPECIES * MAX_SPECIES)),
+        ("beta0", (C.c_double * N_CHANNELS) * (MAX_SPECIES * MAX_SPECIES)),
+        ("r0", (C.c_double * N_CHANNELS) * (MAX_SPECIES * MAX_SPECIES)),
+        ("q", (C.c_double * N_CHANNELS) * (MAX_SPECIES * MAX_SPECIES)),
+    ]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("tile_atoms", C.c_int), ("block_threads", C.c_int), ("n_blocks", C.c_int)]
+
+
+class Plan(C.Structure):
+    _fields_ = [("n_atoms", C.c_int), ("n_orb", C.c_int), ("n_max", C.c_int), ("dtype", C.c_int),
+                ("tile_atoms", C.c_int), ("n_tiles", C.c_int), ("block_threads", C.c_int),
+                ("n_blocks", C.c_int), ("deg_max", C.c_int), ("rows_cap", C.c_int),
+                ("ws_bytes", C.c_size_t)]
+
+
+P = C.c_void_p
+
+
+class System(C.Structure):
+    _fields_ = [
+        ("model", Model),
+        ("n_atoms", C.c_int), ("n_max", C.c_int), ("n_exp", C.c_int), ("dtype", C.c_int),
+        ("species", P), ("n0", P), ("row_ptr", P), ("nbr_j", P), ("order", P),
+        ("n_pairs", C.c_long),
+        ("H_on", P), ("H_bond", P),
+        ("plan", Plan),
+        ("moments_ws", P), ("moments_ws_bytes", C.c_size_t),
+        ("mu", P), ("a", P), ("b", P), ("a_inf", P), ("b_inf", P), ("flags", P),
+        ("energy_ws", P), ("energy_ws_bytes", C.c_size_t),
+        ("n_elec", C.c_double),
+        ("E_F", P), ("N_atom", P), ("U_atom", P), ("dos_atom", P), ("U_total", P),
+    ]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with __graft_entry__.build() "
+                           "(the BOP path has no CPU fallback)")
+    lib = C.CDLL(path)
+    lib.bop_last_error.argtypes = [C.c_char_p, C.c_size_t]
+    lib.bop_neighbours_workspace_size.restype = C.c_size_t
+    lib.bop_neighbours_workspace_size.argtypes = [C.c_int, P, C.c_double]
+    lib.bop_build_neighbours.argtypes = [C.c_int, P, P, C.c_double, C.c_long, P, P, P, P, P,
+                                         C.POINTER(C.c_long), P, C.c_size_t, P]
+    lib.bop_build_H.argtypes = [C.POINTER(Model), C.c_int, P, P, P, P, P, C.c_long, C.c_int, P, P, P]
+    lib.bop_moments_plan_scratch_size.restype = C.c_size_t
+    lib.bop_moments_plan_scratch_size.argtypes = [C.c_int]
+    lib.bop_moments_plan.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, P, P, P, C.POINTER(Tuning),
+                                     P, C.c_size_t, C.POINTER(Plan), P]
+    lib.bop_moments.argtypes = [C.POINTER(Plan), P, P, P, P, P, P, P, C.c_size_t, P]
+    lib.bop_recursion.argtypes = [C.c_int, C.c_int, P, C.c_int, C.c_double, C.c_double, P, P, P, P, P, P]
+    lib.bop_energy_workspace_size.restype = C.c_size_t
+    lib.bop_energy_workspace_size.argtypes = [C.c_int, C.c_int, C.c_int]
+    lib.bop_energy.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, P, P, P, P, P, P, C.c_double, C.c_int,
+                               P, P, P, P, P, P, P, C.c_size_t, P]
+    lib.bop_scf_step.argtypes = [C.POINTER(System), C.c_double, C.c_double, C.c_double, P, P, P, P, P]
+    _lib = lib
+    return lib
+
+
+def _check(rc):
+    if rc != BOP_OK:
+        buf = C.create_string_buffer(512)
+        _lib.bop_last_error(buf, 512)
+        raise BopError(rc, buf.value.decode())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dev(t, dtype=None, name="tensor"):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(_torch().cuda.current_stream().cuda_stream)
+
+
+def _bytes(n, device):
+    torch = _torch()
+    return torch.empty(max(int(n), 1), dtype=torch.uint8, device=device)
+
+
+# ---------------------------------------------------------------------------
+def model_struct(model: dict) -> Model:
+    """Fill the ABI's model struct from a plain model dict (onsite levels,
+    bond-integral tables per ordered species pair and channel)."""
+    m = Model()
+    ns = model["n_species"]
+    if ns > MAX_SPECIES:
+        raise ValueError(f"at most {MAX_SPECIES} species")
+    m.n_species = ns
+    m.n_orb = model["n_orb"]
+    m.r_cut = model["r_cut"]
+    m.d_cut = model.get("d_cut", 0.0)
+    for s in range(ns):
+        for l in range(3):
+            m.onsite[s][l] = model["onsite"][s][l]
+    for pr in range(MAX_SPECIES * MAX_SPECIES):
+        for c in range(N_CHANNELS):
+            m.r0[pr][c] = 1.0
+    for (si, sj), chans in model["bonds"].items():
+        pr = si * ns + sj
+        for name, (f, b0, r0, q) in chans.items():
+            c = CHANNELS.index(name)
+            m.form[pr][c] = f
+            m.beta0[pr][c] = b0
+            m.r0[pr][c] = r0
+            m.q[pr][c] = q
+    return m
+
+
+@dataclass
+class Neighbours:
+    row_ptr: object
+    nbr_j: object
+    nbr_shift: object
+    nbr_d: object
+    order: object
+    n_pairs: int
+
+
+def build_neighbours(pos, cell, r_cut, capacity=None) -> Neighbours:
+    """Periodic neighbour list on the GPU (``bop_build_neighbours``).
+    ``pos`` [N,3] float64 device tensor, ``cell`` 3x3 (host, rows = a1..a3)."""
+    torch = _torch()
+    lib = load()
+    _dev(pos, torch.float64, "pos")
+    n = pos.shape[0]
+    dev = pos.device
+    cell_np = np.ascontiguousarray(cell, dtype=np.float64).reshape(3, 3)
+    cptr = cell_np.ctypes.data_as(C.c_void_p)
+    wsb = lib.bop_neighbours_workspace_size(n, cptr, float(r_cut))
+    if wsb == 0:
+        raise ValueError("invalid cell or cutoff")
+    ws = _bytes(wsb, dev)
+    if capacity is None:
+        vol = abs(np.linalg.det(cell_np))
+        dens = n / vol if vol > 0 else 0.0
+        capacity = int(n * (4.0 / 3.0 * np.pi * r_cut ** 3 * dens * 1.5 + 16))
+    row_ptr = torch.empty(n + 1, dtype=torch.int32, device=dev)
+    order = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    for _ in range(2):
+        nbr_j = torch.empty(max(capacity, 1), dtype=torch.int32, device=dev)
+        nbr_shift = torch.empty((max(capacity, 1), 3), dtype=torch.int32, device=dev)
+        nbr_d = torch.empty((max(capacity, 1), 3), dtype=torch.float64, device=dev)
+        npairs = C.c_long(0)
+        rc = lib.bop_build_neighbours(n, _ptr(pos), cptr, float(r_cut), capacity, _ptr(row_ptr), _ptr(nbr_j),
+                                      _ptr(nbr_shift), _ptr(nbr_d), _ptr(order), C.byref(npairs), _ptr(ws),
+                                      wsb, _stream())
+        if rc == BOP_E_CAPACITY and npairs.value > capacity:
+            capacity = int(npairs.value)
+            continue
+        _check(rc)
+        P_ = int(npairs.value)
+        return Neighbours(row_ptr, nbr_j[:P_], nbr_shift[:P_], nbr_d[:P_], order[:n], P_)
+    raise RuntimeError("neighbour capacity retry failed")
+
+
+def build_H(model: dict, species, nl: Neighbours, shift=None, dtype="f64", H_on=None, H_bond=None):
+    """Onsite levels [N, n_orb] (float64) and bond blocks [P, n_orb, n_orb]
+    in ``dtype`` (``bop_build_H``)."""
+    torch = _torch()
+    lib = load()
+    _dev(species, torch.int32, "species")
+    n = species.shape[0]
+    no = model["n_orb"]
+    dev = species.device
+    tdt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}[dtype]
+    if H_on is None:
+        H_on = torch.empty((n, no), dtype=torch.float64, device=dev)
+    if H_bond is None and nl is not None:
+        H_bond = torch.empty((nl.n_pairs, no, no), dtype=tdt, device=dev)
+    m = model_struct(model)
+    if shift is not None:
+        _dev(shift, torch.float64, "shift")
+    _check(lib.bop_build_H(C.byref(m), n, _ptr(species), _ptr(shift),
+                           _ptr(nl.row_ptr) if nl else None, _ptr(nl.nbr_j) if nl else None,
+                           _ptr(nl.nbr_d) if nl else None, nl.n_pairs if nl else 0, DTYPES[dtype],
+                           _ptr(H_on), _ptr(H_bond), _stream()))
+    return H_on, H_bond
+
+
+def moments_plan(n_atoms, n_orb, n_max, dtype, nl: Neighbours, tuning=None, use_order=True) -> Plan:
+    """Breadth-first sizing of the moment tiles (``bop_moments_plan``)."""
+    torch = _torch()
+    lib = load()
+    dev = nl.row_ptr.device
+    sb = lib.bop_moments_plan_scratch_size(n_atoms)
+    scratch = _bytes(sb, dev)
+    plan = Plan()
+    t = None
+    if tuning:
+        t = Tuning(int(tuning.get("tile_atoms", 0)), int(tuning.get("block_threads", 0)),
+                   int(tuning.get("n_blocks", 0)))
+    _check(lib.bop_moments_plan(n_atoms, n_orb, n_max, DTYPES[dtype], _ptr(nl.row_ptr), _ptr(nl.nbr_j),
+                                _ptr(nl.order) if use_order else None, C.byref(t) if t else None,
+                                _ptr(scratch), sb, C.byref(plan), _stream()))
+    del scratch
+    return plan
+
+
+def moments(plan: Plan, nl: Neighbours, H_on, H_bond, mu=None, ws=None, use_order=True):
+    """Orbital moments mu [N, n_orb, n_max+1] float64 (``bop_moments``)."""
+    torch = _torch()
+    lib = load()
+    dev = H_on.device
+    if mu is None:
+        mu = torch.empty((plan.n_atoms, plan.n_orb, plan.n_max + 1), dtype=torch.float64, device=dev)
+    if ws is None:
+        ws = _bytes(plan.ws_bytes, dev)
+    _check(lib.bop_moments(C.byref(plan), _ptr(nl.row_ptr), _ptr(nl.nbr_j),
+                           _ptr(nl.order) if use_order else None, _ptr(H_on), _ptr(H_bond), _ptr(mu),
+                           _ptr(ws), ws.numel(), _stream()))
+    return mu
+
+
+def n_a(n_max):
+    return (n_max - 1) // 2 + 1 if n_max >= 1 else 0
+
+
+def n_b(n_max):
+    return n_max // 2
+
+
+def recursion(mu_rows, n_max, global_ab=None, out=None):
+    """Recursion coefficients a [R, n_a], b [R, n_b+1], a_inf, b_inf, flags
+    (``bop_recursion``)."""
+    torch = _torch()
+    lib = load()
+    mu_rows = _dev(mu_rows.reshape(-1, n_max + 1), torch.float64, "mu")
+    R = mu_rows.shape[0]
+    dev = mu_rows.device
+    o = out or {}
+    a = o.get("a", torch.empty((R, n_a(n_max)), dtype=torch.float64, device=dev))
+    b = o.get("b", torch.empty((R, n_b(n_max) + 1), dtype=torch.float64, device=dev))
+    ai = o.get("a_inf", torch.empty(R, dtype=torch.float64, device=dev))
+    bi = o.get("b_inf", torch.empty(R, dtype=torch.float64, device=dev))
+    fl = o.get("flags", torch.empty(R, dtype=torch.int32, device=dev))
+    mode, ag, bg = (0, 0.0, 0.0) if global_ab is None else (1, float(global_ab[0]), float(global_ab[1]))
+    _check(lib.bop_recursion(R, n_max, _ptr(mu_rows), mode, ag, bg, _ptr(a), _ptr(b), _ptr(ai), _ptr(bi),
+                             _ptr(fl), _stream()))
+    return {"a": a, "b": b, "a_inf": ai, "b_inf": bi, "flags": fl}
+
+
+def energy(mu, rec, H_on, n_elec, n_max, n_exp=200, E_F=None, ws=None):
+    """Fermi level (bisection, unless ``E_F`` is given as a float or a
+    1-element device tensor), per-atom N, U, n(E_F) and U_total
+    (``bop_energy``)."""
+    torch = _torch()
+    lib = load()
+    n, no = H_on.shape
+    dev = H_on.device
+    if ws is None:
+        ws = _bytes(lib.bop_energy_workspace_size(n, no, n_exp), dev)
+    ef_mode = 0
+    if E_F is None:
+        ef = torch.zeros(1, dtype=torch.float64, device=dev)
+    else:
+        ef_mode = 1
+        ef = E_F if isinstance(E_F, torch.Tensor) else torch.tensor([float(E_F)], dtype=torch.float64, device=dev)
+    out = {k: torch.empty(n, dtype=torch.float64, device=dev) for k in ("N_atom", "U_atom", "dos_atom")}
+    ut = torch.zeros(1, dtype=torch.float64, device=dev)
+    _check(lib.bop_energy(n, no, n_max, n_exp, _ptr(mu), _ptr(rec["a"]), _ptr(rec["b"]), _ptr(rec["a_inf"]),
+                          _ptr(rec["b_inf"]), _ptr(H_on), float(n_elec), ef_mode, _ptr(ef), _ptr(out["N_atom"]),
+                          _ptr(out["U_atom"]), _ptr(out["dos_atom"]), _ptr(ut), _ptr(rec["flags"]), _ptr(ws),
+                          ws.numel(), _stream()))
+    out["E_F"] = ef
+    out["U_total"] = ut
+    return out
+
+
+class EnergyPath:
+    """Neighbours -> H -> moments -> recursion -> energy for one structure,
+    with every buffer allocated once (device tensors) and reused."""
+
+    def __init__(self, pos, cell, species, model: dict, n_max: int, n_exp: int = 200, dtype: str = "f64",
+                 tuning=None, device="cuda"):
+        torch = _torch()
+        load()
+        self.device = torch.device(device)
+        self.model = model
+        self.n_max, self.n_exp, self.dtype = int(n_max), int(n_exp), dtype
+        self.pos = torch.as_tensor(np.ascontiguousarray(pos, np.float64), device=self.device)
+        self.cell = np.ascontiguousarray(cell, np.float64)
+        self.species = torch.as_tensor(np.ascontiguousarray(species, np.int32), device=self.device)
+        self.n = self.pos.shape[0]
+        self.no = model["n_orb"]
+        self.tuning = tuning
+        self.nl = build_neighbours(self.pos, self.cell, model["r_cut"])
+        self.H_on, self.H_bond = build_H(model, self.species, self.nl, dtype=dtype)
+        self.plan = moments_plan(self.n, self.no, self.n_max, dtype, self.nl, tuning)
+        self.mws = _bytes(self.plan.ws_bytes, self.device)
+        self.mu = torch.empty((self.n, self.no, self.n_max + 1), dtype=torch.float64, device=self.device)
+        R = self.n * self.no
+        self.rec = {"a": torch.empty((R, n_a(self.n_max)), dtype=torch.float64, device=self.device),
+                    "b": torch.empty((R, n_b(self.n_max) + 1), dtype=torch.float64, device=self.device),
+                    "a_inf": torch.empty(R, dtype=torch.float64, device=self.device),
+                    "b_inf": torch.empty(R, dtype=torch.float64, device=self.device),
+                    "flags": torch.empty(R, dtype=torch.int32, device=self.device)}
+        self.ews = _bytes(load().bop_energy_workspace_size(self.n, self.no, self.n_exp), self.device)
+
+    def rebuild(self, shift=None):
+        """Neighbours and H again (e.g. for timing the whole path)."""
+        self.nl = build_neighbours(self.pos, self.cell, self.model["r_cut"], capacity=self.nl.n_pairs)
+        build_H(self.model, self.species, self.nl, shift=shift, dtype=self.dtype, H_on=self.H_on,
+                H_bond=self.H_bond)
+
+    def run_moments(self):
+        return moments(self.plan, self.nl, self.H_on, self.H_bond, mu=self.mu, ws=self.mws)
+
+    def run_tail(self, n_elec, E_F=None):
+        recursion(self.mu, self.n_max, out=self.rec)
+        return energy(self.mu, self.rec, self.H_on, n_elec, self.n_max, self.n_exp, E_F=E_F, ws=self.ews)
+
+    def run(self, n_elec, E_F=None):
+        self.run_moments()
+        return self.run_tail(n_elec, E_F)

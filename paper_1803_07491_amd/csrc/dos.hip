@@ -1,0 +1,482 @@
+// FP64 tail of the energy path (App. B of arXiv:1803.07491):
+//  * recursion coefficients from moments (App. B.3, Eqs. momtoa, momtob and the
+//    c_j^n recursion) with the Gershgorin terminator (App. B.5, Eq. gershogorin);
+//  * Chebyshev expansion coefficients sigma_m (Eq. sigma_i), extended beyond
+//    n_max by the chain recursion of App. B.4 with the constant terminator, and
+//    Jackson damping (Eq. Jackson);
+//  * electron counts, bond energies and DOS at E (App. B.2), the Fermi level by
+//    bisection (Sec. II), per-atom sums (App. A.1 Eq. TB-Ubond).
+//
+// The chain recursion is evaluated on the computed levels 0..L-1 plus one
+// level L: beyond the computed coefficients the terminated chain is free
+// (a^ = 0, b^ = 1/2), and a free semi-infinite chain started from rest only
+// passes its input down with a delay of one step, so level L obeys
+// zeta_L^(m+1) = 2 b^_L zeta_(L-1)^(m) exactly and the levels below it see the
+// same values as with the infinite tail.  Each row's chain then fits in
+// registers.
+//
+// Expansion coefficients are stored m-major ([n_exp+1][rows]) so that the
+// per-orbital sums read coalesced columns.  Global sums (electron count,
+// bracket, total energy) use per-block partials reduced in a fixed order by
+// the last block, so results are deterministic.
+#include "bop_internal.h"
+
+#include <cmath>
+
+namespace bop {
+namespace {
+
+constexpr int MAX_NMAX = 40;
+constexpr int DT = 256;        // threads per block in this file
+
+__device__ inline int n_a_of(int n_max) { return n_max >= 1 ? (n_max - 1) / 2 + 1 : 0; }
+__device__ inline int n_b_of(int n_max) { return n_max / 2; }
+
+// ---------------------------------------------------------------------------
+// recursion coefficients and band edges
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(DT)
+k_recursion(int n_rows, int n_max, const double *__restrict__ mu, int bw_mode, double a_glob,
+            double b_glob, double *__restrict__ a, double *__restrict__ b, double *__restrict__ a_inf,
+            double *__restrict__ b_inf, int *__restrict__ flags)
+{
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n_rows) return;
+    const int na = n_a_of(n_max), nb = n_b_of(n_max);
+    double m[MAX_NMAX + 1];
+    const double *mr = mu + (long)r * (n_max + 1);
+    const double m0 = mr[0];
+    int fl = 0;
+    for (int t = 0; t <= n_max; ++t) {
+        m[t] = mr[t] / m0;
+        if (!isfinite(m[t])) fl |= BOP_FLAG_NONFINITE;
+    }
+    double cp[MAX_NMAX / 2 + 3], cc[MAX_NMAX / 2 + 3], d[MAX_NMAX / 2 + 3];
+    for (int j = 0; j < MAX_NMAX / 2 + 3; ++j) { cp[j] = 0.0; cc[j] = 0.0; }
+    cc[0] = 1.0;
+    double *ar = a + (long)r * na, *br = b + (long)r * (nb + 1);
+    br[0] = 0.0;
+    double bn = 0.0;                   // b_n of the current level
+    const double var = (n_max >= 2) ? m[2] - m[1] * m[1] : 0.0;
+    bool broke = false;
+    for (int n = 0; n < na; ++n) {
+        if (broke) { ar[n] = ar[n - 1]; continue; }
+        double s = 0.0;
+        for (int j = 0; j <= n; ++j)
+            for (int l = 0; l <= n; ++l) s += cc[j] * cc[l] * m[j + l + 1];
+        ar[n] = s;
+        if (n + 1 > nb) break;
+        for (int j = 0; j <= n + 1; ++j) d[j] = (j > 0 ? cc[j - 1] : 0.0) - s * cc[j] - bn * cp[j];
+        double b2 = 0.0;
+        for (int j = 0; j <= n + 1; ++j)
+            for (int l = 0; l <= n + 1; ++l) b2 += d[j] * d[l] * m[j + l];
+        if (!(b2 > 1e-14 * var)) {
+            for (int t = n + 1; t <= nb; ++t) br[t] = 0.0;
+            fl |= BOP_FLAG_BREAKDOWN | ((n + 1) << 8);
+            broke = true;
+            continue;
+        }
+        double bb = sqrt(b2);
+        br[n + 1] = bb;
+        for (int j = 0; j <= n + 1; ++j) { cp[j] = cc[j]; cc[j] = d[j] / bb; }
+        bn = bb;
+    }
+    double ai, bi;
+    if (bw_mode == 1) { ai = a_glob; bi = b_glob; }
+    else {
+        double lo = 0.0, hi = 0.0;
+        for (int n = 0; n < na; ++n) {
+            double bl = (n >= 1 && n <= nb) ? br[n] : 0.0;
+            double bh = (n + 1 <= nb) ? br[n + 1] : 0.0;
+            double e0 = ar[n] - bl - bh, e1 = ar[n] + bl + bh;
+            if (n == 0 || e0 < lo) lo = e0;
+            if (n == 0 || e1 > hi) hi = e1;
+        }
+        ai = 0.5 * (hi + lo);
+        bi = 0.25 * (hi - lo);
+    }
+    if (!(bi >= 1e-6)) { bi = 1e-6; fl |= BOP_FLAG_NARROW; }
+    a_inf[r] = ai;
+    b_inf[r] = bi;
+    flags[r] = fl;
+}
+
+// ---------------------------------------------------------------------------
+// expansion coefficients g_m sigma_m, m-major
+// ---------------------------------------------------------------------------
+template <int LM>
+__global__ void __launch_bounds__(DT)
+k_dos_coeffs(int n_rows, int n_max, int n_exp, const double *__restrict__ mu,
+             const double *__restrict__ a, const double *__restrict__ b,
+             const double *__restrict__ a_inf, const double *__restrict__ b_inf,
+             double *__restrict__ gs)
+{
+    __shared__ double s_p[(MAX_NMAX + 1) * (MAX_NMAX + 1)];   // p_mn
+    __shared__ double s_c[(MAX_NMAX + 1) * (MAX_NMAX + 1)];   // binomials
+    __shared__ double s_g[1025];                              // Jackson g_m
+    const int M = n_max + 1;
+    if (threadIdx.x == 0) {
+        for (int t = 0; t < M * M; ++t) { s_p[t] = 0.0; s_c[t] = 0.0; }
+        s_p[0] = 1.0;
+        if (M > 1) s_p[M + 1] = 2.0;
+        for (int m = 1; m + 1 < M; ++m)
+            for (int n = 0; n <= m + 1; ++n)
+                s_p[(m + 1) * M + n] = (n >= 1 ? 2.0 * s_p[m * M + n - 1] : 0.0) - (n <= m - 1 ? s_p[(m - 1) * M + n] : 0.0);
+        for (int n = 0; n < M; ++n) {
+            s_c[n * M] = 1.0;
+            for (int l = 1; l <= n; ++l) s_c[n * M + l] = s_c[(n - 1) * M + l - 1] + (l <= n - 1 ? s_c[(n - 1) * M + l] : 0.0);
+        }
+    }
+    {
+        // Jackson kernel of length n_exp adapted to U polynomials: g_m = g^J_(m+1)/g^J_1
+        const double w = M_PI / (n_exp + 1.0);
+        const double cotw = cos(w) / sin(w);
+        const double g1 = ((double)n_exp * cos(w) + sin(w) * cotw) / (n_exp + 1.0);
+        for (int m = threadIdx.x; m <= n_exp; m += blockDim.x) {
+            int mm = m + 1;
+            double gj = ((double)(n_exp - mm + 1) * cos(w * mm) + sin(w * mm) * cotw) / (n_exp + 1.0);
+            s_g[m] = gj / g1;
+        }
+    }
+    __syncthreads();
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n_rows) return;
+    const int na = n_a_of(n_max), nb = n_b_of(n_max);
+    const double ai = a_inf[r], bi = b_inf[r];
+    const double *mr = mu + (long)r * M;
+    // normalised moments mu^_n
+    double mh[MAX_NMAX + 1];
+    const double m0 = mr[0];
+    for (int n = 0; n < M; ++n) {
+        double s = 0.0, pa = 1.0;           // pa = (-a_inf)^l
+        for (int l = 0; l <= n; ++l) {
+            s += s_c[n * M + l] * pa * (mr[n - l] / m0);
+            pa *= -ai;
+        }
+        mh[n] = s / pow(2.0 * bi, (double)n);
+    }
+    for (int m = 0; m < M && m <= n_exp; ++m) {
+        double s = 0.0;
+        for (int n = 0; n <= m; ++n) s += s_p[m * M + n] * mh[n];
+        gs[(long)m * n_rows + r] = s_g[m] * s;
+    }
+    if (n_exp <= n_max) return;
+    // chain on levels 0..L with the delay level L
+    const int L = na > nb ? na : nb;
+    double ah[LM + 1], bh[LM + 2], z0[LM + 1], z1[LM + 1];
+#pragma unroll
+    for (int k = 0; k <= LM; ++k) {
+        ah[k] = (k < na) ? (a[(long)r * na + k] - ai) / (2.0 * bi) : 0.0;
+        z0[k] = 0.0;
+        z1[k] = 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k <= LM + 1; ++k)
+        bh[k] = (k == 0) ? 0.0 : ((k <= nb) ? b[(long)r * (nb + 1) + k] / (2.0 * bi) : 0.5);
+    z1[0] = 1.0;
+    for (int m = 0; m < n_exp; ++m) {
+        double zn[LM + 1];
+#pragma unroll
+        for (int k = 0; k <= LM; ++k) {
+            double lower = (k > 0) ? z1[k > 0 ? k - 1 : 0] : 0.0;
+            double upper = (k < LM) ? z1[k < LM ? k + 1 : LM] : 0.0;
+            double full = 2.0 * (ah[k] * z1[k] + bh[k] * lower + bh[k + 1] * upper) - z0[k];
+            double delay = 2.0 * bh[k] * lower;
+            zn[k] = (k < L) ? full : ((k == L) ? delay : 0.0);
+        }
+#pragma unroll
+        for (int k = 0; k <= LM; ++k) { z0[k] = z1[k]; z1[k] = zn[k]; }
+        const int mm = m + 1;
+        if (mm > n_max) gs[(long)mm * n_rows + r] = s_g[mm] * z1[0];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// per-orbital sums at energy E
+// ---------------------------------------------------------------------------
+// electron count N(phi) = gs_0 (1 - phi/pi) + sum_k w_k sin(k phi) with
+// w_k = (gs_(k-2) - gs_k) / (pi k) (k >= 2), w_1 = -gs_1 / pi — the chi^ sum of
+// App. B.2 regrouped by frequency.  sin(k phi) by unit-modulus rotation.
+__device__ inline double orbital_count(const double *__restrict__ gs, long n_rows, long r, int n_exp,
+                                       double ai, double bi, double E, const double *s_inv)
+{
+    double eps = (E - ai) / (2.0 * bi);
+    double c = eps < -1.0 ? -1.0 : (eps > 1.0 ? 1.0 : eps);
+    double s = sqrt(fmax(0.0, 1.0 - c * c));
+    double phi = acos(c);
+    double g0 = gs[r];
+    double N = g0 * (1.0 - phi / M_PI);
+    double ck = c, sk = s;              // cos(k phi), sin(k phi) for k = 1
+    double gkm2 = 0.0, gkm1 = g0;      // gs_(k-2), gs_(k-1)
+    double acc = 0.0;
+    for (int k = 1; k <= n_exp + 2; ++k) {
+        double gk = (k <= n_exp) ? gs[(long)k * n_rows + r] : 0.0;
+        double wk = (k >= 2) ? (gkm2 - gk) : -gk;
+        acc = fma(wk * s_inv[k], sk, acc);
+        gkm2 = gkm1;
+        gkm1 = gk;
+        double cn = ck * c - sk * s, sn = sk * c + ck * s;
+        ck = cn;
+        sk = sn;
+    }
+    return N + acc / M_PI;
+}
+
+__device__ inline double block_sum(double v, double *s_red)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) s_red[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int q = 0; q < (int)(blockDim.x >> 6); ++q) t += s_red[q];
+    __syncthreads();
+    return t;    // valid in thread 0
+}
+
+// Fermi state in the workspace: [0] lo, [1] hi, [2] done (as double), then
+// per-block partials; int counter after the doubles.
+struct FermiState { double lo, hi, done, E_F; };
+
+__global__ void __launch_bounds__(DT)
+k_bracket(int n_rows, const double *__restrict__ a_inf, const double *__restrict__ b_inf,
+          double *__restrict__ part, unsigned *__restrict__ counter, FermiState *st)
+{
+    __shared__ double s_lo[DT / 64], s_hi[DT / 64];
+    __shared__ bool s_last;
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    double lo = INFINITY, hi = -INFINITY;
+    if (r < n_rows) { lo = a_inf[r] - 2.0 * b_inf[r]; hi = a_inf[r] + 2.0 * b_inf[r]; }
+    for (int o = 32; o > 0; o >>= 1) { lo = fmin(lo, __shfl_xor(lo, o)); hi = fmax(hi, __shfl_xor(hi, o)); }
+    if ((threadIdx.x & 63) == 0) { s_lo[threadIdx.x >> 6] = lo; s_hi[threadIdx.x >> 6] = hi; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int q = 0; q < DT / 64; ++q) { lo = fmin(lo, s_lo[q]); hi = fmax(hi, s_hi[q]); }
+        part[2 * blockIdx.x] = lo;
+        part[2 * blockIdx.x + 1] = hi;
+        __threadfence();
+        s_last = atomicAdd(counter, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (s_last && threadIdx.x == 0) {
+        __threadfence();
+        double L = INFINITY, H = -INFINITY;
+        for (unsigned q = 0; q < gridDim.x; ++q) {
+            L = fmin(L, __hip_atomic_load(&part[2 * q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+            H = fmax(H, __hip_atomic_load(&part[2 * q + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        }
+        st->lo = L;
+        st->hi = H;
+        st->done = 0.0;
+        *counter = 0;
+    }
+}
+
+// one bisection step: count at the midpoint, last block updates the bracket
+__global__ void __launch_bounds__(DT)
+k_bisect(int n_rows, int n_exp, const double *__restrict__ gs, const double *__restrict__ a_inf,
+         const double *__restrict__ b_inf, double n_elec, double *__restrict__ part,
+         unsigned *__restrict__ counter, FermiState *st)
+{
+    __shared__ double s_inv[1040], s_red[DT / 64];
+    __shared__ bool s_last;
+    const double lo = st->lo, hi = st->hi;
+    if (st->done != 0.0) return;
+    const double mid = 0.5 * (lo + hi);
+    for (int k = threadIdx.x; k <= n_exp + 2; k += blockDim.x) s_inv[k] = k ? 1.0 / k : 0.0;
+    __syncthreads();
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    double v = (r < n_rows) ? orbital_count(gs, n_rows, r, n_exp, a_inf[r], b_inf[r], mid, s_inv) : 0.0;
+    double t = block_sum(v, s_red);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = t;
+        __threadfence();
+        s_last = atomicAdd(counter, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (s_last && threadIdx.x == 0) {
+        __threadfence();
+        double tot = 0.0;
+        for (unsigned q = 0; q < gridDim.x; ++q)
+            tot += __hip_atomic_load(&part[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (mid <= lo || mid >= hi) st->done = 1.0;
+        else if (2.0 * tot < n_elec) st->lo = mid;
+        else st->hi = mid;
+        *counter = 0;
+    }
+}
+
+__global__ void k_fermi_finish(FermiState *st, double *E_F)
+{
+    E_F[0] = 0.5 * (st->lo + st->hi);
+}
+
+// per-atom N, U, n(E_F); total U by fixed-order reduction
+__global__ void __launch_bounds__(DT)
+k_energy(int n_atoms, int no, int n_exp, const double *__restrict__ gs, const double *__restrict__ a_inf,
+         const double *__restrict__ b_inf, const double *__restrict__ H_on, const double *__restrict__ E_F,
+         double *__restrict__ N_atom, double *__restrict__ U_atom, double *__restrict__ dos_atom,
+         int *__restrict__ flags, double *__restrict__ part, unsigned *__restrict__ counter,
+         double *__restrict__ U_total)
+{
+    __shared__ double s_inv[1040], s_red[DT / 64];
+    __shared__ bool s_last;
+    for (int k = threadIdx.x; k <= n_exp + 4; k += blockDim.x) s_inv[k] = k ? 1.0 / k : 0.0;
+    __syncthreads();
+    const double E = E_F[0];
+    const long n_rows = (long)n_atoms * no;
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double Ui = 0.0;
+    if (i < n_atoms) {
+        double sN = 0.0, sU = 0.0, sD = 0.0;
+        for (int a = 0; a < no; ++a) {
+            long r = (long)i * no + a;
+            double ai = a_inf[r], bi = b_inf[r];
+            double eps = (E - ai) / (2.0 * bi);
+            double c = eps < -1.0 ? -1.0 : (eps > 1.0 ? 1.0 : eps);
+            double s = sqrt(fmax(0.0, 1.0 - c * c));
+            double phi = acos(c);
+            // sin((m+1) phi), sin((m+2) phi) and (cos, sin)((m+3) phi), advanced
+            // by unit-modulus rotation; chi^_m, chi^_(m+1) carried along
+            const double c2 = c * c - s * s, s2 = 2.0 * c * s;
+            double w1 = s, w2 = s2;
+            double c3 = c2 * c - s2 * s, w3 = s2 * c + c2 * s;
+            double chi0 = 0.0;
+            double chi1 = 1.0 - phi / M_PI + s2 / (2.0 * M_PI);
+            double N = 0.0, U = 0.0, D = 0.0;
+            for (int m = 0; m <= n_exp; ++m) {
+                // chi^_(m+2) = (sin((m+3) phi)/(m+3) - sin((m+1) phi)/(m+1)) / pi
+                double chi2 = (w3 * s_inv[m + 3] - w1 * s_inv[m + 1]) / M_PI;
+                double g = gs[(long)m * n_rows + r];
+                N = fma(g, chi1, N);
+                U = fma(g, chi2 + chi0, U);
+                D = fma(g, w1, D);
+                chi0 = chi1;
+                chi1 = chi2;
+                double nc = c3 * c - w3 * s, ns = w3 * c + c3 * s;
+                w1 = w2; w2 = w3; w3 = ns; c3 = nc;
+            }
+            U = bi * U + (ai - H_on[r]) * N;
+            D = (eps > -1.0 && eps < 1.0) ? D / (M_PI * bi) : 0.0;
+            if (!(eps > -1.0 && eps < 1.0)) flags[r] |= BOP_FLAG_OUTSIDE;
+            sN += N; sU += U; sD += D;
+        }
+        N_atom[i] = 2.0 * sN;
+        U_atom[i] = 2.0 * sU;
+        dos_atom[i] = 2.0 * sD;
+        Ui = 2.0 * sU;
+    }
+    double t = block_sum(Ui, s_red);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = t;
+        __threadfence();
+        s_last = atomicAdd(counter, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (s_last && threadIdx.x == 0) {
+        __threadfence();
+        double tot = 0.0;
+        for (unsigned q = 0; q < gridDim.x; ++q)
+            tot += __hip_atomic_load(&part[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        U_total[0] = tot;
+        *counter = 0;
+    }
+}
+
+__global__ void k_zero_u32(unsigned *p) { *p = 0; }
+
+struct EnergyWs {
+    double *gs, *part;
+    FermiState *st;
+    unsigned *counter;
+    size_t bytes;
+};
+
+EnergyWs carve(void *base, long n_rows, int n_exp)
+{
+    EnergyWs w{};
+    char *p = (char *)base;
+    auto take = [&](size_t b) { char *r = p; p += align_up(b, 256); return (void *)r; };
+    w.gs = (double *)take(sizeof(double) * (size_t)(n_exp + 1) * (size_t)n_rows);
+    long nblk = (n_rows + DT - 1) / DT + 1;
+    w.part = (double *)take(sizeof(double) * 2 * (size_t)nblk);
+    w.st = (FermiState *)take(sizeof(FermiState));
+    w.counter = (unsigned *)take(sizeof(unsigned));
+    w.bytes = (size_t)(p - (char *)base);
+    return w;
+}
+
+}  // namespace
+}  // namespace bop
+
+using namespace bop;
+
+extern "C" int bop_recursion(int n_rows, int n_max, const double *mu, int bw_mode, double a_glob,
+                             double b_glob, double *a, double *b, double *a_inf, double *b_inf,
+                             int *flags, hipStream_t stream)
+{
+    BOP_REQUIRE(n_rows >= 0, BOP_E_ARG, "bop_recursion: n_rows < 0");
+    BOP_REQUIRE(n_max >= 1 && n_max <= MAX_NMAX, BOP_E_UNSUPPORTED, "bop_recursion: n_max must be 1..%d", MAX_NMAX);
+    BOP_REQUIRE(bw_mode == 0 || bw_mode == 1, BOP_E_ARG, "bop_recursion: bw_mode must be 0 or 1");
+    if (n_rows == 0) return BOP_OK;
+    BOP_REQUIRE(mu && a && b && a_inf && b_inf && flags, BOP_E_ARG, "bop_recursion: NULL array");
+    k_recursion<<<(n_rows + DT - 1) / DT, DT, 0, stream>>>(n_rows, n_max, mu, bw_mode, a_glob, b_glob, a, b,
+                                                           a_inf, b_inf, flags);
+    BOP_LAUNCHED();
+    return BOP_OK;
+}
+
+extern "C" size_t bop_energy_workspace_size(int n_atoms, int n_orb, int n_exp)
+{
+    if (n_atoms < 0 || n_orb <= 0 || n_exp < 0) return 0;
+    return carve(nullptr, (long)n_atoms * n_orb, n_exp).bytes + 256;
+}
+
+extern "C" int bop_energy(int n_atoms, int no, int n_max, int n_exp, const double *mu, const double *a,
+                          const double *b, const double *a_inf, const double *b_inf, const double *H_on,
+                          double n_elec, int ef_mode, double *E_F, double *N_atom, double *U_atom,
+                          double *dos_atom, double *U_total, int *flags, void *ws, size_t ws_bytes,
+                          hipStream_t stream)
+{
+    BOP_REQUIRE(n_atoms > 0 && no > 0, BOP_E_ARG, "bop_energy: n_atoms and n_orb must be > 0");
+    BOP_REQUIRE(n_max >= 1 && n_max <= MAX_NMAX, BOP_E_UNSUPPORTED, "bop_energy: n_max must be 1..%d", MAX_NMAX);
+    BOP_REQUIRE(n_exp >= 1 && n_exp <= 1024, BOP_E_UNSUPPORTED, "bop_energy: n_exp must be 1..1024");
+    BOP_REQUIRE(ef_mode == 0 || ef_mode == 1, BOP_E_ARG, "bop_energy: ef_mode must be 0 or 1");
+    BOP_REQUIRE(mu && a && b && a_inf && b_inf && H_on && E_F && N_atom && U_atom && dos_atom && U_total && flags,
+                BOP_E_ARG, "bop_energy: NULL array");
+    const long R = (long)n_atoms * no;
+    EnergyWs w = carve(ws, R, n_exp);
+    BOP_REQUIRE(ws && ws_bytes >= w.bytes, BOP_E_CAPACITY, "bop_energy: workspace of %zu bytes needed", w.bytes);
+    BOP_REQUIRE(ef_mode == 1 || (n_elec >= 0.0 && n_elec <= 2.0 * (double)R), BOP_E_ARG,
+                "bop_energy: n_elec outside [0, 2 n_rows]");
+    const unsigned nblk = (unsigned)((R + DT - 1) / DT);
+    const int L = (n_max - 1) / 2 + 1 > n_max / 2 ? (n_max - 1) / 2 + 1 : n_max / 2;
+    if (L <= 11) k_dos_coeffs<11><<<nblk, DT, 0, stream>>>((int)R, n_max, n_exp, mu, a, b, a_inf, b_inf, w.gs);
+    else k_dos_coeffs<21><<<nblk, DT, 0, stream>>>((int)R, n_max, n_exp, mu, a, b, a_inf, b_inf, w.gs);
+    BOP_LAUNCHED();
+    k_zero_u32<<<1, 1, 0, stream>>>(w.counter);
+    if (ef_mode == 0) {
+        k_bracket<<<nblk, DT, 0, stream>>>((int)R, a_inf, b_inf, w.part, w.counter, w.st);
+        BOP_LAUNCHED();
+        for (int it = 0; it < 64; ++it)
+            k_bisect<<<nblk, DT, 0, stream>>>((int)R, n_exp, w.gs, a_inf, b_inf, n_elec, w.part, w.counter, w.st);
+        BOP_LAUNCHED();
+        k_fermi_finish<<<1, 1, 0, stream>>>(w.st, E_F);
+        BOP_LAUNCHED();
+    }
+    const unsigned ablk = (unsigned)((n_atoms + DT - 1) / DT);
+    k_energy<<<ablk, DT, 0, stream>>>(n_atoms, no, n_exp, w.gs, a_inf, b_inf, H_on, E_F, N_atom, U_atom,
+                                      dos_atom, flags, w.part, w.counter, U_total);
+    BOP_LAUNCHED();
+    return BOP_OK;
+}
+
+namespace bop {
+void energy_ws_scratch(void *ws, long n_rows, int n_exp, double **part, unsigned **counter)
+{
+    EnergyWs w = carve(ws, n_rows, n_exp);
+    *part = w.part;
+    *counter = w.counter;
+}
+}  // namespace bop

@@ -1,0 +1,184 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle on
+the same seeded inputs.  Bars: neighbour lists bit-exact; FP64 moments and
+energies within 1e-10 relative; FP32 moments within 1e-5 (scale-normalised
+for odd moments, which can vanish)."""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _mu_err(mu, ref):
+    """max over rows/orders of |d mu_n| / scale_n with scale_n = mu_n for even
+    n (positive) and mu_0 (mu_2/mu_0)^(n/2) for odd n."""
+    mu = mu.reshape(-1, mu.shape[-1])
+    ref = ref.reshape(-1, ref.shape[-1])
+    n = np.arange(ref.shape[1])
+    s = np.sqrt(ref[:, 2:3] / ref[:, :1]) if ref.shape[1] > 2 else np.ones((ref.shape[0], 1))
+    scale = np.where(n % 2 == 0, np.abs(ref), ref[:, :1] * s ** n)
+    scale = np.maximum(scale, 1e-300)
+    return float(np.max(np.abs(mu - ref) / scale))
+
+
+def _structures():
+    rng = np.random.default_rng(21)
+    out = {}
+    wl = W.bcc_small()
+    out["bcc_small"] = (wl.pos, wl.cell, wl.species, wl.model, 9)
+    pos, cell = W.cubic_lattice("bcc", 2.87, 1)              # self images, all-pairs search
+    out["bcc_1cell"] = (W.displace(pos, cell, 0.05, rng), cell, np.zeros(2, np.int32),
+                        W.canonical_d_model(3.5, onsite_d=(0.3,)), 7)
+    pos, cell = W.cubic_lattice("bcc", 2.87, 2)              # all-pairs search
+    out["bcc_2cell"] = (W.displace(pos, cell, 0.05, rng), cell, np.zeros(16, np.int32),
+                        W.canonical_d_model(3.5), 8)
+    pos, cell = W.hcp_lattice(2.5529, (3, 2, 2))
+    out["hcp"] = (W.displace(pos, cell, 0.05, rng), cell, np.zeros(pos.shape[0], np.int32),
+                  W.canonical_d_model(3.6), 10)
+    pos, cell = W.cubic_lattice("fcc", 3.5355, 3)
+    spc = W.random_species(108, [54, 54], rng)
+    out["fcc_spd"] = (W.displace(pos, cell, 0.06, rng), cell, spc, W.spd_alloy_model(), 9)
+    pos, cell = W.cubic_lattice("bcc", 2.87, (5, 4, 3))     # 120 atoms: ragged last tile
+    spc = W.random_species(120, [60, 60], rng)
+    out["bcc_alloy"] = (W.displace(pos, cell, 0.05, rng), cell, spc,
+                        W.canonical_d_model(3.5, onsite_d=(0.0, 0.8)), 12)
+    wl = W.dimer(2.6, direction=(0.3, -0.5, 0.8))
+    out["dimer"] = (wl.pos, wl.cell, wl.species, wl.model, 9)
+    return out
+
+
+STRUCTS = _structures()
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+    return torch
+
+
+@pytest.mark.parametrize("name", sorted(STRUCTS))
+def test_neighbours_bit_exact(bop, torch_mod, name):
+    pos, cell, spc, model, _ = STRUCTS[name]
+    ref = O.neighbours(pos, cell, model["r_cut"])
+    nl = bop.build_neighbours(torch_mod.tensor(pos, device="cuda"), cell, model["r_cut"])
+    assert np.array_equal(_np(nl.row_ptr), ref["row_ptr"])
+    assert np.array_equal(_np(nl.nbr_j), ref["nbr_j"])
+    assert np.array_equal(_np(nl.nbr_shift), ref["nbr_shift"])
+    assert np.array_equal(_np(nl.nbr_d).view(np.uint64), ref["nbr_d"].view(np.uint64))
+    order = np.sort(_np(nl.order))
+    assert np.array_equal(order, np.arange(pos.shape[0]))
+
+
+@pytest.mark.parametrize("name", sorted(STRUCTS))
+def test_hamiltonian(bop, torch_mod, name):
+    pos, cell, spc, model, _ = STRUCTS[name]
+    ref_nl = O.neighbours(pos, cell, model["r_cut"])
+    sh = np.linspace(-0.2, 0.3, pos.shape[0])
+    Hon_r, Hb_r = O.build_H(model, spc, ref_nl, shift=sh)
+    nl = bop.build_neighbours(torch_mod.tensor(pos, device="cuda"), cell, model["r_cut"])
+    species = torch_mod.tensor(spc, dtype=torch_mod.int32, device="cuda")
+    shift = torch_mod.tensor(sh, device="cuda")
+    for dt, tol in (("f64", 1e-13), ("f32", 2e-7), ("bf16", 8e-3)):
+        H_on, H_b = bop.build_H(model, species, nl, shift=shift, dtype=dt)
+        np.testing.assert_allclose(_np(H_on), Hon_r, atol=1e-15)
+        err = np.abs(_np(H_b.double()) - Hb_r).max() / np.abs(Hb_r).max()
+        assert err < tol, (dt, err)
+
+
+def _gpu_moments(bop, torch_mod, pos, cell, spc, model, n_max, dtype="f64", tuning=None, use_order=True):
+    nl = bop.build_neighbours(torch_mod.tensor(pos, device="cuda"), cell, model["r_cut"])
+    species = torch_mod.tensor(spc, dtype=torch_mod.int32, device="cuda")
+    H_on, H_b = bop.build_H(model, species, nl, dtype=dtype)
+    plan = bop.moments_plan(pos.shape[0], model["n_orb"], n_max, dtype, nl, tuning, use_order=use_order)
+    mu = bop.moments(plan, nl, H_on, H_b, use_order=use_order)
+    torch_mod.cuda.synchronize()
+    return mu, nl, H_on, H_b, plan
+
+
+@pytest.mark.parametrize("name", sorted(STRUCTS))
+def test_moments_fp64(bop, torch_mod, name):
+    pos, cell, spc, model, n_max = STRUCTS[name]
+    ref_nl = O.neighbours(pos, cell, model["r_cut"])
+    ref = O.moments(ref_nl, *O.build_H(model, spc, ref_nl), n_max)
+    mu, *_ = _gpu_moments(bop, torch_mod, pos, cell, spc, model, n_max)
+    assert _mu_err(_np(mu), ref) < 1e-10
+
+
+@pytest.mark.parametrize("tuning", [{"tile_atoms": 1}, {"tile_atoms": 5, "block_threads": 256},
+                                    {"tile_atoms": 7, "block_threads": 1024, "n_blocks": 3},
+                                    {"block_threads": 256, "n_blocks": 1}])
+def test_moments_tilings(bop, torch_mod, tuning):
+    pos, cell, spc, model, n_max = STRUCTS["bcc_alloy"]
+    ref_nl = O.neighbours(pos, cell, model["r_cut"])
+    ref = O.moments(ref_nl, *O.build_H(model, spc, ref_nl), n_max)
+    for use_order in (True, False):
+        mu, *_ = _gpu_moments(bop, torch_mod, pos, cell, spc, model, n_max, tuning=tuning, use_order=use_order)
+        assert _mu_err(_np(mu), ref) < 1e-10
+
+
+@pytest.mark.parametrize("name", ["bcc_small", "fcc_spd", "hcp"])
+def test_moments_fp32(bop, torch_mod, name):
+    pos, cell, spc, model, n_max = STRUCTS[name]
+    ref_nl = O.neighbours(pos, cell, model["r_cut"])
+    ref = O.moments(ref_nl, *O.build_H(model, spc, ref_nl), n_max)
+    mu, *_ = _gpu_moments(bop, torch_mod, pos, cell, spc, model, n_max, dtype="f32")
+    assert _mu_err(_np(mu), ref) < 1e-5
+
+
+def test_moments_deterministic(bop, torch_mod):
+    pos, cell, spc, model, n_max = STRUCTS["bcc_alloy"]
+    a, *_ = _gpu_moments(bop, torch_mod, pos, cell, spc, model, n_max, tuning={"n_blocks": 7})
+    b, *_ = _gpu_moments(bop, torch_mod, pos, cell, spc, model, n_max, tuning={"n_blocks": 2})
+    assert np.array_equal(_np(a).view(np.uint64), _np(b).view(np.uint64))
+
+
+def test_dimer_closed_form_on_gpu(bop, torch_mod):
+    pos, cell, spc, model, n_max = STRUCTS["dimer"]
+    mu, *_ = _gpu_moments(bop, torch_mod, pos, cell, spc, model, n_max)
+    f = (2.48 / 2.6) ** 5
+    V = np.array([-1.0, 4 / 6, 4 / 6, -1 / 6, -1 / 6]) * f
+    m = _np(mu)[0]
+    for k in range(5):                      # traces are basis independent
+        assert abs(m[:, 2 * k].sum() - np.sum(V ** (2 * k))) < 1e-13 * max(1.0, np.sum(V ** (2 * k)))
+        assert np.max(np.abs(m[:, 2 * k + 1])) < 1e-15
+
+
+@pytest.mark.parametrize("name", ["bcc_small", "fcc_spd", "bcc_alloy", "dimer", "bcc_1cell"])
+def test_energy_path_fp64(bop, torch_mod, name):
+    pos, cell, spc, model, n_max = STRUCTS[name]
+    n = pos.shape[0]
+    nel = {"fcc_spd": np.where(spc == 0, 9.0, 8.0)}.get(name, np.full(n, 6.5))
+    wl = W.Workload(name, pos, cell, spc, model, n_max, 200, nel)
+    ref = O.energy_pipeline(wl)
+    path = bop.EnergyPath(pos, cell, spc, model, n_max, 200, "f64")
+    out = path.run(float(nel.sum()))
+    torch_mod.cuda.synchronize()
+    rec = path.rec
+    np.testing.assert_allclose(_np(rec["a"]), ref["rec"]["a"], atol=1e-10, rtol=1e-10)
+    np.testing.assert_allclose(_np(rec["b"]), ref["rec"]["b"], atol=1e-10, rtol=1e-10)
+    np.testing.assert_allclose(_np(rec["a_inf"]), ref["rec"]["a_inf"], atol=1e-10)
+    np.testing.assert_allclose(_np(rec["b_inf"]), ref["rec"]["b_inf"], atol=1e-10)
+    assert np.array_equal(_np(rec["flags"]) & 0xFFFB, ref["rec"]["flags"] & 0xFFFB)
+    assert abs(float(_np(out["E_F"])[0]) - ref["E_F"]) < 1e-10 * max(1.0, abs(ref["E_F"]))
+    np.testing.assert_allclose(_np(out["N_atom"]), ref["N_atom"], rtol=1e-10, atol=1e-10)
+    np.testing.assert_allclose(_np(out["U_atom"]), ref["U_atom"], rtol=1e-10, atol=1e-10)
+    np.testing.assert_allclose(_np(out["dos_atom"]), ref["dos_atom"], rtol=1e-9, atol=1e-9)
+    assert abs(float(_np(out["U_total"])[0]) - ref["U_total"]) < 1e-10 * abs(ref["U_total"])
+
+
+def test_energy_at_given_fermi_level(bop, torch_mod):
+    pos, cell, spc, model, n_max = STRUCTS["bcc_alloy"]
+    nel = np.full(pos.shape[0], 6.5)
+    wl = W.Workload("x", pos, cell, spc, model, n_max, 200, nel)
+    for ef in (-1.0, 0.4, 5.0):          # 5 eV: above every band (all full)
+        ref = O.energy_pipeline(wl, E_F=ef, sel=np.arange(pos.shape[0], dtype=np.int32))
+        path = bop.EnergyPath(pos, cell, spc, model, n_max, 200, "f64")
+        out = path.run(float(nel.sum()), E_F=ef)
+        np.testing.assert_allclose(_np(out["N_atom"]), ref["N_atom"], rtol=1e-10, atol=1e-10)
+        np.testing.assert_allclose(_np(out["U_atom"]), ref["U_atom"], rtol=1e-10, atol=1e-10)
