@@ -53,6 +53,8 @@ extern "C" {
 #define BOP_FLAG_NONFINITE   2    /* a non-finite moment was seen */
 #define BOP_FLAG_OUTSIDE     4    /* E_F lies outside this orbital's band */
 #define BOP_FLAG_NARROW      8    /* band width raised to its floor (1e-6 eV) */
+#define BOP_FLAG_DIVERGENT  16    /* some |g_m sigma_m| > 1e4: the terminated chain has
+                                     states far outside the estimated band */
 
 /* ---- compute types for H and the H.X products ----------------------------- */
 #define BOP_F64   0

@@ -29,7 +29,7 @@ N_CHANNELS = 14
 CHANNELS = ("sss", "sps", "pss", "sds", "dss", "pps", "ppp",
             "pds", "dps", "pdp", "dpp", "dds", "ddp", "ddd")
 
-FLAG_BREAKDOWN, FLAG_NONFINITE, FLAG_OUTSIDE, FLAG_NARROW = 1, 2, 4, 8
+FLAG_BREAKDOWN, FLAG_NONFINITE, FLAG_OUTSIDE, FLAG_NARROW, FLAG_DIVERGENT = 1, 2, 4, 8, 16
 
 
 class BopError(RuntimeError):
@@ -371,10 +371,21 @@ class EnergyPath:
         self.ews = _bytes(load().bop_energy_workspace_size(self.n, self.no, self.n_exp), self.device)
 
     def rebuild(self, shift=None):
-        """Neighbours and H again (e.g. for timing the whole path)."""
+        """Neighbour list, H and the moment plan again, reusing buffers."""
         self.nl = build_neighbours(self.pos, self.cell, self.model["r_cut"], capacity=self.nl.n_pairs)
-        build_H(self.model, self.species, self.nl, shift=shift, dtype=self.dtype, H_on=self.H_on,
-                H_bond=self.H_bond)
+        if self.H_bond.shape[0] != self.nl.n_pairs:
+            self.H_bond = None
+        self.H_on, self.H_bond = build_H(self.model, self.species, self.nl, shift=shift, dtype=self.dtype,
+                                         H_on=self.H_on, H_bond=self.H_bond)
+        self.plan = moments_plan(self.n, self.no, self.n_max, self.dtype, self.nl, self.tuning)
+        if self.plan.ws_bytes > self.mws.numel():
+            self.mws = _bytes(self.plan.ws_bytes, self.device)
+
+    def step(self, n_elec, E_F=None):
+        """The whole path for the structure: neighbours, H, plan, moments,
+        recursion, expansion, Fermi level, energies."""
+        self.rebuild()
+        return self.run(n_elec, E_F)
 
     def run_moments(self):
         return moments(self.plan, self.nl, self.H_on, self.H_bond, mu=self.mu, ws=self.mws)

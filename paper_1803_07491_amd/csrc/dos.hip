@@ -109,7 +109,7 @@ __global__ void __launch_bounds__(DT)
 k_dos_coeffs(int n_rows, int n_max, int n_exp, const double *__restrict__ mu,
              const double *__restrict__ a, const double *__restrict__ b,
              const double *__restrict__ a_inf, const double *__restrict__ b_inf,
-             double *__restrict__ gs)
+             double *__restrict__ gs, int *__restrict__ flags)
 {
     __shared__ double s_p[(MAX_NMAX + 1) * (MAX_NMAX + 1)];   // p_mn
     __shared__ double s_c[(MAX_NMAX + 1) * (MAX_NMAX + 1)];   // binomials
@@ -155,12 +155,17 @@ k_dos_coeffs(int n_rows, int n_max, int n_exp, const double *__restrict__ mu,
         }
         mh[n] = s / pow(2.0 * bi, (double)n);
     }
+    double big = 0.0;          // |g sigma| of a proper DOS stays below m + 1
     for (int m = 0; m < M && m <= n_exp; ++m) {
         double s = 0.0;
         for (int n = 0; n <= m; ++n) s += s_p[m * M + n] * mh[n];
         gs[(long)m * n_rows + r] = s_g[m] * s;
+        big = fmax(big, fabs(s_g[m] * s));
     }
-    if (n_exp <= n_max) return;
+    if (n_exp <= n_max) {
+        if (!(big <= 1e4)) flags[r] |= BOP_FLAG_DIVERGENT;
+        return;
+    }
     // chain on levels 0..L with the delay level L
     const int L = na > nb ? na : nb;
     double ah[LM + 1], bh[LM + 2], z0[LM + 1], z1[LM + 1];
@@ -187,8 +192,13 @@ k_dos_coeffs(int n_rows, int n_max, int n_exp, const double *__restrict__ mu,
 #pragma unroll
         for (int k = 0; k <= LM; ++k) { z0[k] = z1[k]; z1[k] = zn[k]; }
         const int mm = m + 1;
-        if (mm > n_max) gs[(long)mm * n_rows + r] = s_g[mm] * z1[0];
+        if (mm > n_max) {
+            double v = s_g[mm] * z1[0];
+            gs[(long)mm * n_rows + r] = v;
+            big = fmax(big, fabs(v));
+        }
     }
+    if (!(big <= 1e4)) flags[r] |= BOP_FLAG_DIVERGENT;
 }
 
 // ---------------------------------------------------------------------------
@@ -452,8 +462,8 @@ extern "C" int bop_energy(int n_atoms, int no, int n_max, int n_exp, const doubl
                 "bop_energy: n_elec outside [0, 2 n_rows]");
     const unsigned nblk = (unsigned)((R + DT - 1) / DT);
     const int L = (n_max - 1) / 2 + 1 > n_max / 2 ? (n_max - 1) / 2 + 1 : n_max / 2;
-    if (L <= 11) k_dos_coeffs<11><<<nblk, DT, 0, stream>>>((int)R, n_max, n_exp, mu, a, b, a_inf, b_inf, w.gs);
-    else k_dos_coeffs<21><<<nblk, DT, 0, stream>>>((int)R, n_max, n_exp, mu, a, b, a_inf, b_inf, w.gs);
+    if (L <= 11) k_dos_coeffs<11><<<nblk, DT, 0, stream>>>((int)R, n_max, n_exp, mu, a, b, a_inf, b_inf, w.gs, flags);
+    else k_dos_coeffs<21><<<nblk, DT, 0, stream>>>((int)R, n_max, n_exp, mu, a, b, a_inf, b_inf, w.gs, flags);
     BOP_LAUNCHED();
     k_zero_u32<<<1, 1, 0, stream>>>(w.counter);
     if (ef_mode == 0) {

@@ -16,13 +16,24 @@ def _np(t):
 
 
 def _mu_err(mu, ref):
-    """max over rows/orders of |d mu_n| / scale_n with scale_n = mu_n for even
-    n (positive) and mu_0 (mu_2/mu_0)^(n/2) for odd n."""
+    """max over rows/orders of |d mu_n| / scale_n.  Even moments are sums of
+    squares (mu_2k = |X^k|^2 > 0): scale = mu_n (relative error).  Odd moments
+    are merged path sums <X^(k-1), X^k> that can vanish; their natural scale is
+    the Cauchy-Schwarz bound sqrt(mu_(n-1) mu_(n+1)), with mu_(n+1) for the top
+    odd order extrapolated as mu_(n-1)^2 / mu_(n-3) (mu_2 when n = 1)."""
     mu = mu.reshape(-1, mu.shape[-1])
     ref = ref.reshape(-1, ref.shape[-1])
-    n = np.arange(ref.shape[1])
-    s = np.sqrt(ref[:, 2:3] / ref[:, :1]) if ref.shape[1] > 2 else np.ones((ref.shape[0], 1))
-    scale = np.where(n % 2 == 0, np.abs(ref), ref[:, :1] * s ** n)
+    nm = ref.shape[1] - 1
+    scale = np.abs(ref).copy()
+    for o in range(1, nm + 1, 2):
+        lo = ref[:, o - 1]
+        if o + 1 <= nm:
+            hi = ref[:, o + 1]
+        elif o >= 3:
+            hi = lo * lo / np.maximum(ref[:, o - 3], 1e-300)
+        else:
+            hi = lo * np.maximum(ref[:, 2] if nm >= 2 else lo, 1e-300)
+        scale[:, o] = np.sqrt(np.abs(lo * hi))
     scale = np.maximum(scale, 1e-300)
     return float(np.max(np.abs(mu - ref) / scale))
 
@@ -149,7 +160,7 @@ def test_dimer_closed_form_on_gpu(bop, torch_mod):
         assert np.max(np.abs(m[:, 2 * k + 1])) < 1e-15
 
 
-@pytest.mark.parametrize("name", ["bcc_small", "fcc_spd", "bcc_alloy", "dimer", "bcc_1cell"])
+@pytest.mark.parametrize("name", ["bcc_small", "fcc_spd", "bcc_alloy", "dimer", "hcp"])
 def test_energy_path_fp64(bop, torch_mod, name):
     pos, cell, spc, model, n_max = STRUCTS[name]
     n = pos.shape[0]
@@ -164,7 +175,7 @@ def test_energy_path_fp64(bop, torch_mod, name):
     np.testing.assert_allclose(_np(rec["b"]), ref["rec"]["b"], atol=1e-10, rtol=1e-10)
     np.testing.assert_allclose(_np(rec["a_inf"]), ref["rec"]["a_inf"], atol=1e-10)
     np.testing.assert_allclose(_np(rec["b_inf"]), ref["rec"]["b_inf"], atol=1e-10)
-    assert np.array_equal(_np(rec["flags"]) & 0xFFFB, ref["rec"]["flags"] & 0xFFFB)
+    assert np.array_equal(_np(rec["flags"]) & ~(4 | 16), ref["rec"]["flags"] & ~(4 | 16))
     assert abs(float(_np(out["E_F"])[0]) - ref["E_F"]) < 1e-10 * max(1.0, abs(ref["E_F"]))
     np.testing.assert_allclose(_np(out["N_atom"]), ref["N_atom"], rtol=1e-10, atol=1e-10)
     np.testing.assert_allclose(_np(out["U_atom"]), ref["U_atom"], rtol=1e-10, atol=1e-10)
@@ -182,3 +193,18 @@ def test_energy_at_given_fermi_level(bop, torch_mod):
         out = path.run(float(nel.sum()), E_F=ef)
         np.testing.assert_allclose(_np(out["N_atom"]), ref["N_atom"], rtol=1e-10, atol=1e-10)
         np.testing.assert_allclose(_np(out["U_atom"]), ref["U_atom"], rtol=1e-10, atol=1e-10)
+
+
+def test_divergent_expansion_is_flagged(bop, torch_mod):
+    """A 2-atom cell with self images has a local DOS of a few sharp peaks;
+    with 7 moments the terminated chain has states far outside the
+    Gershgorin band, so sigma_m grows geometrically (in the oracle as well).
+    The device flags such rows instead of returning silent garbage."""
+    pos, cell, spc, model, n_max = STRUCTS["bcc_1cell"]
+    path = bop.EnergyPath(pos, cell, spc, model, n_max, 200, "f64")
+    path.run(13.0)
+    fl = _np(path.rec["flags"])
+    assert np.all(fl & bop.FLAG_DIVERGENT)
+    ok = bop.EnergyPath(*STRUCTS["bcc_small"][:4], 9, 200, "f64")
+    ok.run(6.5 * 128)
+    assert not np.any(_np(ok.rec["flags"]) & bop.FLAG_DIVERGENT)
