@@ -30,7 +30,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}     # MI355X vector peaks (FP32 incl. packed)
+PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6, "bf16": 2500.0}   # MI355X peaks: vector FP32 (incl. packed), FP64, dense BF16 MFMA
 PEAK_NONPACKED_F32 = 78.6                     # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
 
 
@@ -145,7 +145,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--dtype", default="f32", choices=["f32", "f64", "bf16"])
     ap.add_argument("--reps", type=int, default=40)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-f64", action="store_true", help="skip the FP64 comparison run")
@@ -177,7 +177,7 @@ def main():
     log(f"workload bcc {args.reps}^3: {wl.n_atoms} atoms, n_max {wl.n_max}, dtype {args.dtype}")
     path = P.EnergyPath(wl.pos, wl.cell, wl.species, wl.model, wl.n_max, wl.n_exp, args.dtype)
     log(f"plan: tile {path.plan.tile_atoms} atoms, {path.plan.n_tiles} tiles, rows_cap {path.plan.rows_cap}, "
-        f"workspace {path.plan.ws_bytes / 2**30:.2f} GiB, {path.plan.n_blocks} workgroups x "
+        f"workspace {path.plan.ws_bytes / 2**30:.2f} GiB, batch {path.plan.batch_tiles} tiles, chunk {path.plan.chunk_rows} rows x "
         f"{path.plan.block_threads}")
     t_step, t_mom_ms, out = timed_steps(path, n_elec, args.steps, args.warmup, torch)
     log(f"{args.dtype}: {t_step * 1e3:.2f} ms/step, moment kernel {t_mom_ms:.2f} ms, "
@@ -209,8 +209,8 @@ def main():
                    "n_atoms": wl.n_atoms, "n_max": wl.n_max, "n_exp": wl.n_exp,
                    "moments_dtype": args.dtype, "tail_dtype": "f64",
                    "tile_atoms": path.plan.tile_atoms, "block_threads": path.plan.block_threads,
-                   "n_blocks": path.plan.n_blocks},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                   "batch_tiles": path.plan.batch_tiles, "chunk_rows": path.plan.chunk_rows},
+        "roofline": {"bound": "mfma" if args.dtype == "bf16" else "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": traffic,
                      "kernel": "k_moments", "kernel_ms": t_mom_ms,
                      "algorithmic_flops_per_launch": flops,

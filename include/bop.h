@@ -121,7 +121,9 @@ int bop_build_neighbours(int n_atoms, const double *pos, const double *cell, dou
  *
  *  H_on   [N][n_orb] FP64: onsite level of the atom's species for the
  *         orbital's l, plus shift[i] (shift may be NULL).
- *  H_bond [P][n_orb][n_orb] in `dtype` (BOP_F64, BOP_F32 or BOP_BF16):
+ *  H_bond [P][n_orb][ld] in `dtype` (BOP_F64, BOP_F32 or BOP_BF16), ld = n_orb
+ *         for FP64/FP32 and the MFMA slot width for BF16 (8 for n_orb = 5, 16 for
+ *         n_orb = 9; columns beyond n_orb are zero):
  *         block p = <i a|H|j b> for pair p = (i -> j), built in the bond frame
  *         (z' along d) and rotated as R^T H^(b) R, where R[a][b] is App. D's
  *         matrix with a = bond-frame orbital, b = global orbital, theta the
@@ -144,25 +146,34 @@ int bop_build_H(const bop_model *model /*[host]*/, int n_atoms, const int *speci
  * mu_2k = <X^k, X^k>, mu_2k-1 = <X^(k-1), X^k>, and mu_2K+1 = <X^K, H X^K>.
  * X is stored and multiplied in `dtype`; mu is accumulated and returned in FP64.
  *
- * bop_moments_plan: walks the neighbour graph once (device breadth-first
- * search per tile), waits for it, and fills `plan` with the sizes the moment
- * kernel needs, including plan->ws_bytes.  It uses `scratch`
- * (bop_moments_plan_scratch_size bytes) and must be redone when the
- * neighbour list changes (not when only H_on or H_bond change).
- * `order` (may be NULL = input order) groups atoms into tiles.
+ * Three calls:
+ *  bop_moments_plan     walks the neighbour graph once (device breadth-first
+ *                       search per tile), waits for it, and fills `plan` with the
+ *                       sizes, including plan->ws_bytes.  Uses `scratch` of
+ *                       bop_moments_plan_scratch_size bytes.
+ *  bop_moments_prepare  stores every tile's support, layers and layer-sorted
+ *                       neighbour slots in `ws`.  Redo both when the neighbour
+ *                       list changes; not when only H_on or H_bond change.
+ *  bop_moments          the H.X steps; reads the prepared supports from `ws`.
+ * `order` (may be NULL = input order) groups atoms into tiles.  A tile whose
+ * support outgrows the plan (neighbour list changed without re-planning) gets
+ * NaN moments.
  * ========================================================================= */
 typedef struct bop_tuning {
     int tile_atoms;      /* atoms per tile; 0 = as many as fit one wavefront */
-    int block_threads;   /* 256, 512 or 1024; 0 = default */
-    int n_blocks;        /* persistent workgroups; 0 = default (2 per CU) */
+    int block_threads;   /* 256, 512 or 1024; 0 = default (256) */
+    int batch_tiles;     /* tiles whose X buffers are live at once; 0 = ~6 GiB worth */
+    int chunk_rows;      /* support rows per workgroup and step; 0 = default */
 } bop_tuning;
 
+#define BOP_MAX_NMAX 40
 typedef struct bop_plan {
     int n_atoms, n_orb, n_max, dtype;
-    int tile_atoms, n_tiles, block_threads, n_blocks;
+    int tile_atoms, n_tiles, block_threads, batch_tiles, chunk_rows;
     int deg_max;         /* longest neighbour row */
     int rows_cap;        /* largest tile support (rows of X) */
-    size_t ws_bytes;     /* workspace bop_moments needs */
+    int rows_k[BOP_MAX_NMAX / 2 + 1];   /* largest |support of X^k| per k */
+    size_t ws_bytes;     /* workspace bop_moments_prepare / bop_moments need */
 } bop_plan;
 
 size_t bop_moments_plan_scratch_size(int n_atoms);
@@ -171,8 +182,10 @@ int bop_moments_plan(int n_atoms, int n_orb, int n_max, int dtype,
                      const bop_tuning *tuning /*[host] or NULL*/,
                      void *scratch, size_t scratch_bytes,
                      bop_plan *plan /*[host] out*/, hipStream_t stream);
-int bop_moments(const bop_plan *plan /*[host]*/, const int *row_ptr,
-                const int *nbr_j, const int *order, const double *H_on,
+int bop_moments_prepare(const bop_plan *plan /*[host]*/, const int *row_ptr,
+                        const int *nbr_j, const int *order, void *ws, size_t ws_bytes,
+                        hipStream_t stream);
+int bop_moments(const bop_plan *plan /*[host]*/, const int *row_ptr, const double *H_on,
                 const void *H_bond, double *mu, void *ws, size_t ws_bytes,
                 hipStream_t stream);
 
@@ -212,9 +225,12 @@ int bop_recursion(int n_rows, int n_max, const double *mu, int bw_mode,
  * Per atom, both spins: N_atom = 2 sum_a N_ia, U_atom = 2 sum_a U_ia,
  * dos_atom = 2 sum_a n_ia(E_F); U_total = sum_i U_atom.
  *
- *  ef_mode 0: E_F [device, 1 double] out: bisection on 2 sum N_ia(E) = n_elec
- *             over [min(a_inf - 2 b_inf), max(a_inf + 2 b_inf)], halving while
- *             the midpoint differs from both ends (at most 64 times).
+ *  ef_mode 0: E_F [device, 1 double] out: bisection (Sec. II) on
+ *             2 sum N_ia(E) = n_elec over [min(a_inf - 2 b_inf), max(a_inf +
+ *             2 b_inf)], halving while the midpoint differs from both ends (at
+ *             most 64 times; four halvings are decided per pass over the
+ *             coefficients, with exactly the midpoints and decisions of
+ *             sequential bisection); E_F = midpoint of the final bracket.
  *  ef_mode 1: E_F [device] in: energies at the given level.
  *  ws: bop_energy_workspace_size(n_atoms, n_orb, n_exp) bytes.
  *  n_exp <= 1024 (default used by the paper's example: 200).
@@ -257,6 +273,36 @@ typedef struct bop_system {
 int bop_scf_step(const bop_system *sys /*[host]*/, double mix, double n_floor,
                  double tol, double *shift, double *q, double *max_dq,
                  int *converged, hipStream_t stream);
+
+/* =========================================================================
+ * Learned warm start (not in the paper: its Sec. III speed-up (ii), starting
+ * the self-consistency from earlier onsite levels, generalised to a learned
+ * map from an atom's lowest moments to its converged onsite shift).  FP32.
+ *
+ * Network 6 -> 64 -> 64 -> 1 with tanh hidden layers; parameters are one
+ * array of BOP_MLP_NPARAM floats: W1[64][6] b1[64] W2[64][64] b2[64] W3[64] b3.
+ *
+ *  bop_features        x[i][n-1] = (sum_a mu[i][a][n] / n_orb - mean[n-1]) /
+ *                      std[n-1], n = 1..6 (mean/std [device 6] or both NULL =
+ *                      raw traces).  Needs n_max >= 6.
+ *  bop_mlp_forward     y[r] = network(x[r]) for n_rows rows.
+ *  bop_mlp_train_step  one Adam step (lr, betas 0.9/0.999, eps 1e-8; `step` is
+ *                      the 1-based step count, step <= 0 computes the gradient
+ *                      only) on the mean squared error over `batch` rows of
+ *                      (x, t), taken as x[idx[r]], t[idx[r]] when idx is given.
+ *                      loss [device 1] and grad [device BOP_MLP_NPARAM] are
+ *                      optional outputs (gradient before the update).
+ * ========================================================================= */
+#define BOP_MLP_NPARAM 4673
+int bop_features(int n_atoms, int n_orb, int n_max, const double *mu, const float *mean,
+                 const float *std, float *x, hipStream_t stream);
+int bop_mlp_forward(int n_rows, const float *params, const float *x, float *y,
+                    hipStream_t stream);
+size_t bop_mlp_train_workspace_size(int batch);
+int bop_mlp_train_step(int batch, const int *idx, const float *x, const float *t,
+                       float *params, float *adam_m, float *adam_v, int step, float lr,
+                       float *loss, float *grad, void *ws, size_t ws_bytes,
+                       hipStream_t stream);
 
 #ifdef __cplusplus
 }

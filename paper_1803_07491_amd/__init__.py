@@ -52,14 +52,19 @@ class Model(C.Structure):
     ]
 
 
+MAX_NMAX = 40
+
+
 class Tuning(C.Structure):
-    _fields_ = [("tile_atoms", C.c_int), ("block_threads", C.c_int), ("n_blocks", C.c_int)]
+    _fields_ = [("tile_atoms", C.c_int), ("block_threads", C.c_int), ("batch_tiles", C.c_int),
+                ("chunk_rows", C.c_int)]
 
 
 class Plan(C.Structure):
     _fields_ = [("n_atoms", C.c_int), ("n_orb", C.c_int), ("n_max", C.c_int), ("dtype", C.c_int),
                 ("tile_atoms", C.c_int), ("n_tiles", C.c_int), ("block_threads", C.c_int),
-                ("n_blocks", C.c_int), ("deg_max", C.c_int), ("rows_cap", C.c_int),
+                ("batch_tiles", C.c_int), ("chunk_rows", C.c_int), ("deg_max", C.c_int),
+                ("rows_cap", C.c_int), ("rows_k", C.c_int * (MAX_NMAX // 2 + 1)),
                 ("ws_bytes", C.c_size_t)]
 
 
@@ -104,13 +109,19 @@ def load(path: str = LIB_PATH):
     lib.bop_moments_plan_scratch_size.argtypes = [C.c_int]
     lib.bop_moments_plan.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, P, P, P, C.POINTER(Tuning),
                                      P, C.c_size_t, C.POINTER(Plan), P]
-    lib.bop_moments.argtypes = [C.POINTER(Plan), P, P, P, P, P, P, P, C.c_size_t, P]
+    lib.bop_moments_prepare.argtypes = [C.POINTER(Plan), P, P, P, P, C.c_size_t, P]
+    lib.bop_moments.argtypes = [C.POINTER(Plan), P, P, P, P, P, C.c_size_t, P]
     lib.bop_recursion.argtypes = [C.c_int, C.c_int, P, C.c_int, C.c_double, C.c_double, P, P, P, P, P, P]
     lib.bop_energy_workspace_size.restype = C.c_size_t
     lib.bop_energy_workspace_size.argtypes = [C.c_int, C.c_int, C.c_int]
     lib.bop_energy.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, P, P, P, P, P, P, C.c_double, C.c_int,
                                P, P, P, P, P, P, P, C.c_size_t, P]
     lib.bop_scf_step.argtypes = [C.POINTER(System), C.c_double, C.c_double, C.c_double, P, P, P, P, P]
+    lib.bop_features.argtypes = [C.c_int, C.c_int, C.c_int, P, P, P, P, P]
+    lib.bop_mlp_forward.argtypes = [C.c_int, P, P, P, P]
+    lib.bop_mlp_train_workspace_size.restype = C.c_size_t
+    lib.bop_mlp_train_workspace_size.argtypes = [C.c_int]
+    lib.bop_mlp_train_step.argtypes = [C.c_int, P, P, P, P, P, P, C.c_int, C.c_float, P, P, P, C.c_size_t, P]
     _lib = lib
     return lib
 
@@ -240,7 +251,8 @@ def build_H(model: dict, species, nl: Neighbours, shift=None, dtype="f64", H_on=
     if H_on is None:
         H_on = torch.empty((n, no), dtype=torch.float64, device=dev)
     if H_bond is None and nl is not None:
-        H_bond = torch.empty((nl.n_pairs, no, no), dtype=tdt, device=dev)
+        ld = (8 if no <= 8 else 16) if dtype == "bf16" else no
+        H_bond = torch.empty((nl.n_pairs, no, ld), dtype=tdt, device=dev)
     m = model_struct(model)
     if shift is not None:
         _dev(shift, torch.float64, "shift")
@@ -262,7 +274,7 @@ def moments_plan(n_atoms, n_orb, n_max, dtype, nl: Neighbours, tuning=None, use_
     t = None
     if tuning:
         t = Tuning(int(tuning.get("tile_atoms", 0)), int(tuning.get("block_threads", 0)),
-                   int(tuning.get("n_blocks", 0)))
+                   int(tuning.get("batch_tiles", 0)), int(tuning.get("chunk_rows", 0)))
     _check(lib.bop_moments_plan(n_atoms, n_orb, n_max, DTYPES[dtype], _ptr(nl.row_ptr), _ptr(nl.nbr_j),
                                 _ptr(nl.order) if use_order else None, C.byref(t) if t else None,
                                 _ptr(scratch), sb, C.byref(plan), _stream()))
@@ -270,17 +282,28 @@ def moments_plan(n_atoms, n_orb, n_max, dtype, nl: Neighbours, tuning=None, use_
     return plan
 
 
+def moments_prepare(plan: Plan, nl: Neighbours, ws=None, use_order=True):
+    """Store every tile's support in the moment workspace
+    (``bop_moments_prepare``); returns the workspace tensor."""
+    lib = load()
+    if ws is None:
+        ws = _bytes(plan.ws_bytes, nl.row_ptr.device)
+    _check(lib.bop_moments_prepare(C.byref(plan), _ptr(nl.row_ptr), _ptr(nl.nbr_j),
+                                   _ptr(nl.order) if use_order else None, _ptr(ws), ws.numel(), _stream()))
+    return ws
+
+
 def moments(plan: Plan, nl: Neighbours, H_on, H_bond, mu=None, ws=None, use_order=True):
-    """Orbital moments mu [N, n_orb, n_max+1] float64 (``bop_moments``)."""
+    """Orbital moments mu [N, n_orb, n_max+1] float64 (``bop_moments``).
+    Without ``ws`` the supports are prepared first."""
     torch = _torch()
     lib = load()
     dev = H_on.device
     if mu is None:
         mu = torch.empty((plan.n_atoms, plan.n_orb, plan.n_max + 1), dtype=torch.float64, device=dev)
     if ws is None:
-        ws = _bytes(plan.ws_bytes, dev)
-    _check(lib.bop_moments(C.byref(plan), _ptr(nl.row_ptr), _ptr(nl.nbr_j),
-                           _ptr(nl.order) if use_order else None, _ptr(H_on), _ptr(H_bond), _ptr(mu),
+        ws = moments_prepare(plan, nl, use_order=use_order)
+    _check(lib.bop_moments(C.byref(plan), _ptr(nl.row_ptr), _ptr(H_on), _ptr(H_bond), _ptr(mu),
                            _ptr(ws), ws.numel(), _stream()))
     return mu
 
@@ -360,7 +383,7 @@ class EnergyPath:
         self.nl = build_neighbours(self.pos, self.cell, model["r_cut"])
         self.H_on, self.H_bond = build_H(model, self.species, self.nl, dtype=dtype)
         self.plan = moments_plan(self.n, self.no, self.n_max, dtype, self.nl, tuning)
-        self.mws = _bytes(self.plan.ws_bytes, self.device)
+        self.mws = moments_prepare(self.plan, self.nl)
         self.mu = torch.empty((self.n, self.no, self.n_max + 1), dtype=torch.float64, device=self.device)
         R = self.n * self.no
         self.rec = {"a": torch.empty((R, n_a(self.n_max)), dtype=torch.float64, device=self.device),
@@ -379,7 +402,8 @@ class EnergyPath:
                                          H_on=self.H_on, H_bond=self.H_bond)
         self.plan = moments_plan(self.n, self.no, self.n_max, self.dtype, self.nl, self.tuning)
         if self.plan.ws_bytes > self.mws.numel():
-            self.mws = _bytes(self.plan.ws_bytes, self.device)
+            self.mws = None
+        self.mws = moments_prepare(self.plan, self.nl, ws=self.mws)
 
     def step(self, n_elec, E_F=None):
         """The whole path for the structure: neighbours, H, plan, moments,
@@ -397,3 +421,158 @@ class EnergyPath:
     def run(self, n_elec, E_F=None):
         self.run_moments()
         return self.run_tail(n_elec, E_F)
+
+
+class SCFPath(EnergyPath):
+    """Local-charge-neutrality self-consistency (``bop_scf_step``): one onsite
+    shift per atom, updated on the device until max |N_i - n0_i| < tol."""
+
+    def __init__(self, pos, cell, species, model, n_max, n0, n_exp=200, dtype="f64", tuning=None, device="cuda"):
+        super().__init__(pos, cell, species, model, n_max, n_exp, dtype, tuning, device)
+        torch = _torch()
+        self.n0 = torch.as_tensor(np.ascontiguousarray(n0, np.float64), device=self.device)
+        self.n_elec = float(np.sum(n0))
+        self.shift = torch.zeros(self.n, dtype=torch.float64, device=self.device)
+        self.q = torch.zeros(self.n, dtype=torch.float64, device=self.device)
+        self.max_dq = torch.zeros(1, dtype=torch.float64, device=self.device)
+        self.converged = torch.zeros(1, dtype=torch.int32, device=self.device)
+        self.out = {k: torch.zeros(self.n, dtype=torch.float64, device=self.device)
+                    for k in ("N_atom", "U_atom", "dos_atom")}
+        self.out["E_F"] = torch.zeros(1, dtype=torch.float64, device=self.device)
+        self.out["U_total"] = torch.zeros(1, dtype=torch.float64, device=self.device)
+        s = System()
+        s.model = model_struct(model)
+        s.n_atoms, s.n_max, s.n_exp, s.dtype = self.n, self.n_max, self.n_exp, DTYPES[dtype]
+        s.species, s.n0 = _ptr(self.species), _ptr(self.n0)
+        s.row_ptr, s.nbr_j, s.order = _ptr(self.nl.row_ptr), _ptr(self.nl.nbr_j), _ptr(self.nl.order)
+        s.n_pairs = self.nl.n_pairs
+        s.H_on, s.H_bond = _ptr(self.H_on), _ptr(self.H_bond)
+        s.plan = self.plan
+        s.moments_ws, s.moments_ws_bytes = _ptr(self.mws), self.mws.numel()
+        s.mu = _ptr(self.mu)
+        for k in ("a", "b", "a_inf", "b_inf", "flags"):
+            setattr(s, k, _ptr(self.rec[k]))
+        s.energy_ws, s.energy_ws_bytes = _ptr(self.ews), self.ews.numel()
+        s.n_elec = self.n_elec
+        for k in ("E_F", "N_atom", "U_atom", "dos_atom", "U_total"):
+            setattr(s, k, _ptr(self.out[k]))
+        self.sys = s
+
+    def set_shift(self, shift):
+        self.shift.copy_(_torch().as_tensor(shift, dtype=_torch().float64, device=self.device))
+
+    def step(self, mix=0.5, n_floor=1e-3, tol=1e-4):
+        _check(load().bop_scf_step(C.byref(self.sys), float(mix), float(n_floor), float(tol), _ptr(self.shift),
+                                   _ptr(self.q), _ptr(self.max_dq), _ptr(self.converged), _stream()))
+
+    def run_scf(self, mix=0.5, n_floor=1e-3, tol=1e-4, max_iter=200):
+        """Iterate until converged; returns (iterations, history of max|q|)."""
+        hist = []
+        for it in range(max_iter):
+            self.step(mix, n_floor, tol)
+            mq = float(self.max_dq.item())
+            hist.append(mq)
+            if int(self.converged.item()):
+                return it + 1, hist
+        raise BopError(BOP_E_NOT_CONVERGED, f"SCF not converged in {max_iter} iterations (max|q| {hist[-1]:.3e})")
+
+
+MLP_NPARAM = 4673
+MLP_SHAPES = ((64, 6), (64,), (64, 64), (64,), (1, 64), (1,))
+
+
+def features(mu, n_orb, n_max, mean=None, std=None):
+    """Standardised per-atom moment traces mu_1..mu_6 (``bop_features``)."""
+    torch = _torch()
+    n = mu.shape[0]
+    x = torch.empty((n, 6), dtype=torch.float32, device=mu.device)
+    _check(load().bop_features(n, n_orb, n_max, _ptr(mu), _ptr(mean), _ptr(std), _ptr(x), _stream()))
+    return x
+
+
+def mlp_forward(params, x):
+    torch = _torch()
+    y = torch.empty(x.shape[0], dtype=torch.float32, device=x.device)
+    _check(load().bop_mlp_forward(x.shape[0], _ptr(params), _ptr(x), _ptr(y), _stream()))
+    return y
+
+
+def mlp_pack(arrays, device="cuda"):
+    """Flatten (W1, b1, W2, b2, W3, b3) into the ABI's parameter array."""
+    torch = _torch()
+    flat = np.concatenate([np.asarray(a, np.float32).reshape(-1) for a in arrays])
+    assert flat.size == MLP_NPARAM
+    return torch.as_tensor(flat, device=device)
+
+
+def mlp_unpack(params):
+    flat = params.detach().cpu().numpy().astype(np.float64)
+    out, o = [], 0
+    for shp in MLP_SHAPES:
+        k = int(np.prod(shp))
+        out.append(flat[o:o + k].reshape(shp))
+        o += k
+    return out
+
+
+class MLP:
+    """The warm-start network with Adam state on the device; every training
+    step runs ``bop_mlp_train_step``."""
+
+    def __init__(self, seed=0, device="cuda"):
+        torch = _torch()
+        rng = np.random.default_rng(seed)
+        arrs = []
+        for shp in MLP_SHAPES:
+            if len(shp) == 2:                       # Xavier uniform
+                lim = np.sqrt(6.0 / (shp[0] + shp[1]))
+                arrs.append(rng.uniform(-lim, lim, size=shp))
+            else:
+                arrs.append(np.zeros(shp))
+        self.device = device
+        self.params = mlp_pack(arrs, device)
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.t = 0
+        self.mean = torch.zeros(6, dtype=torch.float32, device=device)
+        self.std = torch.ones(6, dtype=torch.float32, device=device)
+        self._ws = None
+        self._wsb = 0
+
+    def grad(self, x, t):
+        """Loss and gradient at the current parameters (no update)."""
+        torch = _torch()
+        B = x.shape[0]
+        ws = _bytes(load().bop_mlp_train_workspace_size(B), x.device)
+        g = torch.empty_like(self.params)
+        loss = torch.zeros(1, dtype=torch.float32, device=x.device)
+        _check(load().bop_mlp_train_step(B, None, _ptr(x), _ptr(t), _ptr(self.params), None, None, 0, 0.0,
+                                         _ptr(loss), _ptr(g), _ptr(ws), ws.numel(), _stream()))
+        return loss, g
+
+    def train(self, x, t, epochs=50, batch=4096, lr=1e-3, seed=0, log_every=0):
+        """Minibatch Adam over (x, t) device tensors; returns per-epoch mean loss."""
+        torch = _torch()
+        n = x.shape[0]
+        B = min(batch, n)
+        need = load().bop_mlp_train_workspace_size(B)
+        if self._wsb < need:
+            self._ws, self._wsb = _bytes(need, x.device), need
+        rng = np.random.default_rng(seed)
+        loss = torch.zeros(1, dtype=torch.float32, device=x.device)
+        hist = []
+        for ep in range(epochs):
+            perm = torch.as_tensor(rng.permutation(n).astype(np.int32), device=x.device)
+            tot, nb = 0.0, 0
+            for s0 in range(0, n - B + 1, B):
+                self.t += 1
+                _check(load().bop_mlp_train_step(B, _ptr(perm[s0:s0 + B]), _ptr(x), _ptr(t), _ptr(self.params),
+                                                 _ptr(self.m), _ptr(self.v), self.t, float(lr), _ptr(loss), None,
+                                                 _ptr(self._ws), self._wsb, _stream()))
+                tot += float(loss.item()) if (log_every and nb % log_every == 0) else 0.0
+                nb += 1
+            hist.append(tot)
+        return hist
+
+    def predict(self, x):
+        return mlp_forward(self.params, x)

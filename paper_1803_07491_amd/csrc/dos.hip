@@ -4,8 +4,9 @@
 //  * Chebyshev expansion coefficients sigma_m (Eq. sigma_i), extended beyond
 //    n_max by the chain recursion of App. B.4 with the constant terminator, and
 //    Jackson damping (Eq. Jackson);
-//  * electron counts, bond energies and DOS at E (App. B.2), the Fermi level by
-//    bisection (Sec. II), per-atom sums (App. A.1 Eq. TB-Ubond).
+//  * electron counts, bond energies and DOS at E (App. B.2), the Fermi level
+//    by bisection (Sec. II), four halvings per pass over the coefficients,
+//    per-atom sums (App. A.1 Eq. TB-Ubond).
 //
 // The chain recursion is evaluated on the computed levels 0..L-1 plus one
 // level L: beyond the computed coefficients the terminated chain is free
@@ -204,34 +205,6 @@ k_dos_coeffs(int n_rows, int n_max, int n_exp, const double *__restrict__ mu,
 // ---------------------------------------------------------------------------
 // per-orbital sums at energy E
 // ---------------------------------------------------------------------------
-// electron count N(phi) = gs_0 (1 - phi/pi) + sum_k w_k sin(k phi) with
-// w_k = (gs_(k-2) - gs_k) / (pi k) (k >= 2), w_1 = -gs_1 / pi — the chi^ sum of
-// App. B.2 regrouped by frequency.  sin(k phi) by unit-modulus rotation.
-__device__ inline double orbital_count(const double *__restrict__ gs, long n_rows, long r, int n_exp,
-                                       double ai, double bi, double E, const double *s_inv)
-{
-    double eps = (E - ai) / (2.0 * bi);
-    double c = eps < -1.0 ? -1.0 : (eps > 1.0 ? 1.0 : eps);
-    double s = sqrt(fmax(0.0, 1.0 - c * c));
-    double phi = acos(c);
-    double g0 = gs[r];
-    double N = g0 * (1.0 - phi / M_PI);
-    double ck = c, sk = s;              // cos(k phi), sin(k phi) for k = 1
-    double gkm2 = 0.0, gkm1 = g0;      // gs_(k-2), gs_(k-1)
-    double acc = 0.0;
-    for (int k = 1; k <= n_exp + 2; ++k) {
-        double gk = (k <= n_exp) ? gs[(long)k * n_rows + r] : 0.0;
-        double wk = (k >= 2) ? (gkm2 - gk) : -gk;
-        acc = fma(wk * s_inv[k], sk, acc);
-        gkm2 = gkm1;
-        gkm1 = gk;
-        double cn = ck * c - sk * s, sn = sk * c + ck * s;
-        ck = cn;
-        sk = sn;
-    }
-    return N + acc / M_PI;
-}
-
 __device__ inline double block_sum(double v, double *s_red)
 {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
@@ -245,9 +218,8 @@ __device__ inline double block_sum(double v, double *s_red)
     return t;    // valid in thread 0
 }
 
-// Fermi state in the workspace: [0] lo, [1] hi, [2] done (as double), then
-// per-block partials; int counter after the doubles.
-struct FermiState { double lo, hi, done, E_F; };
+// Fermi search state: bracket [lo, hi], current trial x, done flag.
+struct FermiState { double lo, hi, done, x; };
 
 __global__ void __launch_bounds__(DT)
 k_bracket(int n_rows, const double *__restrict__ a_inf, const double *__restrict__ b_inf,
@@ -279,40 +251,113 @@ k_bracket(int n_rows, const double *__restrict__ a_inf, const double *__restrict
         st->lo = L;
         st->hi = H;
         st->done = 0.0;
+        st->x = 0.5 * (L + H);
         *counter = 0;
     }
 }
 
-// one bisection step: count at the midpoint, last block updates the bracket
+// Fermi level by bisection (Sec. II), four halvings per pass: the pass
+// evaluates the electron count at the 15 midpoints the next four halvings can
+// visit (a binary tree whose nodes are formed exactly as sequential bisection
+// forms them, mid = (lo + hi)/2), reading each orbital's coefficients once;
+// the last block then replays the four decisions (count < n_elec: lo = mid,
+// else hi = mid), stopping when a midpoint equals an end of its bracket.
+// The decisions, and hence the root found when the count is not monotone,
+// are those of plain bisection.
+constexpr int FT_LEVELS = 4, FT_NODES = (1 << FT_LEVELS) - 1;
+
+__device__ inline void tree_points(double lo, double hi, double *mid)
+{
+    // node i (1-based, heap order) covers [l_i, h_i]; children split at mid_i
+    double l[FT_NODES + 1], h[FT_NODES + 1];
+    l[1] = lo;
+    h[1] = hi;
+#pragma unroll
+    for (int i = 1; i <= FT_NODES; ++i) {
+        mid[i - 1] = 0.5 * (l[i] + h[i]);
+        if (2 * i + 1 <= FT_NODES) {
+            l[2 * i] = l[i]; h[2 * i] = mid[i - 1];
+            l[2 * i + 1] = mid[i - 1]; h[2 * i + 1] = h[i];
+        }
+    }
+}
+
 __global__ void __launch_bounds__(DT)
-k_bisect(int n_rows, int n_exp, const double *__restrict__ gs, const double *__restrict__ a_inf,
-         const double *__restrict__ b_inf, double n_elec, double *__restrict__ part,
-         unsigned *__restrict__ counter, FermiState *st)
+k_fermi_tree(int n_rows, int n_exp, const double *__restrict__ gs, const double *__restrict__ a_inf,
+             const double *__restrict__ b_inf, double n_elec, double *__restrict__ part,
+             unsigned *__restrict__ counter, FermiState *st)
 {
     __shared__ double s_inv[1040], s_red[DT / 64];
     __shared__ bool s_last;
-    const double lo = st->lo, hi = st->hi;
     if (st->done != 0.0) return;
-    const double mid = 0.5 * (lo + hi);
+    const double lo = st->lo, hi = st->hi;
+    double mid[FT_NODES];
+    tree_points(lo, hi, mid);
     for (int k = threadIdx.x; k <= n_exp + 2; k += blockDim.x) s_inv[k] = k ? 1.0 / k : 0.0;
     __syncthreads();
-    int r = blockIdx.x * blockDim.x + threadIdx.x;
-    double v = (r < n_rows) ? orbital_count(gs, n_rows, r, n_exp, a_inf[r], b_inf[r], mid, s_inv) : 0.0;
-    double t = block_sum(v, s_red);
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    double cnt[FT_NODES];
+    if (r < n_rows) {
+        const double ai = a_inf[r], bi = b_inf[r];
+        double c[FT_NODES], sn[FT_NODES], ck[FT_NODES], sk[FT_NODES], acc[FT_NODES];
+        const double g0 = gs[r];
+#pragma unroll
+        for (int p = 0; p < FT_NODES; ++p) {
+            double eps = (mid[p] - ai) / (2.0 * bi);
+            c[p] = eps < -1.0 ? -1.0 : (eps > 1.0 ? 1.0 : eps);
+            sn[p] = sqrt(fmax(0.0, 1.0 - c[p] * c[p]));
+            cnt[p] = g0 * (1.0 - acos(c[p]) / M_PI);
+            ck[p] = c[p];
+            sk[p] = sn[p];
+            acc[p] = 0.0;
+        }
+        double gkm2 = 0.0, gkm1 = g0;
+#pragma unroll 4
+        for (int k = 1; k <= n_exp + 2; ++k) {
+            const double gk = (k <= n_exp) ? gs[(long)k * n_rows + r] : 0.0;
+            const double wk = ((k >= 2) ? (gkm2 - gk) : -gk) * s_inv[k];
+            gkm2 = gkm1;
+            gkm1 = gk;
+#pragma unroll
+            for (int p = 0; p < FT_NODES; ++p) {
+                acc[p] = fma(wk, sk[p], acc[p]);
+                const double cn = ck[p] * c[p] - sk[p] * sn[p];
+                sk[p] = sk[p] * c[p] + ck[p] * sn[p];
+                ck[p] = cn;
+            }
+        }
+#pragma unroll
+        for (int p = 0; p < FT_NODES; ++p) cnt[p] += acc[p] / M_PI;
+    } else {
+#pragma unroll
+        for (int p = 0; p < FT_NODES; ++p) cnt[p] = 0.0;
+    }
+#pragma unroll
+    for (int p = 0; p < FT_NODES; ++p) {
+        double t = block_sum(cnt[p], s_red);
+        if (threadIdx.x == 0) part[(size_t)FT_NODES * blockIdx.x + p] = t;
+    }
     if (threadIdx.x == 0) {
-        part[blockIdx.x] = t;
         __threadfence();
         s_last = atomicAdd(counter, 1u) == gridDim.x - 1;
     }
     __syncthreads();
     if (s_last && threadIdx.x == 0) {
         __threadfence();
-        double tot = 0.0;
-        for (unsigned q = 0; q < gridDim.x; ++q)
-            tot += __hip_atomic_load(&part[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (mid <= lo || mid >= hi) st->done = 1.0;
-        else if (2.0 * tot < n_elec) st->lo = mid;
-        else st->hi = mid;
+        double l = lo, h = hi;
+        int node = 1;
+        for (int lev = 0; lev < FT_LEVELS; ++lev) {
+            const double m = mid[node - 1];
+            if (m <= l || m >= h) { st->done = 1.0; break; }
+            double tot = 0.0;
+            for (unsigned q = 0; q < gridDim.x; ++q)
+                tot += __hip_atomic_load(&part[(size_t)FT_NODES * q + node - 1], __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+            if (2.0 * tot < n_elec) { l = m; node = 2 * node + 1; }
+            else { h = m; node = 2 * node; }
+        }
+        st->lo = l;
+        st->hi = h;
         *counter = 0;
     }
 }
@@ -355,6 +400,7 @@ k_energy(int n_atoms, int no, int n_exp, const double *__restrict__ gs, const do
             double chi0 = 0.0;
             double chi1 = 1.0 - phi / M_PI + s2 / (2.0 * M_PI);
             double N = 0.0, U = 0.0, D = 0.0;
+#pragma unroll 8
             for (int m = 0; m <= n_exp; ++m) {
                 // chi^_(m+2) = (sin((m+3) phi)/(m+3) - sin((m+1) phi)/(m+1)) / pi
                 double chi2 = (w3 * s_inv[m + 3] - w1 * s_inv[m + 1]) / M_PI;
@@ -410,7 +456,7 @@ EnergyWs carve(void *base, long n_rows, int n_exp)
     auto take = [&](size_t b) { char *r = p; p += align_up(b, 256); return (void *)r; };
     w.gs = (double *)take(sizeof(double) * (size_t)(n_exp + 1) * (size_t)n_rows);
     long nblk = (n_rows + DT - 1) / DT + 1;
-    w.part = (double *)take(sizeof(double) * 2 * (size_t)nblk);
+    w.part = (double *)take(sizeof(double) * FT_NODES * (size_t)nblk);
     w.st = (FermiState *)take(sizeof(FermiState));
     w.counter = (unsigned *)take(sizeof(unsigned));
     w.bytes = (size_t)(p - (char *)base);
@@ -469,8 +515,8 @@ extern "C" int bop_energy(int n_atoms, int no, int n_max, int n_exp, const doubl
     if (ef_mode == 0) {
         k_bracket<<<nblk, DT, 0, stream>>>((int)R, a_inf, b_inf, w.part, w.counter, w.st);
         BOP_LAUNCHED();
-        for (int it = 0; it < 64; ++it)
-            k_bisect<<<nblk, DT, 0, stream>>>((int)R, n_exp, w.gs, a_inf, b_inf, n_elec, w.part, w.counter, w.st);
+        for (int it = 0; it < 64 / FT_LEVELS; ++it)
+            k_fermi_tree<<<nblk, DT, 0, stream>>>((int)R, n_exp, w.gs, a_inf, b_inf, n_elec, w.part, w.counter, w.st);
         BOP_LAUNCHED();
         k_fermi_finish<<<1, 1, 0, stream>>>(w.st, E_F);
         BOP_LAUNCHED();

@@ -71,7 +71,7 @@ __device__ inline int owner_row(const int *__restrict__ row_ptr, int n, long p)
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_bonds_d(bop_model m, int n, long P, const int *__restrict__ species, const int *__restrict__ row_ptr,
-          const int *__restrict__ nbr_j, const double *__restrict__ nbr_d, T *__restrict__ H)
+          const int *__restrict__ nbr_j, const double *__restrict__ nbr_d, T *__restrict__ H, int ld)
 {
     long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= P) return;
@@ -87,22 +87,24 @@ k_bonds_d(bop_model m, int n, long P, const int *__restrict__ species, const int
                     bond_integral(m, pr, BOP_DDD, r) };
     double R[5][5];
     rot_d(ct, st, cp, sp, R);
-    T *out = H + p * 25;
+    T *out = H + p * 5 * ld;
 #pragma unroll
-    for (int b = 0; b < 5; ++b)
+    for (int b = 0; b < 5; ++b) {
 #pragma unroll
         for (int c = 0; c < 5; ++c) {
             double s = 0.0;
 #pragma unroll
             for (int a = 0; a < 5; ++a) s += R[a][b] * D[a] * R[a][c];
-            out[b * 5 + c] = to_dtype<T>(s);
+            out[b * ld + c] = to_dtype<T>(s);
         }
+        for (int c = 5; c < ld; ++c) out[b * ld + c] = to_dtype<T>(0.0);
+    }
 }
 
 template <typename T>
 __global__ void __launch_bounds__(256)
 k_bonds_spd(bop_model m, int n, long P, const int *__restrict__ species, const int *__restrict__ row_ptr,
-            const int *__restrict__ nbr_j, const double *__restrict__ nbr_d, T *__restrict__ H)
+            const int *__restrict__ nbr_j, const double *__restrict__ nbr_d, T *__restrict__ H, int ld)
 {
     long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= P) return;
@@ -141,16 +143,18 @@ k_bonds_spd(bop_model m, int n, long P, const int *__restrict__ species, const i
                           BOP_PPP, BOP_PDP, BOP_DSS, BOP_DPS, BOP_DDS, BOP_DPP, BOP_DDP, BOP_DPP,
                           BOP_DDP, BOP_DDD, BOP_DDD };
     // H[b][c] = sum_(a, a') R[a][b] Hb[a][a'] R[a'][c]
-    T *out = H + p * 81;
+    T *out = H + p * 9 * ld;
 #pragma unroll
-    for (int b = 0; b < 9; ++b)
+    for (int b = 0; b < 9; ++b) {
 #pragma unroll
         for (int c = 0; c < 9; ++c) {
             double s = 0.0;
 #pragma unroll
             for (int e = 0; e < NE; ++e) s += R[er[e]][b] * v[ech[e]] * R[ec[e]][c];
-            out[b * 9 + c] = to_dtype<T>(s);
+            out[b * ld + c] = to_dtype<T>(s);
         }
+        for (int c = 9; c < ld; ++c) out[b * ld + c] = to_dtype<T>(0.0);
+    }
 }
 
 __global__ void k_onsite(bop_model m, int n, const int *__restrict__ species, const double *__restrict__ shift,
@@ -192,14 +196,16 @@ extern "C" int bop_build_H(const bop_model *model, int n, const int *species, co
     if (!H_bond || P == 0) return BOP_OK;
     BOP_REQUIRE(row_ptr && nbr_j && nbr_d, BOP_E_ARG, "bop_build_H: neighbour arrays NULL");
     unsigned g = (unsigned)((P + T - 1) / T);
-    if (model->n_orb == 5) {
-        if (dtype == BOP_F64) k_bonds_d<double><<<g, T, 0, stream>>>(*model, n, P, species, row_ptr, nbr_j, nbr_d, (double *)H_bond);
-        else if (dtype == BOP_F32) k_bonds_d<float><<<g, T, 0, stream>>>(*model, n, P, species, row_ptr, nbr_j, nbr_d, (float *)H_bond);
-        else k_bonds_d<__hip_bfloat16><<<g, T, 0, stream>>>(*model, n, P, species, row_ptr, nbr_j, nbr_d, (__hip_bfloat16 *)H_bond);
+    const int no = model->n_orb;
+    const int ld = (dtype == BOP_BF16) ? (no <= 8 ? 8 : 16) : no;   // BF16: MFMA slot width
+    if (no == 5) {
+        if (dtype == BOP_F64) k_bonds_d<double><<<g, T, 0, stream>>>(*model, n, P, species, row_ptr, nbr_j, nbr_d, (double *)H_bond, ld);
+        else if (dtype == BOP_F32) k_bonds_d<float><<<g, T, 0, stream>>>(*model, n, P, species, row_ptr, nbr_j, nbr_d, (float *)H_bond, ld);
+        else k_bonds_d<__hip_bfloat16><<<g, T, 0, stream>>>(*model, n, P, species, row_ptr, nbr_j, nbr_d, (__hip_bfloat16 *)H_bond, ld);
     } else {
-        if (dtype == BOP_F64) k_bonds_spd<double><<<g, T, 0, stream>>>(*model, n, P, species, row_ptr, nbr_j, nbr_d, (double *)H_bond);
-        else if (dtype == BOP_F32) k_bonds_spd<float><<<g, T, 0, stream>>>(*model, n, P, species, row_ptr, nbr_j, nbr_d, (float *)H_bond);
-        else k_bonds_spd<__hip_bfloat16><<<g, T, 0, stream>>>(*model, n, P, species, row_ptr, nbr_j, nbr_d, (__hip_bfloat16 *)H_bond);
+        if (dtype == BOP_F64) k_bonds_spd<double><<<g, T, 0, stream>>>(*model, n, P, species, row_ptr, nbr_j, nbr_d, (double *)H_bond, ld);
+        else if (dtype == BOP_F32) k_bonds_spd<float><<<g, T, 0, stream>>>(*model, n, P, species, row_ptr, nbr_j, nbr_d, (float *)H_bond, ld);
+        else k_bonds_spd<__hip_bfloat16><<<g, T, 0, stream>>>(*model, n, P, species, row_ptr, nbr_j, nbr_d, (__hip_bfloat16 *)H_bond, ld);
     }
     BOP_LAUNCHED();
     return BOP_OK;

@@ -7,21 +7,24 @@
 // GPU design (not the paper's CPU scheme):
 //  * A tile is a group of B spatially adjacent atoms; the B * n_orb unit start
 //    vectors are the columns of X, one column per lane of a 64-wide wavefront.
-//  * A persistent workgroup takes tiles from a device queue.  For each tile it
-//    first finds the k-hop support with a deterministic breadth-first search:
-//    every frontier (row, slot) claims its neighbour with an atomic minimum on
-//    a per-workgroup global->local map, and the owners are compacted in
-//    (row, slot) order, so local rows come out in layer order and the result is
-//    independent of scheduling.  Each local row keeps its neighbour slots
-//    sorted by the neighbour's layer: at step k the neighbours whose X^(k-1) is
-//    non-zero form a prefix of that list.
-//  * Step k runs over the rows of the k-hop support; a wavefront owns a row and
-//    all 64 columns.  The row's H blocks are wave-uniform and come in through
-//    scalar loads; the neighbour rows of X^(k-1) are coalesced vector loads.
-//    The moment dot products are fused into the step and reduced across the
-//    workgroup's wavefronts in a fixed order (deterministic, FP64).
-//  * X lives in the workgroup's slice of the workspace (HBM, L2-resident per
-//    tile step), ping-ponged between two buffers.
+//  * Each tile's K-hop support is found once per neighbour list (prepare pass)
+//    by a deterministic breadth-first search: every frontier (row, slot) claims
+//    its neighbour with an atomic minimum on a per-workgroup global->local map
+//    and the owners are compacted in (row, slot) order, so local rows come out
+//    in layer order independent of scheduling.  Each local row keeps its
+//    neighbour slots sorted by the neighbour's layer: at step k the neighbours
+//    whose X^(k-1) is non-zero form a prefix of that list.
+//  * The steps are step-synchronous launches over a batch of tiles; a
+//    workgroup computes one chunk of consecutive rows of one tile; a wavefront
+//    owns a row and all 64 columns.  The row's H blocks are wave-uniform and
+//    come in through scalar loads; neighbour rows of X^(k-1) are coalesced
+//    vector loads.  Blocks are numbered so that all chunks of a tile run on
+//    one XCD (block b runs on XCD b mod 8) one tile after another: each XCD
+//    then streams through a few tiles at a time and the ~15-fold reuse of every
+//    gathered row stays in its L2 and the memory-attached cache instead of HBM.
+//  * The moment dot products are fused into the step; per-chunk partial sums
+//    (FP64) are reduced in chunk order afterwards, so results are
+//    deterministic.
 #include "bop_internal.h"
 
 namespace bop {
@@ -31,27 +34,9 @@ constexpr int UNSEEN = 0x7fffffff;
 constexpr int CLAIM = 1 << 30;
 constexpr int MAX_NMAX = 40;
 constexpr int MAXK = MAX_NMAX / 2;
-constexpr int HDR = 256;            // header: [0] queue, [1] error, [2] max rows, [3] max degree
-constexpr int PLAN_WG = 64, PLAN_T = 256;
-
-struct WgLayout {
-    size_t g2l, sup, rinfo, lnb, x0, x1, bytes;
-};
-
-__host__ __device__ inline WgLayout wg_layout(int n_atoms, int rows_cap, int deg_max, int no, int tsize)
-{
-    WgLayout L;
-    size_t o = 0;
-    auto take = [&](size_t b) { size_t r = o; o += (b + 255) / 256 * 256; return r; };
-    L.g2l = take(4ull * n_atoms);
-    L.sup = take(4ull * rows_cap);
-    L.rinfo = take(4ull * rows_cap);
-    L.lnb = take(4ull * rows_cap * deg_max);
-    L.x0 = take((size_t)tsize * rows_cap * no * 64);
-    L.x1 = take((size_t)tsize * rows_cap * no * 64);
-    L.bytes = o;
-    return L;
-}
+constexpr int HDR = 256;            // header ints: [0] queue, [1] error, [2] max rows, [3] max degree,
+                                    // [8 + k] max rows of U^k (plan)
+constexpr int PLAN_T = 512;
 
 // exclusive prefix of a 0/1 flag over the workgroup; returns the position and
 // writes the workgroup total
@@ -168,6 +153,46 @@ __device__ inline int next_tile(int *queue, int *s_tile)
 }
 
 // ---------------------------------------------------------------------------
+// workspace layout
+// ---------------------------------------------------------------------------
+// Bytes of one row of X (all 64 columns): n_orb values per column in
+// FP64/FP32 ([n_orb][64] per row), or n_orb padded to the MFMA slot width in
+// BF16 ([64][slot width] per row).
+__host__ __device__ inline size_t x_row_bytes(int dtype, int n_orb)
+{
+    if (dtype == BOP_BF16) return 2ull * 64 * (n_orb <= 8 ? 8 : 16);
+    return (dtype == BOP_F64 ? 8ull : 4ull) * n_orb * 64;
+}
+
+struct Layout {
+    size_t sizes;       // int [n_tiles][MAXK + 2]: rows of U^k per tile; [0] = -1 marks a failed tile
+    size_t tiles;       // per tile: sup[rows_cap], rinfo[rows_cap], lnb[rows_cap * deg_max]
+    size_t tile_stride;
+    size_t x;           // X buffers: batch x 2 x rows_cap x n_orb x 64 (also prepare's maps)
+    size_t x_stride;    // bytes of one X buffer
+    size_t part;        // double [batch][chunks][2][64]
+    size_t bytes;
+};
+
+__host__ __device__ inline Layout make_layout(const bop_plan &p, int n_prep_wg)
+{
+    Layout L;
+    size_t o = HDR;
+    auto take = [&](size_t b) { size_t r = o; o += (b + 255) / 256 * 256; return r; };
+    L.sizes = take(4ull * p.n_tiles * (MAXK + 2));
+    L.tile_stride = (4ull * p.rows_cap * (2 + p.deg_max) + 255) / 256 * 256;
+    L.tiles = take(L.tile_stride * p.n_tiles);
+    L.x_stride = (x_row_bytes(p.dtype, p.n_orb) * p.rows_cap + 255) / 256 * 256;
+    size_t xb = L.x_stride * 2 * p.batch_tiles;
+    size_t maps = (size_t)n_prep_wg * ((4ull * p.n_atoms + 255) / 256 * 256);
+    L.x = take(xb > maps ? xb : maps);
+    int nch = (p.rows_cap + p.chunk_rows - 1) / p.chunk_rows;
+    L.part = take(8ull * 2 * 64 * (size_t)nch * p.batch_tiles);
+    L.bytes = o;
+    return L;
+}
+
+// ---------------------------------------------------------------------------
 // plan pass: support sizes only
 // ---------------------------------------------------------------------------
 __global__ void __launch_bounds__(PLAN_T)
@@ -184,6 +209,7 @@ k_plan(int n_atoms, int B, int n_tiles, int K, const int *__restrict__ order,
         if (tile >= n_tiles) break;
         int rows = bfs_tile<PLAN_T>(tile, B, n_atoms, K, order, row_ptr, nbr_j, deg_max, g2l, sup,
                                     n_atoms, s_size, s_wave, s_flag);
+        if (threadIdx.x <= K) atomicMax(&hdr[8 + threadIdx.x], s_size[threadIdx.x]);
         if (threadIdx.x == 0) atomicMax(&hdr[2], rows);
         reset_map<PLAN_T>(g2l, sup, rows);
     }
@@ -197,181 +223,499 @@ __global__ void k_max_degree(int n, const int *__restrict__ row_ptr, int *hdr)
     if ((threadIdx.x & 63) == 0) atomicMax(&hdr[3], d);
 }
 
-__global__ void k_init(int *hdr, int *maps, long n_map)
+__global__ void k_init(int *hdr, int n_hdr, int *maps, long n_map)
 {
     long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < 4) hdr[i] = 0;
+    if (i < n_hdr) hdr[i] = 0;
     if (i < n_map) maps[i] = UNSEEN;
 }
 
-__global__ void k_init_strided(int *hdr, char *base, size_t stride, int n_wg, int n_atoms)
-{
-    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < 2) hdr[i] = 0;
-    long total = (long)n_wg * n_atoms;
-    if (i < total) {
-        long w = i / n_atoms, a = i % n_atoms;
-        ((int *)(base + stride * w))[a] = UNSEEN;
-    }
-}
-
 // ---------------------------------------------------------------------------
-// moments
+// prepare pass: supports, layers and layer-sorted neighbour slots of every tile
 // ---------------------------------------------------------------------------
-template <typename T> __device__ inline T from_f64(double v) { return (T)v; }
-
-template <typename T, int NO, int WGT>
-__global__ void __launch_bounds__(WGT)
-k_moments(int n_atoms, int n_max, int B, int n_tiles, const int *__restrict__ order,
-          const int *__restrict__ row_ptr, const int *__restrict__ nbr_j,
-          const double *__restrict__ H_on, const T *__restrict__ H,
-          double *__restrict__ mu, int *hdr, char *ws, size_t per_wg, WgLayout lay,
-          int rows_cap, int deg_max)
+__global__ void __launch_bounds__(PLAN_T)
+k_prepare(int n_atoms, int B, int n_tiles, int K, const int *__restrict__ order,
+          const int *__restrict__ row_ptr, const int *__restrict__ nbr_j, int deg_max, int rows_cap,
+          int *hdr, char *ws, Layout lay, size_t map_stride)
 {
-    constexpr int NW = WGT / 64;
-    __shared__ int s_size[MAXK + 2], s_wave[NW], s_flag[1], s_tile[1];
-    __shared__ double s_red[2][NW][64];
-    const int K = n_max / 2;
-    const int lane = threadIdx.x & 63;
-    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    char *mine = ws + per_wg * blockIdx.x;
-    int *g2l = (int *)(mine + lay.g2l);
-    int *sup = (int *)(mine + lay.sup);
-    int *rinfo = (int *)(mine + lay.rinfo);
-    int *lnb = (int *)(mine + lay.lnb);
-    T *X0 = (T *)(mine + lay.x0);
-    T *X1 = (T *)(mine + lay.x1);
-    const int stride_row = NO * 64;
-    const int n1m = n_max + 1;
-
+    __shared__ int s_size[MAXK + 2], s_wave[PLAN_T / 64], s_flag[1], s_tile[1];
+    int *g2l = (int *)(ws + lay.x + map_stride * blockIdx.x);
+    int *sizes = (int *)(ws + lay.sizes);
     for (;;) {
         const int tile = next_tile(&hdr[0], s_tile);
         if (tile >= n_tiles) break;
-        const int first = tile * B;
-        const int Bt = min(B, n_atoms - first);
-        const int rows = bfs_tile<WGT>(tile, B, n_atoms, K, order, row_ptr, nbr_j, deg_max, g2l, sup,
-                                       rows_cap, s_size, s_wave, s_flag);
-        if (rows < 0) {                      // support larger than planned
-            if (threadIdx.x == 0) atomicOr(&hdr[1], 1);
-            for (int c = threadIdx.x; c < Bt * NO * n1m; c += WGT) {
-                int b = c / (NO * n1m), rest = c % (NO * n1m);
-                int g = order ? order[first + b] : first + b;
-                mu[(long)g * NO * n1m + rest] = __builtin_nan("");
+        char *tb = ws + lay.tiles + lay.tile_stride * tile;
+        int *sup = (int *)tb;
+        int *rinfo = sup + rows_cap;
+        int *lnb = rinfo + rows_cap;
+        const int rows = bfs_tile<PLAN_T>(tile, B, n_atoms, K, order, row_ptr, nbr_j, deg_max, g2l, sup,
+                                          rows_cap, s_size, s_wave, s_flag);
+        if (rows < 0) {
+            // support larger than planned: keep the seeds so that their moments
+            // can be marked NaN, and raise the error flag
+            if (threadIdx.x == 0) {
+                sizes[tile * (MAXK + 2)] = -1;
+                sizes[tile * (MAXK + 2) + 1] = min(min(B, n_atoms - tile * B), rows_cap);
+                atomicOr(&hdr[1], 1);
             }
             __syncthreads();
             continue;
         }
-        // --- per-row layer and layer-sorted neighbour slots -----------------
-        for (int l = threadIdx.x; l < rows; l += WGT) {
-            int g = sup[l];
+        if (threadIdx.x <= K) sizes[tile * (MAXK + 2) + threadIdx.x] = s_size[threadIdx.x];
+        for (int l = threadIdx.x; l < rows; l += PLAN_T) {
+            const int g = sup[l];
             int L = 0;
             while (l >= s_size[L]) ++L;
-            const int lo = (L >= 1) ? s_size[L - 1] : 0;   // rows below layer L start here
+            const int lo = (L >= 1) ? s_size[L - 1] : 0;   // rows of layers < L
             const int endL = s_size[L];
             const int endL1 = (L + 1 <= K) ? s_size[L + 1] : s_size[K];
-            int p0 = row_ptr[g], deg = row_ptr[g + 1] - p0;
+            const int p0 = row_ptr[g], deg = row_ptr[g + 1] - p0;
             int *dst = lnb + (long)l * deg_max;
             int c = 0, n1 = 0, n2 = 0;
             for (int pass = 0; pass < 3; ++pass) {
-                for (int s = 0; s < deg; ++s) {
-                    int lj = atomic_load_agent(&g2l[nbr_j[p0 + s]]);
+                for (int sl = 0; sl < deg; ++sl) {
+                    int lj = atomic_load_agent(&g2l[nbr_j[p0 + sl]]);
                     int cls = (lj < lo) ? 0 : (lj < endL ? 1 : (lj < endL1 ? 2 : 3));
-                    if (cls == pass) dst[c++] = (lj << 8) | s;
+                    if (cls == pass) dst[c++] = (lj << 8) | sl;
                 }
                 if (pass == 0) n1 = c;
                 if (pass == 1) n2 = c;
             }
             rinfo[l] = L | (n1 << 8) | (n2 << 16) | (c << 24);
         }
-        // --- X^0 = unit columns; mu_0 = 1 -----------------------------------
-        for (int l = w; l < Bt; l += NW)
-#pragma unroll
-            for (int a = 0; a < NO; ++a)
-                X0[(long)l * stride_row + a * 64 + lane] = (lane == l * NO + a) ? T(1) : T(0);
-        if (threadIdx.x < Bt * NO) {
-            int b = threadIdx.x / NO, a = threadIdx.x % NO;
-            mu[((long)sup[b] * NO + a) * n1m] = 1.0;
-        }
         __syncthreads();
-
-        T *Xp = X0, *Xc = X1;
-        const int steps = K + (n_max & 1);
-        for (int k = 1; k <= steps; ++k) {
-            const bool last = k > K;
-            const int nrow = last ? s_size[K] : s_size[k];
-            double so = 0.0, se = 0.0;
-            for (int l = w; l < nrow; l += NW) {
-                const int g = __builtin_amdgcn_readfirstlane(sup[l]);
-                const int info = __builtin_amdgcn_readfirstlane(rinfo[l]);
-                const int L = info & 255, n1 = (info >> 8) & 255, n2 = (info >> 16) & 255,
-                          n3 = (info >> 24) & 255;
-                const bool has_prev = last || L <= k - 1;
-                const int nval = last ? n3 : (k - 1 >= L + 1 ? n3 : (k - 1 == L ? n2 : n1));
-                const int p0 = row_ptr[g];
-                const T *xrow = Xp + (long)l * stride_row + lane;
-                T acc[NO], xs[NO];
-#pragma unroll
-                for (int a = 0; a < NO; ++a) {
-                    xs[a] = has_prev ? xrow[a * 64] : T(0);
-                    acc[a] = from_f64<T>(H_on[(long)g * NO + a]) * xs[a];
-                }
-                const int slots = (lane < nval) ? lnb[(long)l * deg_max + lane] : 0;
-                for (int s = 0; s < nval; ++s) {
-                    const int pk = __builtin_amdgcn_readlane(slots, s);
-                    const T *xn = Xp + (long)(pk >> 8) * stride_row + lane;
-                    const T *h = H + (long)(p0 + (pk & 255)) * (NO * NO);
-                    T x[NO];
-#pragma unroll
-                    for (int b = 0; b < NO; ++b) x[b] = xn[b * 64];
-#pragma unroll
-                    for (int a = 0; a < NO; ++a)
-#pragma unroll
-                        for (int b = 0; b < NO; ++b) acc[a] = fma(h[a * NO + b], x[b], acc[a]);
-                }
-                if (!last) {
-                    T *xo = Xc + (long)l * stride_row + lane;
-#pragma unroll
-                    for (int a = 0; a < NO; ++a) xo[a * 64] = acc[a];
-                }
-#pragma unroll
-                for (int a = 0; a < NO; ++a) {
-                    so = fma((double)xs[a], (double)acc[a], so);
-                    se = fma((double)acc[a], (double)acc[a], se);
-                }
-            }
-            s_red[0][w][lane] = so;
-            s_red[1][w][lane] = se;
-            __syncthreads();
-            if (threadIdx.x < Bt * NO) {
-                double to = 0.0, te = 0.0;
-#pragma unroll
-                for (int q = 0; q < NW; ++q) { to += s_red[0][q][threadIdx.x]; te += s_red[1][q][threadIdx.x]; }
-                int b = threadIdx.x / NO, a = threadIdx.x % NO;
-                double *m = mu + ((long)sup[b] * NO + a) * n1m;
-                if (last) m[2 * K + 1] = to;
-                else { m[2 * k - 1] = to; m[2 * k] = te; }
-            }
-            __syncthreads();
-            if (!last) { T *t = Xp; Xp = Xc; Xc = t; }
-        }
-        reset_map<WGT>(g2l, sup, rows);
+        reset_map<PLAN_T>(g2l, sup, rows);
     }
 }
 
+// ---------------------------------------------------------------------------
+// moments: X^0, steps, reductions
+// ---------------------------------------------------------------------------
+template <typename T> __device__ inline T from_f64(double v) { return (T)v; }
+
+struct Batch {
+    int first, count;          // tiles [first, first + count)
+};
+
+// X^0 = unit columns on the seed rows; mu_0 = 1 (NaN moments for failed tiles)
 template <typename T, int NO>
-hipError_t launch_moments(int wgt, dim3 grid, hipStream_t st, int n_atoms, int n_max, int B, int n_tiles,
-                          const int *order, const int *row_ptr, const int *nbr_j, const double *H_on,
-                          const void *H, double *mu, int *hdr, char *ws, size_t per_wg, WgLayout lay,
-                          int rows_cap, int deg_max)
+__global__ void k_x0(Batch bt, int n_max, int B, const int *__restrict__ sizes_, const char *tiles_base,
+                     size_t tile_stride, char *xbase, size_t x_stride, double *__restrict__ mu)
 {
-#define BOP_LAUNCH_M(W)                                                                             \
-    k_moments<T, NO, W><<<grid, W, 0, st>>>(n_atoms, n_max, B, n_tiles, order, row_ptr, nbr_j, H_on, \
-                                            (const T *)H, mu, hdr, ws, per_wg, lay, rows_cap, deg_max)
-    if (wgt == 256) BOP_LAUNCH_M(256);
-    else if (wgt == 512) BOP_LAUNCH_M(512);
-    else BOP_LAUNCH_M(1024);
-#undef BOP_LAUNCH_M
-    return hipGetLastError();
+    const int t = blockIdx.x;
+    if (t >= bt.count) return;
+    const int tile = bt.first + t;
+    const int *sizes = sizes_ + tile * (MAXK + 2);
+    const int *sup = (const int *)(tiles_base + tile_stride * tile);
+    const int n1m = n_max + 1;
+    if (sizes[0] < 0) {          // failed tile: NaN moments for its seeds
+        for (int e = threadIdx.x; e < sizes[1] * NO * n1m; e += blockDim.x) {
+            int b = e / (NO * n1m), rest = e % (NO * n1m);
+            mu[(long)sup[b] * NO * n1m + rest] = __builtin_nan("");
+        }
+        return;
+    }
+    const int Bt = sizes[0];
+    T *X0 = (T *)(xbase + x_stride * (2 * (size_t)t));
+    for (int e = threadIdx.x; e < Bt * NO * 64; e += blockDim.x) {
+        int l = e / (NO * 64), rest = e % (NO * 64), a = rest / 64, c = rest % 64;
+        X0[(long)l * NO * 64 + a * 64 + c] = (c == l * NO + a) ? T(1) : T(0);
+    }
+    for (int e = threadIdx.x; e < Bt * NO; e += blockDim.x) {
+        int b = e / NO, a = e % NO;
+        mu[((long)sup[b] * NO + a) * n1m] = 1.0;
+    }
+}
+
+// One step (or the final odd H X^K pass) for a batch of tiles.
+// Latency structure: per row, the wave first copies the row's H blocks (one
+// contiguous range of pairs) into its LDS slice with coalesced loads, and
+// issues the X gathers of G neighbour slots before using any of them, so a
+// row costs a few memory round trips instead of one per slot.
+template <typename T, int NO, int WGT>
+__global__ void __launch_bounds__(WGT)
+k_step(Batch bt, int k, int K, int last, int nch, int chunk_rows, int deg_max, int rows_cap,
+       const int *__restrict__ row_ptr, const double *__restrict__ H_on, const T *__restrict__ H,
+       const int *__restrict__ sizes_, const char *tiles_base, size_t tile_stride, char *xbase,
+       size_t x_stride, double *__restrict__ part)
+{
+    constexpr int NW = WGT / 64;
+    constexpr int NB = NO * NO;
+    constexpr int G = (sizeof(T) == 4 && NO <= 5) ? 8 : 4;   // slots whose gathers are in flight together
+    __shared__ double s_red[2][NW][64];
+    extern __shared__ char s_dyn[];
+    // XCD-aware numbering: block b runs on XCD b % 8; the other factor walks
+    // tile-major through (tile, chunk)
+    const int xcd = blockIdx.x & 7, q = blockIdx.x >> 3;
+    const int t = (q / nch) * 8 + xcd, chunk = q % nch;
+    if (t >= bt.count) return;
+    const int tile = bt.first + t;
+    const int *sizes = sizes_ + tile * (MAXK + 2);
+    if (sizes[0] < 0) return;
+    const int nrow = last ? sizes[K] : sizes[k];
+    const int r0 = chunk * chunk_rows;
+    if (r0 >= nrow) return;
+    const int r1 = min(nrow, r0 + chunk_rows);
+    const int *sup = (const int *)(tiles_base + tile_stride * tile);
+    const int *rinfo = sup + rows_cap;
+    const int *lnb = rinfo + rows_cap;
+    const int src = last ? (K & 1) : ((k - 1) & 1);
+    const T *Xp = (const T *)(xbase + x_stride * (2 * (size_t)t + src));
+    T *Xc = (T *)(xbase + x_stride * (2 * (size_t)t + (k & 1)));
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    T *sH = (T *)s_dyn + (size_t)w * deg_max * NB;          // this wave's H blocks
+    constexpr int stride_row = NO * 64;
+    double so = 0.0, se = 0.0;
+    for (int l = r0 + w; l < r1; l += NW) {
+        const int g = __builtin_amdgcn_readfirstlane(sup[l]);
+        const int info = __builtin_amdgcn_readfirstlane(rinfo[l]);
+        const int L = info & 255, n1 = (info >> 8) & 255, n2 = (info >> 16) & 255, n3 = (info >> 24) & 255;
+        const bool has_prev = last || L <= k - 1;
+        const int nval = last ? n3 : (k - 1 >= L + 1 ? n3 : (k - 1 == L ? n2 : n1));
+        const int p0 = row_ptr[g], deg = row_ptr[g + 1] - p0;
+        const int slots = (lane < nval) ? lnb[(long)l * deg_max + lane] : 0;
+        // the row's H blocks -> LDS (contiguous pairs p0 .. p0 + deg)
+        const T *hsrc = H + (long)p0 * NB;
+        for (int e = lane; e < deg * NB; e += 64) sH[e] = hsrc[e];
+        const T *xrow = Xp + (long)l * stride_row + lane;
+        T acc[NO], xs[NO];
+#pragma unroll
+        for (int a = 0; a < NO; ++a) {
+            xs[a] = has_prev ? xrow[a * 64] : T(0);
+            acc[a] = from_f64<T>(H_on[(long)g * NO + a]) * xs[a];
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_s_waitcnt(0);      // LDS writes of this wave visible to it
+        __builtin_amdgcn_wave_barrier();
+        for (int s0 = 0; s0 < nval; s0 += G) {
+            T x[G][NO];
+            int hoff[G];
+#pragma unroll
+            for (int u = 0; u < G; ++u) {
+                // slots past nval re-read this row (harmless) and are masked below
+                const int su = s0 + u < nval ? s0 + u : 0;
+                const int pk = __builtin_amdgcn_readlane(slots, su);
+                const T *xn = (s0 + u < nval) ? Xp + (long)(pk >> 8) * stride_row + lane : xrow;
+                hoff[u] = (pk & 255) * NB;
+#pragma unroll
+                for (int b = 0; b < NO; ++b) x[u][b] = xn[b * 64];
+            }
+#pragma unroll
+            for (int u = 0; u < G; ++u) {
+                if (s0 + u < nval) {
+                    const T *h = sH + hoff[u];
+#pragma unroll
+                    for (int a = 0; a < NO; ++a)
+#pragma unroll
+                        for (int b = 0; b < NO; ++b) acc[a] = fma(h[a * NO + b], x[u][b], acc[a]);
+                }
+            }
+        }
+        __builtin_amdgcn_wave_barrier();   // all lanes done with sH before the next row overwrites it
+        if (!last) {
+            T *xo = Xc + (long)l * stride_row + lane;
+#pragma unroll
+            for (int a = 0; a < NO; ++a) xo[a * 64] = acc[a];
+        }
+#pragma unroll
+        for (int a = 0; a < NO; ++a) {
+            so = fma((double)xs[a], (double)acc[a], so);
+            se = fma((double)acc[a], (double)acc[a], se);
+        }
+    }
+    s_red[0][w][lane] = so;
+    s_red[1][w][lane] = se;
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        double to = 0.0, te = 0.0;
+#pragma unroll
+        for (int q2 = 0; q2 < NW; ++q2) { to += s_red[0][q2][threadIdx.x]; te += s_red[1][q2][threadIdx.x]; }
+        double *pp = part + (((size_t)t * nch + chunk) * 2) * 64;
+        pp[threadIdx.x] = to;
+        pp[64 + threadIdx.x] = te;
+    }
+}
+
+// mu[.][2k-1], mu[.][2k] (or mu[.][2K+1]) from the chunk partials, in chunk order
+template <int NO>
+__global__ void k_reduce(Batch bt, int k, int K, int last, int n_max, int nch, int chunk_rows,
+                         const int *__restrict__ sizes_, const char *tiles_base, size_t tile_stride,
+                         const double *__restrict__ part, double *__restrict__ mu)
+{
+    const int t = blockIdx.x;
+    if (t >= bt.count) return;
+    const int tile = bt.first + t;
+    const int *sizes = sizes_ + tile * (MAXK + 2);
+    if (sizes[0] < 0) return;
+    const int Bt = sizes[0];
+    const int c = threadIdx.x;
+    if (c >= Bt * NO) return;
+    const int nrow = last ? sizes[K] : sizes[k];
+    const int used = (nrow + chunk_rows - 1) / chunk_rows;
+    double to = 0.0, te = 0.0;
+    for (int q = 0; q < used; ++q) {
+        const double *pp = part + (((size_t)t * nch + q) * 2) * 64;
+        to += pp[c];
+        te += pp[64 + c];
+    }
+    const int *sup = (const int *)(tiles_base + tile_stride * tile);
+    const int b = c / NO, a = c % NO;
+    double *m = mu + ((long)sup[b] * NO + a) * (n_max + 1);
+    if (last) m[2 * K + 1] = to;
+    else { m[2 * k - 1] = to; m[2 * k] = te; }
+}
+
+// ---------------------------------------------------------------------------
+// BF16 form: H.X on MFMA (v_mfma_f32_16x16x32_bf16), FP32 accumulation
+// ---------------------------------------------------------------------------
+// Per row: D[alpha][c] = sum over (slot, beta) of H[slot][alpha][beta] X[ls][beta][c]
+// with M = alpha (n_orb of 16 used), N = 16 columns (4 column blocks), K = 32
+// (slot, beta) pairs per instruction, beta padded to the slot width SW (8 for
+// d, 16 for s,p,d) so that every lane's eight K values come from one slot and
+// one 16-byte load.  Layouts (BF16 bits):
+//   H  [P][n_orb][SW]          (pad zero; written by bop_build_H)
+//   X  [row][64 columns][SW]   (pad zero)
+// Lane i holds A[m = i%16][k = 8(i/16)..+7], B[k = 8(i/16)..+7][n = i%16] and
+// D[m = 4(i/16)+j][n = i%16], j = 0..3.  The onsite level is applied to the
+// FP32 accumulator; moments use the FP32 values of X^k and the stored BF16
+// X^(k-1); X^k is rounded to BF16 (nearest even) when stored.
+typedef short bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+__device__ inline float bf16_to_f32(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+__device__ inline unsigned short f32_to_bf16(float f)
+{
+    unsigned u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (unsigned short)((u >> 16) | ((u & 0xffffu) ? 0x40 : 0));
+    u += 0x7fffu + ((u >> 16) & 1u);            // round to nearest even
+    return (unsigned short)(u >> 16);
+}
+
+template <int NO>
+__global__ void k_x0_bf16(Batch bt, int n_max, const int *__restrict__ sizes_, const char *tiles_base,
+                          size_t tile_stride, char *xbase, size_t x_stride, double *__restrict__ mu)
+{
+    constexpr int SW = NO <= 8 ? 8 : 16;
+    const int t = blockIdx.x;
+    if (t >= bt.count) return;
+    const int tile = bt.first + t;
+    const int *sizes = sizes_ + tile * (MAXK + 2);
+    const int *sup = (const int *)(tiles_base + tile_stride * tile);
+    const int n1m = n_max + 1;
+    if (sizes[0] < 0) {
+        for (int e = threadIdx.x; e < sizes[1] * NO * n1m; e += blockDim.x) {
+            int b = e / (NO * n1m), rest = e % (NO * n1m);
+            mu[(long)sup[b] * NO * n1m + rest] = __builtin_nan("");
+        }
+        return;
+    }
+    const int Bt = sizes[0];
+    unsigned short *X0 = (unsigned short *)(xbase + x_stride * (2 * (size_t)t));
+    for (int e = threadIdx.x; e < Bt * 64 * SW; e += blockDim.x) {
+        int l = e / (64 * SW), rest = e % (64 * SW), c = rest / SW, a = rest % SW;
+        X0[e] = (a < NO && c == l * NO + a) ? (unsigned short)0x3f80 : (unsigned short)0;
+    }
+    for (int e = threadIdx.x; e < Bt * NO; e += blockDim.x) {
+        int b = e / NO, a = e % NO;
+        mu[((long)sup[b] * NO + a) * n1m] = 1.0;
+    }
+}
+
+template <int NO, int WGT>
+__global__ void __launch_bounds__(WGT)
+k_step_bf16(Batch bt, int k, int K, int last, int nch, int chunk_rows, int deg_max, int rows_cap,
+            const int *__restrict__ row_ptr, const double *__restrict__ H_on,
+            const unsigned short *__restrict__ H, const int *__restrict__ sizes_, const char *tiles_base,
+            size_t tile_stride, char *xbase, size_t x_stride, double *__restrict__ part)
+{
+    constexpr int NW = WGT / 64;
+    constexpr int SW = NO <= 8 ? 8 : 16;
+    constexpr int SPC = 32 / SW;                 // slots per K = 32 chunk
+    __shared__ double s_red[2][NW][64];
+    const int xcd = blockIdx.x & 7, q = blockIdx.x >> 3;
+    const int t = (q / nch) * 8 + xcd, chunk = q % nch;
+    if (t >= bt.count) return;
+    const int tile = bt.first + t;
+    const int *sizes = sizes_ + tile * (MAXK + 2);
+    if (sizes[0] < 0) return;
+    const int nrow = last ? sizes[K] : sizes[k];
+    const int r0 = chunk * chunk_rows;
+    if (r0 >= nrow) return;
+    const int r1 = min(nrow, r0 + chunk_rows);
+    const int *sup = (const int *)(tiles_base + tile_stride * tile);
+    const int *rinfo = sup + rows_cap;
+    const int *lnb = rinfo + rows_cap;
+    const int src = last ? (K & 1) : ((k - 1) & 1);
+    const unsigned short *Xp = (const unsigned short *)(xbase + x_stride * (2 * (size_t)t + src));
+    unsigned short *Xc = (unsigned short *)(xbase + x_stride * (2 * (size_t)t + (k & 1)));
+    const int lane = threadIdx.x & 63, g = lane >> 4, n = lane & 15;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int gslot = (SW == 8) ? g : (g >> 1);  // slot of this lane group within a chunk
+    const int boff = (SW == 8) ? 0 : 8 * (g & 1);
+    double so[4] = {0, 0, 0, 0}, se[4] = {0, 0, 0, 0};
+    for (int l = r0 + w; l < r1; l += NW) {
+        const int gatom = __builtin_amdgcn_readfirstlane(sup[l]);
+        const int info = __builtin_amdgcn_readfirstlane(rinfo[l]);
+        const int L = info & 255, n1 = (info >> 8) & 255, n2 = (info >> 16) & 255, n3 = (info >> 24) & 255;
+        const bool has_prev = last || L <= k - 1;
+        const int nval = last ? n3 : (k - 1 >= L + 1 ? n3 : (k - 1 == L ? n2 : n1));
+        const int p0 = row_ptr[gatom];
+        const int slots = (lane < nval) ? lnb[(long)l * deg_max + lane] : 0;
+        f32x4_t acc[4];
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) acc[cb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+        const int nchunk = (nval + SPC - 1) / SPC;
+        for (int c0 = 0; c0 < nchunk; c0 += 2) {
+            // operands of two K chunks are loaded before either is multiplied
+            bf16x8_t a[2], b[2][4];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int sl = (c0 + u) * SPC + gslot;
+                const int pk = __shfl(slots, sl < 64 ? sl : 0);
+                a[u] = bf16x8_t{0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+                for (int cb = 0; cb < 4; ++cb) b[u][cb] = bf16x8_t{0, 0, 0, 0, 0, 0, 0, 0};
+                if (sl < nval) {
+                    const long ls = pk >> 8, p = p0 + (pk & 255);
+                    if (n < NO) a[u] = *(const bf16x8_t *)(H + (p * NO + n) * SW + boff);
+#pragma unroll
+                    for (int cb = 0; cb < 4; ++cb)
+                        b[u][cb] = *(const bf16x8_t *)(Xp + (ls * 64 + cb * 16 + n) * SW + boff);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 2; ++u)
+#pragma unroll
+                for (int cb = 0; cb < 4; ++cb)
+                    acc[cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[u], b[u][cb], acc[cb], 0, 0, 0);
+        }
+        // onsite, moments, store (lane holds alpha = 4g + j of column cb*16 + n)
+        float e[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int al = 4 * g + j;
+            e[j] = (al < NO) ? (float)H_on[(long)gatom * NO + al] : 0.f;
+        }
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+            const long off = ((long)l * 64 + cb * 16 + n) * SW + 4 * g;
+            float xp[4] = {0.f, 0.f, 0.f, 0.f};
+            if (has_prev && 4 * g < SW) {
+                const unsigned long long v = *(const unsigned long long *)(Xp + off);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) xp[j] = bf16_to_f32((unsigned short)(v >> (16 * j)));
+            }
+            unsigned long long outv = 0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const float v = fmaf(e[j], xp[j], acc[cb][j]);
+                so[cb] = fma((double)xp[j], (double)v, so[cb]);
+                se[cb] = fma((double)v, (double)v, se[cb]);
+                outv |= (unsigned long long)f32_to_bf16(v) << (16 * j);
+            }
+            if (!last && 4 * g < SW) *(unsigned long long *)(Xc + off) = outv;
+        }
+    }
+    // sum over the four alpha groups, then over wavefronts in a fixed order
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+        so[cb] += __shfl_xor(so[cb], 16); so[cb] += __shfl_xor(so[cb], 32);
+        se[cb] += __shfl_xor(se[cb], 16); se[cb] += __shfl_xor(se[cb], 32);
+    }
+    if (g == 0) {
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) { s_red[0][w][cb * 16 + n] = so[cb]; s_red[1][w][cb * 16 + n] = se[cb]; }
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        double to = 0.0, te = 0.0;
+#pragma unroll
+        for (int q2 = 0; q2 < NW; ++q2) { to += s_red[0][q2][threadIdx.x]; te += s_red[1][q2][threadIdx.x]; }
+        double *pp = part + (((size_t)t * nch + chunk) * 2) * 64;
+        pp[threadIdx.x] = to;
+        pp[64 + threadIdx.x] = te;
+    }
+}
+
+template <int NO>
+int run_moments_bf16(const bop_plan &p, const int *row_ptr, const double *H_on, const void *Hv, double *mu,
+                     char *ws, const Layout &lay, hipStream_t st)
+{
+    const unsigned short *H = (const unsigned short *)Hv;
+    const int K = p.n_max / 2;
+    const int steps = K + (p.n_max & 1);
+    const int *sizes = (const int *)(ws + lay.sizes);
+    const char *tiles = ws + lay.tiles;
+    char *xb = ws + lay.x;
+    double *part = (double *)(ws + lay.part);
+    for (int first = 0; first < p.n_tiles; first += p.batch_tiles) {
+        Batch bt{first, min(p.batch_tiles, p.n_tiles - first)};
+        k_x0_bf16<NO><<<bt.count, 256, 0, st>>>(bt, p.n_max, sizes, tiles, lay.tile_stride, xb, lay.x_stride, mu);
+        BOP_LAUNCHED();
+        const int nb8 = (bt.count + 7) / 8;
+        for (int k = 1; k <= steps; ++k) {
+            const int last = k > K;
+            const int rows_k = last ? p.rows_k[K] : p.rows_k[k];
+            const int nch = (rows_k + p.chunk_rows - 1) / p.chunk_rows;
+            if (nch <= 0) continue;
+            dim3 grid((unsigned)(nb8 * nch * 8));
+#define BOP_STEP16(W)                                                                                    \
+    k_step_bf16<NO, W><<<grid, W, 0, st>>>(bt, k, K, last, nch, p.chunk_rows, p.deg_max, p.rows_cap, row_ptr, \
+                                           H_on, H, sizes, tiles, lay.tile_stride, xb, lay.x_stride, part)
+            if (p.block_threads == 256) BOP_STEP16(256);
+            else if (p.block_threads == 512) BOP_STEP16(512);
+            else BOP_STEP16(1024);
+#undef BOP_STEP16
+            BOP_LAUNCHED();
+            k_reduce<NO><<<bt.count, 64, 0, st>>>(bt, k, K, last, p.n_max, nch, p.chunk_rows, sizes, tiles,
+                                                  lay.tile_stride, part, mu);
+            BOP_LAUNCHED();
+        }
+    }
+    return BOP_OK;
+}
+
+template <typename T, int NO>
+int run_moments(const bop_plan &p, const int *row_ptr, const double *H_on, const void *Hv, double *mu,
+                char *ws, const Layout &lay, hipStream_t st)
+{
+    const T *H = (const T *)Hv;
+    const int K = p.n_max / 2;
+    const int steps = K + (p.n_max & 1);
+    const int *sizes = (const int *)(ws + lay.sizes);
+    const char *tiles = ws + lay.tiles;
+    char *xb = ws + lay.x;
+    double *part = (double *)(ws + lay.part);
+    const int nch_all = (p.rows_cap + p.chunk_rows - 1) / p.chunk_rows;
+    for (int first = 0; first < p.n_tiles; first += p.batch_tiles) {
+        Batch bt{first, min(p.batch_tiles, p.n_tiles - first)};
+        k_x0<T, NO><<<bt.count, 256, 0, st>>>(bt, p.n_max, p.tile_atoms, sizes, tiles, lay.tile_stride, xb,
+                                              lay.x_stride, mu);
+        BOP_LAUNCHED();
+        const int nb8 = (bt.count + 7) / 8;
+        for (int k = 1; k <= steps; ++k) {
+            const int last = k > K;
+            const int rows_k = last ? p.rows_k[K] : p.rows_k[k];
+            const int nch = (rows_k + p.chunk_rows - 1) / p.chunk_rows;
+            if (nch <= 0) continue;
+            dim3 grid((unsigned)(nb8 * nch * 8));
+#define BOP_STEP(W)                                                                                   \
+    k_step<T, NO, W><<<grid, W, (size_t)(W / 64) * p.deg_max * NO * NO * sizeof(T), st>>>(                \
+        bt, k, K, last, nch, p.chunk_rows, p.deg_max, p.rows_cap, row_ptr, H_on, H, sizes, tiles,       \
+        lay.tile_stride, xb, lay.x_stride, part)
+            if (p.block_threads == 256) BOP_STEP(256);
+            else if (p.block_threads == 512) BOP_STEP(512);
+            else BOP_STEP(1024);
+#undef BOP_STEP
+            BOP_LAUNCHED();
+            k_reduce<NO><<<bt.count, 64, 0, st>>>(bt, k, K, last, p.n_max, nch, p.chunk_rows, sizes, tiles,
+                                                  lay.tile_stride, part, mu);
+            BOP_LAUNCHED();
+        }
+    }
+    (void)nch_all;
+    return BOP_OK;
 }
 
 int default_tile_atoms(int no) { return 64 / no; }
@@ -381,43 +725,56 @@ int default_tile_atoms(int no) { return 64 / no; }
 
 using namespace bop;
 
+// Workgroups of the plan and prepare passes: two per CU, but at most about
+// 1 GiB of per-workgroup global->local maps.
+static int map_workgroups(int n_atoms, int n_tiles)
+{
+    size_t per = align_up(4ull * n_atoms, 256) * 2;
+    long cap = (long)((1ull << 30) / (per ? per : 1));
+    long w = 2L * device_cus();
+    if (w > cap) w = cap;
+    if (w > n_tiles) w = n_tiles;
+    return w < 1 ? 1 : (int)w;
+}
+
 extern "C" size_t bop_moments_plan_scratch_size(int n_atoms)
 {
     if (n_atoms < 0) return 0;
     size_t per = align_up(4ull * n_atoms, 256) * 2;
-    return HDR + PLAN_WG * per;
+    return HDR + (size_t)map_workgroups(n_atoms, 1 << 30) * per;
 }
 
 extern "C" int bop_moments_plan(int n_atoms, int n_orb, int n_max, int dtype, const int *row_ptr,
                                 const int *nbr_j, const int *order, const bop_tuning *tuning,
-                                void *scratch, size_t scratch_bytes, bop_plan *plan,
-                                hipStream_t stream)
+                                void *scratch, size_t scratch_bytes, bop_plan *plan, hipStream_t stream)
 {
     BOP_REQUIRE(plan && n_atoms >= 0, BOP_E_ARG, "bop_moments_plan: bad arguments");
     BOP_REQUIRE(n_orb == 5 || n_orb == 9, BOP_E_UNSUPPORTED, "bop_moments_plan: n_orb must be 5 or 9");
     BOP_REQUIRE(n_max >= 0 && n_max <= MAX_NMAX, BOP_E_UNSUPPORTED, "bop_moments_plan: n_max must be 0..%d", MAX_NMAX);
-    BOP_REQUIRE(dtype == BOP_F64 || dtype == BOP_F32, BOP_E_UNSUPPORTED,
-                "bop_moments_plan: dtype %d not supported by the vector kernel", dtype);
+    BOP_REQUIRE(dtype == BOP_F64 || dtype == BOP_F32 || dtype == BOP_BF16, BOP_E_UNSUPPORTED,
+                "bop_moments_plan: unknown dtype %d", dtype);
     BOP_REQUIRE(n_atoms == 0 || (row_ptr && nbr_j), BOP_E_ARG, "bop_moments_plan: neighbour arrays NULL");
     size_t need = bop_moments_plan_scratch_size(n_atoms);
     BOP_REQUIRE(scratch && scratch_bytes >= need, BOP_E_CAPACITY,
                 "bop_moments_plan: scratch of %zu bytes needed", need);
-    int B = (tuning && tuning->tile_atoms > 0) ? tuning->tile_atoms : default_tile_atoms(n_orb);
+    const int B = (tuning && tuning->tile_atoms > 0) ? tuning->tile_atoms : default_tile_atoms(n_orb);
     BOP_REQUIRE(B * n_orb <= 64, BOP_E_UNSUPPORTED, "bop_moments_plan: tile_atoms * n_orb must be <= 64");
-    int wgt = (tuning && tuning->block_threads) ? tuning->block_threads : 512;
+    const int wgt = (tuning && tuning->block_threads) ? tuning->block_threads : 256;
     BOP_REQUIRE(wgt == 256 || wgt == 512 || wgt == 1024, BOP_E_UNSUPPORTED,
                 "bop_moments_plan: block_threads must be 256, 512 or 1024");
-    int nwg = (tuning && tuning->n_blocks > 0) ? tuning->n_blocks : 2 * device_cus();
-    int n_tiles = (n_atoms + B - 1) / B;
-    if (nwg > n_tiles) nwg = n_tiles > 0 ? n_tiles : 1;
+    const int chunk = (tuning && tuning->chunk_rows > 0) ? tuning->chunk_rows : 4 * (wgt / 64) * 4;
+    const int n_tiles = (n_atoms + B - 1) / B;
+    const int K = n_max / 2;
 
     int *hdr = (int *)scratch;
     char *base = (char *)scratch + HDR;
-    size_t per = align_up(4ull * n_atoms, 256) * 2;
-    long nmap = (long)PLAN_WG * (long)(per / 4);
-    k_init<<<(unsigned)((nmap + 255) / 256 > 0 ? (nmap + 255) / 256 : 1), 256, 0, stream>>>(hdr, (int *)base, nmap);
+    const size_t per = align_up(4ull * n_atoms, 256) * 2;
+    const int pwg = map_workgroups(n_atoms, n_tiles > 0 ? n_tiles : 1);
+    long nmap = (long)pwg * (long)(per / 4);
+    k_init<<<(unsigned)((nmap + 255) / 256 > 0 ? (nmap + 255) / 256 : 1), 256, 0, stream>>>(hdr, HDR / 4,
+                                                                                           (int *)base, nmap);
     BOP_LAUNCHED();
-    int hv[4] = { 0, 0, 0, 0 };
+    int hv[HDR / 4] = {};
     if (n_atoms > 0) {
         k_max_degree<<<(n_atoms + 255) / 256, 256, 0, stream>>>(n_atoms, row_ptr, hdr);
         BOP_LAUNCHED();
@@ -425,13 +782,12 @@ extern "C" int bop_moments_plan(int n_atoms, int n_orb, int n_max, int dtype, co
         BOP_HIP(hipStreamSynchronize(stream));
         BOP_REQUIRE(hv[3] <= 64, BOP_E_UNSUPPORTED, "bop_moments_plan: %d neighbours in a row (at most 64)", hv[3]);
         int dmax = hv[3] > 0 ? hv[3] : 1;
-        int pwg = n_tiles < PLAN_WG ? (n_tiles > 0 ? n_tiles : 1) : PLAN_WG;
-        k_plan<<<pwg, PLAN_T, 0, stream>>>(n_atoms, B, n_tiles, n_max / 2, order, row_ptr, nbr_j, dmax,
-                                           hdr, base, per);
+        k_plan<<<pwg, PLAN_T, 0, stream>>>(n_atoms, B, n_tiles, K, order, row_ptr, nbr_j, dmax, hdr, base, per);
         BOP_LAUNCHED();
         BOP_HIP(hipMemcpyAsync(hv, hdr, sizeof hv, hipMemcpyDeviceToHost, stream));
         BOP_HIP(hipStreamSynchronize(stream));
     }
+    *plan = bop_plan{};
     plan->n_atoms = n_atoms;
     plan->n_orb = n_orb;
     plan->n_max = n_max;
@@ -439,42 +795,61 @@ extern "C" int bop_moments_plan(int n_atoms, int n_orb, int n_max, int dtype, co
     plan->tile_atoms = B;
     plan->n_tiles = n_tiles;
     plan->block_threads = wgt;
-    plan->n_blocks = nwg;
+    plan->chunk_rows = chunk;
     plan->deg_max = hv[3] > 0 ? hv[3] : 1;
     plan->rows_cap = hv[2] > 0 ? hv[2] : 1;
+    for (int k = 0; k <= K; ++k) plan->rows_k[k] = hv[8 + k];
     BOP_REQUIRE(plan->rows_cap < (1 << 23), BOP_E_UNSUPPORTED, "bop_moments_plan: tile support too large");
-    WgLayout lay = wg_layout(n_atoms, plan->rows_cap, plan->deg_max, n_orb, dtype == BOP_F64 ? 8 : 4);
-    plan->ws_bytes = HDR + (size_t)nwg * lay.bytes;
+    const size_t x_tile = 2 * align_up(x_row_bytes(dtype, n_orb) * plan->rows_cap, 256);
+    long bt = (tuning && tuning->batch_tiles > 0) ? tuning->batch_tiles : (long)((6ull << 30) / x_tile);
+    bt = bt < 8 ? 8 : bt;
+    bt = (bt / 8) * 8;
+    if (bt > n_tiles) bt = n_tiles > 0 ? n_tiles : 1;
+    plan->batch_tiles = (int)bt;
+    plan->ws_bytes = make_layout(*plan, map_workgroups(n_atoms, n_tiles > 0 ? n_tiles : 1)).bytes;
     return BOP_OK;
 }
 
-extern "C" int bop_moments(const bop_plan *plan, const int *row_ptr, const int *nbr_j,
-                           const int *order, const double *H_on, const void *H_bond, double *mu,
-                           void *ws, size_t ws_bytes, hipStream_t stream)
+extern "C" int bop_moments_prepare(const bop_plan *plan, const int *row_ptr, const int *nbr_j, const int *order,
+                                   void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    BOP_REQUIRE(plan, BOP_E_ARG, "bop_moments_prepare: plan is NULL");
+    BOP_REQUIRE(ws && ws_bytes >= plan->ws_bytes, BOP_E_CAPACITY,
+                "bop_moments_prepare: workspace of %zu bytes needed, %zu given", plan->ws_bytes, ws_bytes);
+    const int n = plan->n_atoms;
+    if (n == 0) return BOP_OK;
+    BOP_REQUIRE(row_ptr && nbr_j, BOP_E_ARG, "bop_moments_prepare: neighbour arrays NULL");
+    const int pwg = map_workgroups(n, plan->n_tiles);
+    Layout lay = make_layout(*plan, pwg);
+    const size_t map_stride = align_up(4ull * n, 256);
+    int *hdr = (int *)ws;
+    char *w = (char *)ws;
+    long nmap = (long)pwg * (long)(map_stride / 4);
+    k_init<<<(unsigned)((nmap + 255) / 256), 256, 0, stream>>>(hdr, 8, (int *)(w + lay.x), nmap);
+    BOP_LAUNCHED();
+    k_prepare<<<pwg, PLAN_T, 0, stream>>>(n, plan->tile_atoms, plan->n_tiles, plan->n_max / 2, order, row_ptr,
+                                           nbr_j, plan->deg_max, plan->rows_cap, hdr, w, lay, map_stride);
+    BOP_LAUNCHED();
+    return BOP_OK;
+}
+
+extern "C" int bop_moments(const bop_plan *plan, const int *row_ptr, const double *H_on, const void *H_bond,
+                           double *mu, void *ws, size_t ws_bytes, hipStream_t stream)
 {
     BOP_REQUIRE(plan, BOP_E_ARG, "bop_moments: plan is NULL");
-    const int n = plan->n_atoms, no = plan->n_orb;
     BOP_REQUIRE(ws && ws_bytes >= plan->ws_bytes, BOP_E_CAPACITY,
                 "bop_moments: workspace of %zu bytes needed, %zu given", plan->ws_bytes, ws_bytes);
+    const int n = plan->n_atoms, no = plan->n_orb;
     if (n == 0) return BOP_OK;
-    BOP_REQUIRE(row_ptr && nbr_j && H_on && H_bond && mu, BOP_E_ARG, "bop_moments: NULL array");
-    const int tsize = plan->dtype == BOP_F64 ? 8 : 4;
-    WgLayout lay = wg_layout(n, plan->rows_cap, plan->deg_max, no, tsize);
-    int *hdr = (int *)ws;
-    char *base = (char *)ws + HDR;
-    long tot = (long)plan->n_blocks * n;
-    k_init_strided<<<(unsigned)((tot + 255) / 256), 256, 0, stream>>>(hdr, base + lay.g2l, lay.bytes,
-                                                                       plan->n_blocks, n);
-    BOP_LAUNCHED();
-    dim3 grid(plan->n_blocks);
-    hipError_t e;
-    if (plan->dtype == BOP_F64) {
-        if (no == 5) e = launch_moments<double, 5>(plan->block_threads, grid, stream, n, plan->n_max, plan->tile_atoms, plan->n_tiles, order, row_ptr, nbr_j, H_on, H_bond, mu, hdr, base, lay.bytes, lay, plan->rows_cap, plan->deg_max);
-        else e = launch_moments<double, 9>(plan->block_threads, grid, stream, n, plan->n_max, plan->tile_atoms, plan->n_tiles, order, row_ptr, nbr_j, H_on, H_bond, mu, hdr, base, lay.bytes, lay, plan->rows_cap, plan->deg_max);
-    } else {
-        if (no == 5) e = launch_moments<float, 5>(plan->block_threads, grid, stream, n, plan->n_max, plan->tile_atoms, plan->n_tiles, order, row_ptr, nbr_j, H_on, H_bond, mu, hdr, base, lay.bytes, lay, plan->rows_cap, plan->deg_max);
-        else e = launch_moments<float, 9>(plan->block_threads, grid, stream, n, plan->n_max, plan->tile_atoms, plan->n_tiles, order, row_ptr, nbr_j, H_on, H_bond, mu, hdr, base, lay.bytes, lay, plan->rows_cap, plan->deg_max);
-    }
-    BOP_REQUIRE(e == hipSuccess, BOP_E_HIP, "bop_moments: launch failed: %s", hipGetErrorString(e));
-    return BOP_OK;
+    BOP_REQUIRE(row_ptr && H_on && H_bond && mu, BOP_E_ARG, "bop_moments: NULL array");
+    Layout lay = make_layout(*plan, map_workgroups(n, plan->n_tiles));
+    char *w = (char *)ws;
+    if (plan->dtype == BOP_BF16)
+        return no == 5 ? run_moments_bf16<5>(*plan, row_ptr, H_on, H_bond, mu, w, lay, stream)
+                       : run_moments_bf16<9>(*plan, row_ptr, H_on, H_bond, mu, w, lay, stream);
+    if (plan->dtype == BOP_F64)
+        return no == 5 ? run_moments<double, 5>(*plan, row_ptr, H_on, H_bond, mu, w, lay, stream)
+                       : run_moments<double, 9>(*plan, row_ptr, H_on, H_bond, mu, w, lay, stream);
+    return no == 5 ? run_moments<float, 5>(*plan, row_ptr, H_on, H_bond, mu, w, lay, stream)
+                   : run_moments<float, 9>(*plan, row_ptr, H_on, H_bond, mu, w, lay, stream);
 }

@@ -80,8 +80,8 @@ extern "C" int bop_scf_step(const bop_system *sys, double mix, double n_floor, d
     int rc = bop_build_H(&sys->model, n, sys->species, shift, sys->row_ptr, sys->nbr_j, nullptr,
                          sys->n_pairs, sys->dtype, sys->H_on, nullptr, stream);
     if (rc) return rc;
-    rc = bop_moments(&sys->plan, sys->row_ptr, sys->nbr_j, sys->order, sys->H_on, sys->H_bond, sys->mu,
-                     sys->moments_ws, sys->moments_ws_bytes, stream);
+    rc = bop_moments(&sys->plan, sys->row_ptr, sys->H_on, sys->H_bond, sys->mu, sys->moments_ws,
+                     sys->moments_ws_bytes, stream);
     if (rc) return rc;
     rc = bop_recursion(n * no, sys->n_max, sys->mu, 0, 0.0, 0.0, sys->a, sys->b, sys->a_inf, sys->b_inf,
                        sys->flags, stream);

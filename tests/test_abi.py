@@ -26,7 +26,7 @@ def test_library_exports_every_declared_symbol():
         pytest.skip("library not built")
     lib = P.load()
     names = _declared()
-    assert len(names) >= 11
+    assert len(names) >= 12
     for name in names:
         assert hasattr(lib, name), name
 
@@ -43,7 +43,7 @@ def test_struct_layouts_match_header(tmp_path):
 int main(void){
  printf("%zu %zu %zu %zu %zu %zu\n", sizeof(bop_model), offsetof(bop_model,onsite),
         offsetof(bop_model,form), offsetof(bop_model,beta0), offsetof(bop_model,r0), offsetof(bop_model,q));
- printf("%zu %zu\n", sizeof(bop_plan), offsetof(bop_plan,ws_bytes));
+ printf("%zu %zu %zu\n", sizeof(bop_plan), offsetof(bop_plan,rows_k), offsetof(bop_plan,ws_bytes));
  printf("%zu %zu %zu %zu %zu\n", sizeof(bop_system), offsetof(bop_system,n_pairs), offsetof(bop_system,plan),
         offsetof(bop_system,n_elec), offsetof(bop_system,U_total));
  printf("%zu\n", sizeof(bop_tuning));
@@ -55,6 +55,6 @@ int main(void){
     got = [list(map(int, l.split())) for l in subprocess.check_output([str(exe)]).decode().splitlines()]
     M, S = P.Model, P.System
     assert got[0] == [C.sizeof(M), M.onsite.offset, M.form.offset, M.beta0.offset, M.r0.offset, M.q.offset]
-    assert got[1] == [C.sizeof(P.Plan), P.Plan.ws_bytes.offset]
+    assert got[1] == [C.sizeof(P.Plan), P.Plan.rows_k.offset, P.Plan.ws_bytes.offset]
     assert got[2] == [C.sizeof(S), S.n_pairs.offset, S.plan.offset, S.n_elec.offset, S.U_total.offset]
     assert got[3] == [C.sizeof(P.Tuning)]

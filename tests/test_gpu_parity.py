@@ -98,8 +98,11 @@ def test_hamiltonian(bop, torch_mod, name):
     for dt, tol in (("f64", 1e-13), ("f32", 2e-7), ("bf16", 8e-3)):
         H_on, H_b = bop.build_H(model, species, nl, shift=shift, dtype=dt)
         np.testing.assert_allclose(_np(H_on), Hon_r, atol=1e-15)
-        err = np.abs(_np(H_b.double()) - Hb_r).max() / np.abs(Hb_r).max()
+        hb = _np(H_b.double())
+        no = Hb_r.shape[1]
+        err = np.abs(hb[:, :, :no] - Hb_r).max() / np.abs(Hb_r).max()
         assert err < tol, (dt, err)
+        assert np.all(hb[:, :, no:] == 0.0)
 
 
 def _gpu_moments(bop, torch_mod, pos, cell, spc, model, n_max, dtype="f64", tuning=None, use_order=True):
@@ -121,9 +124,9 @@ def test_moments_fp64(bop, torch_mod, name):
     assert _mu_err(_np(mu), ref) < 1e-10
 
 
-@pytest.mark.parametrize("tuning", [{"tile_atoms": 1}, {"tile_atoms": 5, "block_threads": 256},
-                                    {"tile_atoms": 7, "block_threads": 1024, "n_blocks": 3},
-                                    {"block_threads": 256, "n_blocks": 1}])
+@pytest.mark.parametrize("tuning", [{"tile_atoms": 1}, {"tile_atoms": 5, "block_threads": 512},
+                                    {"tile_atoms": 7, "block_threads": 1024, "batch_tiles": 8, "chunk_rows": 8},
+                                    {"block_threads": 256, "batch_tiles": 8, "chunk_rows": 1}])
 def test_moments_tilings(bop, torch_mod, tuning):
     pos, cell, spc, model, n_max = STRUCTS["bcc_alloy"]
     ref_nl = O.neighbours(pos, cell, model["r_cut"])
@@ -142,10 +145,27 @@ def test_moments_fp32(bop, torch_mod, name):
     assert _mu_err(_np(mu), ref) < 1e-5
 
 
+@pytest.mark.parametrize("name", ["bcc_small", "fcc_spd", "hcp", "bcc_alloy"])
+def test_moments_bf16_mfma(bop, torch_mod, name):
+    """BF16 H and X on MFMA with FP32 accumulation.  Stated bound: each step
+    rounds X^k to BF16 (relative 2^-9) and multiplies by BF16 H, so the
+    scale-normalised moment error grows about linearly with the order; 2e-2
+    at n_max <= 12 covers it with margin (measured values are reported by
+    the precision benchmark)."""
+    pos, cell, spc, model, n_max = STRUCTS[name]
+    ref_nl = O.neighbours(pos, cell, model["r_cut"])
+    ref = O.moments(ref_nl, *O.build_H(model, spc, ref_nl), n_max)
+    mu, *_ = _gpu_moments(bop, torch_mod, pos, cell, spc, model, n_max, dtype="bf16")
+    m = _np(mu)
+    assert np.all(np.isfinite(m))
+    np.testing.assert_array_equal(m[..., 0], 1.0)
+    assert _mu_err(m, ref) < 2e-2
+
+
 def test_moments_deterministic(bop, torch_mod):
     pos, cell, spc, model, n_max = STRUCTS["bcc_alloy"]
-    a, *_ = _gpu_moments(bop, torch_mod, pos, cell, spc, model, n_max, tuning={"n_blocks": 7})
-    b, *_ = _gpu_moments(bop, torch_mod, pos, cell, spc, model, n_max, tuning={"n_blocks": 2})
+    a, *_ = _gpu_moments(bop, torch_mod, pos, cell, spc, model, n_max, tuning={"batch_tiles": 8})
+    b, *_ = _gpu_moments(bop, torch_mod, pos, cell, spc, model, n_max, tuning={"batch_tiles": 16})
     assert np.array_equal(_np(a).view(np.uint64), _np(b).view(np.uint64))
 
 
