@@ -190,6 +190,33 @@ int bop_moments(const bop_plan *plan /*[host]*/, const int *row_ptr, const doubl
                 hipStream_t stream);
 
 /* =========================================================================
+ * Recursion coefficients straight from the H.X products: the Lanczos chain
+ * (Sec. "Density of states" of App. B, the tridiagonal Hamiltonian of the
+ * recursion method; App. B.3 for the coefficients' definition).
+ *
+ * Same plan, tiles, supports and workspace as bop_moments (prepare first).
+ * Per orbital row: u_0 = the unit start vector, a_k = <u_k, H u_k - b_k
+ * u_(k-1)>, b_(k+1) = |H u_k - a_k u_k - b_k u_(k-1)|, u_(k+1) = that vector /
+ * b_(k+1), for a_k, k < n_a and b_k, 1 <= k <= n_b: in exact arithmetic the
+ * coefficients bop_recursion derives from the moments up to n_max.  The
+ * vectors are stored in the plan's dtype and kept orthonormal by construction,
+ * so FP32 and BF16 rounding shows up in a_n, b_n at about the unit roundoff
+ * times |H|, where the moment route amplifies it (ill-conditioned Hankel
+ * map).  Inner products and coefficients are FP64.
+ * Breakdown: b_(k+1)^2 <= thr * b_1^2 (thr = 1e-14 FP64, 1e-10 FP32, 1e-5
+ * BF16) sets that and later b to 0, repeats a, and flags BOP_FLAG_BREAKDOWN |
+ * level << 8, as the moment route does.  Seeds of a failed tile get NaN
+ * coefficients and BOP_FLAG_NONFINITE.
+ *
+ *  a [N*n_orb][n_a], b [N*n_orb][n_b+1] (b[.][0] = 0), flags [N*n_orb] out.
+ *  Follow with bop_recursion(mu = NULL) for the terminator and bop_energy(mu
+ *  = NULL), which take every sigma_m from the chain.
+ * ========================================================================= */
+int bop_lanczos(const bop_plan *plan /*[host]*/, const int *row_ptr, const double *H_on,
+                const void *H_bond, double *a, double *b, int *flags, void *ws,
+                size_t ws_bytes, hipStream_t stream);
+
+/* =========================================================================
  * Recursion coefficients and terminator (App. B.3, App. B.5), FP64.
  *
  * Per row (one orbital; mu normalised by its mu_0): a_n for n < n_a =
@@ -204,6 +231,8 @@ int bop_moments(const bop_plan *plan /*[host]*/, const int *row_ptr, const doubl
  *
  *  mu [n_rows][n_max+1] -> a [n_rows][n_a], b [n_rows][n_b+1],
  *  a_inf, b_inf, flags [n_rows].   n_max <= 40.
+ *  mu = NULL: a, b (and flags) are inputs from bop_lanczos; only a_inf, b_inf
+ *  and the flags the terminator adds are written.
  * ========================================================================= */
 int bop_recursion(int n_rows, int n_max, const double *mu, int bw_mode,
                   double a_glob, double b_glob, double *a, double *b,
@@ -234,6 +263,8 @@ int bop_recursion(int n_rows, int n_max, const double *mu, int bw_mode,
  *  ef_mode 1: E_F [device] in: energies at the given level.
  *  ws: bop_energy_workspace_size(n_atoms, n_orb, n_exp) bytes.
  *  n_exp <= 1024 (default used by the paper's example: 200).
+ *  mu = NULL (Lanczos form): sigma_m for every m from the chain, which equals
+ *  the moment route for m <= n_max in exact arithmetic.
  * ========================================================================= */
 size_t bop_energy_workspace_size(int n_atoms, int n_orb, int n_exp);
 int bop_energy(int n_atoms, int n_orb, int n_max, int n_exp, const double *mu,
@@ -251,10 +282,12 @@ int bop_energy(int n_atoms, int n_orb, int n_max, int n_exp, const double *mu,
  * unchanged; else shift_i += mix q_i / max(n_i(E_F), n_floor) followed by
  * removal of the mean shift (shift + c with E_F + c is the same state).
  * Everything stays on the device; the host loops until *converged.
+ * method 0: moments + bop_recursion; method 1: bop_lanczos (mu unused).
  * ========================================================================= */
 typedef struct bop_system {
     bop_model model;
     int n_atoms, n_max, n_exp, dtype;
+    int method;
     const int *species;            /* [N] */
     const double *n0;              /* [N] reference electrons per atom */
     const int *row_ptr, *nbr_j, *order;

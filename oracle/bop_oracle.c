@@ -635,6 +635,11 @@ void or_jackson(int n_exp, double *g)
  * m <= n_max, which equal the moment route in exact arithmetic.
  * Reading: the first sum of the extended DOS formula in App. B.4 is taken to
  * start at m = 0 (sigma_0 = 1 normalises the DOS).
+ * Reading (degenerate band): where the terminator's b_inf sits at its floor
+ * (a band of zero width, e.g. an atom without neighbours), the normalised
+ * moments divide rounding noise by (2 b_inf)^n and the moment route is
+ * meaningless in floating point; such rows take every sigma_m from the chain,
+ * which is exact for them (and equal to the moment route in exact arithmetic).
  */
 void or_dos_coeffs(int n_rows, int n_max, int n_exp, const double *mu,
                    const double *a, const double *b, const double *a_inf,
@@ -675,7 +680,9 @@ void or_dos_coeffs(int n_rows, int n_max, int n_exp, const double *mu,
                 mh[n] = s / pow(2.0 * bi, n);
             }
             double *out = &gsig[(long)r * (n_exp + 1)];
-            for (int m = 0; m <= n_max && m <= n_exp; ++m) {
+            const int n_mom = bi > 1e-6 ? n_max : 0;
+            out[0] = 1.0;
+            for (int m = 0; m <= n_mom && m <= n_exp; ++m) {
                 double s = 0.0;
                 for (int n = 0; n <= m; ++n) s += p[m * M + n] * mh[n];
                 out[m] = s;
@@ -698,8 +705,8 @@ void or_dos_coeffs(int n_rows, int n_max, int n_exp, const double *mu,
                 for (int k = top + 1; k <= n_exp + 2; ++k) z2[k] = 0.0;
                 double *t = z0; z0 = z1; z1 = z2; z2 = t;
                 int mm = m + 1;
-                if (mm > n_max) out[mm] = z1[0];
-                else if (sig_chain) sig_chain[(long)r * (n_max + 1) + mm] = z1[0];
+                if (mm > n_mom) out[mm] = z1[0];
+                if (mm <= n_max && sig_chain) sig_chain[(long)r * (n_max + 1) + mm] = z1[0];
             }
             for (int m = 0; m <= n_exp; ++m) out[m] *= g[m];
         }

@@ -75,6 +75,7 @@ class System(C.Structure):
     _fields_ = [
         ("model", Model),
         ("n_atoms", C.c_int), ("n_max", C.c_int), ("n_exp", C.c_int), ("dtype", C.c_int),
+        ("method", C.c_int),
         ("species", P), ("n0", P), ("row_ptr", P), ("nbr_j", P), ("order", P),
         ("n_pairs", C.c_long),
         ("H_on", P), ("H_bond", P),
@@ -150,7 +151,14 @@ def _dev(t, dtype=None, name="tensor"):
 
 
 def _ptr(t):
-    return None if t is None else C.c_void_p(t.data_ptr())
+    if t is None:
+        return None
+    p = t.data_ptr()
+    if p == 0 and t.numel() == 0:
+        # torch reports NULL for empty views; keep the storage's address so an
+        # empty array still passes as a valid pointer
+        p = t.untyped_storage().data_ptr()
+    return C.c_void_p(p) if p else None
 
 
 def _stream():
@@ -252,7 +260,8 @@ def build_H(model: dict, species, nl: Neighbours, shift=None, dtype="f64", H_on=
         H_on = torch.empty((n, no), dtype=torch.float64, device=dev)
     if H_bond is None and nl is not None:
         ld = (8 if no <= 8 else 16) if dtype == "bf16" else no
-        H_bond = torch.empty((nl.n_pairs, no, ld), dtype=tdt, device=dev)
+        # at least one row, so the pointer is valid when there are no pairs
+        H_bond = torch.empty((max(nl.n_pairs, 1), no, ld), dtype=tdt, device=dev)[: nl.n_pairs]
     m = model_struct(model)
     if shift is not None:
         _dev(shift, torch.float64, "shift")
@@ -306,6 +315,39 @@ def moments(plan: Plan, nl: Neighbours, H_on, H_bond, mu=None, ws=None, use_orde
     _check(lib.bop_moments(C.byref(plan), _ptr(nl.row_ptr), _ptr(H_on), _ptr(H_bond), _ptr(mu),
                            _ptr(ws), ws.numel(), _stream()))
     return mu
+
+
+def lanczos(plan: Plan, nl: Neighbours, H_on, H_bond, out=None, ws=None, use_order=True):
+    """Recursion coefficients a [R, n_a], b [R, n_b+1] and flags [R] straight
+    from the H.X products (``bop_lanczos``); R = N * n_orb."""
+    torch = _torch()
+    lib = load()
+    dev = H_on.device
+    R = plan.n_atoms * plan.n_orb
+    o = out or {}
+    a = o.get("a", torch.empty((R, n_a(plan.n_max)), dtype=torch.float64, device=dev))
+    b = o.get("b", torch.empty((R, n_b(plan.n_max) + 1), dtype=torch.float64, device=dev))
+    fl = o.get("flags", torch.empty(R, dtype=torch.int32, device=dev))
+    if ws is None:
+        ws = moments_prepare(plan, nl, use_order=use_order)
+    _check(lib.bop_lanczos(C.byref(plan), _ptr(nl.row_ptr), _ptr(H_on), _ptr(H_bond), _ptr(a), _ptr(b), _ptr(fl),
+                           _ptr(ws), ws.numel(), _stream()))
+    return {"a": a, "b": b, "flags": fl}
+
+
+def terminator(rec, n_max, global_ab=None):
+    """a_inf, b_inf (and terminator flags) for coefficients from ``lanczos``
+    (``bop_recursion`` with mu = NULL); updates and returns ``rec``."""
+    torch = _torch()
+    R = rec["a"].shape[0] if n_a(n_max) else rec["b"].shape[0]
+    dev = rec["b"].device
+    for k in ("a_inf", "b_inf"):
+        if k not in rec:
+            rec[k] = torch.empty(R, dtype=torch.float64, device=dev)
+    mode, ag, bg = (0, 0.0, 0.0) if global_ab is None else (1, float(global_ab[0]), float(global_ab[1]))
+    _check(load().bop_recursion(R, n_max, None, mode, ag, bg, _ptr(rec["a"]), _ptr(rec["b"]), _ptr(rec["a_inf"]),
+                                _ptr(rec["b_inf"]), _ptr(rec["flags"]), _stream()))
+    return rec
 
 
 def n_a(n_max):
@@ -368,9 +410,12 @@ class EnergyPath:
     with every buffer allocated once (device tensors) and reused."""
 
     def __init__(self, pos, cell, species, model: dict, n_max: int, n_exp: int = 200, dtype: str = "f64",
-                 tuning=None, device="cuda"):
+                 tuning=None, device="cuda", method: str = "moments"):
         torch = _torch()
         load()
+        if method not in ("moments", "lanczos"):
+            raise ValueError("method must be 'moments' or 'lanczos'")
+        self.method = method
         self.device = torch.device(device)
         self.model = model
         self.n_max, self.n_exp, self.dtype = int(n_max), int(n_exp), dtype
@@ -412,9 +457,16 @@ class EnergyPath:
         return self.run(n_elec, E_F)
 
     def run_moments(self):
+        """The H.X passes: moments, or with method 'lanczos' the recursion
+        coefficients."""
+        if self.method == "lanczos":
+            return lanczos(self.plan, self.nl, self.H_on, self.H_bond, out=self.rec, ws=self.mws)
         return moments(self.plan, self.nl, self.H_on, self.H_bond, mu=self.mu, ws=self.mws)
 
     def run_tail(self, n_elec, E_F=None):
+        if self.method == "lanczos":
+            terminator(self.rec, self.n_max)
+            return energy(None, self.rec, self.H_on, n_elec, self.n_max, self.n_exp, E_F=E_F, ws=self.ews)
         recursion(self.mu, self.n_max, out=self.rec)
         return energy(self.mu, self.rec, self.H_on, n_elec, self.n_max, self.n_exp, E_F=E_F, ws=self.ews)
 
@@ -427,8 +479,9 @@ class SCFPath(EnergyPath):
     """Local-charge-neutrality self-consistency (``bop_scf_step``): one onsite
     shift per atom, updated on the device until max |N_i - n0_i| < tol."""
 
-    def __init__(self, pos, cell, species, model, n_max, n0, n_exp=200, dtype="f64", tuning=None, device="cuda"):
-        super().__init__(pos, cell, species, model, n_max, n_exp, dtype, tuning, device)
+    def __init__(self, pos, cell, species, model, n_max, n0, n_exp=200, dtype="f64", tuning=None, device="cuda",
+                 method="moments"):
+        super().__init__(pos, cell, species, model, n_max, n_exp, dtype, tuning, device, method)
         torch = _torch()
         self.n0 = torch.as_tensor(np.ascontiguousarray(n0, np.float64), device=self.device)
         self.n_elec = float(np.sum(n0))
@@ -443,6 +496,7 @@ class SCFPath(EnergyPath):
         s = System()
         s.model = model_struct(model)
         s.n_atoms, s.n_max, s.n_exp, s.dtype = self.n, self.n_max, self.n_exp, DTYPES[dtype]
+        s.method = 1 if method == "lanczos" else 0
         s.species, s.n0 = _ptr(self.species), _ptr(self.n0)
         s.row_ptr, s.nbr_j, s.order = _ptr(self.nl.row_ptr), _ptr(self.nl.nbr_j), _ptr(self.nl.order)
         s.n_pairs = self.nl.n_pairs

@@ -44,10 +44,17 @@ k_recursion(int n_rows, int n_max, const double *__restrict__ mu, int bw_mode, d
     int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n_rows) return;
     const int na = n_a_of(n_max), nb = n_b_of(n_max);
+    double *ar = a + (long)r * na, *br = b + (long)r * (nb + 1);
+    int fl = 0;
+    if (!mu) {
+        // a, b given (Lanczos form); keep its breakdown and non-finite flags
+        fl = flags[r];
+        goto terminator;
+    }
+    {
     double m[MAX_NMAX + 1];
     const double *mr = mu + (long)r * (n_max + 1);
     const double m0 = mr[0];
-    int fl = 0;
     for (int t = 0; t <= n_max; ++t) {
         m[t] = mr[t] / m0;
         if (!isfinite(m[t])) fl |= BOP_FLAG_NONFINITE;
@@ -55,7 +62,6 @@ k_recursion(int n_rows, int n_max, const double *__restrict__ mu, int bw_mode, d
     double cp[MAX_NMAX / 2 + 3], cc[MAX_NMAX / 2 + 3], d[MAX_NMAX / 2 + 3];
     for (int j = 0; j < MAX_NMAX / 2 + 3; ++j) { cp[j] = 0.0; cc[j] = 0.0; }
     cc[0] = 1.0;
-    double *ar = a + (long)r * na, *br = b + (long)r * (nb + 1);
     br[0] = 0.0;
     double bn = 0.0;                   // b_n of the current level
     const double var = (n_max >= 2) ? m[2] - m[1] * m[1] : 0.0;
@@ -82,6 +88,8 @@ k_recursion(int n_rows, int n_max, const double *__restrict__ mu, int bw_mode, d
         for (int j = 0; j <= n + 1; ++j) { cp[j] = cc[j]; cc[j] = d[j] / bb; }
         bn = bb;
     }
+    }
+terminator:
     double ai, bi;
     if (bw_mode == 1) { ai = a_glob; bi = b_glob; }
     else {
@@ -144,6 +152,14 @@ k_dos_coeffs(int n_rows, int n_max, int n_exp, const double *__restrict__ mu,
     if (r >= n_rows) return;
     const int na = n_a_of(n_max), nb = n_b_of(n_max);
     const double ai = a_inf[r], bi = b_inf[r];
+    // Every sigma_m comes from the chain without moments (Lanczos form) and for
+    // a band of zero width (b_inf at its floor), where the normalised moments
+    // would divide rounding noise by (2 b_inf)^n.
+    const int n_mom = (mu && bi > 1e-6) ? n_max : 0;
+    double big = 0.0;          // |g sigma| of a proper DOS stays below m + 1
+    if (n_mom == 0) {
+        gs[r] = s_g[0];
+    } else {
     const double *mr = mu + (long)r * M;
     // normalised moments mu^_n
     double mh[MAX_NMAX + 1];
@@ -156,14 +172,14 @@ k_dos_coeffs(int n_rows, int n_max, int n_exp, const double *__restrict__ mu,
         }
         mh[n] = s / pow(2.0 * bi, (double)n);
     }
-    double big = 0.0;          // |g sigma| of a proper DOS stays below m + 1
     for (int m = 0; m < M && m <= n_exp; ++m) {
         double s = 0.0;
         for (int n = 0; n <= m; ++n) s += s_p[m * M + n] * mh[n];
         gs[(long)m * n_rows + r] = s_g[m] * s;
         big = fmax(big, fabs(s_g[m] * s));
     }
-    if (n_exp <= n_max) {
+    }
+    if (n_exp <= n_mom) {
         if (!(big <= 1e4)) flags[r] |= BOP_FLAG_DIVERGENT;
         return;
     }
@@ -193,7 +209,7 @@ k_dos_coeffs(int n_rows, int n_max, int n_exp, const double *__restrict__ mu,
 #pragma unroll
         for (int k = 0; k <= LM; ++k) { z0[k] = z1[k]; z1[k] = zn[k]; }
         const int mm = m + 1;
-        if (mm > n_max) {
+        if (mm > n_mom) {
             double v = s_g[mm] * z1[0];
             gs[(long)mm * n_rows + r] = v;
             big = fmax(big, fabs(v));
@@ -476,7 +492,7 @@ extern "C" int bop_recursion(int n_rows, int n_max, const double *mu, int bw_mod
     BOP_REQUIRE(n_max >= 1 && n_max <= MAX_NMAX, BOP_E_UNSUPPORTED, "bop_recursion: n_max must be 1..%d", MAX_NMAX);
     BOP_REQUIRE(bw_mode == 0 || bw_mode == 1, BOP_E_ARG, "bop_recursion: bw_mode must be 0 or 1");
     if (n_rows == 0) return BOP_OK;
-    BOP_REQUIRE(mu && a && b && a_inf && b_inf && flags, BOP_E_ARG, "bop_recursion: NULL array");
+    BOP_REQUIRE(a && b && a_inf && b_inf && flags, BOP_E_ARG, "bop_recursion: NULL array");
     k_recursion<<<(n_rows + DT - 1) / DT, DT, 0, stream>>>(n_rows, n_max, mu, bw_mode, a_glob, b_glob, a, b,
                                                            a_inf, b_inf, flags);
     BOP_LAUNCHED();
@@ -499,7 +515,7 @@ extern "C" int bop_energy(int n_atoms, int no, int n_max, int n_exp, const doubl
     BOP_REQUIRE(n_max >= 1 && n_max <= MAX_NMAX, BOP_E_UNSUPPORTED, "bop_energy: n_max must be 1..%d", MAX_NMAX);
     BOP_REQUIRE(n_exp >= 1 && n_exp <= 1024, BOP_E_UNSUPPORTED, "bop_energy: n_exp must be 1..1024");
     BOP_REQUIRE(ef_mode == 0 || ef_mode == 1, BOP_E_ARG, "bop_energy: ef_mode must be 0 or 1");
-    BOP_REQUIRE(mu && a && b && a_inf && b_inf && H_on && E_F && N_atom && U_atom && dos_atom && U_total && flags,
+    BOP_REQUIRE(a && b && a_inf && b_inf && H_on && E_F && N_atom && U_atom && dos_atom && U_total && flags,
                 BOP_E_ARG, "bop_energy: NULL array");
     const long R = (long)n_atoms * no;
     EnergyWs w = carve(ws, R, n_exp);

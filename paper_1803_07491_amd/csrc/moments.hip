@@ -171,6 +171,7 @@ struct Layout {
     size_t x;           // X buffers: batch x 2 x rows_cap x n_orb x 64 (also prepare's maps)
     size_t x_stride;    // bytes of one X buffer
     size_t part;        // double [batch][chunks][2][64]
+    size_t lc;          // double [batch][4][64]: Lanczos column coefficients
     size_t bytes;
 };
 
@@ -188,6 +189,7 @@ __host__ __device__ inline Layout make_layout(const bop_plan &p, int n_prep_wg)
     L.x = take(xb > maps ? xb : maps);
     int nch = (p.rows_cap + p.chunk_rows - 1) / p.chunk_rows;
     L.part = take(8ull * 2 * 64 * (size_t)nch * p.batch_tiles);
+    L.lc = take(8ull * 4 * 64 * p.batch_tiles);
     L.bytes = o;
     return L;
 }
@@ -332,12 +334,19 @@ __global__ void k_x0(Batch bt, int n_max, int B, const int *__restrict__ sizes_,
 // contiguous range of pairs) into its LDS slice with coalesced loads, and
 // issues the X gathers of G neighbour slots before using any of them, so a
 // row costs a few memory round trips instead of one per slot.
-template <typename T, int NO, int WGT>
+//
+// LANCZOS = 1: the same product for Lanczos level k - 1 (the support of H u_(k-1)
+// is that of X^k).  The buffer read holds r_(k-1) = u_(k-1) / s, the buffer
+// written holds r_(k-2) on entry; per column (lane) lc gives s = 1/|r_(k-1)| and
+// beta = b_(k-1) * s_(k-2).  The row stores y' = s H r_(k-1) - beta r_(k-2) in
+// place of r_(k-2) and the partial sums give <r_(k-1), y'> (a_(k-1) = s times
+// that); the update kernel then forms r_k = y' - a_(k-1) u_(k-1).
+template <typename T, int NO, int WGT, int LANCZOS>
 __global__ void __launch_bounds__(WGT)
 k_step(Batch bt, int k, int K, int last, int nch, int chunk_rows, int deg_max, int rows_cap,
        const int *__restrict__ row_ptr, const double *__restrict__ H_on, const T *__restrict__ H,
        const int *__restrict__ sizes_, const char *tiles_base, size_t tile_stride, char *xbase,
-       size_t x_stride, double *__restrict__ part)
+       size_t x_stride, double *__restrict__ part, const double *__restrict__ lc)
 {
     constexpr int NW = WGT / 64;
     constexpr int NB = NO * NO;
@@ -367,6 +376,11 @@ k_step(Batch bt, int k, int K, int last, int nch, int chunk_rows, int deg_max, i
     T *sH = (T *)s_dyn + (size_t)w * deg_max * NB;          // this wave's H blocks
     constexpr int stride_row = NO * 64;
     double so = 0.0, se = 0.0;
+    T ls = T(1), lbeta = T(0);
+    if (LANCZOS) {
+        ls = (T)lc[((size_t)t * 4 + 0) * 64 + lane];
+        lbeta = (T)lc[((size_t)t * 4 + 1) * 64 + lane];
+    }
     for (int l = r0 + w; l < r1; l += NW) {
         const int g = __builtin_amdgcn_readfirstlane(sup[l]);
         const int info = __builtin_amdgcn_readfirstlane(rinfo[l]);
@@ -413,15 +427,23 @@ k_step(Batch bt, int k, int K, int last, int nch, int chunk_rows, int deg_max, i
             }
         }
         __builtin_amdgcn_wave_barrier();   // all lanes done with sH before the next row overwrites it
+        T *xo = Xc + (long)l * stride_row + lane;
+        if (LANCZOS) {
+            const bool has_prev2 = L <= k - 2;
+#pragma unroll
+            for (int a = 0; a < NO; ++a) {
+                const T xm = has_prev2 ? xo[a * 64] : T(0);
+                acc[a] = acc[a] * ls - lbeta * xm;
+            }
+        }
         if (!last) {
-            T *xo = Xc + (long)l * stride_row + lane;
 #pragma unroll
             for (int a = 0; a < NO; ++a) xo[a * 64] = acc[a];
         }
 #pragma unroll
         for (int a = 0; a < NO; ++a) {
             so = fma((double)xs[a], (double)acc[a], so);
-            se = fma((double)acc[a], (double)acc[a], se);
+            if (!LANCZOS) se = fma((double)acc[a], (double)acc[a], se);
         }
     }
     s_red[0][w][lane] = so;
@@ -522,12 +544,15 @@ __global__ void k_x0_bf16(Batch bt, int n_max, const int *__restrict__ sizes_, c
     }
 }
 
-template <int NO, int WGT>
+// LANCZOS = 1: the Lanczos product of k_step (same column coefficients), with
+// r_(k-2) read from the BF16 buffer that y' replaces.
+template <int NO, int WGT, int LANCZOS>
 __global__ void __launch_bounds__(WGT)
 k_step_bf16(Batch bt, int k, int K, int last, int nch, int chunk_rows, int deg_max, int rows_cap,
             const int *__restrict__ row_ptr, const double *__restrict__ H_on,
             const unsigned short *__restrict__ H, const int *__restrict__ sizes_, const char *tiles_base,
-            size_t tile_stride, char *xbase, size_t x_stride, double *__restrict__ part)
+            size_t tile_stride, char *xbase, size_t x_stride, double *__restrict__ part,
+            const double *__restrict__ lc)
 {
     constexpr int NW = WGT / 64;
     constexpr int SW = NO <= 8 ? 8 : 16;
@@ -554,6 +579,14 @@ k_step_bf16(Batch bt, int k, int K, int last, int nch, int chunk_rows, int deg_m
     const int gslot = (SW == 8) ? g : (g >> 1);  // slot of this lane group within a chunk
     const int boff = (SW == 8) ? 0 : 8 * (g & 1);
     double so[4] = {0, 0, 0, 0}, se[4] = {0, 0, 0, 0};
+    float ls[4] = {1.f, 1.f, 1.f, 1.f}, lbeta[4] = {0.f, 0.f, 0.f, 0.f};
+    if (LANCZOS) {
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+            ls[cb] = (float)lc[((size_t)t * 4 + 0) * 64 + cb * 16 + n];
+            lbeta[cb] = (float)lc[((size_t)t * 4 + 1) * 64 + cb * 16 + n];
+        }
+    }
     for (int l = r0 + w; l < r1; l += NW) {
         const int gatom = __builtin_amdgcn_readfirstlane(sup[l]);
         const int info = __builtin_amdgcn_readfirstlane(rinfo[l]);
@@ -606,12 +639,19 @@ k_step_bf16(Batch bt, int k, int K, int last, int nch, int chunk_rows, int deg_m
 #pragma unroll
                 for (int j = 0; j < 4; ++j) xp[j] = bf16_to_f32((unsigned short)(v >> (16 * j)));
             }
+            float xm[4] = {0.f, 0.f, 0.f, 0.f};
+            if (LANCZOS && L <= k - 2 && 4 * g < SW) {
+                const unsigned long long v = *(const unsigned long long *)(Xc + off);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) xm[j] = bf16_to_f32((unsigned short)(v >> (16 * j)));
+            }
             unsigned long long outv = 0;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const float v = fmaf(e[j], xp[j], acc[cb][j]);
+                float v = fmaf(e[j], xp[j], acc[cb][j]);
+                if (LANCZOS) v = v * ls[cb] - lbeta[cb] * xm[j];
                 so[cb] = fma((double)xp[j], (double)v, so[cb]);
-                se[cb] = fma((double)v, (double)v, se[cb]);
+                if (!LANCZOS) se[cb] = fma((double)v, (double)v, se[cb]);
                 outv |= (unsigned long long)f32_to_bf16(v) << (16 * j);
             }
             if (!last && 4 * g < SW) *(unsigned long long *)(Xc + off) = outv;
@@ -661,8 +701,9 @@ int run_moments_bf16(const bop_plan &p, const int *row_ptr, const double *H_on, 
             if (nch <= 0) continue;
             dim3 grid((unsigned)(nb8 * nch * 8));
 #define BOP_STEP16(W)                                                                                    \
-    k_step_bf16<NO, W><<<grid, W, 0, st>>>(bt, k, K, last, nch, p.chunk_rows, p.deg_max, p.rows_cap, row_ptr, \
-                                           H_on, H, sizes, tiles, lay.tile_stride, xb, lay.x_stride, part)
+    k_step_bf16<NO, W, 0><<<grid, W, 0, st>>>(bt, k, K, last, nch, p.chunk_rows, p.deg_max, p.rows_cap,       \
+                                              row_ptr, H_on, H, sizes, tiles, lay.tile_stride, xb, lay.x_stride, \
+                                              part, nullptr)
             if (p.block_threads == 256) BOP_STEP16(256);
             else if (p.block_threads == 512) BOP_STEP16(512);
             else BOP_STEP16(1024);
@@ -701,9 +742,9 @@ int run_moments(const bop_plan &p, const int *row_ptr, const double *H_on, const
             if (nch <= 0) continue;
             dim3 grid((unsigned)(nb8 * nch * 8));
 #define BOP_STEP(W)                                                                                   \
-    k_step<T, NO, W><<<grid, W, (size_t)(W / 64) * p.deg_max * NO * NO * sizeof(T), st>>>(                \
+    k_step<T, NO, W, 0><<<grid, W, (size_t)(W / 64) * p.deg_max * NO * NO * sizeof(T), st>>>(             \
         bt, k, K, last, nch, p.chunk_rows, p.deg_max, p.rows_cap, row_ptr, H_on, H, sizes, tiles,       \
-        lay.tile_stride, xb, lay.x_stride, part)
+        lay.tile_stride, xb, lay.x_stride, part, nullptr)
             if (p.block_threads == 256) BOP_STEP(256);
             else if (p.block_threads == 512) BOP_STEP(512);
             else BOP_STEP(1024);
@@ -715,6 +756,264 @@ int run_moments(const bop_plan &p, const int *row_ptr, const double *H_on, const
         }
     }
     (void)nch_all;
+    return BOP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Lanczos form: the recursion coefficients straight from the H.X products
+// ---------------------------------------------------------------------------
+// The chain of App. B.3 is built column by column with the Lanczos algorithm
+// (u_0 = unit start vector, b_(k+1) u_(k+1) = H u_k - a_k u_k - b_k u_(k-1),
+// a_k = <u_k, H u_k>), which gives the same a_n, b_n as the moments but keeps
+// the vectors orthonormal, so rounding of the stored vectors in FP32 or BF16
+// perturbs a_n, b_n by about the unit roundoff times |H| instead of being
+// amplified by the ill-conditioned moments-to-coefficients map.  Vectors are
+// stored unnormalised (r_k = |r_k| u_k) and scaled by the per-column factor
+// when read, so a level costs one product pass, one elementwise update pass and
+// two per-column reductions.
+//
+// Column coefficients lc[t][.][c]: [0] s_k = 1/|r_k|, [1] beta_k = b_k s_(k-1),
+// [2] a_k s_k, [3] s_(k-1).
+
+// unit start vectors, coefficients of level 0, b_0 = 0 and flags; NaN
+// coefficients for the seeds of failed tiles
+template <typename T, int NO>
+__global__ void k_l0(Batch bt, int n_max, const int *__restrict__ sizes_, const char *tiles_base,
+                     size_t tile_stride, char *xbase, size_t x_stride, double *__restrict__ lc,
+                     double *__restrict__ a, double *__restrict__ b, int *__restrict__ flags, int bf16)
+{
+    const int t = blockIdx.x;
+    if (t >= bt.count) return;
+    const int tile = bt.first + t;
+    const int *sizes = sizes_ + tile * (MAXK + 2);
+    const int *sup = (const int *)(tiles_base + tile_stride * tile);
+    const int na = n_max >= 1 ? (n_max - 1) / 2 + 1 : 0, nb = n_max / 2;
+    const int Bt = sizes[0] < 0 ? sizes[1] : sizes[0];
+    const bool failed = sizes[0] < 0;
+    for (int e = threadIdx.x; e < Bt * NO; e += blockDim.x) {
+        const long gr = (long)sup[e / NO] * NO + e % NO;
+        for (int j = 0; j < na; ++j) a[gr * na + j] = failed ? __builtin_nan("") : 0.0;
+        for (int j = 0; j <= nb; ++j) b[gr * (nb + 1) + j] = (failed && j > 0) ? __builtin_nan("") : 0.0;
+        flags[gr] = failed ? BOP_FLAG_NONFINITE : 0;
+    }
+    if (failed) return;
+    if (threadIdx.x < 64) {
+        double *l = lc + (size_t)t * 4 * 64;
+        l[threadIdx.x] = threadIdx.x < Bt * NO ? 1.0 : 0.0;
+        l[64 + threadIdx.x] = 0.0;
+        l[128 + threadIdx.x] = 0.0;
+        l[192 + threadIdx.x] = 0.0;
+    }
+    if (bf16) {
+        constexpr int SW = NO <= 8 ? 8 : 16;
+        unsigned short *X0 = (unsigned short *)(xbase + x_stride * (2 * (size_t)t));
+        for (int e = threadIdx.x; e < Bt * 64 * SW; e += blockDim.x) {
+            int l = e / (64 * SW), rest = e % (64 * SW), c = rest / SW, al = rest % SW;
+            X0[e] = (al < NO && c == l * NO + al) ? (unsigned short)0x3f80 : (unsigned short)0;
+        }
+    } else {
+        T *X0 = (T *)(xbase + x_stride * (2 * (size_t)t));
+        for (int e = threadIdx.x; e < Bt * NO * 64; e += blockDim.x) {
+            int l = e / (NO * 64), rest = e % (NO * 64), al = rest / 64, c = rest % 64;
+            X0[(long)l * NO * 64 + al * 64 + c] = (c == l * NO + al) ? T(1) : T(0);
+        }
+    }
+}
+
+// r_k = y' - a_(k-1) s_(k-1) r_(k-1) on the rows of the support of X^k (k is
+// the moment-step index, level k - 1), in place of y'; partial sums of |r_k|^2.
+// A thread owns one column of a row: n_orb values in the [n_orb][64] layout,
+// or the slot-width vector in the BF16 [64][slot width] layout.
+template <typename T, int NO, int WGT, int BF>
+__global__ void __launch_bounds__(WGT)
+k_lupdate(Batch bt, int k, int nch, int chunk_rows, int rows_cap, const int *__restrict__ sizes_,
+          const char *tiles_base, size_t tile_stride, char *xbase, size_t x_stride,
+          const double *__restrict__ lc, double *__restrict__ part)
+{
+    constexpr int NW = WGT / 64;
+    __shared__ double s_red[NW][64];
+    const int xcd = blockIdx.x & 7, q = blockIdx.x >> 3;
+    const int t = (q / nch) * 8 + xcd, chunk = q % nch;
+    if (t >= bt.count) return;
+    const int tile = bt.first + t;
+    const int *sizes = sizes_ + tile * (MAXK + 2);
+    if (sizes[0] < 0) return;
+    const int nrow = sizes[k];
+    const int r0 = chunk * chunk_rows;
+    if (r0 >= nrow) return;
+    const int r1 = min(nrow, r0 + chunk_rows);
+    const int *sup = (const int *)(tiles_base + tile_stride * tile);
+    const int *rinfo = sup + rows_cap;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int src = (k - 1) & 1, dst = k & 1;
+    const double as = lc[((size_t)t * 4 + 2) * 64 + lane];
+    double se = 0.0;
+    if (BF) {
+        constexpr int SW = NO <= 8 ? 8 : 16;
+        const unsigned short *Xp = (const unsigned short *)(xbase + x_stride * (2 * (size_t)t + src));
+        unsigned short *Xc = (unsigned short *)(xbase + x_stride * (2 * (size_t)t + dst));
+        const float asf = (float)as;
+        for (int l = r0 + w; l < r1; l += NW) {
+            const bool hp = (rinfo[l] & 255) <= k - 1;
+            const long off = ((long)l * 64 + lane) * SW;
+#pragma unroll
+            for (int al = 0; al < NO; ++al) {
+                const float y = bf16_to_f32(Xc[off + al]);
+                const float x = hp ? bf16_to_f32(Xp[off + al]) : 0.f;
+                const float r = fmaf(-asf, x, y);
+                const unsigned short rb = f32_to_bf16(r);
+                Xc[off + al] = rb;
+                const double rd = (double)bf16_to_f32(rb);
+                se = fma(rd, rd, se);
+            }
+        }
+    } else {
+        const T *Xp = (const T *)(xbase + x_stride * (2 * (size_t)t + src));
+        T *Xc = (T *)(xbase + x_stride * (2 * (size_t)t + dst));
+        const T ast = (T)as;
+        for (int l = r0 + w; l < r1; l += NW) {
+            const bool hp = (rinfo[l] & 255) <= k - 1;
+            const long off = (long)l * NO * 64 + lane;
+#pragma unroll
+            for (int al = 0; al < NO; ++al) {
+                const T x = hp ? Xp[off + al * 64] : T(0);
+                const T r = Xc[off + al * 64] - ast * x;
+                Xc[off + al * 64] = r;
+                se = fma((double)r, (double)r, se);
+            }
+        }
+    }
+    s_red[w][lane] = se;
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        double tot = 0.0;
+#pragma unroll
+        for (int q2 = 0; q2 < NW; ++q2) tot += s_red[q2][threadIdx.x];
+        part[(((size_t)t * nch + chunk) * 2 + 1) * 64 + threadIdx.x] = tot;
+    }
+}
+
+// Per-column reduction of level k - 1 in chunk order.  which = 0: a_(k-1) from
+// the product pass (slot 0); which = 1: b_k from the update pass (slot 1), with
+// the breakdown test of the moment route (b_k^2 <= thr * b_1^2 ends the chain,
+// later a repeat the last one and later b are zero).
+__global__ void k_lreduce(Batch bt, int k, int K, int last, int which, int n_max, int no, int nch,
+                          int chunk_rows, double thr, const int *__restrict__ sizes_, const char *tiles_base,
+                          size_t tile_stride, const double *__restrict__ part, double *__restrict__ lc,
+                          double *__restrict__ a, double *__restrict__ b, int *__restrict__ flags)
+{
+    const int t = blockIdx.x;
+    if (t >= bt.count) return;
+    const int tile = bt.first + t;
+    const int *sizes = sizes_ + tile * (MAXK + 2);
+    if (sizes[0] < 0) return;
+    const int c = threadIdx.x;
+    if (c >= sizes[0] * no) return;
+    const int nrow = last ? sizes[K] : sizes[k];
+    const int used = (nrow + chunk_rows - 1) / chunk_rows;
+    double sum = 0.0;
+    for (int q = 0; q < used; ++q) sum += part[(((size_t)t * nch + q) * 2 + which) * 64 + c];
+    const int *sup = (const int *)(tiles_base + tile_stride * tile);
+    const long gr = (long)sup[c / no] * no + c % no;
+    const int na = n_max >= 1 ? (n_max - 1) / 2 + 1 : 0, nb = n_max / 2;
+    const int lev = k - 1;
+    double *l = lc + (size_t)t * 4 * 64;
+    int fl = flags[gr];
+    const bool broke = fl & BOP_FLAG_BREAKDOWN;
+    if (!isfinite(sum)) fl |= BOP_FLAG_NONFINITE;
+    if (which == 0) {
+        const double s = l[c];
+        const double av = broke ? a[gr * na + lev - 1] : s * sum;
+        a[gr * na + lev] = av;
+        l[128 + c] = broke ? 0.0 : av * s;
+    } else {
+        if (!broke) {
+            const double var = lev == 0 ? sum : b[gr * (nb + 1) + 1] * b[gr * (nb + 1) + 1];
+            if (!(sum > thr * var) || !(sum > 0.0)) {
+                for (int j = lev + 1; j <= nb; ++j) b[gr * (nb + 1) + j] = 0.0;
+                fl |= BOP_FLAG_BREAKDOWN | ((lev + 1) << 8);
+                l[192 + c] = l[c];
+                l[c] = 0.0;
+                l[64 + c] = 0.0;
+            } else {
+                const double bb = sqrt(sum);
+                b[gr * (nb + 1) + lev + 1] = bb;
+                l[192 + c] = l[c];
+                l[64 + c] = bb * l[c];
+                l[c] = 1.0 / bb;
+            }
+        }
+    }
+    flags[gr] = fl;
+}
+
+template <typename T, int NO>
+int run_lanczos(const bop_plan &p, const int *row_ptr, const double *H_on, const void *Hv, double *a, double *b,
+                int *flags, char *ws, const Layout &lay, hipStream_t st)
+{
+    const int K = p.n_max / 2;
+    const int steps = K + (p.n_max & 1);
+    const int *sizes = (const int *)(ws + lay.sizes);
+    const char *tiles = ws + lay.tiles;
+    char *xb = ws + lay.x;
+    double *part = (double *)(ws + lay.part);
+    double *lc = (double *)(ws + lay.lc);
+    const bool bf = p.dtype == BOP_BF16;
+    // breakdown threshold on b^2 relative to b_1^2, above the rounding level of the stored vectors
+    const double thr = p.dtype == BOP_F64 ? 1e-14 : (p.dtype == BOP_F32 ? 1e-10 : 1e-5);
+    for (int first = 0; first < p.n_tiles; first += p.batch_tiles) {
+        Batch bt{first, min(p.batch_tiles, p.n_tiles - first)};
+        k_l0<T, NO><<<bt.count, 256, 0, st>>>(bt, p.n_max, sizes, tiles, lay.tile_stride, xb, lay.x_stride, lc, a,
+                                              b, flags, bf ? 1 : 0);
+        BOP_LAUNCHED();
+        const int nb8 = (bt.count + 7) / 8;
+        for (int k = 1; k <= steps; ++k) {
+            const int last = k > K;
+            const int rows_k = last ? p.rows_k[K] : p.rows_k[k];
+            const int nch = (rows_k + p.chunk_rows - 1) / p.chunk_rows;
+            if (nch <= 0) continue;
+            dim3 grid((unsigned)(nb8 * nch * 8));
+            if (bf) {
+#define BOP_LSTEP16(W)                                                                                   \
+    k_step_bf16<NO, W, 1><<<grid, W, 0, st>>>(bt, k, K, last, nch, p.chunk_rows, p.deg_max, p.rows_cap, \
+                                              row_ptr, H_on, (const unsigned short *)Hv, sizes, tiles,   \
+                                              lay.tile_stride, xb, lay.x_stride, part, lc)
+                if (p.block_threads == 256) BOP_LSTEP16(256);
+                else if (p.block_threads == 512) BOP_LSTEP16(512);
+                else BOP_LSTEP16(1024);
+#undef BOP_LSTEP16
+            } else {
+#define BOP_LSTEP(W)                                                                                  \
+    k_step<T, NO, W, 1><<<grid, W, (size_t)(W / 64) * p.deg_max * NO * NO * sizeof(T), st>>>(             \
+        bt, k, K, last, nch, p.chunk_rows, p.deg_max, p.rows_cap, row_ptr, H_on, (const T *)Hv, sizes,  \
+        tiles, lay.tile_stride, xb, lay.x_stride, part, lc)
+                if (p.block_threads == 256) BOP_LSTEP(256);
+                else if (p.block_threads == 512) BOP_LSTEP(512);
+                else BOP_LSTEP(1024);
+#undef BOP_LSTEP
+            }
+            BOP_LAUNCHED();
+            k_lreduce<<<bt.count, 64, 0, st>>>(bt, k, K, last, 0, p.n_max, NO, nch, p.chunk_rows, thr, sizes, tiles,
+                                               lay.tile_stride, part, lc, a, b, flags);
+            BOP_LAUNCHED();
+            if (last) continue;
+#define BOP_LUPD(W)                                                                                        \
+    do {                                                                                                   \
+        if (bf) k_lupdate<T, NO, W, 1><<<grid, W, 0, st>>>(bt, k, nch, p.chunk_rows, p.rows_cap, sizes, tiles, \
+                                                           lay.tile_stride, xb, lay.x_stride, lc, part);   \
+        else k_lupdate<T, NO, W, 0><<<grid, W, 0, st>>>(bt, k, nch, p.chunk_rows, p.rows_cap, sizes, tiles,    \
+                                                        lay.tile_stride, xb, lay.x_stride, lc, part);      \
+    } while (0)
+            if (p.block_threads == 256) BOP_LUPD(256);
+            else if (p.block_threads == 512) BOP_LUPD(512);
+            else BOP_LUPD(1024);
+#undef BOP_LUPD
+            BOP_LAUNCHED();
+            k_lreduce<<<bt.count, 64, 0, st>>>(bt, k, K, last, 1, p.n_max, NO, nch, p.chunk_rows, thr, sizes, tiles,
+                                               lay.tile_stride, part, lc, a, b, flags);
+            BOP_LAUNCHED();
+        }
+    }
     return BOP_OK;
 }
 
@@ -852,4 +1151,23 @@ extern "C" int bop_moments(const bop_plan *plan, const int *row_ptr, const doubl
                        : run_moments<double, 9>(*plan, row_ptr, H_on, H_bond, mu, w, lay, stream);
     return no == 5 ? run_moments<float, 5>(*plan, row_ptr, H_on, H_bond, mu, w, lay, stream)
                    : run_moments<float, 9>(*plan, row_ptr, H_on, H_bond, mu, w, lay, stream);
+}
+
+extern "C" int bop_lanczos(const bop_plan *plan, const int *row_ptr, const double *H_on, const void *H_bond,
+                           double *a, double *b, int *flags, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    BOP_REQUIRE(plan, BOP_E_ARG, "bop_lanczos: plan is NULL");
+    BOP_REQUIRE(ws && ws_bytes >= plan->ws_bytes, BOP_E_CAPACITY,
+                "bop_lanczos: workspace of %zu bytes needed, %zu given", plan->ws_bytes, ws_bytes);
+    const int n = plan->n_atoms, no = plan->n_orb;
+    if (n == 0) return BOP_OK;
+    BOP_REQUIRE(row_ptr && H_on && H_bond && b && flags && (a || plan->n_max == 0), BOP_E_ARG,
+                "bop_lanczos: NULL array");
+    Layout lay = make_layout(*plan, map_workgroups(n, plan->n_tiles));
+    char *w = (char *)ws;
+    if (plan->dtype == BOP_F64)
+        return no == 5 ? run_lanczos<double, 5>(*plan, row_ptr, H_on, H_bond, a, b, flags, w, lay, stream)
+                       : run_lanczos<double, 9>(*plan, row_ptr, H_on, H_bond, a, b, flags, w, lay, stream);
+    return no == 5 ? run_lanczos<float, 5>(*plan, row_ptr, H_on, H_bond, a, b, flags, w, lay, stream)
+                   : run_lanczos<float, 9>(*plan, row_ptr, H_on, H_bond, a, b, flags, w, lay, stream);
 }

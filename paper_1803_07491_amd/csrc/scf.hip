@@ -80,13 +80,19 @@ extern "C" int bop_scf_step(const bop_system *sys, double mix, double n_floor, d
     int rc = bop_build_H(&sys->model, n, sys->species, shift, sys->row_ptr, sys->nbr_j, nullptr,
                          sys->n_pairs, sys->dtype, sys->H_on, nullptr, stream);
     if (rc) return rc;
-    rc = bop_moments(&sys->plan, sys->row_ptr, sys->H_on, sys->H_bond, sys->mu, sys->moments_ws,
-                     sys->moments_ws_bytes, stream);
+    BOP_REQUIRE(sys->method == 0 || sys->method == 1, BOP_E_ARG, "bop_scf_step: method must be 0 or 1");
+    const double *mu = sys->method == 0 ? sys->mu : nullptr;
+    if (sys->method == 0)
+        rc = bop_moments(&sys->plan, sys->row_ptr, sys->H_on, sys->H_bond, sys->mu, sys->moments_ws,
+                         sys->moments_ws_bytes, stream);
+    else
+        rc = bop_lanczos(&sys->plan, sys->row_ptr, sys->H_on, sys->H_bond, sys->a, sys->b, sys->flags,
+                         sys->moments_ws, sys->moments_ws_bytes, stream);
     if (rc) return rc;
-    rc = bop_recursion(n * no, sys->n_max, sys->mu, 0, 0.0, 0.0, sys->a, sys->b, sys->a_inf, sys->b_inf,
+    rc = bop_recursion(n * no, sys->n_max, mu, 0, 0.0, 0.0, sys->a, sys->b, sys->a_inf, sys->b_inf,
                        sys->flags, stream);
     if (rc) return rc;
-    rc = bop_energy(n, no, sys->n_max, sys->n_exp, sys->mu, sys->a, sys->b, sys->a_inf, sys->b_inf,
+    rc = bop_energy(n, no, sys->n_max, sys->n_exp, mu, sys->a, sys->b, sys->a_inf, sys->b_inf,
                     sys->H_on, sys->n_elec, 0, sys->E_F, sys->N_atom, sys->U_atom, sys->dos_atom,
                     sys->U_total, sys->flags, sys->energy_ws, sys->energy_ws_bytes, stream);
     if (rc) return rc;

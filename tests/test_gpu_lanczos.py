@@ -1,0 +1,127 @@
+"""The Lanczos form (bop_lanczos): recursion coefficients straight from the
+H.X products, against the oracle's coefficients from the moments (App. B.3)
+and its energies; FP32 and BF16 within stated bounds; breakdown on an
+isolated atom; tiling invariance; SCF in FP32."""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+from test_gpu_parity import STRUCTS, _np
+
+pytestmark = pytest.mark.gpu
+
+
+def _wl(name):
+    pos, cell, spc, model, n_max = STRUCTS[name]
+    n = pos.shape[0]
+    nel = {"fcc_spd": np.where(spc == 0, 9.0, 8.0)}.get(name, np.full(n, 6.5))
+    return W.Workload(name, pos, cell, spc, model, n_max, 200, nel)
+
+
+def _run(bop, wl, dtype, tuning=None, E_F=None):
+    p = bop.EnergyPath(wl.pos, wl.cell, wl.species, wl.model, wl.n_max, wl.n_exp, dtype, tuning=tuning,
+                       method="lanczos")
+    out = p.run(float(np.sum(wl.n_elec)), E_F=E_F)
+    return p, out
+
+
+# FP64: the moment route loses about 1e-16 times the condition number of the
+# moments-to-coefficients map (up to ~1e5 at these orders); 1e-9 eV covers it.
+@pytest.mark.parametrize("name", ["bcc_small", "fcc_spd", "bcc_alloy", "dimer", "hcp", "bcc_2cell"])
+def test_lanczos_fp64_matches_oracle(bop, name):
+    wl = _wl(name)
+    ref = O.energy_pipeline(wl)
+    p, out = _run(bop, wl, "f64")
+    rec = p.rec
+    np.testing.assert_allclose(_np(rec["a"]), ref["rec"]["a"], atol=1e-9)
+    np.testing.assert_allclose(_np(rec["b"]), ref["rec"]["b"], atol=1e-9)
+    np.testing.assert_allclose(_np(rec["a_inf"]), ref["rec"]["a_inf"], atol=1e-9)
+    np.testing.assert_allclose(_np(rec["b_inf"]), ref["rec"]["b_inf"], atol=1e-9)
+    assert np.array_equal(_np(rec["flags"]) & ~(4 | 16), ref["rec"]["flags"] & ~(4 | 16))
+    assert abs(float(_np(out["E_F"])[0]) - ref["E_F"]) < 1e-8
+    np.testing.assert_allclose(_np(out["N_atom"]), ref["N_atom"], atol=1e-8)
+    np.testing.assert_allclose(_np(out["U_atom"]), ref["U_atom"], atol=1e-8)
+    assert abs(float(_np(out["U_total"])[0]) - ref["U_total"]) < 1e-9 * abs(ref["U_total"])
+
+
+# FP32 vectors: coefficients within 1e-5 eV, energies within 1e-5 relative.
+@pytest.mark.parametrize("name", ["bcc_small", "fcc_spd", "bcc_alloy", "hcp"])
+def test_lanczos_fp32(bop, name):
+    wl = _wl(name)
+    ref = O.energy_pipeline(wl)
+    p, out = _run(bop, wl, "f32")
+    np.testing.assert_allclose(_np(p.rec["a"]), ref["rec"]["a"], atol=1e-5)
+    np.testing.assert_allclose(_np(p.rec["b"]), ref["rec"]["b"], atol=1e-5)
+    u = float(_np(out["U_total"])[0])
+    assert abs(u - ref["U_total"]) < 1e-5 * abs(ref["U_total"])
+    np.testing.assert_allclose(_np(out["N_atom"]), ref["N_atom"], atol=1e-4)
+
+
+# BF16 vectors and blocks on MFMA: the stated bound is 0.1 eV on a_n, b_n and
+# 2e-3 relative on the total bond energy (unit roundoff 2^-9 per stored value).
+@pytest.mark.parametrize("name", ["bcc_small", "bcc_alloy", "fcc_spd"])
+def test_lanczos_bf16_bound(bop, name):
+    wl = _wl(name)
+    ref = O.energy_pipeline(wl)
+    p, out = _run(bop, wl, "bf16")
+    ea = np.max(np.abs(_np(p.rec["a"]) - ref["rec"]["a"]))
+    eb = np.max(np.abs(_np(p.rec["b"]) - ref["rec"]["b"]))
+    u = float(_np(out["U_total"])[0])
+    eu = abs(u - ref["U_total"]) / abs(ref["U_total"])
+    print(f"{name}: bf16 a {ea:.2e} b {eb:.2e} U rel {eu:.2e} ({abs(u - ref['U_total']) / wl.n_atoms * 1e3:.3f} meV/atom)")
+    assert ea < 0.1 and eb < 0.1
+    assert eu < 2e-3
+
+
+def test_lanczos_isolated_atoms_break_down(bop):
+    """Atoms without neighbours: b_1 = 0, the chain ends at level 1, a_n
+    repeat the onsite level; same flags as the moment route."""
+    pos = np.array([[1.0, 1.0, 1.0], [9.0, 9.0, 9.0]])
+    cell = np.eye(3) * 20.0
+    spc = np.array([0, 1], np.int32)
+    wl = W.Workload("iso", pos, cell, spc, W.canonical_d_model(3.5, onsite_d=(0.0, 0.8)), 6, 200,
+                    np.array([6.0, 5.0]))
+    ref = O.energy_pipeline(wl)
+    for method in ("moments", "lanczos"):
+        p = bop.EnergyPath(pos, cell, spc, wl.model, 6, 200, "f64", method=method)
+        out = p.run(11.0)
+        assert np.array_equal(_np(p.rec["flags"]) & 0xff01, ref["rec"]["flags"] & 0xff01), method
+        np.testing.assert_allclose(_np(p.rec["a"]), ref["rec"]["a"], atol=1e-12)
+        np.testing.assert_allclose(_np(p.rec["b"]), ref["rec"]["b"], atol=1e-12)
+        np.testing.assert_allclose(_np(out["N_atom"]), ref["N_atom"], atol=1e-9)
+
+
+@pytest.mark.parametrize("tuning", [{"tile_atoms": 1}, {"tile_atoms": 7, "block_threads": 1024, "batch_tiles": 8,
+                                                         "chunk_rows": 8}])
+def test_lanczos_tilings(bop, tuning):
+    wl = _wl("bcc_alloy")
+    p0, _ = _run(bop, wl, "f64")
+    p1, _ = _run(bop, wl, "f64", tuning=tuning)
+    np.testing.assert_allclose(_np(p1.rec["a"]), _np(p0.rec["a"]), atol=1e-12)
+    np.testing.assert_allclose(_np(p1.rec["b"]), _np(p0.rec["b"]), atol=1e-12)
+
+
+def test_lanczos_high_order_spd_fp32(bop):
+    """20 levels' worth of coefficients (n_max 20) on the s,p,d alloy, where
+    FP32 moments are useless: FP32 Lanczos stays within 1e-4 eV of FP64
+    Lanczos."""
+    wl = W.fcc_alloy_spd(reps=3)
+    wl.n_max = 20
+    p64, o64 = _run(bop, wl, "f64")
+    p32, o32 = _run(bop, wl, "f32")
+    np.testing.assert_allclose(_np(p32.rec["a"]), _np(p64.rec["a"]), atol=1e-4)
+    np.testing.assert_allclose(_np(p32.rec["b"]), _np(p64.rec["b"]), atol=1e-4)
+    du = abs(float(_np(o32["U_total"])[0]) - float(_np(o64["U_total"])[0])) / wl.n_atoms
+    assert du < 1e-5
+
+
+def test_lanczos_scf_fp32_matches_oracle(bop):
+    from test_gpu_scf import _alloy
+    wl = _alloy()
+    shift_ref, hist_ref, r_ref = O.scf(wl, mix=0.5, tol=1e-4, max_iter=100)
+    s = bop.SCFPath(wl.pos, wl.cell, wl.species, wl.model, wl.n_max, wl.n_elec, 200, "f32", method="lanczos")
+    iters, hist = s.run_scf(mix=0.5, tol=1e-4, max_iter=100)
+    assert abs(iters - len(hist_ref)) <= 1
+    np.testing.assert_allclose(s.shift.cpu().numpy(), shift_ref, atol=1e-4)

@@ -245,3 +245,22 @@ def test_mlp_gradients_vs_finite_differences():
             fd = (lp - lm) / (2 * h)
             g = grads[k].reshape(-1)[idx]
             assert abs(fd - g) <= 1e-7 * max(1.0, abs(g))
+
+
+def test_isolated_atoms_are_delta_bands():
+    """Atoms without neighbours have a delta-function local DOS at their
+    onsite level: the chain ends at level 1 (breakdown), b_inf sits at its
+    floor and the expansion must reproduce a filled d shell (10 electrons) on
+    the deeper atom and the remaining electron on the other, with zero bond
+    energy (U is measured from the onsite level)."""
+    pos = np.array([[1.0, 1.0, 1.0], [9.0, 9.0, 9.0]])
+    cell = np.eye(3) * 20.0
+    spc = np.array([0, 1], np.int32)
+    wl = W.Workload("iso", pos, cell, spc, W.canonical_d_model(3.5, onsite_d=(0.0, 0.8)), 6, 200,
+                    np.array([6.0, 5.0]))
+    r = O.energy_pipeline(wl)
+    assert np.all(r["rec"]["flags"] & 1)
+    assert np.all((r["rec"]["flags"] >> 8) == 1)
+    np.testing.assert_allclose(r["N_atom"], [10.0, 1.0], atol=1e-6)
+    np.testing.assert_allclose(r["U_atom"], [0.0, 0.0], atol=1e-6)
+    assert abs(r["E_F"] - 0.8) < 1e-5
