@@ -161,9 +161,9 @@ int bop_build_H(const bop_model *model /*[host]*/, int n_atoms, const int *speci
  * ========================================================================= */
 typedef struct bop_tuning {
     int tile_atoms;      /* atoms per tile; 0 = as many as fit one wavefront */
-    int block_threads;   /* 256, 512 or 1024; 0 = default (256) */
+    int block_threads;   /* 256, 512 or 1024; 0 = default (512) */
     int batch_tiles;     /* tiles whose X buffers are live at once; 0 = ~6 GiB worth */
-    int chunk_rows;      /* support rows per workgroup and step; 0 = default */
+    int chunk_rows;      /* support rows per workgroup and step; 0 = default (64) */
 } bop_tuning;
 
 #define BOP_MAX_NMAX 40
@@ -188,6 +188,28 @@ int bop_moments_prepare(const bop_plan *plan /*[host]*/, const int *row_ptr,
 int bop_moments(const bop_plan *plan /*[host]*/, const int *row_ptr, const double *H_on,
                 const void *H_bond, double *mu, void *ws, size_t ws_bytes,
                 hipStream_t stream);
+
+/* =========================================================================
+ * Batched form: many independent periodic structures as one block-diagonal
+ * neighbour graph (moments of each structure are those of its own cell, Eq.
+ * momDOS, since no pair joins two structures), so one plan / prepare /
+ * bop_moments (or bop_lanczos) sequence covers the batch; bop_moments
+ * enqueues kernels only (no synchronisation, no allocation) and can be
+ * captured in a HIP graph and replayed.
+ *
+ * Joins per-structure neighbour lists (each from bop_build_neighbours on its
+ * own cell) into global ones.  Structure s owns atoms [atom_off[s],
+ * atom_off[s+1]) and pairs [pair_off[s], pair_off[s+1]).
+ *   atom_off, pair_off [n_structs+1] (device, int)
+ *   row_ptr_local [n_atoms + n_structs]: structure s's own row_ptr (n_s + 1
+ *                 entries, local pair indices) at atom_off[s] + s
+ *   nbr_j_local [P], order_local [n_atoms]: local atom indices, concatenated
+ *   out: row_ptr [n_atoms+1], nbr_j [P], order [n_atoms] (global indices)
+ * nbr_d and species concatenate unchanged.
+ * ========================================================================= */
+int bop_batch_concat(int n_structs, int n_atoms, const int *atom_off, const int *pair_off,
+                     const int *row_ptr_local, const int *nbr_j_local, const int *order_local,
+                     int *row_ptr, int *nbr_j, int *order, hipStream_t stream);
 
 /* =========================================================================
  * Recursion coefficients straight from the H.X products: the Lanczos chain

@@ -1,0 +1,160 @@
+"""Batched moments over many ragged periodic structures.
+
+The structures' neighbour lists are built one by one (each on its own cell)
+and joined by ``bop_batch_concat`` into one block-diagonal graph; one moment
+plan and one prepare pass then cover the batch, and the moment launch
+sequence (``bop_moments`` or ``bop_lanczos``) is captured once in a HIP graph
+and replayed.  ``PerStructure`` is the plain alternative: one plan and one
+launch sequence per structure.  ``autotune`` times candidate tilings on the
+batch itself and keeps the fastest.
+
+Everything numeric runs in the HIP library; this module only sequences calls
+and marshals arguments.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import (Neighbours, build_H, build_neighbours, lanczos, load, moments, moments_plan,
+               moments_prepare, n_a, n_b, _check, _ptr, _stream, _torch)
+
+
+class BatchedMoments:
+    def __init__(self, structures, model, n_max, dtype="f32", tuning=None, method="moments", device="cuda"):
+        torch = _torch()
+        load()
+        self.device = torch.device(device)
+        self.model, self.n_max, self.dtype, self.method = model, int(n_max), dtype, method
+        nls, species, sizes = [], [], []
+        for wl in structures:
+            pos = torch.as_tensor(np.ascontiguousarray(wl.pos, np.float64), device=self.device)
+            nls.append(build_neighbours(pos, wl.cell, model["r_cut"]))
+            species.append(np.asarray(wl.species, np.int32))
+            sizes.append(len(wl.species))
+        self.sizes = np.array(sizes)
+        self.n_structs = len(structures)
+        atom_off = np.concatenate([[0], np.cumsum(self.sizes)]).astype(np.int32)
+        pair_off = np.concatenate([[0], np.cumsum([nl.n_pairs for nl in nls])]).astype(np.int32)
+        self.atom_off, self.pair_off = atom_off, pair_off
+        self.n = int(atom_off[-1])
+        P = int(pair_off[-1])
+        cat = lambda ts: torch.cat(ts) if ts else None
+        row_ptr_local = cat([nl.row_ptr for nl in nls])
+        nbr_j_local = cat([nl.nbr_j for nl in nls])
+        order_local = cat([nl.order for nl in nls])
+        nbr_d = cat([nl.nbr_d for nl in nls])
+        d_atom_off = torch.as_tensor(atom_off, device=self.device)
+        d_pair_off = torch.as_tensor(pair_off, device=self.device)
+        row_ptr = torch.empty(self.n + 1, dtype=torch.int32, device=self.device)
+        nbr_j = torch.empty(max(P, 1), dtype=torch.int32, device=self.device)[:P]
+        order = torch.empty(max(self.n, 1), dtype=torch.int32, device=self.device)[: self.n]
+        _check(load().bop_batch_concat(self.n_structs, self.n, _ptr(d_atom_off), _ptr(d_pair_off), _ptr(row_ptr_local),
+                                       _ptr(nbr_j_local), _ptr(order_local), _ptr(row_ptr), _ptr(nbr_j), _ptr(order),
+                                       _stream()))
+        self.nl = Neighbours(row_ptr, nbr_j, None, nbr_d, order, P)
+        self.species = torch.as_tensor(np.concatenate(species), device=self.device)
+        self.H_on, self.H_bond = build_H(model, self.species, self.nl, dtype=dtype)
+        self.no = model["n_orb"]
+        self.set_tuning(tuning)
+        self.graph = None
+
+    def set_tuning(self, tuning):
+        torch = _torch()
+        self.tuning = tuning
+        self.plan = moments_plan(self.n, self.no, self.n_max, self.dtype, self.nl, tuning)
+        self.ws = moments_prepare(self.plan, self.nl)
+        R = self.n * self.no
+        self.mu = torch.empty((self.n, self.no, self.n_max + 1), dtype=torch.float64, device=self.device)
+        self.rec = {"a": torch.empty((R, n_a(self.n_max)), dtype=torch.float64, device=self.device),
+                    "b": torch.empty((R, n_b(self.n_max) + 1), dtype=torch.float64, device=self.device),
+                    "flags": torch.empty(R, dtype=torch.int32, device=self.device)}
+        self.graph = None
+
+    def run(self):
+        """One launch sequence over the whole batch (eager)."""
+        if self.method == "lanczos":
+            return lanczos(self.plan, self.nl, self.H_on, self.H_bond, out=self.rec, ws=self.ws)
+        return moments(self.plan, self.nl, self.H_on, self.H_bond, mu=self.mu, ws=self.ws)
+
+    def capture(self):
+        """Record the launch sequence in a HIP graph (after one eager run on
+        the capture stream)."""
+        torch = _torch()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            self.run()
+        torch.cuda.current_stream().wait_stream(s)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.run()
+        self.graph = g
+        return g
+
+    def replay(self):
+        if self.graph is None:
+            self.capture()
+        self.graph.replay()
+
+    def structure_mu(self, s):
+        return self.mu[self.atom_off[s]:self.atom_off[s + 1]]
+
+
+class PerStructure:
+    """One plan and one moment launch sequence per structure."""
+
+    def __init__(self, structures, model, n_max, dtype="f32", tuning=None, device="cuda"):
+        torch = _torch()
+        self.items = []
+        for wl in structures:
+            pos = torch.as_tensor(np.ascontiguousarray(wl.pos, np.float64), device=device)
+            nl = build_neighbours(pos, wl.cell, model["r_cut"])
+            sp = torch.as_tensor(np.asarray(wl.species, np.int32), device=device)
+            H_on, H_bond = build_H(model, sp, nl, dtype=dtype)
+            plan = moments_plan(len(wl.species), model["n_orb"], n_max, dtype, nl, tuning)
+            ws = moments_prepare(plan, nl)
+            mu = torch.empty((len(wl.species), model["n_orb"], n_max + 1), dtype=torch.float64, device=device)
+            self.items.append((plan, nl, H_on, H_bond, mu, ws))
+
+    def run(self):
+        for plan, nl, H_on, H_bond, mu, ws in self.items:
+            moments(plan, nl, H_on, H_bond, mu=mu, ws=ws)
+
+
+CANDIDATES = [dict(tile_atoms=ta, block_threads=bt, chunk_rows=cr)
+              for ta in (0, 6) for bt in (256, 512, 1024) for cr in (16, 32, 64, 128)]
+
+
+def autotune(batch: BatchedMoments, candidates=CANDIDATES, reps=2, log=None):
+    """Time each candidate tiling (graph replays) on the batch and keep the
+    fastest; returns (best tuning dict, {key: ms})."""
+    torch = _torch()
+    times = {}
+    best = None
+    for cand in candidates:
+        try:
+            batch.set_tuning(cand)
+        except Exception as e:          # e.g. a tiling the plan rejects
+            if log:
+                log(f"skip {cand}: {e}")
+            continue
+        batch.capture()
+        batch.replay()
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record()
+        for _ in range(reps):
+            batch.replay()
+        ev[1].record()
+        torch.cuda.synchronize()
+        ms = ev[0].elapsed_time(ev[1]) / reps
+        key = f"tile{cand.get('tile_atoms', 0)}_wg{cand.get('block_threads', 0)}_chunk{cand.get('chunk_rows', 0)}"
+        times[key] = ms
+        if log:
+            log(f"{key}: {ms:.2f} ms")
+        if best is None or ms < best[1]:
+            best = (cand, ms)
+    batch.set_tuning(best[0])
+    return best[0], times

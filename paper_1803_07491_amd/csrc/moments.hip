@@ -1058,10 +1058,10 @@ extern "C" int bop_moments_plan(int n_atoms, int n_orb, int n_max, int dtype, co
                 "bop_moments_plan: scratch of %zu bytes needed", need);
     const int B = (tuning && tuning->tile_atoms > 0) ? tuning->tile_atoms : default_tile_atoms(n_orb);
     BOP_REQUIRE(B * n_orb <= 64, BOP_E_UNSUPPORTED, "bop_moments_plan: tile_atoms * n_orb must be <= 64");
-    const int wgt = (tuning && tuning->block_threads) ? tuning->block_threads : 256;
+    const int wgt = (tuning && tuning->block_threads) ? tuning->block_threads : 512;
     BOP_REQUIRE(wgt == 256 || wgt == 512 || wgt == 1024, BOP_E_UNSUPPORTED,
                 "bop_moments_plan: block_threads must be 256, 512 or 1024");
-    const int chunk = (tuning && tuning->chunk_rows > 0) ? tuning->chunk_rows : 4 * (wgt / 64) * 4;
+    const int chunk = (tuning && tuning->chunk_rows > 0) ? tuning->chunk_rows : 64;
     const int n_tiles = (n_atoms + B - 1) / B;
     const int K = n_max / 2;
 

@@ -30,6 +30,7 @@ parametrisations and the bcc transition-metal example of its Appendix B):
 from __future__ import annotations
 
 import math
+import os
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -115,56 +116,132 @@ def random_species(n: int, counts, rng) -> np.ndarray:
     return lab[rng.permutation(n)].astype(np.int32)
 
 
+_PACK = None
+
+
+def _packing_lib():
+    """The C accept/reject loop (workloads/_packing.c), built with the host
+    compiler on first use; None (pure Python loop) if that is not possible."""
+    global _PACK
+    if _PACK is not None:
+        return _PACK or None
+    import ctypes
+    import shutil
+    import subprocess
+    here = os.path.dirname(os.path.abspath(__file__))
+    so = os.path.join(here, "_packing.so")
+    src = os.path.join(here, "_packing.c")
+    try:
+        if not os.path.exists(so) or os.path.getmtime(so) < os.path.getmtime(src):
+            gcc = shutil.which("gcc")
+            if gcc is None:
+                _PACK = False
+                return None
+            tmp = so + f".{os.getpid()}.tmp"
+            subprocess.run([gcc, "-O2", "-shared", "-fPIC", "-o", tmp, src, "-lm"], check=True)
+            os.replace(tmp, so)
+        _PACK = ctypes.CDLL(so)
+    except (OSError, subprocess.CalledProcessError):
+        _PACK = False
+        return None
+    return _PACK
+
+
 def random_dense_packing(n: int, density: float, dmin: float, rng,
                          sweeps: int = 200) -> tuple[np.ndarray, np.ndarray]:
     """Hard-sphere Monte Carlo in a cubic box: start from a simple-cubic
     arrangement at the target density, then ``sweeps`` sweeps of random
-    single-particle moves that are accepted only if no pair comes closer
-    than ``dmin`` (periodic minimum image)."""
+    single-particle moves (periodic minimum image).  A move is accepted if the
+    particle keeps ``dmin`` from every other one, or, while the start-up
+    arrangement is still closer than ``dmin``, if it strictly increases the
+    particle's nearest distance; the smallest separation never decreases.
+    The accept/reject loop runs in C when a host compiler is available (same
+    random numbers, same result)."""
     L = (n / density) ** (1.0 / 3.0)
-    m = int(math.ceil(n ** (1.0 / 3.0)))
-    g = np.stack(np.meshgrid(np.arange(m), np.arange(m), np.arange(m),
-                             indexing="ij"), -1).reshape(-1, 3)[:n]
-    pos = (g + 0.5) * (L / m)
+    # start: n random sites of the simple-cubic, bcc or fcc arrangement of the
+    # box with the largest nearest-neighbour distance
+    best = None
+    for basis, nn in ((np.zeros((1, 3)), 1.0),
+                      (np.array([[0, 0, 0], [0.5, 0.5, 0.5]]), math.sqrt(3.0) / 2.0),
+                      (np.array([[0, 0, 0], [0.5, 0.5, 0], [0.5, 0, 0.5], [0, 0.5, 0.5]]), 1.0 / math.sqrt(2.0))):
+        mm = int(math.ceil((n / len(basis)) ** (1.0 / 3.0) - 1e-9))
+        if best is None or L / mm * nn > best[0]:
+            best = (L / mm * nn, mm, basis)
+    _, m, basis = best
+    g = np.stack(np.meshgrid(np.arange(m), np.arange(m), np.arange(m), indexing="ij"), -1).reshape(-1, 3)
+    sites = (g[:, None, :] + basis[None, :, :] + 0.25).reshape(-1, 3) * (L / m)
+    pos = sites[np.sort(rng.permutation(len(sites))[:n])]
     cell = np.diag([L, L, L])
     # bin grid for overlap checks
     nb = max(1, int(L // dmin))
     w = L / nb
-    step = 0.5 * (L / m - dmin) if L / m > dmin else 0.1 * dmin
-    step = max(step, 0.05)
+    step = 0.1 * dmin
 
     def bins_of(p):
         return np.minimum((p // w).astype(int), nb - 1)
+
+    def min_sep(p):
+        out = np.inf
+        for i0 in range(0, n, 512):
+            d = p[i0:i0 + 512, None, :] - p[None, :, :]
+            d -= L * np.round(d / L)
+            r2 = (d * d).sum(-1)
+            r2[np.arange(min(512, n - i0)), np.arange(i0, min(i0 + 512, n))] = np.inf
+            out = min(out, float(r2.min()))
+        return math.sqrt(out)
+
+    lib = _packing_lib()
+    if lib is not None:
+        import ctypes as C
+        done = 0
+        # the given sweeps, then more (at most 2000) while a pair is still closer than dmin
+        while done < sweeps or (done < sweeps + 2000 and done % 50 == 0 and min_sep(pos) < dmin) \
+                or (sweeps < done < sweeps + 2000 and done % 50 != 0):
+            perm = np.ascontiguousarray(rng.permutation(n), dtype=np.int64)
+            disp = np.ascontiguousarray(rng.uniform(-step, step, (n, 3)))
+            pos = np.ascontiguousarray(pos, dtype=np.float64)
+            lib.rdp_sweeps(C.c_int(n), C.c_double(L), C.c_double(dmin), C.c_int(nb), C.c_int(1),
+                           perm.ctypes.data_as(C.c_void_p), disp.ctypes.data_as(C.c_void_p),
+                           pos.ctypes.data_as(C.c_void_p))
+            done += 1
+        return wrap(pos, cell), cell
 
     b = bins_of(pos)
     from collections import defaultdict
     grid = defaultdict(list)
     for i in range(n):
         grid[tuple(b[i])].append(i)
-    rng_moves = rng
-    for _ in range(sweeps):
-        for i in rng_moves.permutation(n):
-            trial = (pos[i] + rng_moves.uniform(-step, step, 3)) % L
+
+    def nearest(i, t, tb, stop):
+        best = 1e300
+        for dx in (-1, 0, 1):
+            for dy in (-1, 0, 1):
+                for dz in (-1, 0, 1):
+                    key = ((tb[0] + dx) % nb, (tb[1] + dy) % nb, (tb[2] + dz) % nb)
+                    for j in grid.get(key, ()):
+                        if j == i:
+                            continue
+                        d = t - pos[j]
+                        d -= L * np.round(d / L)
+                        r2 = float(d @ d)
+                        best = min(best, r2)
+                        if best < stop:
+                            return best
+        return best
+
+    done = 0
+    while done < sweeps or (done < sweeps + 2000 and done % 50 == 0 and min_sep(pos) < dmin) \
+            or (sweeps < done < sweeps + 2000 and done % 50 != 0):
+        done += 1
+        perm = rng.permutation(n)
+        disp = rng.uniform(-step, step, (n, 3))
+        for q, i in enumerate(perm):
+            trial = (pos[i] + disp[q]) % L
             tb = bins_of(trial[None])[0]
-            ok = True
-            for dx in (-1, 0, 1):
-                for dy in (-1, 0, 1):
-                    for dz in (-1, 0, 1):
-                        key = ((tb[0] + dx) % nb, (tb[1] + dy) % nb, (tb[2] + dz) % nb)
-                        for j in grid.get(key, ()):
-                            if j == i:
-                                continue
-                            d = trial - pos[j]
-                            d -= L * np.round(d / L)
-                            if d @ d < dmin * dmin:
-                                ok = False
-                                break
-                        if not ok:
-                            break
-                    if not ok:
-                        break
-                if not ok:
-                    break
+            mt = nearest(i, trial, tb, dmin * dmin)
+            ok = mt >= dmin * dmin
+            if not ok:
+                ok = nearest(i, trial, tb, -1.0) > nearest(i, pos[i], b[i], -1.0)
             if ok:
                 ob = tuple(b[i])
                 grid[ob].remove(i)
