@@ -3,6 +3,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <hip/hip_bf16.h>
+#include <cmath>
 #include <cstdarg>
 #include <cstdint>
 #include <cstdio>
@@ -56,6 +57,41 @@ void energy_ws_scratch(void *ws, long n_rows, int n_exp, double **part, unsigned
 int device_cus();
 
 // Small device helpers -------------------------------------------------------
+// Combination of per-block partials part[q * stride + off], q < n, by all
+// threads of one block in a fixed order (thread t takes q = t, t + blockDim.x,
+// ...; then a fixed tree over the block), so the result does not depend on
+// scheduling.  op 0: sum, 1: min, 2: max.  Valid in thread 0.  Every thread of
+// the block must call it; s_red holds blockDim.x / 64 doubles.
+__device__ inline double block_combine(double v, int op, double *s_red)
+{
+    for (int o = 32; o > 0; o >>= 1) {
+        const double u = __shfl_xor(v, o);
+        v = op == 0 ? v + u : (op == 1 ? fmin(v, u) : fmax(v, u));
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) s_red[w] = v;
+    __syncthreads();
+    double t = v;
+    if (threadIdx.x == 0) {
+        t = s_red[0];
+        for (int q = 1; q < (int)(blockDim.x >> 6); ++q)
+            t = op == 0 ? t + s_red[q] : (op == 1 ? fmin(t, s_red[q]) : fmax(t, s_red[q]));
+    }
+    __syncthreads();
+    return t;
+}
+
+__device__ inline double partials_combine(const double *part, unsigned n, size_t stride, size_t off, int op,
+                                          double *s_red)
+{
+    double v = op == 0 ? 0.0 : (op == 1 ? INFINITY : -INFINITY);
+    for (unsigned q = threadIdx.x; q < n; q += blockDim.x) {
+        const double x = __hip_atomic_load(&part[q * stride + off], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        v = op == 0 ? v + x : (op == 1 ? fmin(v, x) : fmax(v, x));
+    }
+    return block_combine(v, op, s_red);
+}
+
 __device__ inline int atomic_load_agent(const int *p)
 {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

@@ -257,18 +257,17 @@ k_bracket(int n_rows, const double *__restrict__ a_inf, const double *__restrict
         s_last = atomicAdd(counter, 1u) == gridDim.x - 1;
     }
     __syncthreads();
-    if (s_last && threadIdx.x == 0) {
+    if (s_last) {
         __threadfence();
-        double L = INFINITY, H = -INFINITY;
-        for (unsigned q = 0; q < gridDim.x; ++q) {
-            L = fmin(L, __hip_atomic_load(&part[2 * q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-            H = fmax(H, __hip_atomic_load(&part[2 * q + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        const double L = partials_combine(part, gridDim.x, 2, 0, 1, s_lo);
+        const double H = partials_combine(part, gridDim.x, 2, 1, 2, s_lo);
+        if (threadIdx.x == 0) {
+            st->lo = L;
+            st->hi = H;
+            st->done = 0.0;
+            st->x = 0.5 * (L + H);
+            *counter = 0;
         }
-        st->lo = L;
-        st->hi = H;
-        st->done = 0.0;
-        st->x = 0.5 * (L + H);
-        *counter = 0;
     }
 }
 
@@ -298,6 +297,11 @@ __device__ inline void tree_points(double lo, double hi, double *mid)
     }
 }
 
+// Two lanes share an orbital row: lane h of the pair takes nodes 8h .. 8h+7
+// (the last lane 7 nodes), which halves the registers per lane and doubles
+// the rows' loads in flight; both lanes read the same coefficients.
+constexpr int FT_HALF = (FT_NODES + 1) / 2;
+
 __global__ void __launch_bounds__(DT)
 k_fermi_tree(int n_rows, int n_exp, const double *__restrict__ gs, const double *__restrict__ a_inf,
              const double *__restrict__ b_inf, double n_elec, double *__restrict__ part,
@@ -311,21 +315,23 @@ k_fermi_tree(int n_rows, int n_exp, const double *__restrict__ gs, const double 
     tree_points(lo, hi, mid);
     for (int k = threadIdx.x; k <= n_exp + 2; k += blockDim.x) s_inv[k] = k ? 1.0 / k : 0.0;
     __syncthreads();
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    double cnt[FT_NODES];
+    const long gt = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = (int)(gt >> 1), h = (int)(gt & 1);
+    double cnt[FT_HALF];
     if (r < n_rows) {
         const double ai = a_inf[r], bi = b_inf[r];
-        double c[FT_NODES], sn[FT_NODES], ck[FT_NODES], sk[FT_NODES], acc[FT_NODES];
+        double c[FT_HALF], sn[FT_HALF], ck[FT_HALF], sk[FT_HALF], acc[FT_HALF];
         const double g0 = gs[r];
 #pragma unroll
-        for (int p = 0; p < FT_NODES; ++p) {
+        for (int j = 0; j < FT_HALF; ++j) {
+            const int p = h * FT_HALF + j < FT_NODES ? h * FT_HALF + j : FT_NODES - 1;
             double eps = (mid[p] - ai) / (2.0 * bi);
-            c[p] = eps < -1.0 ? -1.0 : (eps > 1.0 ? 1.0 : eps);
-            sn[p] = sqrt(fmax(0.0, 1.0 - c[p] * c[p]));
-            cnt[p] = g0 * (1.0 - acos(c[p]) / M_PI);
-            ck[p] = c[p];
-            sk[p] = sn[p];
-            acc[p] = 0.0;
+            c[j] = eps < -1.0 ? -1.0 : (eps > 1.0 ? 1.0 : eps);
+            sn[j] = sqrt(fmax(0.0, 1.0 - c[j] * c[j]));
+            cnt[j] = g0 * (1.0 - acos(c[j]) / M_PI);
+            ck[j] = c[j];
+            sk[j] = sn[j];
+            acc[j] = 0.0;
         }
         double gkm2 = 0.0, gkm1 = g0;
 #pragma unroll 4
@@ -335,22 +341,23 @@ k_fermi_tree(int n_rows, int n_exp, const double *__restrict__ gs, const double 
             gkm2 = gkm1;
             gkm1 = gk;
 #pragma unroll
-            for (int p = 0; p < FT_NODES; ++p) {
-                acc[p] = fma(wk, sk[p], acc[p]);
-                const double cn = ck[p] * c[p] - sk[p] * sn[p];
-                sk[p] = sk[p] * c[p] + ck[p] * sn[p];
-                ck[p] = cn;
+            for (int j = 0; j < FT_HALF; ++j) {
+                acc[j] = fma(wk, sk[j], acc[j]);
+                const double cn = ck[j] * c[j] - sk[j] * sn[j];
+                sk[j] = sk[j] * c[j] + ck[j] * sn[j];
+                ck[j] = cn;
             }
         }
 #pragma unroll
-        for (int p = 0; p < FT_NODES; ++p) cnt[p] += acc[p] / M_PI;
+        for (int j = 0; j < FT_HALF; ++j) cnt[j] += acc[j] / M_PI;
     } else {
 #pragma unroll
-        for (int p = 0; p < FT_NODES; ++p) cnt[p] = 0.0;
+        for (int j = 0; j < FT_HALF; ++j) cnt[j] = 0.0;
     }
 #pragma unroll
     for (int p = 0; p < FT_NODES; ++p) {
-        double t = block_sum(cnt[p], s_red);
+        const double v = (h == p / FT_HALF) ? cnt[p % FT_HALF] : 0.0;
+        double t = block_sum(v, s_red);
         if (threadIdx.x == 0) part[(size_t)FT_NODES * blockIdx.x + p] = t;
     }
     if (threadIdx.x == 0) {
@@ -358,23 +365,24 @@ k_fermi_tree(int n_rows, int n_exp, const double *__restrict__ gs, const double 
         s_last = atomicAdd(counter, 1u) == gridDim.x - 1;
     }
     __syncthreads();
-    if (s_last && threadIdx.x == 0) {
+    if (s_last) {
         __threadfence();
-        double l = lo, h = hi;
-        int node = 1;
-        for (int lev = 0; lev < FT_LEVELS; ++lev) {
-            const double m = mid[node - 1];
-            if (m <= l || m >= h) { st->done = 1.0; break; }
-            double tot = 0.0;
-            for (unsigned q = 0; q < gridDim.x; ++q)
-                tot += __hip_atomic_load(&part[(size_t)FT_NODES * q + node - 1], __ATOMIC_RELAXED,
-                                         __HIP_MEMORY_SCOPE_AGENT);
-            if (2.0 * tot < n_elec) { l = m; node = 2 * node + 1; }
-            else { h = m; node = 2 * node; }
+        double tot[FT_NODES];
+#pragma unroll
+        for (int p = 0; p < FT_NODES; ++p) tot[p] = partials_combine(part, gridDim.x, FT_NODES, p, 0, s_red);
+        if (threadIdx.x == 0) {
+            double l = lo, hh = hi;
+            int node = 1;
+            for (int lev = 0; lev < FT_LEVELS; ++lev) {
+                const double m = mid[node - 1];
+                if (m <= l || m >= hh) { st->done = 1.0; break; }
+                if (2.0 * tot[node - 1] < n_elec) { l = m; node = 2 * node + 1; }
+                else { hh = m; node = 2 * node; }
+            }
+            st->lo = l;
+            st->hi = hh;
+            *counter = 0;
         }
-        st->lo = l;
-        st->hi = h;
-        *counter = 0;
     }
 }
 
@@ -446,13 +454,13 @@ k_energy(int n_atoms, int no, int n_exp, const double *__restrict__ gs, const do
         s_last = atomicAdd(counter, 1u) == gridDim.x - 1;
     }
     __syncthreads();
-    if (s_last && threadIdx.x == 0) {
+    if (s_last) {
         __threadfence();
-        double tot = 0.0;
-        for (unsigned q = 0; q < gridDim.x; ++q)
-            tot += __hip_atomic_load(&part[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        U_total[0] = tot;
-        *counter = 0;
+        const double tot = partials_combine(part, gridDim.x, 1, 0, 0, s_red);
+        if (threadIdx.x == 0) {
+            U_total[0] = tot;
+            *counter = 0;
+        }
     }
 }
 
@@ -471,7 +479,7 @@ EnergyWs carve(void *base, long n_rows, int n_exp)
     char *p = (char *)base;
     auto take = [&](size_t b) { char *r = p; p += align_up(b, 256); return (void *)r; };
     w.gs = (double *)take(sizeof(double) * (size_t)(n_exp + 1) * (size_t)n_rows);
-    long nblk = (n_rows + DT - 1) / DT + 1;
+    long nblk = 2 * ((n_rows + DT - 1) / DT) + 1;       // two lanes per row in the Fermi passes
     w.part = (double *)take(sizeof(double) * FT_NODES * (size_t)nblk);
     w.st = (FermiState *)take(sizeof(FermiState));
     w.counter = (unsigned *)take(sizeof(unsigned));
@@ -532,7 +540,8 @@ extern "C" int bop_energy(int n_atoms, int no, int n_max, int n_exp, const doubl
         k_bracket<<<nblk, DT, 0, stream>>>((int)R, a_inf, b_inf, w.part, w.counter, w.st);
         BOP_LAUNCHED();
         for (int it = 0; it < 64 / FT_LEVELS; ++it)
-            k_fermi_tree<<<nblk, DT, 0, stream>>>((int)R, n_exp, w.gs, a_inf, b_inf, n_elec, w.part, w.counter, w.st);
+            k_fermi_tree<<<(unsigned)((2 * R + DT - 1) / DT), DT, 0, stream>>>((int)R, n_exp, w.gs, a_inf, b_inf, n_elec,
+                                                                            w.part, w.counter, w.st);
         BOP_LAUNCHED();
         k_fermi_finish<<<1, 1, 0, stream>>>(w.st, E_F);
         BOP_LAUNCHED();

@@ -19,7 +19,7 @@ k_scf_measure(int n, const double *__restrict__ N_atom, const double *__restrict
               double tol, double *__restrict__ q, double *__restrict__ part, unsigned *__restrict__ counter,
               double *__restrict__ max_dq, int *__restrict__ converged, double *__restrict__ mean_out)
 {
-    __shared__ double s_m[ST / 64], s_s[ST / 64];
+    __shared__ double s_m[ST / 64], s_s[ST / 64], s_comb[ST / 64];
     __shared__ bool s_last;
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     double mq = 0.0, sum = 0.0;
@@ -42,17 +42,16 @@ k_scf_measure(int n, const double *__restrict__ N_atom, const double *__restrict
         s_last = atomicAdd(counter, 1u) == gridDim.x - 1;
     }
     __syncthreads();
-    if (s_last && threadIdx.x == 0) {
+    if (s_last) {
         __threadfence();
-        double m = 0.0, t = 0.0;
-        for (unsigned b = 0; b < gridDim.x; ++b) {
-            m = fmax(m, __hip_atomic_load(&part[2 * b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-            t += __hip_atomic_load(&part[2 * b + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const double m = fmax(0.0, partials_combine(part, gridDim.x, 2, 0, 2, s_comb));
+        const double t = partials_combine(part, gridDim.x, 2, 1, 0, s_comb);
+        if (threadIdx.x == 0) {
+            max_dq[0] = m;
+            converged[0] = m < tol;
+            mean_out[0] = t / n;
+            *counter = 0;
         }
-        max_dq[0] = m;
-        converged[0] = m < tol;
-        mean_out[0] = t / n;
-        *counter = 0;
     }
 }
 

@@ -1,0 +1,75 @@
+"""Edge cases through the C ABI: empty input, the smallest and largest
+moment orders, rejected sizes, the neighbour-capacity retry."""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+from test_gpu_parity import STRUCTS, _np
+
+pytestmark = pytest.mark.gpu
+
+
+def test_empty_structure(bop):
+    import torch
+    pos = torch.zeros((0, 3), dtype=torch.float64, device="cuda")
+    nl = bop.build_neighbours(pos, np.eye(3) * 10.0, 3.5)
+    assert nl.n_pairs == 0
+    assert int(nl.row_ptr.cpu()[0]) == 0
+    sp = torch.zeros(0, dtype=torch.int32, device="cuda")
+    m = W.canonical_d_model(3.5)
+    H_on, H_bond = bop.build_H(m, sp, nl)
+    plan = bop.moments_plan(0, 5, 8, "f64", nl)
+    assert plan.n_tiles == 0
+    mu = bop.moments(plan, nl, H_on, H_bond)
+    assert mu.shape == (0, 5, 9)
+
+
+@pytest.mark.parametrize("n_max", [1, 2, 3])
+@pytest.mark.parametrize("method", ["moments", "lanczos"])
+def test_lowest_orders(bop, n_max, method):
+    pos, cell, spc, model, _ = STRUCTS["bcc_alloy"]
+    wl = W.Workload("x", pos, cell, spc, model, n_max, 200, np.full(pos.shape[0], 6.5))
+    ref = O.energy_pipeline(wl)
+    p = bop.EnergyPath(pos, cell, spc, model, n_max, 200, "f64", method=method)
+    out = p.run(float(wl.n_elec.sum()))
+    np.testing.assert_allclose(_np(p.rec["a"]), ref["rec"]["a"], atol=1e-10)
+    np.testing.assert_allclose(_np(p.rec["b"]), ref["rec"]["b"], atol=1e-10)
+    np.testing.assert_allclose(_np(out["U_atom"]), ref["U_atom"], atol=1e-8)
+
+
+def test_highest_order(bop):
+    """n_max = 40 (the largest supported): FP64 moments of a small cell
+    against the oracle, odd moments on the Cauchy-Schwarz scale."""
+    from test_gpu_parity import _mu_err
+    wl = W.bcc_small()
+    nl = O.neighbours(wl.pos, wl.cell, wl.model["r_cut"])
+    H_on, H_b = O.build_H(wl.model, wl.species, nl)
+    ref = O.moments(nl, H_on, H_b, 40)
+    p = bop.EnergyPath(wl.pos, wl.cell, wl.species, wl.model, 40, 200, "f64")
+    p.run_moments()
+    assert _mu_err(_np(p.mu), ref) < 1e-10
+
+
+def test_unsupported_sizes_are_rejected(bop):
+    wl = W.bcc_small()
+    with pytest.raises(bop.BopError) as e:
+        bop.EnergyPath(wl.pos, wl.cell, wl.species, wl.model, 41, 200, "f64")
+    assert e.value.code == bop.BOP_E_UNSUPPORTED
+    # more than 64 neighbours in a row
+    big = W.canonical_d_model(6.5)
+    with pytest.raises(bop.BopError) as e:
+        bop.EnergyPath(wl.pos, wl.cell, wl.species, big, 4, 200, "f64")
+    assert e.value.code == bop.BOP_E_UNSUPPORTED
+
+
+def test_neighbour_capacity_retry(bop):
+    import torch
+    wl = W.bcc_small()
+    pos = torch.as_tensor(wl.pos, device="cuda")
+    full = bop.build_neighbours(pos, wl.cell, wl.model["r_cut"])
+    small = bop.build_neighbours(pos, wl.cell, wl.model["r_cut"], capacity=10)
+    assert small.n_pairs == full.n_pairs
+    assert torch.equal(small.nbr_j, full.nbr_j)
+    assert torch.equal(small.row_ptr, full.row_ptr)
