@@ -30,7 +30,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6, "bf16": 2500.0}   # MI355X peaks: vector FP32 (incl. packed), FP64, dense BF16 MFMA
+PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6, "bf16": 2500.0, "f16": 157.3}   # MI355X peaks: vector FP32 (incl. packed), FP64, dense BF16 MFMA
 PEAK_NONPACKED_F32 = 78.6                     # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
 
 
@@ -145,7 +145,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--dtype", default="f32", choices=["f32", "f64", "bf16"])
+    ap.add_argument("--dtype", default="f32", choices=["f32", "f64", "bf16", "f16"],
+                    help="H.X arithmetic/storage; f16 = FP16 vectors with FP32 H and arithmetic (Lanczos form)")
     ap.add_argument("--method", default="moments", choices=["moments", "lanczos"],
                     help="moments then FP64 recursion, or the recursion straight from the H.X products")
     ap.add_argument("--reps", type=int, default=40)

@@ -60,6 +60,7 @@ extern "C" {
 #define BOP_F64   0
 #define BOP_F32   1
 #define BOP_BF16  2
+#define BOP_F16   3   /* H.X vectors stored in FP16, FP32 H and arithmetic; Lanczos form only */
 
 /* ---- tight-binding model (host struct, passed by value to kernels) -------- */
 #define BOP_MAX_SPECIES 3
@@ -121,7 +122,8 @@ int bop_build_neighbours(int n_atoms, const double *pos, const double *cell, dou
  *
  *  H_on   [N][n_orb] FP64: onsite level of the atom's species for the
  *         orbital's l, plus shift[i] (shift may be NULL).
- *  H_bond [P][n_orb][ld] in `dtype` (BOP_F64, BOP_F32 or BOP_BF16), ld = n_orb
+ *  H_bond [P][n_orb][ld] in `dtype` (BOP_F64, BOP_F32 or BOP_BF16; BOP_F16 gives FP32
+ *  blocks), ld = n_orb
  *         for FP64/FP32 and the MFMA slot width for BF16 (8 for n_orb = 5, 16 for
  *         n_orb = 9; columns beyond n_orb are zero):
  *         block p = <i a|H|j b> for pair p = (i -> j), built in the bond frame

@@ -22,8 +22,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libbop.so")
 
 BOP_OK, BOP_E_ARG, BOP_E_CAPACITY, BOP_E_HIP, BOP_E_UNSUPPORTED, BOP_E_NOT_CONVERGED = 0, -1, -2, -3, -4, -5
-F64, F32, BF16 = 0, 1, 2
-DTYPES = {"f64": F64, "f32": F32, "bf16": BF16}
+F64, F32, BF16, F16 = 0, 1, 2, 3
+DTYPES = {"f64": F64, "f32": F32, "bf16": BF16, "f16": F16}
 MAX_SPECIES = 3
 N_CHANNELS = 14
 CHANNELS = ("sss", "sps", "pss", "sds", "dss", "pps", "ppp",
@@ -255,7 +255,8 @@ def build_H(model: dict, species, nl: Neighbours, shift=None, dtype="f64", H_on=
     n = species.shape[0]
     no = model["n_orb"]
     dev = species.device
-    tdt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16}[dtype]
+    # f16 (FP16 storage of the Lanczos vectors) uses FP32 blocks
+    tdt = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16, "f16": torch.float32}[dtype]
     if H_on is None:
         H_on = torch.empty((n, no), dtype=torch.float64, device=dev)
     if H_bond is None and nl is not None:

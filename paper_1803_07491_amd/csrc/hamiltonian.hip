@@ -185,6 +185,7 @@ extern "C" int bop_build_H(const bop_model *model, int n, const int *species, co
                 "bop_build_H: n_orb must be 5 or 9 (got %d)", model->n_orb);
     BOP_REQUIRE(model->n_species >= 1 && model->n_species <= BOP_MAX_SPECIES, BOP_E_UNSUPPORTED,
                 "bop_build_H: 1..%d species supported", BOP_MAX_SPECIES);
+    if (dtype == BOP_F16) dtype = BOP_F32;     // FP16 storage of the vectors uses FP32 blocks
     BOP_REQUIRE(dtype == BOP_F64 || dtype == BOP_F32 || dtype == BOP_BF16, BOP_E_UNSUPPORTED,
                 "bop_build_H: unknown dtype %d", dtype);
     BOP_REQUIRE(n == 0 || (species && H_on), BOP_E_ARG, "bop_build_H: species/H_on NULL");

@@ -161,7 +161,7 @@ __device__ inline int next_tile(int *queue, int *s_tile)
 __host__ __device__ inline size_t x_row_bytes(int dtype, int n_orb)
 {
     if (dtype == BOP_BF16) return 2ull * 64 * (n_orb <= 8 ? 8 : 16);
-    return (dtype == BOP_F64 ? 8ull : 4ull) * n_orb * 64;
+    return (dtype == BOP_F64 ? 8ull : (dtype == BOP_F16 ? 2ull : 4ull)) * n_orb * 64;
 }
 
 struct Layout {
@@ -341,7 +341,7 @@ __global__ void k_x0(Batch bt, int n_max, int B, const int *__restrict__ sizes_,
 // beta = b_(k-1) * s_(k-2).  The row stores y' = s H r_(k-1) - beta r_(k-2) in
 // place of r_(k-2) and the partial sums give <r_(k-1), y'> (a_(k-1) = s times
 // that); the update kernel then forms r_k = y' - a_(k-1) u_(k-1).
-template <typename T, int NO, int WGT, int LANCZOS>
+template <typename T, int NO, int WGT, int LANCZOS, typename S = T>
 __global__ void __launch_bounds__(WGT)
 k_step(Batch bt, int k, int K, int last, int nch, int chunk_rows, int deg_max, int rows_cap,
        const int *__restrict__ row_ptr, const double *__restrict__ H_on, const T *__restrict__ H,
@@ -350,7 +350,11 @@ k_step(Batch bt, int k, int K, int last, int nch, int chunk_rows, int deg_max, i
 {
     constexpr int NW = WGT / 64;
     constexpr int NB = NO * NO;
-    constexpr int G = (sizeof(T) == 4 && NO <= 5) ? 8 : 4;   // slots whose gathers are in flight together
+    // slots whose gathers are in flight together.  The step is latency bound
+    // and occupancy decides it: 4 FP32 slots keep the d kernel at 60 VGPRs
+    // (8 waves per SIMD), faster than 8 slots at 6 waves; FP64 rows are two or
+    // four times wider, and 2 (d) or 1 (s,p,d) slots measured fastest there.
+    constexpr int G = sizeof(T) == 8 ? (NO <= 5 ? 2 : 1) : 4;
     __shared__ double s_red[2][NW][64];
     extern __shared__ char s_dyn[];
     // XCD-aware numbering: block b runs on XCD b % 8; the other factor walks
@@ -369,8 +373,8 @@ k_step(Batch bt, int k, int K, int last, int nch, int chunk_rows, int deg_max, i
     const int *rinfo = sup + rows_cap;
     const int *lnb = rinfo + rows_cap;
     const int src = last ? (K & 1) : ((k - 1) & 1);
-    const T *Xp = (const T *)(xbase + x_stride * (2 * (size_t)t + src));
-    T *Xc = (T *)(xbase + x_stride * (2 * (size_t)t + (k & 1)));
+    const S *Xp = (const S *)(xbase + x_stride * (2 * (size_t)t + src));
+    S *Xc = (S *)(xbase + x_stride * (2 * (size_t)t + (k & 1)));
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     T *sH = (T *)s_dyn + (size_t)w * deg_max * NB;          // this wave's H blocks
@@ -381,27 +385,41 @@ k_step(Batch bt, int k, int K, int last, int nch, int chunk_rows, int deg_max, i
         ls = (T)lc[((size_t)t * 4 + 0) * 64 + lane];
         lbeta = (T)lc[((size_t)t * 4 + 1) * 64 + lane];
     }
-    for (int l = r0 + w; l < r1; l += NW) {
-        const int g = __builtin_amdgcn_readfirstlane(sup[l]);
-        const int info = __builtin_amdgcn_readfirstlane(rinfo[l]);
+    // the next row's atom, layer word, slot list and pair range are fetched while
+    // the current row computes, which takes their dependent loads off the
+    // critical path
+    int l = r0 + w;
+    int g_n = 0, info_n = 0, slots_n = 0, p0_n = 0, p1_n = 0;
+    if (l < r1) {
+        g_n = __builtin_amdgcn_readfirstlane(sup[l]);
+        info_n = __builtin_amdgcn_readfirstlane(rinfo[l]);
+        slots_n = lane < deg_max ? lnb[(long)l * deg_max + lane] : 0;
+        p0_n = row_ptr[g_n];
+        p1_n = row_ptr[g_n + 1];
+    }
+    for (; l < r1; l += NW) {
+        const int g = g_n, info = info_n, slots_all = slots_n, p0 = p0_n, deg = p1_n - p0_n;
+        if (l + NW < r1) {
+            g_n = __builtin_amdgcn_readfirstlane(sup[l + NW]);
+            info_n = __builtin_amdgcn_readfirstlane(rinfo[l + NW]);
+            slots_n = lane < deg_max ? lnb[(long)(l + NW) * deg_max + lane] : 0;
+            p0_n = row_ptr[g_n];
+            p1_n = row_ptr[g_n + 1];
+        }
         const int L = info & 255, n1 = (info >> 8) & 255, n2 = (info >> 16) & 255, n3 = (info >> 24) & 255;
         const bool has_prev = last || L <= k - 1;
         const int nval = last ? n3 : (k - 1 >= L + 1 ? n3 : (k - 1 == L ? n2 : n1));
-        const int p0 = row_ptr[g], deg = row_ptr[g + 1] - p0;
-        const int slots = (lane < nval) ? lnb[(long)l * deg_max + lane] : 0;
+        const int slots = (lane < nval) ? slots_all : 0;
         // the row's H blocks -> LDS (contiguous pairs p0 .. p0 + deg)
         const T *hsrc = H + (long)p0 * NB;
         for (int e = lane; e < deg * NB; e += 64) sH[e] = hsrc[e];
-        const T *xrow = Xp + (long)l * stride_row + lane;
+        const S *xrow = Xp + (long)l * stride_row + lane;
         T acc[NO], xs[NO];
 #pragma unroll
         for (int a = 0; a < NO; ++a) {
-            xs[a] = has_prev ? xrow[a * 64] : T(0);
+            xs[a] = has_prev ? (T)xrow[a * 64] : T(0);
             acc[a] = from_f64<T>(H_on[(long)g * NO + a]) * xs[a];
         }
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_s_waitcnt(0);      // LDS writes of this wave visible to it
-        __builtin_amdgcn_wave_barrier();
         for (int s0 = 0; s0 < nval; s0 += G) {
             T x[G][NO];
             int hoff[G];
@@ -410,10 +428,15 @@ k_step(Batch bt, int k, int K, int last, int nch, int chunk_rows, int deg_max, i
                 // slots past nval re-read this row (harmless) and are masked below
                 const int su = s0 + u < nval ? s0 + u : 0;
                 const int pk = __builtin_amdgcn_readlane(slots, su);
-                const T *xn = (s0 + u < nval) ? Xp + (long)(pk >> 8) * stride_row + lane : xrow;
+                const S *xn = (s0 + u < nval) ? Xp + (long)(pk >> 8) * stride_row + lane : xrow;
                 hoff[u] = (pk & 255) * NB;
 #pragma unroll
-                for (int b = 0; b < NO; ++b) x[u][b] = xn[b * 64];
+                for (int b = 0; b < NO; ++b) x[u][b] = (T)xn[b * 64];
+            }
+            if (s0 == 0) {
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_s_waitcnt(0);      // LDS writes of this wave visible to it
+                __builtin_amdgcn_wave_barrier();
             }
 #pragma unroll
             for (int u = 0; u < G; ++u) {
@@ -427,18 +450,18 @@ k_step(Batch bt, int k, int K, int last, int nch, int chunk_rows, int deg_max, i
             }
         }
         __builtin_amdgcn_wave_barrier();   // all lanes done with sH before the next row overwrites it
-        T *xo = Xc + (long)l * stride_row + lane;
+        S *xo = Xc + (long)l * stride_row + lane;
         if (LANCZOS) {
             const bool has_prev2 = L <= k - 2;
 #pragma unroll
             for (int a = 0; a < NO; ++a) {
-                const T xm = has_prev2 ? xo[a * 64] : T(0);
+                const T xm = has_prev2 ? (T)xo[a * 64] : T(0);
                 acc[a] = acc[a] * ls - lbeta * xm;
             }
         }
         if (!last) {
 #pragma unroll
-            for (int a = 0; a < NO; ++a) xo[a * 64] = acc[a];
+            for (int a = 0; a < NO; ++a) xo[a * 64] = (S)acc[a];
         }
 #pragma unroll
         for (int a = 0; a < NO; ++a) {
@@ -777,7 +800,7 @@ int run_moments(const bop_plan &p, const int *row_ptr, const double *H_on, const
 
 // unit start vectors, coefficients of level 0, b_0 = 0 and flags; NaN
 // coefficients for the seeds of failed tiles
-template <typename T, int NO>
+template <typename T, int NO, typename S = T>
 __global__ void k_l0(Batch bt, int n_max, const int *__restrict__ sizes_, const char *tiles_base,
                      size_t tile_stride, char *xbase, size_t x_stride, double *__restrict__ lc,
                      double *__restrict__ a, double *__restrict__ b, int *__restrict__ flags, int bf16)
@@ -812,10 +835,10 @@ __global__ void k_l0(Batch bt, int n_max, const int *__restrict__ sizes_, const 
             X0[e] = (al < NO && c == l * NO + al) ? (unsigned short)0x3f80 : (unsigned short)0;
         }
     } else {
-        T *X0 = (T *)(xbase + x_stride * (2 * (size_t)t));
+        S *X0 = (S *)(xbase + x_stride * (2 * (size_t)t));
         for (int e = threadIdx.x; e < Bt * NO * 64; e += blockDim.x) {
             int l = e / (NO * 64), rest = e % (NO * 64), al = rest / 64, c = rest % 64;
-            X0[(long)l * NO * 64 + al * 64 + c] = (c == l * NO + al) ? T(1) : T(0);
+            X0[(long)l * NO * 64 + al * 64 + c] = (c == l * NO + al) ? S(1) : S(0);
         }
     }
 }
@@ -824,7 +847,7 @@ __global__ void k_l0(Batch bt, int n_max, const int *__restrict__ sizes_, const 
 // the moment-step index, level k - 1), in place of y'; partial sums of |r_k|^2.
 // A thread owns one column of a row: n_orb values in the [n_orb][64] layout,
 // or the slot-width vector in the BF16 [64][slot width] layout.
-template <typename T, int NO, int WGT, int BF>
+template <typename T, int NO, int WGT, int BF, typename S = T>
 __global__ void __launch_bounds__(WGT)
 k_lupdate(Batch bt, int k, int nch, int chunk_rows, int rows_cap, const int *__restrict__ sizes_,
           const char *tiles_base, size_t tile_stride, char *xbase, size_t x_stride,
@@ -868,18 +891,19 @@ k_lupdate(Batch bt, int k, int nch, int chunk_rows, int rows_cap, const int *__r
             }
         }
     } else {
-        const T *Xp = (const T *)(xbase + x_stride * (2 * (size_t)t + src));
-        T *Xc = (T *)(xbase + x_stride * (2 * (size_t)t + dst));
+        const S *Xp = (const S *)(xbase + x_stride * (2 * (size_t)t + src));
+        S *Xc = (S *)(xbase + x_stride * (2 * (size_t)t + dst));
         const T ast = (T)as;
         for (int l = r0 + w; l < r1; l += NW) {
             const bool hp = (rinfo[l] & 255) <= k - 1;
             const long off = (long)l * NO * 64 + lane;
 #pragma unroll
             for (int al = 0; al < NO; ++al) {
-                const T x = hp ? Xp[off + al * 64] : T(0);
-                const T r = Xc[off + al * 64] - ast * x;
-                Xc[off + al * 64] = r;
-                se = fma((double)r, (double)r, se);
+                const T x = hp ? (T)Xp[off + al * 64] : T(0);
+                const S rs = (S)((T)Xc[off + al * 64] - ast * x);
+                Xc[off + al * 64] = rs;
+                const double r = (double)(T)rs;          // the norm of the vector as stored
+                se = fma(r, r, se);
             }
         }
     }
@@ -947,7 +971,7 @@ __global__ void k_lreduce(Batch bt, int k, int K, int last, int which, int n_max
     flags[gr] = fl;
 }
 
-template <typename T, int NO>
+template <typename T, int NO, typename S = T>
 int run_lanczos(const bop_plan &p, const int *row_ptr, const double *H_on, const void *Hv, double *a, double *b,
                 int *flags, char *ws, const Layout &lay, hipStream_t st)
 {
@@ -960,10 +984,10 @@ int run_lanczos(const bop_plan &p, const int *row_ptr, const double *H_on, const
     double *lc = (double *)(ws + lay.lc);
     const bool bf = p.dtype == BOP_BF16;
     // breakdown threshold on b^2 relative to b_1^2, above the rounding level of the stored vectors
-    const double thr = p.dtype == BOP_F64 ? 1e-14 : (p.dtype == BOP_F32 ? 1e-10 : 1e-5);
+    const double thr = p.dtype == BOP_F64 ? 1e-14 : (p.dtype == BOP_F32 ? 1e-10 : (p.dtype == BOP_F16 ? 1e-7 : 1e-5));
     for (int first = 0; first < p.n_tiles; first += p.batch_tiles) {
         Batch bt{first, min(p.batch_tiles, p.n_tiles - first)};
-        k_l0<T, NO><<<bt.count, 256, 0, st>>>(bt, p.n_max, sizes, tiles, lay.tile_stride, xb, lay.x_stride, lc, a,
+        k_l0<T, NO, S><<<bt.count, 256, 0, st>>>(bt, p.n_max, sizes, tiles, lay.tile_stride, xb, lay.x_stride, lc, a,
                                               b, flags, bf ? 1 : 0);
         BOP_LAUNCHED();
         const int nb8 = (bt.count + 7) / 8;
@@ -984,7 +1008,7 @@ int run_lanczos(const bop_plan &p, const int *row_ptr, const double *H_on, const
 #undef BOP_LSTEP16
             } else {
 #define BOP_LSTEP(W)                                                                                  \
-    k_step<T, NO, W, 1><<<grid, W, (size_t)(W / 64) * p.deg_max * NO * NO * sizeof(T), st>>>(             \
+    k_step<T, NO, W, 1, S><<<grid, W, (size_t)(W / 64) * p.deg_max * NO * NO * sizeof(T), st>>>(          \
         bt, k, K, last, nch, p.chunk_rows, p.deg_max, p.rows_cap, row_ptr, H_on, (const T *)Hv, sizes,  \
         tiles, lay.tile_stride, xb, lay.x_stride, part, lc)
                 if (p.block_threads == 256) BOP_LSTEP(256);
@@ -1001,7 +1025,7 @@ int run_lanczos(const bop_plan &p, const int *row_ptr, const double *H_on, const
     do {                                                                                                   \
         if (bf) k_lupdate<T, NO, W, 1><<<grid, W, 0, st>>>(bt, k, nch, p.chunk_rows, p.rows_cap, sizes, tiles, \
                                                            lay.tile_stride, xb, lay.x_stride, lc, part);   \
-        else k_lupdate<T, NO, W, 0><<<grid, W, 0, st>>>(bt, k, nch, p.chunk_rows, p.rows_cap, sizes, tiles,    \
+        else k_lupdate<T, NO, W, 0, S><<<grid, W, 0, st>>>(bt, k, nch, p.chunk_rows, p.rows_cap, sizes, tiles, \
                                                         lay.tile_stride, xb, lay.x_stride, lc, part);      \
     } while (0)
             if (p.block_threads == 256) BOP_LUPD(256);
@@ -1050,7 +1074,7 @@ extern "C" int bop_moments_plan(int n_atoms, int n_orb, int n_max, int dtype, co
     BOP_REQUIRE(plan && n_atoms >= 0, BOP_E_ARG, "bop_moments_plan: bad arguments");
     BOP_REQUIRE(n_orb == 5 || n_orb == 9, BOP_E_UNSUPPORTED, "bop_moments_plan: n_orb must be 5 or 9");
     BOP_REQUIRE(n_max >= 0 && n_max <= MAX_NMAX, BOP_E_UNSUPPORTED, "bop_moments_plan: n_max must be 0..%d", MAX_NMAX);
-    BOP_REQUIRE(dtype == BOP_F64 || dtype == BOP_F32 || dtype == BOP_BF16, BOP_E_UNSUPPORTED,
+    BOP_REQUIRE(dtype == BOP_F64 || dtype == BOP_F32 || dtype == BOP_BF16 || dtype == BOP_F16, BOP_E_UNSUPPORTED,
                 "bop_moments_plan: unknown dtype %d", dtype);
     BOP_REQUIRE(n_atoms == 0 || (row_ptr && nbr_j), BOP_E_ARG, "bop_moments_plan: neighbour arrays NULL");
     size_t need = bop_moments_plan_scratch_size(n_atoms);
@@ -1081,6 +1105,10 @@ extern "C" int bop_moments_plan(int n_atoms, int n_orb, int n_max, int dtype, co
         BOP_HIP(hipStreamSynchronize(stream));
         BOP_REQUIRE(hv[3] <= 64, BOP_E_UNSUPPORTED, "bop_moments_plan: %d neighbours in a row (at most 64)", hv[3]);
         int dmax = hv[3] > 0 ? hv[3] : 1;
+        // the breadth-first claims encode (row, slot) entries as CLAIM + entry < 2^31
+        BOP_REQUIRE((long)n_atoms * dmax < (1L << 30), BOP_E_UNSUPPORTED,
+                    "bop_moments_plan: %d atoms x %d neighbours too large for one plan (split the structure)", n_atoms,
+                    dmax);
         k_plan<<<pwg, PLAN_T, 0, stream>>>(n_atoms, B, n_tiles, K, order, row_ptr, nbr_j, dmax, hdr, base, per);
         BOP_LAUNCHED();
         BOP_HIP(hipMemcpyAsync(hv, hdr, sizeof hv, hipMemcpyDeviceToHost, stream));
@@ -1143,6 +1171,8 @@ extern "C" int bop_moments(const bop_plan *plan, const int *row_ptr, const doubl
     BOP_REQUIRE(row_ptr && H_on && H_bond && mu, BOP_E_ARG, "bop_moments: NULL array");
     Layout lay = make_layout(*plan, map_workgroups(n, plan->n_tiles));
     char *w = (char *)ws;
+    BOP_REQUIRE(plan->dtype != BOP_F16, BOP_E_UNSUPPORTED,
+                "bop_moments: FP16 vector storage is for the Lanczos form (bop_lanczos) only");
     if (plan->dtype == BOP_BF16)
         return no == 5 ? run_moments_bf16<5>(*plan, row_ptr, H_on, H_bond, mu, w, lay, stream)
                        : run_moments_bf16<9>(*plan, row_ptr, H_on, H_bond, mu, w, lay, stream);
@@ -1168,6 +1198,9 @@ extern "C" int bop_lanczos(const bop_plan *plan, const int *row_ptr, const doubl
     if (plan->dtype == BOP_F64)
         return no == 5 ? run_lanczos<double, 5>(*plan, row_ptr, H_on, H_bond, a, b, flags, w, lay, stream)
                        : run_lanczos<double, 9>(*plan, row_ptr, H_on, H_bond, a, b, flags, w, lay, stream);
+    if (plan->dtype == BOP_F16)
+        return no == 5 ? run_lanczos<float, 5, _Float16>(*plan, row_ptr, H_on, H_bond, a, b, flags, w, lay, stream)
+                       : run_lanczos<float, 9, _Float16>(*plan, row_ptr, H_on, H_bond, a, b, flags, w, lay, stream);
     return no == 5 ? run_lanczos<float, 5>(*plan, row_ptr, H_on, H_bond, a, b, flags, w, lay, stream)
                    : run_lanczos<float, 9>(*plan, row_ptr, H_on, H_bond, a, b, flags, w, lay, stream);
 }

@@ -125,3 +125,28 @@ def test_lanczos_scf_fp32_matches_oracle(bop):
     iters, hist = s.run_scf(mix=0.5, tol=1e-4, max_iter=100)
     assert abs(iters - len(hist_ref)) <= 1
     np.testing.assert_allclose(s.shift.cpu().numpy(), shift_ref, atol=1e-4)
+
+
+# FP16 storage of the Lanczos vectors (FP32 H and arithmetic): unit roundoff
+# 2^-11 per stored value times the spectral radius of these Hamiltonians
+# (about 10 eV) bounds a_n, b_n by 5e-3 eV; U within 1e-4 relative.
+@pytest.mark.parametrize("name", ["bcc_small", "bcc_alloy", "fcc_spd", "hcp"])
+def test_lanczos_fp16_storage_bound(bop, name):
+    wl = _wl(name)
+    ref = O.energy_pipeline(wl)
+    p, out = _run(bop, wl, "f16")
+    ea = np.max(np.abs(_np(p.rec["a"]) - ref["rec"]["a"]))
+    eb = np.max(np.abs(_np(p.rec["b"]) - ref["rec"]["b"]))
+    u = float(_np(out["U_total"])[0])
+    eu = abs(u - ref["U_total"]) / abs(ref["U_total"])
+    print(f"{name}: f16 a {ea:.2e} b {eb:.2e} U rel {eu:.2e} ({abs(u - ref['U_total']) / wl.n_atoms * 1e3:.4f} meV/atom)")
+    assert ea < 5e-3 and eb < 5e-3
+    assert eu < 1e-4
+
+
+def test_moments_reject_fp16_storage(bop):
+    wl = _wl("bcc_small")
+    p = bop.EnergyPath(wl.pos, wl.cell, wl.species, wl.model, wl.n_max, 200, "f16", method="moments")
+    with pytest.raises(bop.BopError) as e:
+        p.run_moments()
+    assert e.value.code == bop.BOP_E_UNSUPPORTED
