@@ -165,7 +165,8 @@ typedef struct bop_tuning {
     int tile_atoms;      /* atoms per tile; 0 = as many as fit one wavefront */
     int block_threads;   /* 256, 512 or 1024; 0 = default (512) */
     int batch_tiles;     /* tiles whose X buffers are live at once; 0 = ~6 GiB worth */
-    int chunk_rows;      /* support rows per workgroup and step; 0 = default (64) */
+    int chunk_rows;      /* support rows per workgroup and step (the rows are dealt to the
+                            workgroups of a tile in wave-sized groups, round robin); 0 = default (64) */
 } bop_tuning;
 
 #define BOP_MAX_NMAX 40

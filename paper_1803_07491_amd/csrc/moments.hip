@@ -15,16 +15,18 @@
 //    neighbour slots sorted by the neighbour's layer: at step k the neighbours
 //    whose X^(k-1) is non-zero form a prefix of that list.
 //  * The steps are step-synchronous launches over a batch of tiles; a
-//    workgroup computes one chunk of consecutive rows of one tile; a wavefront
-//    owns a row and all 64 columns.  The row's H blocks are wave-uniform and
-//    come in through scalar loads; neighbour rows of X^(k-1) are coalesced
+//    wavefront owns a row and all 64 columns.  The row's H blocks are copied
+//    to LDS with coalesced loads; neighbour rows of X^(k-1) are coalesced
 //    vector loads.  Blocks are numbered so that all chunks of a tile run on
-//    one XCD (block b runs on XCD b mod 8) one tile after another: each XCD
-//    then streams through a few tiles at a time and the ~15-fold reuse of every
-//    gathered row stays in its L2 and the memory-attached cache instead of HBM.
+//    one XCD (block b runs on XCD b mod 8) one tile after another, and the
+//    rows are dealt to the tile's chunks in wave-sized groups round robin, so
+//    the rows in flight on an XCD form
+//    one window of consecutive rows in layer order.  Their neighbours then sit
+//    in a few nearby patches of adjacent layers, and the ~15-fold reuse of
+//    every gathered row stays in the XCD's L2 instead of going to memory.
 //  * The moment dot products are fused into the step; per-chunk partial sums
 //    (FP64) are reduced in chunk order afterwards, so results are
-//    deterministic.
+//    deterministic for a given plan.
 #include "bop_internal.h"
 
 namespace bop {
@@ -37,6 +39,16 @@ constexpr int MAXK = MAX_NMAX / 2;
 constexpr int HDR = 256;            // header ints: [0] queue, [1] error, [2] max rows, [3] max degree,
                                     // [8 + k] max rows of U^k (plan)
 constexpr int PLAN_T = 512;
+
+// Row assignment of the step kernels: a tile with nrow rows at this step uses
+// nct = tile_chunks(..) of the launch's chunks, and chunk c < nct takes the
+// wave-sized row groups c, c + nct, c + 2 nct, ...  nct depends on the tile
+// alone, so the grouping of the partial sums (and the rounding of the moments)
+// does not change with the other tiles of the plan.
+__device__ inline int tile_chunks(int nrow, int chunk_rows, int nw)
+{
+    return min((nrow + chunk_rows - 1) / chunk_rows, (nrow + nw - 1) / nw);
+}
 
 // exclusive prefix of a 0/1 flag over the workgroup; returns the position and
 // writes the workgroup total
@@ -366,9 +378,9 @@ k_step(Batch bt, int k, int K, int last, int nch, int chunk_rows, int deg_max, i
     const int *sizes = sizes_ + tile * (MAXK + 2);
     if (sizes[0] < 0) return;
     const int nrow = last ? sizes[K] : sizes[k];
-    const int r0 = chunk * chunk_rows;
-    if (r0 >= nrow) return;
-    const int r1 = min(nrow, r0 + chunk_rows);
+    const int nct = tile_chunks(nrow, chunk_rows, NW);
+    if (chunk >= nct) return;
+    const int RS = nct * NW;                                 // row stride of this chunk
     const int *sup = (const int *)(tiles_base + tile_stride * tile);
     const int *rinfo = sup + rows_cap;
     const int *lnb = rinfo + rows_cap;
@@ -388,21 +400,21 @@ k_step(Batch bt, int k, int K, int last, int nch, int chunk_rows, int deg_max, i
     // the next row's atom, layer word, slot list and pair range are fetched while
     // the current row computes, which takes their dependent loads off the
     // critical path
-    int l = r0 + w;
+    int l = chunk * NW + w;
     int g_n = 0, info_n = 0, slots_n = 0, p0_n = 0, p1_n = 0;
-    if (l < r1) {
+    if (l < nrow) {
         g_n = __builtin_amdgcn_readfirstlane(sup[l]);
         info_n = __builtin_amdgcn_readfirstlane(rinfo[l]);
         slots_n = lane < deg_max ? lnb[(long)l * deg_max + lane] : 0;
         p0_n = row_ptr[g_n];
         p1_n = row_ptr[g_n + 1];
     }
-    for (; l < r1; l += NW) {
+    for (; l < nrow; l += RS) {
         const int g = g_n, info = info_n, slots_all = slots_n, p0 = p0_n, deg = p1_n - p0_n;
-        if (l + NW < r1) {
-            g_n = __builtin_amdgcn_readfirstlane(sup[l + NW]);
-            info_n = __builtin_amdgcn_readfirstlane(rinfo[l + NW]);
-            slots_n = lane < deg_max ? lnb[(long)(l + NW) * deg_max + lane] : 0;
+        if (l + RS < nrow) {
+            g_n = __builtin_amdgcn_readfirstlane(sup[l + RS]);
+            info_n = __builtin_amdgcn_readfirstlane(rinfo[l + RS]);
+            slots_n = lane < deg_max ? lnb[(long)(l + RS) * deg_max + lane] : 0;
             p0_n = row_ptr[g_n];
             p1_n = row_ptr[g_n + 1];
         }
@@ -484,7 +496,7 @@ k_step(Batch bt, int k, int K, int last, int nch, int chunk_rows, int deg_max, i
 
 // mu[.][2k-1], mu[.][2k] (or mu[.][2K+1]) from the chunk partials, in chunk order
 template <int NO>
-__global__ void k_reduce(Batch bt, int k, int K, int last, int n_max, int nch, int chunk_rows,
+__global__ void k_reduce(Batch bt, int k, int K, int last, int n_max, int nch, int chunk_rows, int nw,
                          const int *__restrict__ sizes_, const char *tiles_base, size_t tile_stride,
                          const double *__restrict__ part, double *__restrict__ mu)
 {
@@ -497,7 +509,7 @@ __global__ void k_reduce(Batch bt, int k, int K, int last, int n_max, int nch, i
     const int c = threadIdx.x;
     if (c >= Bt * NO) return;
     const int nrow = last ? sizes[K] : sizes[k];
-    const int used = (nrow + chunk_rows - 1) / chunk_rows;
+    const int used = tile_chunks(nrow, chunk_rows, nw);
     double to = 0.0, te = 0.0;
     for (int q = 0; q < used; ++q) {
         const double *pp = part + (((size_t)t * nch + q) * 2) * 64;
@@ -588,9 +600,8 @@ k_step_bf16(Batch bt, int k, int K, int last, int nch, int chunk_rows, int deg_m
     const int *sizes = sizes_ + tile * (MAXK + 2);
     if (sizes[0] < 0) return;
     const int nrow = last ? sizes[K] : sizes[k];
-    const int r0 = chunk * chunk_rows;
-    if (r0 >= nrow) return;
-    const int r1 = min(nrow, r0 + chunk_rows);
+    const int nct = tile_chunks(nrow, chunk_rows, NW);
+    if (chunk >= nct) return;
     const int *sup = (const int *)(tiles_base + tile_stride * tile);
     const int *rinfo = sup + rows_cap;
     const int *lnb = rinfo + rows_cap;
@@ -610,7 +621,7 @@ k_step_bf16(Batch bt, int k, int K, int last, int nch, int chunk_rows, int deg_m
             lbeta[cb] = (float)lc[((size_t)t * 4 + 1) * 64 + cb * 16 + n];
         }
     }
-    for (int l = r0 + w; l < r1; l += NW) {
+    for (int l = chunk * NW + w; l < nrow; l += nct * NW) {
         const int gatom = __builtin_amdgcn_readfirstlane(sup[l]);
         const int info = __builtin_amdgcn_readfirstlane(rinfo[l]);
         const int L = info & 255, n1 = (info >> 8) & 255, n2 = (info >> 16) & 255, n3 = (info >> 24) & 255;
@@ -732,7 +743,7 @@ int run_moments_bf16(const bop_plan &p, const int *row_ptr, const double *H_on, 
             else BOP_STEP16(1024);
 #undef BOP_STEP16
             BOP_LAUNCHED();
-            k_reduce<NO><<<bt.count, 64, 0, st>>>(bt, k, K, last, p.n_max, nch, p.chunk_rows, sizes, tiles,
+            k_reduce<NO><<<bt.count, 64, 0, st>>>(bt, k, K, last, p.n_max, nch, p.chunk_rows, p.block_threads / 64, sizes, tiles,
                                                   lay.tile_stride, part, mu);
             BOP_LAUNCHED();
         }
@@ -751,7 +762,6 @@ int run_moments(const bop_plan &p, const int *row_ptr, const double *H_on, const
     const char *tiles = ws + lay.tiles;
     char *xb = ws + lay.x;
     double *part = (double *)(ws + lay.part);
-    const int nch_all = (p.rows_cap + p.chunk_rows - 1) / p.chunk_rows;
     for (int first = 0; first < p.n_tiles; first += p.batch_tiles) {
         Batch bt{first, min(p.batch_tiles, p.n_tiles - first)};
         k_x0<T, NO><<<bt.count, 256, 0, st>>>(bt, p.n_max, p.tile_atoms, sizes, tiles, lay.tile_stride, xb,
@@ -773,12 +783,11 @@ int run_moments(const bop_plan &p, const int *row_ptr, const double *H_on, const
             else BOP_STEP(1024);
 #undef BOP_STEP
             BOP_LAUNCHED();
-            k_reduce<NO><<<bt.count, 64, 0, st>>>(bt, k, K, last, p.n_max, nch, p.chunk_rows, sizes, tiles,
+            k_reduce<NO><<<bt.count, 64, 0, st>>>(bt, k, K, last, p.n_max, nch, p.chunk_rows, p.block_threads / 64, sizes, tiles,
                                                   lay.tile_stride, part, mu);
             BOP_LAUNCHED();
         }
     }
-    (void)nch_all;
     return BOP_OK;
 }
 
@@ -862,9 +871,8 @@ k_lupdate(Batch bt, int k, int nch, int chunk_rows, int rows_cap, const int *__r
     const int *sizes = sizes_ + tile * (MAXK + 2);
     if (sizes[0] < 0) return;
     const int nrow = sizes[k];
-    const int r0 = chunk * chunk_rows;
-    if (r0 >= nrow) return;
-    const int r1 = min(nrow, r0 + chunk_rows);
+    const int nct = tile_chunks(nrow, chunk_rows, NW);
+    if (chunk >= nct) return;
     const int *sup = (const int *)(tiles_base + tile_stride * tile);
     const int *rinfo = sup + rows_cap;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -876,7 +884,7 @@ k_lupdate(Batch bt, int k, int nch, int chunk_rows, int rows_cap, const int *__r
         const unsigned short *Xp = (const unsigned short *)(xbase + x_stride * (2 * (size_t)t + src));
         unsigned short *Xc = (unsigned short *)(xbase + x_stride * (2 * (size_t)t + dst));
         const float asf = (float)as;
-        for (int l = r0 + w; l < r1; l += NW) {
+        for (int l = chunk * NW + w; l < nrow; l += nct * NW) {
             const bool hp = (rinfo[l] & 255) <= k - 1;
             const long off = ((long)l * 64 + lane) * SW;
 #pragma unroll
@@ -894,7 +902,7 @@ k_lupdate(Batch bt, int k, int nch, int chunk_rows, int rows_cap, const int *__r
         const S *Xp = (const S *)(xbase + x_stride * (2 * (size_t)t + src));
         S *Xc = (S *)(xbase + x_stride * (2 * (size_t)t + dst));
         const T ast = (T)as;
-        for (int l = r0 + w; l < r1; l += NW) {
+        for (int l = chunk * NW + w; l < nrow; l += nct * NW) {
             const bool hp = (rinfo[l] & 255) <= k - 1;
             const long off = (long)l * NO * 64 + lane;
 #pragma unroll
@@ -922,7 +930,7 @@ k_lupdate(Batch bt, int k, int nch, int chunk_rows, int rows_cap, const int *__r
 // the breakdown test of the moment route (b_k^2 <= thr * b_1^2 ends the chain,
 // later a repeat the last one and later b are zero).
 __global__ void k_lreduce(Batch bt, int k, int K, int last, int which, int n_max, int no, int nch,
-                          int chunk_rows, double thr, const int *__restrict__ sizes_, const char *tiles_base,
+                          int chunk_rows, int nw, double thr, const int *__restrict__ sizes_, const char *tiles_base,
                           size_t tile_stride, const double *__restrict__ part, double *__restrict__ lc,
                           double *__restrict__ a, double *__restrict__ b, int *__restrict__ flags)
 {
@@ -934,7 +942,7 @@ __global__ void k_lreduce(Batch bt, int k, int K, int last, int which, int n_max
     const int c = threadIdx.x;
     if (c >= sizes[0] * no) return;
     const int nrow = last ? sizes[K] : sizes[k];
-    const int used = (nrow + chunk_rows - 1) / chunk_rows;
+    const int used = tile_chunks(nrow, chunk_rows, nw);
     double sum = 0.0;
     for (int q = 0; q < used; ++q) sum += part[(((size_t)t * nch + q) * 2 + which) * 64 + c];
     const int *sup = (const int *)(tiles_base + tile_stride * tile);
@@ -1017,7 +1025,7 @@ int run_lanczos(const bop_plan &p, const int *row_ptr, const double *H_on, const
 #undef BOP_LSTEP
             }
             BOP_LAUNCHED();
-            k_lreduce<<<bt.count, 64, 0, st>>>(bt, k, K, last, 0, p.n_max, NO, nch, p.chunk_rows, thr, sizes, tiles,
+            k_lreduce<<<bt.count, 64, 0, st>>>(bt, k, K, last, 0, p.n_max, NO, nch, p.chunk_rows, p.block_threads / 64, thr, sizes, tiles,
                                                lay.tile_stride, part, lc, a, b, flags);
             BOP_LAUNCHED();
             if (last) continue;
@@ -1033,7 +1041,7 @@ int run_lanczos(const bop_plan &p, const int *row_ptr, const double *H_on, const
             else BOP_LUPD(1024);
 #undef BOP_LUPD
             BOP_LAUNCHED();
-            k_lreduce<<<bt.count, 64, 0, st>>>(bt, k, K, last, 1, p.n_max, NO, nch, p.chunk_rows, thr, sizes, tiles,
+            k_lreduce<<<bt.count, 64, 0, st>>>(bt, k, K, last, 1, p.n_max, NO, nch, p.chunk_rows, p.block_threads / 64, thr, sizes, tiles,
                                                lay.tile_stride, part, lc, a, b, flags);
             BOP_LAUNCHED();
         }
