@@ -50,6 +50,17 @@ __device__ inline int tile_chunks(int nrow, int chunk_rows, int nw)
     return min((nrow + chunk_rows - 1) / chunk_rows, (nrow + nw - 1) / nw);
 }
 
+// The global->local maps of the support search are private to one workgroup
+// (all of whose waves share a CU), so workgroup scope is enough for them; it
+// keeps the map traffic in the XCD's L2, where device-scope atomics and stores
+// would go through to memory, the L2s of the XCDs not being coherent.
+__device__ inline int wg_load(const int *p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); }
+__device__ inline void wg_store(int *p, int v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); }
+__device__ inline void wg_min(int *p, int v)
+{
+    __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 // exclusive prefix of a 0/1 flag over the workgroup; returns the position and
 // writes the workgroup total
 template <int WGT>
@@ -77,6 +88,11 @@ __device__ inline int wg_scan01(int own, int *s_wave, int &total)
 // X^k| for k = 0..K (layer order), sup[0..s_size[K]) lists the global atoms and
 // g2l maps them to local rows.  Returns -1 (with g2l restored) if the support
 // would exceed rows_cap.
+//
+// Layer k: every (frontier row t, slot s) entry e = (t - begin) * deg_max + s,
+// one per thread, proposes itself for its neighbour with an atomic minimum, and
+// the neighbours won by their smallest entry are appended in entry order, so
+// the row order does not depend on scheduling.
 template <int WGT>
 __device__ int bfs_tile(int tile, int B, int n_atoms, int K, const int *__restrict__ order,
                         const int *__restrict__ row_ptr, const int *__restrict__ nbr_j, int deg_max,
@@ -88,12 +104,12 @@ __device__ int bfs_tile(int tile, int B, int n_atoms, int K, const int *__restri
     if (tid < Bt && tid < rows_cap) {
         int g = order ? order[first + tid] : first + tid;
         sup[tid] = g;
-        atomic_store_agent(&g2l[g], tid);
+        wg_store(&g2l[g], tid);
     }
     if (tid == 0) { s_size[0] = Bt; s_flag[0] = 0; }
     __syncthreads();
     if (Bt > rows_cap) {
-        for (int t = tid; t < rows_cap; t += WGT) atomic_store_agent(&g2l[sup[t]], UNSEEN);
+        for (int t = tid; t < rows_cap; t += WGT) wg_store(&g2l[sup[t]], UNSEEN);
         __syncthreads();
         return -1;
     }
@@ -104,7 +120,7 @@ __device__ int bfs_tile(int tile, int B, int n_atoms, int K, const int *__restri
             int t = begin + (int)(e / deg_max), s = (int)(e % deg_max);
             int g = sup[t];
             int p0 = row_ptr[g], deg = row_ptr[g + 1] - p0;
-            if (s < deg) atomicMin(&g2l[nbr_j[p0 + s]], CLAIM + (int)e);
+            if (s < deg) wg_min(&g2l[nbr_j[p0 + s]], CLAIM + (int)e);
         }
         __syncthreads();
         int base = end;
@@ -117,14 +133,14 @@ __device__ int bfs_tile(int tile, int B, int n_atoms, int K, const int *__restri
                 int p0 = row_ptr[g], deg = row_ptr[g + 1] - p0;
                 if (s < deg) {
                     j = nbr_j[p0 + s];
-                    own = atomic_load_agent(&g2l[j]) == CLAIM + (int)e;
+                    own = wg_load(&g2l[j]) == CLAIM + (int)e;
                 }
             }
             int tot;
             int pos = wg_scan01<WGT>(own, s_wave, tot);
             if (own) {
                 int idx = base + pos;
-                if (idx < rows_cap) { sup[idx] = j; atomic_store_agent(&g2l[j], idx); }
+                if (idx < rows_cap) { sup[idx] = j; wg_store(&g2l[j], idx); }
                 else s_flag[0] = 1;
             }
             base += tot;
@@ -132,12 +148,12 @@ __device__ int bfs_tile(int tile, int B, int n_atoms, int K, const int *__restri
         __syncthreads();
         if (s_flag[0]) {
             // restore the map: every claimed atom neighbours this frontier
-            for (int t = tid; t < min(base, rows_cap); t += WGT) atomic_store_agent(&g2l[sup[t]], UNSEEN);
+            for (int t = tid; t < min(base, rows_cap); t += WGT) wg_store(&g2l[sup[t]], UNSEEN);
             for (long e = tid; e < nent; e += WGT) {
                 int t = begin + (int)(e / deg_max), s = (int)(e % deg_max);
                 int g = sup[t];
                 int p0 = row_ptr[g], deg = row_ptr[g + 1] - p0;
-                if (s < deg) atomic_store_agent(&g2l[nbr_j[p0 + s]], UNSEEN);
+                if (s < deg) wg_store(&g2l[nbr_j[p0 + s]], UNSEEN);
             }
             __syncthreads();
             return -1;
@@ -151,7 +167,7 @@ __device__ int bfs_tile(int tile, int B, int n_atoms, int K, const int *__restri
 template <int WGT>
 __device__ inline void reset_map(int *g2l, const int *sup, int rows)
 {
-    for (int t = threadIdx.x; t < rows; t += WGT) atomic_store_agent(&g2l[sup[t]], UNSEEN);
+    for (int t = threadIdx.x; t < rows; t += WGT) wg_store(&g2l[sup[t]], UNSEEN);
     __syncthreads();
 }
 
@@ -276,6 +292,9 @@ k_prepare(int n_atoms, int B, int n_tiles, int K, const int *__restrict__ order,
             continue;
         }
         if (threadIdx.x <= K) sizes[tile * (MAXK + 2) + threadIdx.x] = s_size[threadIdx.x];
+        // per row: neighbour slots by class (0: layer < L, 1: layer L, 2: layer
+        // L + 1, 3: outside the support), stable in slot order within a class;
+        // one sweep counts, a second places, slot loads issued eight at a time
         for (int l = threadIdx.x; l < rows; l += PLAN_T) {
             const int g = sup[l];
             int L = 0;
@@ -285,16 +304,26 @@ k_prepare(int n_atoms, int B, int n_tiles, int K, const int *__restrict__ order,
             const int endL1 = (L + 1 <= K) ? s_size[L + 1] : s_size[K];
             const int p0 = row_ptr[g], deg = row_ptr[g + 1] - p0;
             int *dst = lnb + (long)l * deg_max;
-            int c = 0, n1 = 0, n2 = 0;
-            for (int pass = 0; pass < 3; ++pass) {
-                for (int sl = 0; sl < deg; ++sl) {
-                    int lj = atomic_load_agent(&g2l[nbr_j[p0 + sl]]);
-                    int cls = (lj < lo) ? 0 : (lj < endL ? 1 : (lj < endL1 ? 2 : 3));
-                    if (cls == pass) dst[c++] = (lj << 8) | sl;
+            int cnt[3] = {0, 0, 0};
+            for (int pass = 0; pass < 2; ++pass) {
+                int o[3] = {0, cnt[0], cnt[0] + cnt[1]};
+                for (int s0 = 0; s0 < deg; s0 += 8) {
+                    int lj[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) lj[u] = (s0 + u < deg) ? nbr_j[p0 + s0 + u] : -1;
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) lj[u] = lj[u] >= 0 ? wg_load(&g2l[lj[u]]) : UNSEEN;
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const int cls = (lj[u] < lo) ? 0 : (lj[u] < endL ? 1 : (lj[u] < endL1 ? 2 : 3));
+                        if (cls < 3) {
+                            if (pass == 0) ++cnt[cls];
+                            else dst[o[cls]++] = (lj[u] << 8) | (s0 + u);
+                        }
+                    }
                 }
-                if (pass == 0) n1 = c;
-                if (pass == 1) n2 = c;
             }
+            const int n1 = cnt[0], n2 = cnt[0] + cnt[1], c = n2 + cnt[2];
             rinfo[l] = L | (n1 << 8) | (n2 << 16) | (c << 24);
         }
         __syncthreads();
