@@ -161,7 +161,8 @@ def main():
     ap.add_argument("--reps-scf", type=int, default=50)
     ap.add_argument("--reps-spd", type=int, default=30)
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="only run a 1 GiB device copy (for scaling HBM counters)")
+                    help="only run a device copy (for scaling HBM counters)")
+    ap.add_argument("--copy-gib", type=int, default=1, help="size of the calibration copy in GiB")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -172,7 +173,7 @@ def main():
 
     import torch
     if args.copy_calibration:
-        x = torch.ones(1 << 28, dtype=torch.float32, device="cuda")   # 1 GiB
+        x = torch.ones(args.copy_gib << 28, dtype=torch.float32, device="cuda")
         y = torch.empty_like(x)
         for _ in range(3):
             y.copy_(x)

@@ -540,10 +540,18 @@ __global__ void k_reduce(Batch bt, int k, int K, int last, int n_max, int nch, i
     const int nrow = last ? sizes[K] : sizes[k];
     const int used = tile_chunks(nrow, chunk_rows, nw);
     double to = 0.0, te = 0.0;
-    for (int q = 0; q < used; ++q) {
-        const double *pp = part + (((size_t)t * nch + q) * 2) * 64;
-        to += pp[c];
-        te += pp[64 + c];
+    // eight chunks' loads in flight, added in chunk order
+    for (int q0 = 0; q0 < used; q0 += 8) {
+        double vo[8], ve[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const double *pp = part + (((size_t)t * nch + min(q0 + u, used - 1)) * 2) * 64;
+            vo[u] = pp[c];
+            ve[u] = pp[64 + c];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (q0 + u < used) { to += vo[u]; te += ve[u]; }
     }
     const int *sup = (const int *)(tiles_base + tile_stride * tile);
     const int b = c / NO, a = c % NO;
@@ -973,7 +981,15 @@ __global__ void k_lreduce(Batch bt, int k, int K, int last, int which, int n_max
     const int nrow = last ? sizes[K] : sizes[k];
     const int used = tile_chunks(nrow, chunk_rows, nw);
     double sum = 0.0;
-    for (int q = 0; q < used; ++q) sum += part[(((size_t)t * nch + q) * 2 + which) * 64 + c];
+    // eight chunks' loads in flight, added in chunk order
+    for (int q0 = 0; q0 < used; q0 += 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = part[(((size_t)t * nch + min(q0 + u, used - 1)) * 2 + which) * 64 + c];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (q0 + u < used) sum += v[u];
+    }
     const int *sup = (const int *)(tiles_base + tile_stride * tile);
     const long gr = (long)sup[c / no] * no + c % no;
     const int na = n_max >= 1 ? (n_max - 1) / 2 + 1 : 0, nb = n_max / 2;
