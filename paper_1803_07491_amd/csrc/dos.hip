@@ -320,36 +320,38 @@ k_fermi_tree(int n_rows, int n_exp, const double *__restrict__ gs, const double 
     double cnt[FT_HALF];
     if (r < n_rows) {
         const double ai = a_inf[r], bi = b_inf[r];
-        double c[FT_HALF], sn[FT_HALF], ck[FT_HALF], sk[FT_HALF], acc[FT_HALF];
+        double sn[FT_HALF], twoc[FT_HALF], b1[FT_HALF], b2[FT_HALF];
         const double g0 = gs[r];
 #pragma unroll
         for (int j = 0; j < FT_HALF; ++j) {
             const int p = h * FT_HALF + j < FT_NODES ? h * FT_HALF + j : FT_NODES - 1;
             double eps = (mid[p] - ai) / (2.0 * bi);
-            c[j] = eps < -1.0 ? -1.0 : (eps > 1.0 ? 1.0 : eps);
-            sn[j] = sqrt(fmax(0.0, 1.0 - c[j] * c[j]));
-            cnt[j] = g0 * (1.0 - acos(c[j]) / M_PI);
-            ck[j] = c[j];
-            sk[j] = sn[j];
-            acc[j] = 0.0;
+            const double c = eps < -1.0 ? -1.0 : (eps > 1.0 ? 1.0 : eps);
+            sn[j] = sqrt(fmax(0.0, 1.0 - c * c));
+            cnt[j] = g0 * (1.0 - acos(c) / M_PI);
+            twoc[j] = 2.0 * c;
+            b1[j] = 0.0;
+            b2[j] = 0.0;
         }
-        double gkm2 = 0.0, gkm1 = g0;
+        // sum_k w_k sin(k theta) = sin(theta) sum_k w_k U_(k-1)(cos theta), by
+        // Clenshaw's recurrence from the highest term down; w_k = (g_(k-2) - g_k) / k
+        // (w_1 = -g_1), with g_k = 0 beyond n_exp
+        double gk = 0.0, gkm1 = 0.0;
 #pragma unroll 4
-        for (int k = 1; k <= n_exp + 2; ++k) {
-            const double gk = (k <= n_exp) ? gs[(long)k * n_rows + r] : 0.0;
+        for (int k = n_exp + 2; k >= 1; --k) {
+            const double gkm2 = (k >= 2) ? gs[(long)(k - 2) * n_rows + r] : 0.0;
             const double wk = ((k >= 2) ? (gkm2 - gk) : -gk) * s_inv[k];
-            gkm2 = gkm1;
-            gkm1 = gk;
+            gk = gkm1;
+            gkm1 = gkm2;
 #pragma unroll
             for (int j = 0; j < FT_HALF; ++j) {
-                acc[j] = fma(wk, sk[j], acc[j]);
-                const double cn = ck[j] * c[j] - sk[j] * sn[j];
-                sk[j] = sk[j] * c[j] + ck[j] * sn[j];
-                ck[j] = cn;
+                const double bn = fma(twoc[j], b1[j], wk - b2[j]);
+                b2[j] = b1[j];
+                b1[j] = bn;
             }
         }
 #pragma unroll
-        for (int j = 0; j < FT_HALF; ++j) cnt[j] += acc[j] / M_PI;
+        for (int j = 0; j < FT_HALF; ++j) cnt[j] += sn[j] * b1[j] / M_PI;
     } else {
 #pragma unroll
         for (int j = 0; j < FT_HALF; ++j) cnt[j] = 0.0;
