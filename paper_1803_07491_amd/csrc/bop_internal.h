@@ -55,6 +55,8 @@ void energy_ws_scratch(void *ws, long n_rows, int n_exp, double **part, unsigned
 
 // Number of compute units of the current device (cached per device).
 int device_cus();
+// Largest LDS allocation of one workgroup on the current device (cached).
+int device_lds_per_block();
 
 // Small device helpers -------------------------------------------------------
 // Combination of per-block partials part[q * stride + off], q < n, by all

@@ -18,22 +18,27 @@ void set_error(const char *fmt, ...)
     va_end(ap);
 }
 
-int device_cus()
+// a device attribute of the current device, cached per (device, slot)
+static int cached_attr(int slot, hipDeviceAttribute_t attr, int fallback)
 {
     static std::mutex mu;
-    static std::vector<int> cache;
+    static std::vector<int> cache[2];
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipGetDevice(&dev) != hipSuccess) return fallback;
     std::lock_guard<std::mutex> lk(mu);
-    if ((int)cache.size() <= dev) cache.resize(dev + 1, 0);
-    if (!cache[dev]) {
-        int cu = 0;
-        if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cu <= 0)
-            cu = 256;
-        cache[dev] = cu;
+    std::vector<int> &c = cache[slot];
+    if ((int)c.size() <= dev) c.resize(dev + 1, 0);
+    if (!c[dev]) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, attr, dev) != hipSuccess || v <= 0) v = fallback;
+        c[dev] = v;
     }
-    return cache[dev];
+    return c[dev];
 }
+
+int device_cus() { return cached_attr(0, hipDeviceAttributeMultiprocessorCount, 256); }
+
+int device_lds_per_block() { return cached_attr(1, hipDeviceAttributeMaxSharedMemoryPerBlock, 65536); }
 
 // ---------------------------------------------------------------------------
 // exclusive scan: 1024 items per block (256 threads x 4), block totals scanned

@@ -382,7 +382,7 @@ __global__ void k_x0(Batch bt, int n_max, int B, const int *__restrict__ sizes_,
 // beta = b_(k-1) * s_(k-2).  The row stores y' = s H r_(k-1) - beta r_(k-2) in
 // place of r_(k-2) and the partial sums give <r_(k-1), y'> (a_(k-1) = s times
 // that); the update kernel then forms r_k = y' - a_(k-1) u_(k-1).
-template <typename T, int NO, int WGT, int LANCZOS, typename S = T>
+template <typename T, int NO, int WGT, int LANCZOS, typename S = T, bool HS = false>
 __global__ void __launch_bounds__(WGT)
 k_step(Batch bt, int k, int K, int last, int nch, int chunk_rows, int deg_max, int rows_cap,
        const int *__restrict__ row_ptr, const double *__restrict__ H_on, const T *__restrict__ H,
@@ -451,9 +451,15 @@ k_step(Batch bt, int k, int K, int last, int nch, int chunk_rows, int deg_max, i
         const bool has_prev = last || L <= k - 1;
         const int nval = last ? n3 : (k - 1 >= L + 1 ? n3 : (k - 1 == L ? n2 : n1));
         const int slots = (lane < nval) ? slots_all : 0;
-        // the row's H blocks -> LDS (contiguous pairs p0 .. p0 + deg)
+        // the row's H blocks (contiguous pairs p0 .. p0 + deg): staged in LDS
+        // with coalesced loads, or (HS) read with scalar loads straight into
+        // SGPR operands from their wave-uniform addresses.  HS measured 11-34%
+        // faster for FP64 and slower for FP32; FP32 uses it only where the LDS
+        // slice would not fit a workgroup.
+        constexpr bool H_SCALAR = HS;
         const T *hsrc = H + (long)p0 * NB;
-        for (int e = lane; e < deg * NB; e += 64) sH[e] = hsrc[e];
+        if (!H_SCALAR)
+            for (int e = lane; e < deg * NB; e += 64) sH[e] = hsrc[e];
         const S *xrow = Xp + (long)l * stride_row + lane;
         T acc[NO], xs[NO];
 #pragma unroll
@@ -482,7 +488,7 @@ k_step(Batch bt, int k, int K, int last, int nch, int chunk_rows, int deg_max, i
 #pragma unroll
             for (int u = 0; u < G; ++u) {
                 if (s0 + u < nval) {
-                    const T *h = sH + hoff[u];
+                    const T *h = H_SCALAR ? hsrc + hoff[u] : sH + hoff[u];
 #pragma unroll
                     for (int a = 0; a < NO; ++a)
 #pragma unroll
@@ -749,6 +755,13 @@ k_step_bf16(Batch bt, int k, int K, int last, int nch, int chunk_rows, int deg_m
     }
 }
 
+// dynamic LDS of a step launch that stages the rows' H blocks (one slice of
+// deg_max blocks per wavefront)
+static inline size_t h_lds_bytes(const bop_plan &p, int wgt, size_t elem)
+{
+    return (size_t)(wgt / 64) * p.deg_max * p.n_orb * p.n_orb * elem;
+}
+
 template <int NO>
 int run_moments_bf16(const bop_plan &p, const int *row_ptr, const double *H_on, const void *Hv, double *mu,
                      char *ws, const Layout &lay, hipStream_t st)
@@ -799,6 +812,7 @@ int run_moments(const bop_plan &p, const int *row_ptr, const double *H_on, const
     const char *tiles = ws + lay.tiles;
     char *xb = ws + lay.x;
     double *part = (double *)(ws + lay.part);
+    const size_t lds_max = (size_t)device_lds_per_block();
     for (int first = 0; first < p.n_tiles; first += p.batch_tiles) {
         Batch bt{first, min(p.batch_tiles, p.n_tiles - first)};
         k_x0<T, NO><<<bt.count, 256, 0, st>>>(bt, p.n_max, p.tile_atoms, sizes, tiles, lay.tile_stride, xb,
@@ -811,14 +825,24 @@ int run_moments(const bop_plan &p, const int *row_ptr, const double *H_on, const
             const int nch = (rows_k + p.chunk_rows - 1) / p.chunk_rows;
             if (nch <= 0) continue;
             dim3 grid((unsigned)(nb8 * nch * 8));
+#define BOP_STEP_ARGS                                                                                 \
+    bt, k, K, last, nch, p.chunk_rows, p.deg_max, p.rows_cap, row_ptr, H_on, H, sizes, tiles,           \
+        lay.tile_stride, xb, lay.x_stride, part, nullptr
 #define BOP_STEP(W)                                                                                   \
-    k_step<T, NO, W, 0><<<grid, W, (size_t)(W / 64) * p.deg_max * NO * NO * sizeof(T), st>>>(             \
-        bt, k, K, last, nch, p.chunk_rows, p.deg_max, p.rows_cap, row_ptr, H_on, H, sizes, tiles,       \
-        lay.tile_stride, xb, lay.x_stride, part, nullptr)
+    do {                                                                                              \
+        const size_t lds = h_lds_bytes(p, W, sizeof(T));                                              \
+        if constexpr (sizeof(T) == 8) {                                                               \
+            k_step<T, NO, W, 0, T, true><<<grid, W, 0, st>>>(BOP_STEP_ARGS);                          \
+        } else {                                                                                      \
+            if (lds > lds_max) k_step<T, NO, W, 0, T, true><<<grid, W, 0, st>>>(BOP_STEP_ARGS);       \
+            else k_step<T, NO, W, 0, T, false><<<grid, W, lds, st>>>(BOP_STEP_ARGS);                  \
+        }                                                                                             \
+    } while (0)
             if (p.block_threads == 256) BOP_STEP(256);
             else if (p.block_threads == 512) BOP_STEP(512);
             else BOP_STEP(1024);
 #undef BOP_STEP
+#undef BOP_STEP_ARGS
             BOP_LAUNCHED();
             k_reduce<NO><<<bt.count, 64, 0, st>>>(bt, k, K, last, p.n_max, nch, p.chunk_rows, p.block_threads / 64, sizes, tiles,
                                                   lay.tile_stride, part, mu);
@@ -1034,6 +1058,7 @@ int run_lanczos(const bop_plan &p, const int *row_ptr, const double *H_on, const
     const char *tiles = ws + lay.tiles;
     char *xb = ws + lay.x;
     double *part = (double *)(ws + lay.part);
+    const size_t lds_max = (size_t)device_lds_per_block();
     double *lc = (double *)(ws + lay.lc);
     const bool bf = p.dtype == BOP_BF16;
     // breakdown threshold on b^2 relative to b_1^2, above the rounding level of the stored vectors
@@ -1060,14 +1085,24 @@ int run_lanczos(const bop_plan &p, const int *row_ptr, const double *H_on, const
                 else BOP_LSTEP16(1024);
 #undef BOP_LSTEP16
             } else {
+#define BOP_LSTEP_ARGS                                                                                \
+    bt, k, K, last, nch, p.chunk_rows, p.deg_max, p.rows_cap, row_ptr, H_on, (const T *)Hv, sizes,      \
+        tiles, lay.tile_stride, xb, lay.x_stride, part, lc
 #define BOP_LSTEP(W)                                                                                  \
-    k_step<T, NO, W, 1, S><<<grid, W, (size_t)(W / 64) * p.deg_max * NO * NO * sizeof(T), st>>>(          \
-        bt, k, K, last, nch, p.chunk_rows, p.deg_max, p.rows_cap, row_ptr, H_on, (const T *)Hv, sizes,  \
-        tiles, lay.tile_stride, xb, lay.x_stride, part, lc)
+    do {                                                                                              \
+        const size_t lds = h_lds_bytes(p, W, sizeof(T));                                              \
+        if constexpr (sizeof(T) == 8) {                                                               \
+            k_step<T, NO, W, 1, S, true><<<grid, W, 0, st>>>(BOP_LSTEP_ARGS);                         \
+        } else {                                                                                      \
+            if (lds > lds_max) k_step<T, NO, W, 1, S, true><<<grid, W, 0, st>>>(BOP_LSTEP_ARGS);      \
+            else k_step<T, NO, W, 1, S, false><<<grid, W, lds, st>>>(BOP_LSTEP_ARGS);                 \
+        }                                                                                             \
+    } while (0)
                 if (p.block_threads == 256) BOP_LSTEP(256);
                 else if (p.block_threads == 512) BOP_LSTEP(512);
                 else BOP_LSTEP(1024);
 #undef BOP_LSTEP
+#undef BOP_LSTEP_ARGS
             }
             BOP_LAUNCHED();
             k_lreduce<<<bt.count, 64, 0, st>>>(bt, k, K, last, 0, p.n_max, NO, nch, p.chunk_rows, p.block_threads / 64, thr, sizes, tiles,

@@ -150,3 +150,28 @@ def test_moments_reject_fp16_storage(bop):
     with pytest.raises(bop.BopError) as e:
         p.run_moments()
     assert e.value.code == bop.BOP_E_UNSUPPORTED
+
+
+# FP32 step kernels stage each row's H blocks in LDS unless the slice (waves x
+# deg_max blocks) exceeds a workgroup's LDS; then they read them with scalar
+# loads, as FP64 always does.  fcc s,p,d with three shells inside the cutoff
+# (42 neighbours) at 1024 threads needs 16 x 42 x 81 x 4 B = 218 KB, more than
+# any workgroup can hold, so this runs the scalar-load form in FP32.
+def test_fp32_wide_rows_read_h_with_scalar_loads(bop):
+    rng = np.random.default_rng(33)
+    pos, cell = W.cubic_lattice("fcc", 3.5355, 3)
+    spc = W.random_species(108, [54, 54], rng)
+    model = W.spd_alloy_model(r_cut=4.5)
+    wl = W.Workload("fcc_spd_3shell", W.displace(pos, cell, 0.04, rng), cell, spc, model, 6, 200,
+                    np.where(spc == 0, 9.0, 8.0))
+    ref_nl = O.neighbours(wl.pos, wl.cell, model["r_cut"])
+    assert np.diff(ref_nl["row_ptr"]).max() >= 40
+    ref = O.energy_pipeline(wl)
+    wide = {"block_threads": 1024}
+    p, out = _run(bop, wl, "f32", tuning=wide)
+    np.testing.assert_allclose(_np(p.rec["a"]), ref["rec"]["a"], atol=1e-5)
+    np.testing.assert_allclose(_np(p.rec["b"]), ref["rec"]["b"], atol=1e-5)
+    m = bop.EnergyPath(wl.pos, wl.cell, wl.species, model, wl.n_max, wl.n_exp, "f32", tuning=wide)
+    m.run_moments()
+    from test_gpu_parity import _mu_err
+    assert _mu_err(_np(m.mu), O.moments(ref_nl, *O.build_H(model, spc, ref_nl), wl.n_max)) < 1e-5
