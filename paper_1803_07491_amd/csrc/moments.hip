@@ -370,11 +370,30 @@ __global__ void k_x0(Batch bt, int n_max, int B, const int *__restrict__ sizes_,
     }
 }
 
+// Asynchronous copy of n floats from global memory into an LDS slice
+// (global_load_lds: lane i's dword lands at the slice base + 4 i for every
+// 64-float chunk); completion is counted by vmcnt like any vector load.
+__device__ inline void h_to_lds(const float *src, float *dst, int n, int lane)
+{
+    for (int e = 0; e < n; e += 64)
+        if (e + lane < n)
+            __builtin_amdgcn_global_load_lds((const void *)(src + e + lane),
+                                             (__attribute__((address_space(3))) void *)(dst + e), 4, 0, 0);
+}
+
+// Floats of one wave's LDS slice of H blocks (deg_max blocks, whole 64-float
+// chunks so that the copy never writes past it).
+__host__ __device__ inline int h_slice(int deg_max, int nb) { return (deg_max * nb + 63) / 64 * 64; }
+
 // One step (or the final odd H X^K pass) for a batch of tiles.
-// Latency structure: per row, the wave first copies the row's H blocks (one
-// contiguous range of pairs) into its LDS slice with coalesced loads, and
-// issues the X gathers of G neighbour slots before using any of them, so a
-// row costs a few memory round trips instead of one per slot.
+// Latency structure: the H blocks of a wave's next row (one contiguous range
+// of pairs) are copied into its LDS slice asynchronously as soon as the
+// current row's products are done, so they arrive with the next row's first
+// gathers; the X gathers of G neighbour slots are issued before any of them is
+// used, so a row costs a few memory round trips instead of one per slot.  X^k
+// is written with non-temporal stores: it is read only by the next launch,
+// long after it would have left L2, where it would evict the rows being
+// gathered.
 //
 // LANCZOS = 1: the same product for Lanczos level k - 1 (the support of H u_(k-1)
 // is that of X^k).  The buffer read holds r_(k-1) = u_(k-1) / s, the buffer
@@ -418,7 +437,7 @@ k_step(Batch bt, int k, int K, int last, int nch, int chunk_rows, int deg_max, i
     S *Xc = (S *)(xbase + x_stride * (2 * (size_t)t + (k & 1)));
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    T *sH = (T *)s_dyn + (size_t)w * deg_max * NB;          // this wave's H blocks
+    T *sH = (T *)s_dyn + (size_t)w * h_slice(deg_max, NB);  // this wave's H blocks
     constexpr int stride_row = NO * 64;
     double so = 0.0, se = 0.0;
     T ls = T(1), lbeta = T(0);
@@ -437,6 +456,7 @@ k_step(Batch bt, int k, int K, int last, int nch, int chunk_rows, int deg_max, i
         slots_n = lane < deg_max ? lnb[(long)l * deg_max + lane] : 0;
         p0_n = row_ptr[g_n];
         p1_n = row_ptr[g_n + 1];
+        if constexpr (!HS) h_to_lds((const float *)(H + (long)p0_n * NB), (float *)sH, (p1_n - p0_n) * NB, lane);
     }
     for (; l < nrow; l += RS) {
         const int g = g_n, info = info_n, slots_all = slots_n, p0 = p0_n, deg = p1_n - p0_n;
@@ -451,15 +471,14 @@ k_step(Batch bt, int k, int K, int last, int nch, int chunk_rows, int deg_max, i
         const bool has_prev = last || L <= k - 1;
         const int nval = last ? n3 : (k - 1 >= L + 1 ? n3 : (k - 1 == L ? n2 : n1));
         const int slots = (lane < nval) ? slots_all : 0;
-        // the row's H blocks (contiguous pairs p0 .. p0 + deg): staged in LDS
-        // with coalesced loads, or (HS) read with scalar loads straight into
-        // SGPR operands from their wave-uniform addresses.  HS measured 11-34%
-        // faster for FP64 and slower for FP32; FP32 uses it only where the LDS
-        // slice would not fit a workgroup.
+        // the row's H blocks (contiguous pairs p0 .. p0 + deg): in the LDS slice
+        // (copied there after the previous row), or (HS) read with scalar loads
+        // straight into SGPR operands from their wave-uniform addresses.  HS
+        // measured 11-34% faster for FP64 and slower for FP32; FP32 uses it only
+        // where the LDS slice would not fit a workgroup.
         constexpr bool H_SCALAR = HS;
         const T *hsrc = H + (long)p0 * NB;
-        if (!H_SCALAR)
-            for (int e = lane; e < deg * NB; e += 64) sH[e] = hsrc[e];
+        (void)deg;
         const S *xrow = Xp + (long)l * stride_row + lane;
         T acc[NO], xs[NO];
 #pragma unroll
@@ -482,7 +501,7 @@ k_step(Batch bt, int k, int K, int last, int nch, int chunk_rows, int deg_max, i
             }
             if (s0 == 0) {
                 __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_s_waitcnt(0);      // LDS writes of this wave visible to it
+                __builtin_amdgcn_s_waitcnt(0);      // the row's H blocks have reached LDS
                 __builtin_amdgcn_wave_barrier();
             }
 #pragma unroll
@@ -496,7 +515,11 @@ k_step(Batch bt, int k, int K, int last, int nch, int chunk_rows, int deg_max, i
                 }
             }
         }
-        __builtin_amdgcn_wave_barrier();   // all lanes done with sH before the next row overwrites it
+        __builtin_amdgcn_wave_barrier();   // all lanes done with sH before the next row's copy
+        if constexpr (!HS) {
+            if (nval == 0) __builtin_amdgcn_s_waitcnt(0);   // this row's copy (unused) has landed
+            if (l + RS < nrow) h_to_lds((const float *)(H + (long)p0_n * NB), (float *)sH, (p1_n - p0_n) * NB, lane);
+        }
         S *xo = Xc + (long)l * stride_row + lane;
         if (LANCZOS) {
             const bool has_prev2 = L <= k - 2;
@@ -508,7 +531,7 @@ k_step(Batch bt, int k, int K, int last, int nch, int chunk_rows, int deg_max, i
         }
         if (!last) {
 #pragma unroll
-            for (int a = 0; a < NO; ++a) xo[a * 64] = (S)acc[a];
+            for (int a = 0; a < NO; ++a) __builtin_nontemporal_store((S)acc[a], &xo[a * 64]);
         }
 #pragma unroll
         for (int a = 0; a < NO; ++a) {
@@ -759,7 +782,7 @@ k_step_bf16(Batch bt, int k, int K, int last, int nch, int chunk_rows, int deg_m
 // deg_max blocks per wavefront)
 static inline size_t h_lds_bytes(const bop_plan &p, int wgt, size_t elem)
 {
-    return (size_t)(wgt / 64) * p.deg_max * p.n_orb * p.n_orb * elem;
+    return (size_t)(wgt / 64) * h_slice(p.deg_max, p.n_orb * p.n_orb) * elem;
 }
 
 template <int NO>
