@@ -167,6 +167,9 @@ typedef struct bop_tuning {
     int batch_tiles;     /* tiles whose X buffers are live at once; 0 = ~6 GiB worth */
     int chunk_rows;      /* support rows per workgroup and step (the rows are dealt to the
                             workgroups of a tile in wave-sized groups, round robin); 0 = default (64) */
+    int plan_search;     /* support sizes in bop_moments_plan: 0 = automatic, 1 = visited bitmap in
+                            LDS (up to 524,288 atoms), 2 = per-workgroup map in `scratch`; both
+                            give the same plan */
 } bop_tuning;
 
 #define BOP_MAX_NMAX 40

@@ -57,7 +57,7 @@ MAX_NMAX = 40
 
 class Tuning(C.Structure):
     _fields_ = [("tile_atoms", C.c_int), ("block_threads", C.c_int), ("batch_tiles", C.c_int),
-                ("chunk_rows", C.c_int)]
+                ("chunk_rows", C.c_int), ("plan_search", C.c_int)]
 
 
 class Plan(C.Structure):
@@ -284,7 +284,8 @@ def moments_plan(n_atoms, n_orb, n_max, dtype, nl: Neighbours, tuning=None, use_
     t = None
     if tuning:
         t = Tuning(int(tuning.get("tile_atoms", 0)), int(tuning.get("block_threads", 0)),
-                   int(tuning.get("batch_tiles", 0)), int(tuning.get("chunk_rows", 0)))
+                   int(tuning.get("batch_tiles", 0)), int(tuning.get("chunk_rows", 0)),
+                   int(tuning.get("plan_search", 0)))
     _check(lib.bop_moments_plan(n_atoms, n_orb, n_max, DTYPES[dtype], _ptr(nl.row_ptr), _ptr(nl.nbr_j),
                                 _ptr(nl.order) if use_order else None, C.byref(t) if t else None,
                                 _ptr(scratch), sb, C.byref(plan), _stream()))

@@ -245,6 +245,70 @@ k_plan(int n_atoms, int B, int n_tiles, int K, const int *__restrict__ order,
     }
 }
 
+// Plan pass with a visited bitmap in LDS (systems small enough for one bit
+// per atom in a workgroup's LDS).  The layer sizes do not depend on the order
+// in which a layer's atoms are found, so each frontier entry claims its
+// neighbour with one LDS atomic OR and the new atoms are appended in any order
+// (a wave-level ballot and one LDS counter), instead of the ordered claim and
+// compaction the prepare pass needs.
+__global__ void __launch_bounds__(PLAN_T)
+k_plan_bits(int n_atoms, int B, int n_tiles, int K, const int *__restrict__ order,
+            const int *__restrict__ row_ptr, const int *__restrict__ nbr_j, int deg_max,
+            int *hdr, char *scratch, size_t per_wg)
+{
+    extern __shared__ unsigned s_bits[];
+    __shared__ int s_size[MAXK + 2], s_tile[1], s_cnt[1];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int nw = (n_atoms + 31) / 32;
+    for (int i = tid; i < nw; i += PLAN_T) s_bits[i] = 0u;
+    __syncthreads();
+    int *sup = (int *)(scratch + per_wg * blockIdx.x);
+    for (;;) {
+        const int tile = next_tile(&hdr[0], s_tile);
+        if (tile >= n_tiles) break;
+        const int first = tile * B, Bt = min(B, n_atoms - first);
+        if (tid < Bt) {
+            const int g = order ? order[first + tid] : first + tid;
+            sup[tid] = g;
+            atomicOr(&s_bits[g >> 5], 1u << (g & 31));
+        }
+        if (tid == 0) { s_size[0] = Bt; s_cnt[0] = Bt; }
+        __syncthreads();
+        for (int k = 1; k <= K; ++k) {
+            const int begin = (k >= 2) ? s_size[k - 2] : 0, end = s_size[k - 1];
+            const long nent = (long)(end - begin) * deg_max;
+            for (long c0 = 0; c0 < nent; c0 += PLAN_T) {
+                const long e = c0 + tid;
+                int j = -1;
+                bool fresh = false;
+                if (e < nent) {
+                    const int t = begin + (int)(e / deg_max), sl = (int)(e % deg_max);
+                    const int g = sup[t];
+                    const int p0 = row_ptr[g], deg = row_ptr[g + 1] - p0;
+                    if (sl < deg) {
+                        j = nbr_j[p0 + sl];
+                        const unsigned bit = 1u << (j & 31);
+                        fresh = !(atomicOr(&s_bits[j >> 5], bit) & bit);
+                    }
+                }
+                const unsigned long long m = __ballot(fresh);
+                int at = 0;
+                if (lane == 0 && m) at = atomicAdd(&s_cnt[0], (int)__popcll(m));
+                at = __shfl(at, 0);
+                if (fresh) sup[at + __popcll(m & ((1ull << lane) - 1ull))] = j;
+            }
+            __syncthreads();
+            if (tid == 0) s_size[k] = s_cnt[0];
+            __syncthreads();
+        }
+        const int rows = s_size[K];
+        if (tid <= K) atomicMax(&hdr[8 + tid], s_size[tid]);
+        if (tid == 0) atomicMax(&hdr[2], rows);
+        for (int t = tid; t < rows; t += PLAN_T) s_bits[sup[t] >> 5] = 0u;
+        __syncthreads();
+    }
+}
+
 __global__ void k_max_degree(int n, const int *__restrict__ row_ptr, int *hdr)
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1233,7 +1297,15 @@ extern "C" int bop_moments_plan(int n_atoms, int n_orb, int n_max, int dtype, co
     char *base = (char *)scratch + HDR;
     const size_t per = align_up(4ull * n_atoms, 256) * 2;
     const int pwg = map_workgroups(n_atoms, n_tiles > 0 ? n_tiles : 1);
-    long nmap = (long)pwg * (long)(per / 4);
+    // one bit per atom in LDS when that fits a workgroup (two per CU)
+    const size_t bits_bytes = 4ull * ((n_atoms + 31) / 32);
+    const int search = tuning ? tuning->plan_search : 0;
+    BOP_REQUIRE(search >= 0 && search <= 2, BOP_E_ARG, "bop_moments_plan: plan_search must be 0, 1 or 2");
+    const bool fits = bits_bytes <= (size_t)device_lds_per_block() && bits_bytes <= 64 * 1024;
+    BOP_REQUIRE(search != 1 || fits, BOP_E_UNSUPPORTED, "bop_moments_plan: %d atoms too many for the LDS bitmap",
+                n_atoms);
+    const bool bits = search == 1 || (search == 0 && fits);
+    long nmap = bits ? 0 : (long)pwg * (long)(per / 4);
     k_init<<<(unsigned)((nmap + 255) / 256 > 0 ? (nmap + 255) / 256 : 1), 256, 0, stream>>>(hdr, HDR / 4,
                                                                                            (int *)base, nmap);
     BOP_LAUNCHED();
@@ -1249,7 +1321,11 @@ extern "C" int bop_moments_plan(int n_atoms, int n_orb, int n_max, int dtype, co
         BOP_REQUIRE((long)n_atoms * dmax < (1L << 30), BOP_E_UNSUPPORTED,
                     "bop_moments_plan: %d atoms x %d neighbours too large for one plan (split the structure)", n_atoms,
                     dmax);
-        k_plan<<<pwg, PLAN_T, 0, stream>>>(n_atoms, B, n_tiles, K, order, row_ptr, nbr_j, dmax, hdr, base, per);
+        if (bits)
+            k_plan_bits<<<pwg, PLAN_T, bits_bytes, stream>>>(n_atoms, B, n_tiles, K, order, row_ptr, nbr_j, dmax,
+                                                            hdr, base, per);
+        else
+            k_plan<<<pwg, PLAN_T, 0, stream>>>(n_atoms, B, n_tiles, K, order, row_ptr, nbr_j, dmax, hdr, base, per);
         BOP_LAUNCHED();
         BOP_HIP(hipMemcpyAsync(hv, hdr, sizeof hv, hipMemcpyDeviceToHost, stream));
         BOP_HIP(hipStreamSynchronize(stream));

@@ -228,3 +228,19 @@ def test_divergent_expansion_is_flagged(bop, torch_mod):
     ok = bop.EnergyPath(*STRUCTS["bcc_small"][:4], 9, 200, "f64")
     ok.run(6.5 * 128)
     assert not np.any(_np(ok.rec["flags"]) & bop.FLAG_DIVERGENT)
+
+
+# The plan's support sizes come from a visited bitmap in LDS (structures up to
+# 524,288 atoms) or from the per-workgroup maps of the ordered search; both
+# searches must give the same plan, hence the same supports and moments.
+@pytest.mark.parametrize("name", ["bcc_small", "fcc_spd", "bcc_alloy", "bcc_1cell"])
+def test_plan_searches_agree(bop, torch_mod, name):
+    pos, cell, spc, model, n_max = STRUCTS[name]
+    mus, plans = [], []
+    for search in (1, 2):
+        mu, nl, H_on, H_b, plan = _gpu_moments(bop, torch_mod, pos, cell, spc, model, n_max,
+                                               tuning={"plan_search": search})
+        mus.append(_np(mu))
+        plans.append((plan.rows_cap, list(plan.rows_k), plan.deg_max, plan.n_tiles, plan.ws_bytes))
+    assert plans[0] == plans[1]
+    assert np.array_equal(mus[0], mus[1])
