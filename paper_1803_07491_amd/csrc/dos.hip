@@ -234,6 +234,30 @@ __device__ inline double block_sum(double v, double *s_red)
     return t;    // valid in thread 0
 }
 
+// Block sums of N values per thread at once: each wave folds its values with
+// shuffles, one barrier, then thread p < N adds the waves' values in wave
+// order (the same additions, in the same order, as N separate block_sum calls).
+// Result valid in thread p for value p.
+template <int N>
+__device__ inline double block_sum_n(double (&v)[N], double *s_red /* N x (DT / 64) */)
+{
+    constexpr int NW = DT / 64;
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+        for (int o = 32; o > 0; o >>= 1) v[j] += __shfl_xor(v[j], o);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) {
+#pragma unroll
+        for (int j = 0; j < N; ++j) s_red[j * NW + w] = v[j];
+    }
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x < N)
+        for (int q = 0; q < NW; ++q) t += s_red[threadIdx.x * NW + q];
+    __syncthreads();
+    return t;
+}
+
 // Fermi search state: bracket [lo, hi], current trial x, done flag.
 struct FermiState { double lo, hi, done, x; };
 
@@ -307,12 +331,10 @@ k_fermi_tree(int n_rows, int n_exp, const double *__restrict__ gs, const double 
              const double *__restrict__ b_inf, double n_elec, double *__restrict__ part,
              unsigned *__restrict__ counter, FermiState *st)
 {
-    __shared__ double s_inv[1040], s_red[DT / 64];
+    __shared__ double s_inv[1040], s_red[FT_NODES * (DT / 64)], s_tot[FT_NODES];
     __shared__ bool s_last;
     if (st->done != 0.0) return;
     const double lo = st->lo, hi = st->hi;
-    double mid[FT_NODES];
-    tree_points(lo, hi, mid);
     for (int k = threadIdx.x; k <= n_exp + 2; k += blockDim.x) s_inv[k] = k ? 1.0 / k : 0.0;
     __syncthreads();
     const long gt = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -320,18 +342,21 @@ k_fermi_tree(int n_rows, int n_exp, const double *__restrict__ gs, const double 
     double cnt[FT_HALF];
     if (r < n_rows) {
         const double ai = a_inf[r], bi = b_inf[r];
-        double sn[FT_HALF], twoc[FT_HALF], b1[FT_HALF], b2[FT_HALF];
-        const double g0 = gs[r];
+        // only 2 cos(theta) and the two Clenshaw terms per node stay live in
+        // the loop (the midpoints, sin(theta) and the arccos term are formed
+        // before and after it), which keeps the kernel's registers low
+        double twoc[FT_HALF], b1[FT_HALF], b2[FT_HALF];
+        {
+            double mid[FT_NODES];
+            tree_points(lo, hi, mid);
 #pragma unroll
-        for (int j = 0; j < FT_HALF; ++j) {
-            const int p = h * FT_HALF + j < FT_NODES ? h * FT_HALF + j : FT_NODES - 1;
-            double eps = (mid[p] - ai) / (2.0 * bi);
-            const double c = eps < -1.0 ? -1.0 : (eps > 1.0 ? 1.0 : eps);
-            sn[j] = sqrt(fmax(0.0, 1.0 - c * c));
-            cnt[j] = g0 * (1.0 - acos(c) / M_PI);
-            twoc[j] = 2.0 * c;
-            b1[j] = 0.0;
-            b2[j] = 0.0;
+            for (int j = 0; j < FT_HALF; ++j) {
+                const int p = h * FT_HALF + j < FT_NODES ? h * FT_HALF + j : FT_NODES - 1;
+                double eps = (mid[p] - ai) / (2.0 * bi);
+                twoc[j] = 2.0 * (eps < -1.0 ? -1.0 : (eps > 1.0 ? 1.0 : eps));
+                b1[j] = 0.0;
+                b2[j] = 0.0;
+            }
         }
         // sum_k w_k sin(k theta) = sin(theta) sum_k w_k U_(k-1)(cos theta), by
         // Clenshaw's recurrence from the highest term down; w_k = (g_(k-2) - g_k) / k
@@ -350,18 +375,25 @@ k_fermi_tree(int n_rows, int n_exp, const double *__restrict__ gs, const double 
                 b1[j] = bn;
             }
         }
+        const double g0 = gs[r];
 #pragma unroll
-        for (int j = 0; j < FT_HALF; ++j) cnt[j] += sn[j] * b1[j] / M_PI;
+        for (int j = 0; j < FT_HALF; ++j) {
+            const double c = 0.5 * twoc[j];
+            const double sn = sqrt(fmax(0.0, 1.0 - c * c));
+            cnt[j] = g0 * (1.0 - acos(c) / M_PI) + sn * b1[j] / M_PI;
+        }
     } else {
 #pragma unroll
         for (int j = 0; j < FT_HALF; ++j) cnt[j] = 0.0;
     }
+    {
+        double v[FT_NODES];
 #pragma unroll
-    for (int p = 0; p < FT_NODES; ++p) {
-        const double v = (h == p / FT_HALF) ? cnt[p % FT_HALF] : 0.0;
-        double t = block_sum(v, s_red);
-        if (threadIdx.x == 0) part[(size_t)FT_NODES * blockIdx.x + p] = t;
+        for (int p = 0; p < FT_NODES; ++p) v[p] = (h == p / FT_HALF) ? cnt[p % FT_HALF] : 0.0;
+        const double t = block_sum_n<FT_NODES>(v, s_red);
+        if (threadIdx.x < FT_NODES) part[(size_t)FT_NODES * blockIdx.x + threadIdx.x] = t;
     }
+    __syncthreads();
     if (threadIdx.x == 0) {
         __threadfence();
         s_last = atomicAdd(counter, 1u) == gridDim.x - 1;
@@ -369,10 +401,24 @@ k_fermi_tree(int n_rows, int n_exp, const double *__restrict__ gs, const double 
     __syncthreads();
     if (s_last) {
         __threadfence();
-        double tot[FT_NODES];
+        // all nodes' block partials in one pass: thread t takes blocks t, t + DT,
+        // ... in order, then the fixed wave tree
+        double acc[FT_NODES];
 #pragma unroll
-        for (int p = 0; p < FT_NODES; ++p) tot[p] = partials_combine(part, gridDim.x, FT_NODES, p, 0, s_red);
+        for (int p = 0; p < FT_NODES; ++p) acc[p] = 0.0;
+        for (unsigned q = threadIdx.x; q < gridDim.x; q += blockDim.x)
+#pragma unroll
+            for (int p = 0; p < FT_NODES; ++p)
+                acc[p] += __hip_atomic_load(&part[(size_t)q * FT_NODES + p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const double t = block_sum_n<FT_NODES>(acc, s_red);
+        if (threadIdx.x < FT_NODES) s_tot[threadIdx.x] = t;
+        __syncthreads();
         if (threadIdx.x == 0) {
+            double tot[FT_NODES];
+#pragma unroll
+            for (int p = 0; p < FT_NODES; ++p) tot[p] = s_tot[p];
+            double mid[FT_NODES];
+            tree_points(lo, hi, mid);
             double l = lo, hh = hi;
             int node = 1;
             for (int lev = 0; lev < FT_LEVELS; ++lev) {
