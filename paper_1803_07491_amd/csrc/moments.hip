@@ -15,15 +15,20 @@
 //    neighbour slots sorted by the neighbour's layer: at step k the neighbours
 //    whose X^(k-1) is non-zero form a prefix of that list.
 //  * The steps are step-synchronous launches over a batch of tiles; a
-//    wavefront owns a row and all 64 columns.  The row's H blocks are copied
-//    to LDS with coalesced loads; neighbour rows of X^(k-1) are coalesced
-//    vector loads.  Blocks are numbered so that all chunks of a tile run on
-//    one XCD (block b runs on XCD b mod 8) one tile after another, and the
+//    wavefront owns a row and all 64 columns.  The row's H blocks reach the
+//    wave's LDS slice by an asynchronous copy issued after the previous row
+//    (FP32), or are read with scalar loads (FP64); neighbour rows of X^(k-1)
+//    are coalesced vector loads in double-buffered groups; X^k is written with
+//    non-temporal stores.  Blocks are numbered so that all chunks of a tile run
+//    on one XCD (block b runs on XCD b mod 8) one tile after another, and the
 //    rows are dealt to the tile's chunks in wave-sized groups round robin, so
-//    the rows in flight on an XCD form
-//    one window of consecutive rows in layer order.  Their neighbours then sit
-//    in a few nearby patches of adjacent layers, and the ~15-fold reuse of
-//    every gathered row stays in the XCD's L2 instead of going to memory.
+//    the rows in flight on an XCD form one window of consecutive rows in layer
+//    order.  Their neighbours then sit in a few nearby patches of adjacent
+//    layers, and the ~15-fold reuse of every gathered row stays in the XCD's
+//    L2 instead of going to memory.
+//  * The plan pass only needs the layer sizes and finds them with a visited
+//    bitmap in LDS (unordered appends); the prepare pass does the ordered
+//    search above.
 //  * The moment dot products are fused into the step; per-chunk partial sums
 //    (FP64) are reduced in chunk order afterwards, so results are
 //    deterministic for a given plan.
