@@ -123,16 +123,22 @@ int bop_build_neighbours(int n_atoms, const double *pos, const double *cell, dou
  *
  *  H_on   [N][n_orb] FP64: onsite level of the atom's species for the
  *         orbital's l, plus shift[i] (shift may be NULL).
- *  H_bond [P][n_orb][ld] in `dtype` (BOP_F64, BOP_F32 or BOP_BF16; BOP_F16 gives FP32
- *  blocks), ld = n_orb
- *         for FP64/FP32 and the MFMA slot width for BF16 (8 for n_orb = 5, 16 for
- *         n_orb = 9; columns beyond n_orb are zero):
+ *  H_bond in `dtype` (BOP_F64, BOP_F32 or BOP_BF16; BOP_F16 gives FP32 blocks):
+ *         n_orb = 9: [P][9][ld], ld = 9 (FP64/FP32) or 16 (BF16, the MFMA slot
+ *         width; columns beyond n_orb are zero);
+ *         n_orb = 5, BF16: [P][5][8], columns 5..7 zero;
+ *         n_orb = 5, FP64/FP32: [P][BOP_D_PACKED] packed.  A d-d block is
+ *         symmetric (every Slater-Koster d-d matrix is), so only its upper
+ *         triangle is stored: entry (a, b), a <= b, at a*5 - a(a-1)/2 + (b - a),
+ *         and value 15 is zero.  This is the layout bop_moments and
+ *         bop_lanczos read for n_orb = 5 in FP64/FP32.
  *         block p = <i a|H|j b> for pair p = (i -> j), built in the bond frame
  *         (z' along d) and rotated as R^T H^(b) R, where R[a][b] is App. D's
  *         matrix with a = bond-frame orbital, b = global orbital, theta the
  *         polar angle and phi the azimuth of d (taken from direction cosines).
  *         H_bond = NULL updates H_on only (self-consistency steps).
  * ========================================================================= */
+#define BOP_D_PACKED 16     /* values per packed d-d block (15 + one zero) */
 int bop_build_H(const bop_model *model /*[host]*/, int n_atoms, const int *species,
                 const double *shift, const int *row_ptr, const int *nbr_j,
                 const double *nbr_d, long n_pairs, int dtype,

@@ -246,9 +246,13 @@ def build_neighbours(pos, cell, r_cut, capacity=None) -> Neighbours:
     raise RuntimeError("neighbour capacity retry failed")
 
 
+D_PACKED = 16   # values per packed d-d block (BOP_D_PACKED)
+
+
 def build_H(model: dict, species, nl: Neighbours, shift=None, dtype="f64", H_on=None, H_bond=None):
-    """Onsite levels [N, n_orb] (float64) and bond blocks [P, n_orb, n_orb]
-    in ``dtype`` (``bop_build_H``)."""
+    """Onsite levels [N, n_orb] (float64) and bond blocks in ``dtype``
+    (``bop_build_H``): [P, 16] packed symmetric d-d blocks for n_orb = 5 in
+    FP64/FP32, else [P, n_orb, ld]."""
     torch = _torch()
     lib = load()
     _dev(species, torch.int32, "species")
@@ -261,8 +265,9 @@ def build_H(model: dict, species, nl: Neighbours, shift=None, dtype="f64", H_on=
         H_on = torch.empty((n, no), dtype=torch.float64, device=dev)
     if H_bond is None and nl is not None:
         ld = (8 if no <= 8 else 16) if dtype == "bf16" else no
+        shape = (D_PACKED,) if (no == 5 and dtype != "bf16") else (no, ld)
         # at least one row, so the pointer is valid when there are no pairs
-        H_bond = torch.empty((max(nl.n_pairs, 1), no, ld), dtype=tdt, device=dev)[: nl.n_pairs]
+        H_bond = torch.empty((max(nl.n_pairs, 1),) + shape, dtype=tdt, device=dev)[: nl.n_pairs]
     m = model_struct(model)
     if shift is not None:
         _dev(shift, torch.float64, "shift")

@@ -43,6 +43,13 @@ void set_error(const char *fmt, ...);
 
 __host__ __device__ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+// Packed d-d bond block (FP64/FP32): entry (a, b) of the symmetric 5 x 5
+// block, upper triangle row-major; BOP_D_PACKED values per block, the last 0.
+__host__ __device__ constexpr int d_packed_index(int a, int b)
+{
+    return a <= b ? a * 5 - a * (a - 1) / 2 + (b - a) : b * 5 - b * (b - 1) / 2 + (a - b);
+}
+
 // Bytes of scratch an exclusive scan of n ints needs.
 size_t scan_scratch_bytes(long n);
 // out[0..n] = exclusive prefix sum of in[0..n-1] (out[n] = total), int32.

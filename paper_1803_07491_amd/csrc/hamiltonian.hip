@@ -87,6 +87,21 @@ k_bonds_d(bop_model m, int n, long P, const int *__restrict__ species, const int
                     bond_integral(m, pr, BOP_DDD, r) };
     double R[5][5];
     rot_d(ct, st, cp, sp, R);
+    if constexpr (sizeof(T) >= 4) {
+        // FP64/FP32: the symmetric block packed, upper triangle row-major
+        T *out = H + p * BOP_D_PACKED;
+#pragma unroll
+        for (int b = 0; b < 5; ++b)
+#pragma unroll
+            for (int c = b; c < 5; ++c) {
+                double s = 0.0;
+#pragma unroll
+                for (int a = 0; a < 5; ++a) s += R[a][b] * D[a] * R[a][c];
+                out[d_packed_index(b, c)] = to_dtype<T>(s);
+            }
+        out[BOP_D_PACKED - 1] = to_dtype<T>(0.0);
+        return;
+    }
     T *out = H + p * 5 * ld;
 #pragma unroll
     for (int b = 0; b < 5; ++b) {

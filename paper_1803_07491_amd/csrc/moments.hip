@@ -478,7 +478,9 @@ k_step(Batch bt, int k, int K, int last, int nch, int chunk_rows, int deg_max, i
        size_t x_stride, double *__restrict__ part, const double *__restrict__ lc)
 {
     constexpr int NW = WGT / 64;
-    constexpr int NB = NO * NO;
+    // values per H block: d-d blocks are stored packed (symmetric, upper
+    // triangle), s,p,d blocks in full
+    constexpr int NB = NO == 5 ? BOP_D_PACKED : NO * NO;
     // Slots whose gathers are in flight together.  Occupancy decides the step:
     // FP32 takes groups of 2 slots, double-buffered (the next group's gathers
     // are issued before the current one is multiplied), which keeps the d
@@ -580,7 +582,8 @@ k_step(Batch bt, int k, int K, int last, int nch, int chunk_rows, int deg_max, i
 #pragma unroll
                     for (int a = 0; a < NO; ++a)
 #pragma unroll
-                        for (int b = 0; b < NO; ++b) acc[a] = fma(h[a * NO + b], x[u][b], acc[a]);
+                        for (int b = 0; b < NO; ++b)
+                            acc[a] = fma(h[NO == 5 ? d_packed_index(a, b) : a * NO + b], x[u][b], acc[a]);
                 }
             }
         };
@@ -880,7 +883,7 @@ k_step_bf16(Batch bt, int k, int K, int last, int nch, int chunk_rows, int deg_m
 // deg_max blocks per wavefront)
 static inline size_t h_lds_bytes(const bop_plan &p, int wgt, size_t elem)
 {
-    return (size_t)(wgt / 64) * h_slice(p.deg_max, p.n_orb * p.n_orb) * elem;
+    return (size_t)(wgt / 64) * h_slice(p.deg_max, p.n_orb == 5 ? BOP_D_PACKED : p.n_orb * p.n_orb) * elem;
 }
 
 template <int NO>

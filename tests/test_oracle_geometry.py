@@ -161,6 +161,26 @@ def test_dd_blocks_textbook_closed_forms():
         assert abs(np.sum(H * H) - (s * s + 2 * p * p + 2 * d * d)) < 1e-13
 
 
+def test_dd_blocks_are_symmetric():
+    """Every d-d block is a symmetric matrix, H_ij[a][b] = H_ij[b][a] (the
+    bond-frame block is diagonal, and its rotation R^T D R stays symmetric),
+    also for an A-B pair of different species: the premise of storing d-d
+    blocks as their upper triangle."""
+    model = W.canonical_d_model(3.5, onsite_d=(0.0, 0.8))
+    ab = {"dds": (W.FORM_EXP, -1.3, 2.5, 1.7), "ddp": (W.FORM_EXP, 0.7, 2.5, 1.7),
+          "ddd": (W.FORM_EXP, -0.2, 2.5, 1.7)}
+    model["bonds"][(0, 1)] = model["bonds"][(1, 0)] = ab
+    model["bonds"][(1, 1)] = {k: (f, 0.9 * b, r0, q) for k, (f, b, r0, q) in ab.items()}
+    rng = np.random.default_rng(17)
+    pos, cell = W.cubic_lattice("bcc", 2.87, 3)
+    pos = W.displace(pos, cell, 0.08, rng)
+    spc = W.random_species(pos.shape[0], [27, 27], rng)
+    nl = O.neighbours(pos, cell, model["r_cut"])
+    _, H_b = O.build_H(model, spc, nl)
+    assert H_b.shape[1:] == (5, 5) and H_b.shape[0] > 0
+    assert np.max(np.abs(H_b - H_b.transpose(0, 2, 1))) <= 1e-15 * np.max(np.abs(H_b))
+
+
 def test_spd_blocks_textbook_closed_forms_and_hermiticity():
     """s-s, s-p and p-p elements against the Slater-Koster table
     E_ss = V_sss, E_s,x = l V_sps, E_x,x = l^2 V_pps + (1-l^2) V_ppp,
