@@ -450,6 +450,17 @@ __device__ inline void h_to_lds(const float *src, float *dst, int n, int lane)
                                              (__attribute__((address_space(3))) void *)(dst + e), 4, 0, 0);
 }
 
+// The same copy 16 bytes per lane (global_load_lds_dwordx4: lane i's 16 bytes
+// land at the slice base + 16 i for every 256-float chunk); n a multiple of 4,
+// src and dst 16-byte aligned.  One instruction moves 1 KB.
+__device__ inline void h_to_lds16(const float *src, float *dst, int n, int lane)
+{
+    for (int e = 0; e < n; e += 256)
+        if (e + 4 * lane < n)
+            __builtin_amdgcn_global_load_lds((const void *)(src + e + 4 * lane),
+                                             (__attribute__((address_space(3))) void *)(dst + e), 16, 0, 0);
+}
+
 // Floats of one wave's LDS slice of H blocks (deg_max blocks, whole 64-float
 // chunks so that the copy never writes past it).
 __host__ __device__ inline int h_slice(int deg_max, int nb) { return (deg_max * nb + 63) / 64 * 64; }
@@ -520,6 +531,12 @@ k_step(Batch bt, int k, int K, int last, int nch, int chunk_rows, int deg_max, i
         ls = (T)lc[((size_t)t * 4 + 0) * 64 + lane];
         lbeta = (T)lc[((size_t)t * 4 + 1) * 64 + lane];
     }
+    // a row's H blocks into the LDS slice: 16 bytes per lane where every block
+    // is a whole number of 16-byte units (packed FP32 d-d blocks, 64 bytes)
+    auto h_copy = [&](const float *src, float *dst, int n) {
+        if constexpr (sizeof(T) == 4 && (NB * sizeof(T)) % 16 == 0) h_to_lds16(src, dst, n, lane);
+        else h_to_lds(src, dst, n, lane);
+    };
     // the next row's atom, layer word, slot list and pair range are fetched while
     // the current row computes, which takes their dependent loads off the
     // critical path
@@ -531,7 +548,7 @@ k_step(Batch bt, int k, int K, int last, int nch, int chunk_rows, int deg_max, i
         slots_n = lane < deg_max ? lnb[(long)l * deg_max + lane] : 0;
         p0_n = row_ptr[g_n];
         p1_n = row_ptr[g_n + 1];
-        if constexpr (!HS) h_to_lds((const float *)(H + (long)p0_n * NB), (float *)sH, (p1_n - p0_n) * NB, lane);
+        if constexpr (!HS) h_copy((const float *)(H + (long)p0_n * NB), (float *)sH, (p1_n - p0_n) * NB);
     }
     for (; l < nrow; l += RS) {
         const int g = g_n, info = info_n, slots_all = slots_n, p0 = p0_n, deg = p1_n - p0_n;
@@ -619,7 +636,7 @@ k_step(Batch bt, int k, int K, int last, int nch, int chunk_rows, int deg_max, i
         __builtin_amdgcn_wave_barrier();   // all lanes done with sH before the next row's copy
         if constexpr (!HS) {
             if (nval == 0) __builtin_amdgcn_s_waitcnt(0);   // this row's copy (unused) has landed
-            if (l + RS < nrow) h_to_lds((const float *)(H + (long)p0_n * NB), (float *)sH, (p1_n - p0_n) * NB, lane);
+            if (l + RS < nrow) h_copy((const float *)(H + (long)p0_n * NB), (float *)sH, (p1_n - p0_n) * NB);
         }
         S *xo = Xc + (long)l * stride_row + lane;
         if (LANCZOS) {
