@@ -186,6 +186,9 @@ typedef struct bop_plan {
     int deg_max;         /* longest neighbour row */
     int rows_cap;        /* largest tile support (rows of X) */
     int rows_k[BOP_MAX_NMAX / 2 + 1];   /* largest |support of X^k| per k */
+    int search;          /* support search used by the plan and by bop_moments_prepare:
+                            1 = bitmaps in LDS (rows of a layer in ascending atom index),
+                            2 = per-workgroup map (rows in order of discovery) */
     size_t ws_bytes;     /* workspace bop_moments_prepare / bop_moments need */
 } bop_plan;
 

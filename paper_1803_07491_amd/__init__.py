@@ -65,7 +65,7 @@ class Plan(C.Structure):
                 ("tile_atoms", C.c_int), ("n_tiles", C.c_int), ("block_threads", C.c_int),
                 ("batch_tiles", C.c_int), ("chunk_rows", C.c_int), ("deg_max", C.c_int),
                 ("rows_cap", C.c_int), ("rows_k", C.c_int * (MAX_NMAX // 2 + 1)),
-                ("ws_bytes", C.c_size_t)]
+                ("search", C.c_int), ("ws_bytes", C.c_size_t)]
 
 
 P = C.c_void_p

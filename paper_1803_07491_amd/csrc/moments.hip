@@ -169,6 +169,112 @@ __device__ int bfs_tile(int tile, int B, int n_atoms, int K, const int *__restri
     return s_size[K];
 }
 
+// rows with at most this many neighbours classify their slots in one sweep
+constexpr int PREP_REG = 24;
+
+// exclusive prefix of v over the workgroup (thread order); writes the total
+template <int WGT>
+__device__ inline int wg_scan_excl(int v, int *s_wave, int &total)
+{
+    constexpr int NW = WGT / 64;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int inc = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int u = __shfl_up(inc, o);
+        if (lane >= o) inc += u;
+    }
+    if (lane == 63) s_wave[w] = inc;
+    __syncthreads();
+    int off = 0, tot = 0;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) {
+        const int c = s_wave[q];
+        off += (q < w) ? c : 0;
+        tot += c;
+    }
+    __syncthreads();
+    total = tot;
+    return off + inc - v;
+}
+
+// The same search with two bitmaps in LDS (one bit per atom): visited atoms,
+// and the atoms found for the current layer.  Each frontier (row, slot) sets
+// its neighbour's bit in the layer bitmap unless visited; the layer is then
+// listed in ascending atom index by a scan of that bitmap, so the row order
+// does not depend on scheduling.  g2l gets the local rows as in bfs_tile.
+// Both bitmaps are all zero on entry and on return.
+template <int WGT>
+__device__ int bfs_tile_bits(int tile, int B, int n_atoms, int K, const int *__restrict__ order,
+                             const int *__restrict__ row_ptr, const int *__restrict__ nbr_j, int deg_max,
+                             int *g2l, int *sup, int rows_cap, int *s_size, int *s_wave, unsigned *s_vis,
+                             unsigned *s_new, int nw)
+{
+    const int tid = threadIdx.x;
+    const int first = tile * B;
+    const int Bt = min(B, n_atoms - first);
+    if (tid < Bt && tid < rows_cap) {
+        const int g = order ? order[first + tid] : first + tid;
+        sup[tid] = g;
+        if (Bt <= rows_cap) {
+            wg_store(&g2l[g], tid);
+            atomicOr(&s_vis[g >> 5], 1u << (g & 31));
+        }
+    }
+    if (tid == 0) s_size[0] = Bt;
+    __syncthreads();
+    if (Bt > rows_cap) return -1;
+    const int per = (nw + WGT - 1) / WGT;
+    const int w0 = min(tid * per, nw), w1 = min(w0 + per, nw);
+    for (int k = 1; k <= K; ++k) {
+        const int begin = (k >= 2) ? s_size[k - 2] : 0, end = s_size[k - 1];
+        const long nent = (long)(end - begin) * deg_max;
+        for (long e = tid; e < nent; e += WGT) {
+            const int t = begin + (int)(e / deg_max), sl = (int)(e % deg_max);
+            const int g = sup[t];
+            const int p0 = row_ptr[g], deg = row_ptr[g + 1] - p0;
+            if (sl < deg) {
+                const int j = nbr_j[p0 + sl];
+                const unsigned bit = 1u << (j & 31);
+                if (!(s_vis[j >> 5] & bit)) atomicOr(&s_new[j >> 5], bit);
+            }
+        }
+        __syncthreads();
+        int cnt = 0;
+        for (int w = w0; w < w1; ++w) cnt += __popc(s_new[w]);
+        int tot;
+        int idx = end + wg_scan_excl<WGT>(cnt, s_wave, tot);
+        const bool over = end + tot > rows_cap;
+        for (int w = w0; w < w1; ++w) {
+            unsigned m = s_new[w];
+            if (!m) continue;
+            s_new[w] = 0u;
+            s_vis[w] |= m;
+            if (over) continue;
+            while (m) {
+                const int j = w * 32 + (__ffs(m) - 1);
+                m &= m - 1u;
+                sup[idx] = j;
+                wg_store(&g2l[j], idx);
+                ++idx;
+            }
+        }
+        __syncthreads();
+        if (over) {
+            for (int w = tid; w < nw; w += WGT) s_vis[w] = 0u;
+            for (int t = tid; t < end; t += WGT) wg_store(&g2l[sup[t]], UNSEEN);
+            __syncthreads();
+            return -1;
+        }
+        if (tid == 0) s_size[k] = end + tot;
+        __syncthreads();
+    }
+    const int rows = s_size[K];
+    for (int t = tid; t < rows; t += WGT) s_vis[sup[t] >> 5] = 0u;
+    __syncthreads();
+    return rows;
+}
+
 template <int WGT>
 __device__ inline void reset_map(int *g2l, const int *sup, int rows)
 {
@@ -332,12 +438,19 @@ __global__ void k_init(int *hdr, int n_hdr, int *maps, long n_map)
 // ---------------------------------------------------------------------------
 // prepare pass: supports, layers and layer-sorted neighbour slots of every tile
 // ---------------------------------------------------------------------------
+template <bool BITS>
 __global__ void __launch_bounds__(PLAN_T)
 k_prepare(int n_atoms, int B, int n_tiles, int K, const int *__restrict__ order,
           const int *__restrict__ row_ptr, const int *__restrict__ nbr_j, int deg_max, int rows_cap,
           int *hdr, char *ws, Layout lay, size_t map_stride)
 {
     __shared__ int s_size[MAXK + 2], s_wave[PLAN_T / 64], s_flag[1], s_tile[1];
+    extern __shared__ unsigned s_bits2[];        // BITS: visited and layer bitmaps
+    const int nw = (n_atoms + 31) / 32;
+    if constexpr (BITS) {
+        for (int i = threadIdx.x; i < 2 * nw; i += PLAN_T) s_bits2[i] = 0u;
+        __syncthreads();
+    }
     int *g2l = (int *)(ws + lay.x + map_stride * blockIdx.x);
     int *sizes = (int *)(ws + lay.sizes);
     for (;;) {
@@ -347,8 +460,10 @@ k_prepare(int n_atoms, int B, int n_tiles, int K, const int *__restrict__ order,
         int *sup = (int *)tb;
         int *rinfo = sup + rows_cap;
         int *lnb = rinfo + rows_cap;
-        const int rows = bfs_tile<PLAN_T>(tile, B, n_atoms, K, order, row_ptr, nbr_j, deg_max, g2l, sup,
-                                          rows_cap, s_size, s_wave, s_flag);
+        const int rows = BITS ? bfs_tile_bits<PLAN_T>(tile, B, n_atoms, K, order, row_ptr, nbr_j, deg_max, g2l,
+                                                      sup, rows_cap, s_size, s_wave, s_bits2, s_bits2 + nw, nw)
+                              : bfs_tile<PLAN_T>(tile, B, n_atoms, K, order, row_ptr, nbr_j, deg_max, g2l, sup,
+                                                 rows_cap, s_size, s_wave, s_flag);
         if (rows < 0) {
             // support larger than planned: keep the seeds so that their moments
             // can be marked NaN, and raise the error flag
@@ -374,6 +489,29 @@ k_prepare(int n_atoms, int B, int n_tiles, int K, const int *__restrict__ order,
             const int p0 = row_ptr[g], deg = row_ptr[g + 1] - p0;
             int *dst = lnb + (long)l * deg_max;
             int cnt[3] = {0, 0, 0};
+            if (deg <= PREP_REG) {
+                // one sweep: all slots' local rows in registers, then count and place
+                int lj[PREP_REG];
+#pragma unroll
+                for (int u = 0; u < PREP_REG; ++u) lj[u] = (u < deg) ? nbr_j[p0 + u] : -1;
+#pragma unroll
+                for (int u = 0; u < PREP_REG; ++u) lj[u] = lj[u] >= 0 ? wg_load(&g2l[lj[u]]) : UNSEEN;
+                int cls[PREP_REG];
+#pragma unroll
+                for (int u = 0; u < PREP_REG; ++u) {
+                    cls[u] = (lj[u] < lo) ? 0 : (lj[u] < endL ? 1 : (lj[u] < endL1 ? 2 : 3));
+                    cnt[0] += cls[u] == 0;
+                    cnt[1] += cls[u] == 1;
+                    cnt[2] += cls[u] == 2;
+                }
+                int o[3] = {0, cnt[0], cnt[0] + cnt[1]};
+#pragma unroll
+                for (int u = 0; u < PREP_REG; ++u) {
+                    if (cls[u] == 0) dst[o[0]++] = (lj[u] << 8) | u;
+                    else if (cls[u] == 1) dst[o[1]++] = (lj[u] << 8) | u;
+                    else if (cls[u] == 2) dst[o[2]++] = (lj[u] << 8) | u;
+                }
+            } else
             for (int pass = 0; pass < 2; ++pass) {
                 int o[3] = {0, cnt[0], cnt[0] + cnt[1]};
                 for (int s0 = 0; s0 < deg; s0 += 8) {
@@ -1367,6 +1505,7 @@ extern "C" int bop_moments_plan(int n_atoms, int n_orb, int n_max, int dtype, co
     plan->deg_max = hv[3] > 0 ? hv[3] : 1;
     plan->rows_cap = hv[2] > 0 ? hv[2] : 1;
     for (int k = 0; k <= K; ++k) plan->rows_k[k] = hv[8 + k];
+    plan->search = bits ? 1 : 2;
     BOP_REQUIRE(plan->rows_cap < (1 << 23), BOP_E_UNSUPPORTED, "bop_moments_plan: tile support too large");
     const size_t x_tile = 2 * align_up(x_row_bytes(dtype, n_orb) * plan->rows_cap, 256);
     long bt = (tuning && tuning->batch_tiles > 0) ? tuning->batch_tiles : (long)((6ull << 30) / x_tile);
@@ -1395,8 +1534,17 @@ extern "C" int bop_moments_prepare(const bop_plan *plan, const int *row_ptr, con
     long nmap = (long)pwg * (long)(map_stride / 4);
     k_init<<<(unsigned)((nmap + 255) / 256), 256, 0, stream>>>(hdr, 8, (int *)(w + lay.x), nmap);
     BOP_LAUNCHED();
-    k_prepare<<<pwg, PLAN_T, 0, stream>>>(n, plan->tile_atoms, plan->n_tiles, plan->n_max / 2, order, row_ptr,
-                                           nbr_j, plan->deg_max, plan->rows_cap, hdr, w, lay, map_stride);
+    // the ordered search with two LDS bitmaps where they fit a workgroup
+    const size_t bits2 = 2 * 4ull * ((n + 31) / 32);
+    const bool bits = plan->search == 1 && bits2 <= (size_t)device_lds_per_block() && bits2 <= 128 * 1024;
+    if (bits)
+        k_prepare<true><<<pwg, PLAN_T, bits2, stream>>>(n, plan->tile_atoms, plan->n_tiles, plan->n_max / 2, order,
+                                                        row_ptr, nbr_j, plan->deg_max, plan->rows_cap, hdr, w, lay,
+                                                        map_stride);
+    else
+        k_prepare<false><<<pwg, PLAN_T, 0, stream>>>(n, plan->tile_atoms, plan->n_tiles, plan->n_max / 2, order,
+                                                     row_ptr, nbr_j, plan->deg_max, plan->rows_cap, hdr, w, lay,
+                                                     map_stride);
     BOP_LAUNCHED();
     return BOP_OK;
 }
