@@ -258,8 +258,8 @@ __device__ inline double block_sum_n(double (&v)[N], double *s_red /* N x (DT / 
     return t;
 }
 
-// Fermi search state: bracket [lo, hi], current trial x, done flag.
-struct FermiState { double lo, hi, done, x; };
+// Fermi search state: bracket [lo, hi], done flag, halvings taken so far.
+struct FermiState { double lo, hi, done, halvings; };
 
 __global__ void __launch_bounds__(DT)
 k_bracket(int n_rows, const double *__restrict__ a_inf, const double *__restrict__ b_inf,
@@ -289,7 +289,7 @@ k_bracket(int n_rows, const double *__restrict__ a_inf, const double *__restrict
             st->lo = L;
             st->hi = H;
             st->done = 0.0;
-            st->x = 0.5 * (L + H);
+            st->halvings = 0.0;
             *counter = 0;
         }
     }
@@ -304,6 +304,8 @@ k_bracket(int n_rows, const double *__restrict__ a_inf, const double *__restrict
 // The decisions, and hence the root found when the count is not monotone,
 // are those of plain bisection.
 constexpr int FT_LEVELS = 4, FT_NODES = (1 << FT_LEVELS) - 1;
+constexpr int FT_MAX_HALVINGS = 64;                           // as many as plain bisection takes at most
+constexpr int FT_PASSES = (FT_MAX_HALVINGS + FT_LEVELS - 1) / FT_LEVELS;
 
 __device__ inline void tree_points(double lo, double hi, double *mid)
 {
@@ -421,14 +423,17 @@ k_fermi_tree(int n_rows, int n_exp, const double *__restrict__ gs, const double 
             tree_points(lo, hi, mid);
             double l = lo, hh = hi;
             int node = 1;
+            double nh = st->halvings;
             for (int lev = 0; lev < FT_LEVELS; ++lev) {
                 const double m = mid[node - 1];
-                if (m <= l || m >= hh) { st->done = 1.0; break; }
+                if (nh >= FT_MAX_HALVINGS || m <= l || m >= hh) { st->done = 1.0; break; }
                 if (2.0 * tot[node - 1] < n_elec) { l = m; node = 2 * node + 1; }
                 else { hh = m; node = 2 * node; }
+                nh += 1.0;
             }
             st->lo = l;
             st->hi = hh;
+            st->halvings = nh;
             *counter = 0;
         }
     }
@@ -587,7 +592,7 @@ extern "C" int bop_energy(int n_atoms, int no, int n_max, int n_exp, const doubl
     if (ef_mode == 0) {
         k_bracket<<<nblk, DT, 0, stream>>>((int)R, a_inf, b_inf, w.part, w.counter, w.st);
         BOP_LAUNCHED();
-        for (int it = 0; it < 64 / FT_LEVELS; ++it)
+        for (int it = 0; it < FT_PASSES; ++it)
             k_fermi_tree<<<(unsigned)((2 * R + DT - 1) / DT), DT, 0, stream>>>((int)R, n_exp, w.gs, a_inf, b_inf, n_elec,
                                                                             w.part, w.counter, w.st);
         BOP_LAUNCHED();
