@@ -110,6 +110,97 @@ terminator:
     flags[r] = fl;
 }
 
+// The same recursion with its arrays in registers, for moments up to NM: the
+// loops over the levels and orbital indices are unrolled with compile-time
+// bounds, so no array needs indexing at run time.  The additions are the
+// generic kernel's, in the same order.
+template <int NM>
+__global__ void __launch_bounds__(DT)
+k_recursion_reg(int n_rows, int n_max, const double *__restrict__ mu, int bw_mode, double a_glob,
+                double b_glob, double *__restrict__ a, double *__restrict__ b, double *__restrict__ a_inf,
+                double *__restrict__ b_inf, int *__restrict__ flags)
+{
+    constexpr int NA = (NM - 1) / 2 + 1;       // levels of a
+    constexpr int NB = NM / 2;                  // levels of b
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n_rows) return;
+    const int na = n_a_of(n_max), nb = n_b_of(n_max);
+    double *ar = a + (long)r * na, *br = b + (long)r * (nb + 1);
+    int fl = 0;
+    double m[NM + 1];
+    const double *mr = mu + (long)r * (n_max + 1);
+    const double m0 = mr[0];
+#pragma unroll
+    for (int t = 0; t <= NM; ++t) {
+        m[t] = (t <= n_max) ? mr[t] / m0 : 0.0;
+        if (t <= n_max && !isfinite(m[t])) fl |= BOP_FLAG_NONFINITE;
+    }
+    double av[NA], bv[NB + 2];
+    double cp[NB + 2], cc[NB + 2], d[NB + 2];
+#pragma unroll
+    for (int j = 0; j < NB + 2; ++j) { cp[j] = 0.0; cc[j] = 0.0; d[j] = 0.0; bv[j] = 0.0; }
+    cc[0] = 1.0;
+    double bn = 0.0;
+    const double var = (n_max >= 2) ? m[2] - m[1] * m[1] : 0.0;
+    bool broke = false, done = false;
+#pragma unroll
+    for (int n = 0; n < NA; ++n) {
+        av[n] = 0.0;
+        if (n >= na || done) continue;
+        if (broke) { av[n] = av[n > 0 ? n - 1 : 0]; continue; }
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j <= n; ++j)
+#pragma unroll
+            for (int l = 0; l <= n; ++l) s += cc[j] * cc[l] * m[j + l + 1];
+        av[n] = s;
+        if (n + 1 > nb) { done = true; continue; }
+#pragma unroll
+        for (int j = 0; j <= n + 1; ++j) d[j] = (j > 0 ? cc[j - 1] : 0.0) - s * cc[j] - bn * cp[j];
+        double b2 = 0.0;
+#pragma unroll
+        for (int j = 0; j <= n + 1; ++j)
+#pragma unroll
+            for (int l = 0; l <= n + 1; ++l) b2 += d[j] * d[l] * m[j + l];
+        if (!(b2 > 1e-14 * var)) {
+            fl |= BOP_FLAG_BREAKDOWN | ((n + 1) << 8);
+            broke = true;
+            continue;
+        }
+        const double bb = sqrt(b2);
+        bv[n + 1] = bb;
+#pragma unroll
+        for (int j = 0; j <= n + 1; ++j) { cp[j] = cc[j]; cc[j] = d[j] / bb; }
+        bn = bb;
+    }
+#pragma unroll
+    for (int n = 0; n < NA; ++n)
+        if (n < na) ar[n] = av[n];
+#pragma unroll
+    for (int n = 0; n <= NB; ++n)
+        if (n <= nb) br[n] = bv[n];
+    double ai, bi;
+    if (bw_mode == 1) { ai = a_glob; bi = b_glob; }
+    else {
+        double lo = 0.0, hi = 0.0;
+#pragma unroll
+        for (int n = 0; n < NA; ++n) {
+            if (n >= na) continue;
+            const double bl = (n >= 1 && n <= nb) ? bv[n] : 0.0;
+            const double bh = (n + 1 <= nb) ? bv[n + 1] : 0.0;
+            const double e0 = av[n] - bl - bh, e1 = av[n] + bl + bh;
+            if (n == 0 || e0 < lo) lo = e0;
+            if (n == 0 || e1 > hi) hi = e1;
+        }
+        ai = 0.5 * (hi + lo);
+        bi = 0.25 * (hi - lo);
+    }
+    if (!(bi >= 1e-6)) { bi = 1e-6; fl |= BOP_FLAG_NARROW; }
+    a_inf[r] = ai;
+    b_inf[r] = bi;
+    flags[r] = fl;
+}
+
 // ---------------------------------------------------------------------------
 // expansion coefficients g_m sigma_m, m-major
 // ---------------------------------------------------------------------------
@@ -554,6 +645,10 @@ extern "C" int bop_recursion(int n_rows, int n_max, const double *mu, int bw_mod
     BOP_REQUIRE(bw_mode == 0 || bw_mode == 1, BOP_E_ARG, "bop_recursion: bw_mode must be 0 or 1");
     if (n_rows == 0) return BOP_OK;
     BOP_REQUIRE(a && b && a_inf && b_inf && flags, BOP_E_ARG, "bop_recursion: NULL array");
+    if (mu && n_max <= 20)
+        k_recursion_reg<20><<<(n_rows + DT - 1) / DT, DT, 0, stream>>>(n_rows, n_max, mu, bw_mode, a_glob, b_glob,
+                                                                       a, b, a_inf, b_inf, flags);
+    else
     k_recursion<<<(n_rows + DT - 1) / DT, DT, 0, stream>>>(n_rows, n_max, mu, bw_mode, a_glob, b_glob, a, b,
                                                            a_inf, b_inf, flags);
     BOP_LAUNCHED();

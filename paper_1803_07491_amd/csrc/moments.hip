@@ -314,6 +314,29 @@ struct Layout {
     size_t bytes;
 };
 
+// Where each step's chunk partials start (doubles, for batch_tiles tiles) and
+// how many chunks the step has.
+struct StepParts {
+    long off[MAXK + 2];
+    int nch[MAXK + 2];
+    size_t total_chunks;
+};
+
+__host__ __device__ inline StepParts step_parts(const bop_plan &p)
+{
+    StepParts sp{};
+    const int K = p.n_max / 2, steps = K + (p.n_max & 1);
+    size_t tot = 0;
+    for (int k = 1; k <= steps && k <= MAXK + 1; ++k) {
+        const int rows_k = k > K ? p.rows_k[K] : p.rows_k[k];
+        sp.nch[k] = (rows_k + p.chunk_rows - 1) / p.chunk_rows;
+        sp.off[k] = (long)(tot * 2 * 64 * (size_t)p.batch_tiles);
+        tot += (size_t)sp.nch[k];
+    }
+    sp.total_chunks = tot;
+    return sp;
+}
+
 __host__ __device__ inline Layout make_layout(const bop_plan &p, int n_prep_wg)
 {
     Layout L;
@@ -326,8 +349,11 @@ __host__ __device__ inline Layout make_layout(const bop_plan &p, int n_prep_wg)
     size_t xb = L.x_stride * 2 * p.batch_tiles;
     size_t maps = (size_t)n_prep_wg * ((4ull * p.n_atoms + 255) / 256 * 256);
     L.x = take(xb > maps ? xb : maps);
-    int nch = (p.rows_cap + p.chunk_rows - 1) / p.chunk_rows;
-    L.part = take(8ull * 2 * 64 * (size_t)nch * p.batch_tiles);
+    // chunk partials: one step's worth for the Lanczos form, every step's for
+    // the moment form (reduced after the batch's last step)
+    const size_t nch = (p.rows_cap + p.chunk_rows - 1) / p.chunk_rows;
+    const size_t nch_all = step_parts(p).total_chunks;
+    L.part = take(8ull * 2 * 64 * (nch > nch_all ? nch : nch_all) * p.batch_tiles);
     L.lc = take(8ull * 4 * 64 * p.batch_tiles);
     L.bytes = o;
     return L;
@@ -808,14 +834,18 @@ k_step(Batch bt, int k, int K, int last, int nch, int chunk_rows, int deg_max, i
     }
 }
 
-// mu[.][2k-1], mu[.][2k] (or mu[.][2K+1]) from the chunk partials, in chunk order
+// mu[.][2k-1], mu[.][2k] (or mu[.][2K+1]) from the chunk partials, in chunk
+// order; one launch after a batch's last step, block (tile, step k - 1)
 template <int NO>
-__global__ void k_reduce(Batch bt, int k, int K, int last, int n_max, int nch, int chunk_rows, int nw,
+__global__ void k_reduce(Batch bt, int K, int n_max, StepParts sp, int chunk_rows, int nw,
                          const int *__restrict__ sizes_, const char *tiles_base, size_t tile_stride,
-                         const double *__restrict__ part, double *__restrict__ mu)
+                         const double *__restrict__ part_all, double *__restrict__ mu)
 {
     const int t = blockIdx.x;
-    if (t >= bt.count) return;
+    const int k = blockIdx.y + 1, last = k > K;
+    const int nch = sp.nch[k];
+    if (t >= bt.count || nch <= 0) return;
+    const double *part = part_all + sp.off[k];
     const int tile = bt.first + t;
     const int *sizes = sizes_ + tile * (MAXK + 2);
     if (sizes[0] < 0) return;
@@ -1052,6 +1082,7 @@ int run_moments_bf16(const bop_plan &p, const int *row_ptr, const double *H_on, 
     const char *tiles = ws + lay.tiles;
     char *xb = ws + lay.x;
     double *part = (double *)(ws + lay.part);
+    const StepParts sp = step_parts(p);
     for (int first = 0; first < p.n_tiles; first += p.batch_tiles) {
         Batch bt{first, min(p.batch_tiles, p.n_tiles - first)};
         k_x0_bf16<NO><<<bt.count, 256, 0, st>>>(bt, p.n_max, sizes, tiles, lay.tile_stride, xb, lay.x_stride, mu);
@@ -1066,14 +1097,16 @@ int run_moments_bf16(const bop_plan &p, const int *row_ptr, const double *H_on, 
 #define BOP_STEP16(W)                                                                                    \
     k_step_bf16<NO, W, 0><<<grid, W, 0, st>>>(bt, k, K, last, nch, p.chunk_rows, p.deg_max, p.rows_cap,       \
                                               row_ptr, H_on, H, sizes, tiles, lay.tile_stride, xb, lay.x_stride, \
-                                              part, nullptr)
+                                              part + sp.off[k], nullptr)
             if (p.block_threads == 256) BOP_STEP16(256);
             else if (p.block_threads == 512) BOP_STEP16(512);
             else BOP_STEP16(1024);
 #undef BOP_STEP16
             BOP_LAUNCHED();
-            k_reduce<NO><<<bt.count, 64, 0, st>>>(bt, k, K, last, p.n_max, nch, p.chunk_rows, p.block_threads / 64, sizes, tiles,
-                                                  lay.tile_stride, part, mu);
+        }
+        if (steps > 0) {
+            k_reduce<NO><<<dim3((unsigned)bt.count, (unsigned)steps), 64, 0, st>>>(
+                bt, K, p.n_max, sp, p.chunk_rows, p.block_threads / 64, sizes, tiles, lay.tile_stride, part, mu);
             BOP_LAUNCHED();
         }
     }
@@ -1091,6 +1124,7 @@ int run_moments(const bop_plan &p, const int *row_ptr, const double *H_on, const
     const char *tiles = ws + lay.tiles;
     char *xb = ws + lay.x;
     double *part = (double *)(ws + lay.part);
+    const StepParts sp = step_parts(p);
     const size_t lds_max = (size_t)device_lds_per_block();
     for (int first = 0; first < p.n_tiles; first += p.batch_tiles) {
         Batch bt{first, min(p.batch_tiles, p.n_tiles - first)};
@@ -1106,7 +1140,7 @@ int run_moments(const bop_plan &p, const int *row_ptr, const double *H_on, const
             dim3 grid((unsigned)(nb8 * nch * 8));
 #define BOP_STEP_ARGS                                                                                 \
     bt, k, K, last, nch, p.chunk_rows, p.deg_max, p.rows_cap, row_ptr, H_on, H, sizes, tiles,           \
-        lay.tile_stride, xb, lay.x_stride, part, nullptr
+        lay.tile_stride, xb, lay.x_stride, part + sp.off[k], nullptr
 #define BOP_STEP(W)                                                                                   \
     do {                                                                                              \
         const size_t lds = h_lds_bytes(p, W, sizeof(T));                                              \
@@ -1123,8 +1157,10 @@ int run_moments(const bop_plan &p, const int *row_ptr, const double *H_on, const
 #undef BOP_STEP
 #undef BOP_STEP_ARGS
             BOP_LAUNCHED();
-            k_reduce<NO><<<bt.count, 64, 0, st>>>(bt, k, K, last, p.n_max, nch, p.chunk_rows, p.block_threads / 64, sizes, tiles,
-                                                  lay.tile_stride, part, mu);
+        }
+        if (steps > 0) {
+            k_reduce<NO><<<dim3((unsigned)bt.count, (unsigned)steps), 64, 0, st>>>(
+                bt, K, p.n_max, sp, p.chunk_rows, p.block_threads / 64, sizes, tiles, lay.tile_stride, part, mu);
             BOP_LAUNCHED();
         }
     }
