@@ -73,3 +73,27 @@ def test_neighbour_capacity_retry(bop):
     assert small.n_pairs == full.n_pairs
     assert torch.equal(small.nbr_j, full.nbr_j)
     assert torch.equal(small.row_ptr, full.row_ptr)
+
+
+def test_recursion_register_and_generic_kernels(bop):
+    """bop_recursion keeps its arrays in registers up to n_max = 20 and
+    indexes them at run time above.  Level n uses only the moments up to
+    2n + 1, so the coefficients that n_max = 20 and n_max = 21 share are the
+    same arithmetic in the two kernels and must agree bit for bit; both are
+    compared with the oracle's recursion on the same (oracle) moments."""
+    import torch
+    wl = W.bcc_small()
+    nl = O.neighbours(wl.pos, wl.cell, wl.model["r_cut"])
+    H_on, H_b = O.build_H(wl.model, wl.species, nl)
+    mu21 = O.moments(nl, H_on, H_b, 21).reshape(-1, 22)
+    got = {}
+    for n_max in (20, 21):
+        mu = np.ascontiguousarray(mu21[:, :n_max + 1])
+        got[n_max] = {k: _np(v) for k, v in bop.recursion(torch.as_tensor(mu, device="cuda"), n_max).items()}
+        ref = O.recursion(mu, n_max)
+        for k in ("a", "b"):
+            err = np.max(np.abs(got[n_max][k] - ref[k]))
+            assert err < 1e-9, (n_max, k, err)
+        assert np.array_equal(got[n_max]["flags"] & 0xff, ref["flags"] & 0xff)
+    assert np.array_equal(got[21]["a"][:, :10], got[20]["a"])
+    assert np.array_equal(got[21]["b"][:, :11], got[20]["b"])
