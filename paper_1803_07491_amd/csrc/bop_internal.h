@@ -58,7 +58,7 @@ int exclusive_scan(const int *in, int *out, long n, void *scratch, hipStream_t s
 
 // Reduction scratch inside a bop_energy workspace (partials for at least
 // ceil(n_rows/256)+1 blocks, two doubles each, and a zeroed counter).
-void energy_ws_scratch(void *ws, long n_rows, int n_exp, double **part, unsigned **counter);
+double *energy_ws_scratch(void *ws, long n_rows, int n_exp);   // block-partial scratch
 
 // Number of compute units of the current device (cached per device).
 int device_cus();

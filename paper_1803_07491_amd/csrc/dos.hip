@@ -18,8 +18,9 @@
 //
 // Expansion coefficients are stored m-major ([n_exp+1][rows]) so that the
 // per-orbital sums read coalesced columns.  Global sums (electron count,
-// bracket, total energy) use per-block partials reduced in a fixed order by
-// the last block, so results are deterministic.
+// bracket, total energy) use per-block partials reduced in a fixed order by a
+// one-block launch that follows, so results are deterministic and no block
+// needs a device-scope fence (which would write back L2).
 #include "bop_internal.h"
 
 #include <cmath>
@@ -354,10 +355,9 @@ struct FermiState { double lo, hi, done, halvings; };
 
 __global__ void __launch_bounds__(DT)
 k_bracket(int n_rows, const double *__restrict__ a_inf, const double *__restrict__ b_inf,
-          double *__restrict__ part, unsigned *__restrict__ counter, FermiState *st)
+          double *__restrict__ part)
 {
     __shared__ double s_lo[DT / 64], s_hi[DT / 64];
-    __shared__ bool s_last;
     int r = blockIdx.x * blockDim.x + threadIdx.x;
     double lo = INFINITY, hi = -INFINITY;
     if (r < n_rows) { lo = a_inf[r] - 2.0 * b_inf[r]; hi = a_inf[r] + 2.0 * b_inf[r]; }
@@ -368,21 +368,23 @@ k_bracket(int n_rows, const double *__restrict__ a_inf, const double *__restrict
         for (int q = 0; q < DT / 64; ++q) { lo = fmin(lo, s_lo[q]); hi = fmax(hi, s_hi[q]); }
         part[2 * blockIdx.x] = lo;
         part[2 * blockIdx.x + 1] = hi;
-        __threadfence();
-        s_last = atomicAdd(counter, 1u) == gridDim.x - 1;
     }
-    __syncthreads();
-    if (s_last) {
-        __threadfence();
-        const double L = partials_combine(part, gridDim.x, 2, 0, 1, s_lo);
-        const double H = partials_combine(part, gridDim.x, 2, 1, 2, s_lo);
-        if (threadIdx.x == 0) {
-            st->lo = L;
-            st->hi = H;
-            st->done = 0.0;
-            st->halvings = 0.0;
-            *counter = 0;
-        }
+}
+
+// The bracket from the block partials (one block, fixed order).  Global sums
+// and extrema are finished in a launch of their own: a last-block scheme
+// would need a device-scope fence in every block, which writes back L2.
+__global__ void __launch_bounds__(DT)
+k_bracket_pick(unsigned n_blocks, const double *__restrict__ part, FermiState *st)
+{
+    __shared__ double s_red[DT / 64];
+    const double L = partials_combine(part, n_blocks, 2, 0, 1, s_red);
+    const double H = partials_combine(part, n_blocks, 2, 1, 2, s_red);
+    if (threadIdx.x == 0) {
+        st->lo = L;
+        st->hi = H;
+        st->done = 0.0;
+        st->halvings = 0.0;
     }
 }
 
@@ -390,10 +392,9 @@ k_bracket(int n_rows, const double *__restrict__ a_inf, const double *__restrict
 // evaluates the electron count at the 15 midpoints the next four halvings can
 // visit (a binary tree whose nodes are formed exactly as sequential bisection
 // forms them, mid = (lo + hi)/2), reading each orbital's coefficients once;
-// the last block then replays the four decisions (count < n_elec: lo = mid,
-// else hi = mid), stopping when a midpoint equals an end of its bracket.
-// The decisions, and hence the root found when the count is not monotone,
-// are those of plain bisection.
+// a one-block launch then replays the four decisions.  The decisions, and
+// hence the root found when the count is not monotone, are those of plain
+// bisection.
 constexpr int FT_LEVELS = 4, FT_NODES = (1 << FT_LEVELS) - 1;
 constexpr int FT_MAX_HALVINGS = 64;                           // as many as plain bisection takes at most
 constexpr int FT_PASSES = (FT_MAX_HALVINGS + FT_LEVELS - 1) / FT_LEVELS;
@@ -421,11 +422,9 @@ constexpr int FT_HALF = (FT_NODES + 1) / 2;
 
 __global__ void __launch_bounds__(DT)
 k_fermi_tree(int n_rows, int n_exp, const double *__restrict__ gs, const double *__restrict__ a_inf,
-             const double *__restrict__ b_inf, double n_elec, double *__restrict__ part,
-             unsigned *__restrict__ counter, FermiState *st)
+             const double *__restrict__ b_inf, double *__restrict__ part, const FermiState *st)
 {
-    __shared__ double s_inv[1040], s_red[FT_NODES * (DT / 64)], s_tot[FT_NODES];
-    __shared__ bool s_last;
+    __shared__ double s_inv[1040], s_red[FT_NODES * (DT / 64)];
     if (st->done != 0.0) return;
     const double lo = st->lo, hi = st->hi;
     for (int k = threadIdx.x; k <= n_exp + 2; k += blockDim.x) s_inv[k] = k ? 1.0 / k : 0.0;
@@ -486,47 +485,48 @@ k_fermi_tree(int n_rows, int n_exp, const double *__restrict__ gs, const double 
         const double t = block_sum_n<FT_NODES>(v, s_red);
         if (threadIdx.x < FT_NODES) part[(size_t)FT_NODES * blockIdx.x + threadIdx.x] = t;
     }
+}
+
+// The pass's decisions, in a launch of its own (one block) so that no block
+// of the pass needs a device-scope fence: the block partials of every node
+// are summed in a fixed order (thread t takes blocks t, t + DT, ..., then the
+// fixed wave tree), and the four decisions are replayed (count < n_elec:
+// lo = mid, else hi = mid), stopping when a midpoint equals an end of its
+// bracket or after the most halvings plain bisection takes.
+__global__ void __launch_bounds__(DT)
+k_fermi_pick(unsigned n_blocks, double n_elec, const double *__restrict__ part, FermiState *st)
+{
+    __shared__ double s_red[FT_NODES * (DT / 64)], s_tot[FT_NODES];
+    if (st->done != 0.0) return;
+    const double lo = st->lo, hi = st->hi;
+    double acc[FT_NODES];
+#pragma unroll
+    for (int p = 0; p < FT_NODES; ++p) acc[p] = 0.0;
+    for (unsigned q = threadIdx.x; q < n_blocks; q += blockDim.x)
+#pragma unroll
+        for (int p = 0; p < FT_NODES; ++p) acc[p] += part[(size_t)q * FT_NODES + p];
+    const double t = block_sum_n<FT_NODES>(acc, s_red);
+    if (threadIdx.x < FT_NODES) s_tot[threadIdx.x] = t;
     __syncthreads();
     if (threadIdx.x == 0) {
-        __threadfence();
-        s_last = atomicAdd(counter, 1u) == gridDim.x - 1;
-    }
-    __syncthreads();
-    if (s_last) {
-        __threadfence();
-        // all nodes' block partials in one pass: thread t takes blocks t, t + DT,
-        // ... in order, then the fixed wave tree
-        double acc[FT_NODES];
+        double tot[FT_NODES];
 #pragma unroll
-        for (int p = 0; p < FT_NODES; ++p) acc[p] = 0.0;
-        for (unsigned q = threadIdx.x; q < gridDim.x; q += blockDim.x)
-#pragma unroll
-            for (int p = 0; p < FT_NODES; ++p)
-                acc[p] += __hip_atomic_load(&part[(size_t)q * FT_NODES + p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const double t = block_sum_n<FT_NODES>(acc, s_red);
-        if (threadIdx.x < FT_NODES) s_tot[threadIdx.x] = t;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double tot[FT_NODES];
-#pragma unroll
-            for (int p = 0; p < FT_NODES; ++p) tot[p] = s_tot[p];
-            double mid[FT_NODES];
-            tree_points(lo, hi, mid);
-            double l = lo, hh = hi;
-            int node = 1;
-            double nh = st->halvings;
-            for (int lev = 0; lev < FT_LEVELS; ++lev) {
-                const double m = mid[node - 1];
-                if (nh >= FT_MAX_HALVINGS || m <= l || m >= hh) { st->done = 1.0; break; }
-                if (2.0 * tot[node - 1] < n_elec) { l = m; node = 2 * node + 1; }
-                else { hh = m; node = 2 * node; }
-                nh += 1.0;
-            }
-            st->lo = l;
-            st->hi = hh;
-            st->halvings = nh;
-            *counter = 0;
+        for (int p = 0; p < FT_NODES; ++p) tot[p] = s_tot[p];
+        double mid[FT_NODES];
+        tree_points(lo, hi, mid);
+        double l = lo, hh = hi;
+        int node = 1;
+        double nh = st->halvings;
+        for (int lev = 0; lev < FT_LEVELS; ++lev) {
+            const double m = mid[node - 1];
+            if (nh >= FT_MAX_HALVINGS || m <= l || m >= hh) { st->done = 1.0; break; }
+            if (2.0 * tot[node - 1] < n_elec) { l = m; node = 2 * node + 1; }
+            else { hh = m; node = 2 * node; }
+            nh += 1.0;
         }
+        st->lo = l;
+        st->hi = hh;
+        st->halvings = nh;
     }
 }
 
@@ -540,11 +540,9 @@ __global__ void __launch_bounds__(DT)
 k_energy(int n_atoms, int no, int n_exp, const double *__restrict__ gs, const double *__restrict__ a_inf,
          const double *__restrict__ b_inf, const double *__restrict__ H_on, const double *__restrict__ E_F,
          double *__restrict__ N_atom, double *__restrict__ U_atom, double *__restrict__ dos_atom,
-         int *__restrict__ flags, double *__restrict__ part, unsigned *__restrict__ counter,
-         double *__restrict__ U_total)
+         int *__restrict__ flags, double *__restrict__ part)
 {
     __shared__ double s_inv[1040], s_red[DT / 64];
-    __shared__ bool s_last;
     for (int k = threadIdx.x; k <= n_exp + 4; k += blockDim.x) s_inv[k] = k ? 1.0 / k : 0.0;
     __syncthreads();
     const double E = E_F[0];
@@ -592,28 +590,21 @@ k_energy(int n_atoms, int no, int n_exp, const double *__restrict__ gs, const do
         Ui = 2.0 * sU;
     }
     double t = block_sum(Ui, s_red);
-    if (threadIdx.x == 0) {
-        part[blockIdx.x] = t;
-        __threadfence();
-        s_last = atomicAdd(counter, 1u) == gridDim.x - 1;
-    }
-    __syncthreads();
-    if (s_last) {
-        __threadfence();
-        const double tot = partials_combine(part, gridDim.x, 1, 0, 0, s_red);
-        if (threadIdx.x == 0) {
-            U_total[0] = tot;
-            *counter = 0;
-        }
-    }
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
-__global__ void k_zero_u32(unsigned *p) { *p = 0; }
+// total U from the block partials (one block, fixed order)
+__global__ void __launch_bounds__(DT)
+k_energy_total(unsigned n_blocks, const double *__restrict__ part, double *__restrict__ U_total)
+{
+    __shared__ double s_red[DT / 64];
+    const double tot = partials_combine(part, n_blocks, 1, 0, 0, s_red);
+    if (threadIdx.x == 0) U_total[0] = tot;
+}
 
 struct EnergyWs {
     double *gs, *part;
     FermiState *st;
-    unsigned *counter;
     size_t bytes;
 };
 
@@ -626,7 +617,6 @@ EnergyWs carve(void *base, long n_rows, int n_exp)
     long nblk = 2 * ((n_rows + DT - 1) / DT) + 1;       // two lanes per row in the Fermi passes
     w.part = (double *)take(sizeof(double) * FT_NODES * (size_t)nblk);
     w.st = (FermiState *)take(sizeof(FermiState));
-    w.counter = (unsigned *)take(sizeof(unsigned));
     w.bytes = (size_t)(p - (char *)base);
     return w;
 }
@@ -683,29 +673,30 @@ extern "C" int bop_energy(int n_atoms, int no, int n_max, int n_exp, const doubl
     if (L <= 11) k_dos_coeffs<11><<<nblk, DT, 0, stream>>>((int)R, n_max, n_exp, mu, a, b, a_inf, b_inf, w.gs, flags);
     else k_dos_coeffs<21><<<nblk, DT, 0, stream>>>((int)R, n_max, n_exp, mu, a, b, a_inf, b_inf, w.gs, flags);
     BOP_LAUNCHED();
-    k_zero_u32<<<1, 1, 0, stream>>>(w.counter);
     if (ef_mode == 0) {
-        k_bracket<<<nblk, DT, 0, stream>>>((int)R, a_inf, b_inf, w.part, w.counter, w.st);
+        k_bracket<<<nblk, DT, 0, stream>>>((int)R, a_inf, b_inf, w.part);
+        k_bracket_pick<<<1, DT, 0, stream>>>(nblk, w.part, w.st);
         BOP_LAUNCHED();
-        for (int it = 0; it < FT_PASSES; ++it)
-            k_fermi_tree<<<(unsigned)((2 * R + DT - 1) / DT), DT, 0, stream>>>((int)R, n_exp, w.gs, a_inf, b_inf, n_elec,
-                                                                            w.part, w.counter, w.st);
+        const unsigned fblk = (unsigned)((2 * R + DT - 1) / DT);
+        for (int it = 0; it < FT_PASSES; ++it) {
+            k_fermi_tree<<<fblk, DT, 0, stream>>>((int)R, n_exp, w.gs, a_inf, b_inf, w.part, w.st);
+            k_fermi_pick<<<1, DT, 0, stream>>>(fblk, n_elec, w.part, w.st);
+        }
         BOP_LAUNCHED();
         k_fermi_finish<<<1, 1, 0, stream>>>(w.st, E_F);
         BOP_LAUNCHED();
     }
     const unsigned ablk = (unsigned)((n_atoms + DT - 1) / DT);
     k_energy<<<ablk, DT, 0, stream>>>(n_atoms, no, n_exp, w.gs, a_inf, b_inf, H_on, E_F, N_atom, U_atom,
-                                      dos_atom, flags, w.part, w.counter, U_total);
+                                      dos_atom, flags, w.part);
+    k_energy_total<<<1, DT, 0, stream>>>(ablk, w.part, U_total);
     BOP_LAUNCHED();
     return BOP_OK;
 }
 
 namespace bop {
-void energy_ws_scratch(void *ws, long n_rows, int n_exp, double **part, unsigned **counter)
+double *energy_ws_scratch(void *ws, long n_rows, int n_exp)
 {
-    EnergyWs w = carve(ws, n_rows, n_exp);
-    *part = w.part;
-    *counter = w.counter;
+    return carve(ws, n_rows, n_exp).part;
 }
 }  // namespace bop

@@ -16,11 +16,9 @@ constexpr int ST = 256;
 __global__ void __launch_bounds__(ST)
 k_scf_measure(int n, const double *__restrict__ N_atom, const double *__restrict__ dos,
               const double *__restrict__ n0, const double *__restrict__ shift, double mix, double n_floor,
-              double tol, double *__restrict__ q, double *__restrict__ part, unsigned *__restrict__ counter,
-              double *__restrict__ max_dq, int *__restrict__ converged, double *__restrict__ mean_out)
+              double *__restrict__ q, double *__restrict__ part)
 {
-    __shared__ double s_m[ST / 64], s_s[ST / 64], s_comb[ST / 64];
-    __shared__ bool s_last;
+    __shared__ double s_m[ST / 64], s_s[ST / 64];
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     double mq = 0.0, sum = 0.0;
     if (i < n) {
@@ -38,20 +36,22 @@ k_scf_measure(int n, const double *__restrict__ N_atom, const double *__restrict
         for (int w = 0; w < ST / 64; ++w) { m = fmax(m, s_m[w]); t += s_s[w]; }
         part[2 * blockIdx.x] = m;
         part[2 * blockIdx.x + 1] = t;
-        __threadfence();
-        s_last = atomicAdd(counter, 1u) == gridDim.x - 1;
     }
-    __syncthreads();
-    if (s_last) {
-        __threadfence();
-        const double m = fmax(0.0, partials_combine(part, gridDim.x, 2, 0, 2, s_comb));
-        const double t = partials_combine(part, gridDim.x, 2, 1, 0, s_comb);
-        if (threadIdx.x == 0) {
-            max_dq[0] = m;
-            converged[0] = m < tol;
-            mean_out[0] = t / n;
-            *counter = 0;
-        }
+}
+
+// max |q| and the mean new shift from the block partials (one block, fixed
+// order; a launch of its own, so that no block needs a device-scope fence)
+__global__ void __launch_bounds__(ST)
+k_scf_total(unsigned n_blocks, int n, double tol, const double *__restrict__ part, double *__restrict__ max_dq,
+            int *__restrict__ converged, double *__restrict__ mean_out)
+{
+    __shared__ double s_comb[ST / 64];
+    const double m = fmax(0.0, partials_combine(part, n_blocks, 2, 0, 2, s_comb));
+    const double t = partials_combine(part, n_blocks, 2, 1, 0, s_comb);
+    if (threadIdx.x == 0) {
+        max_dq[0] = m;
+        converged[0] = m < tol;
+        mean_out[0] = t / n;
     }
 }
 
@@ -95,13 +95,11 @@ extern "C" int bop_scf_step(const bop_system *sys, double mix, double n_floor, d
                     sys->H_on, sys->n_elec, 0, sys->E_F, sys->N_atom, sys->U_atom, sys->dos_atom,
                     sys->U_total, sys->flags, sys->energy_ws, sys->energy_ws_bytes, stream);
     if (rc) return rc;
-    double *part;
-    unsigned *counter;
-    energy_ws_scratch(sys->energy_ws, (long)n * no, sys->n_exp, &part, &counter);
+    double *part = energy_ws_scratch(sys->energy_ws, (long)n * no, sys->n_exp);
     const unsigned nb = (unsigned)((n + ST - 1) / ST);
     double *mean = part + 2 * (size_t)nb;    // one slot past the partials
-    k_scf_measure<<<nb, ST, 0, stream>>>(n, sys->N_atom, sys->dos_atom, sys->n0, shift, mix, n_floor, tol, q,
-                                        part, counter, max_dq, converged, mean);
+    k_scf_measure<<<nb, ST, 0, stream>>>(n, sys->N_atom, sys->dos_atom, sys->n0, shift, mix, n_floor, q, part);
+    k_scf_total<<<1, ST, 0, stream>>>(nb, n, tol, part, max_dq, converged, mean);
     BOP_LAUNCHED();
     k_scf_apply<<<nb, ST, 0, stream>>>(n, q, sys->dos_atom, mix, n_floor, converged, mean, shift);
     BOP_LAUNCHED();
