@@ -300,7 +300,8 @@ int bop_recursion(int n_rows, int n_max, const double *mu, int bw_mode,
  *             sequential bisection); E_F = midpoint of the final bracket.
  *  ef_mode 1: E_F [device] in: energies at the given level.
  *  ws: bop_energy_workspace_size(n_atoms, n_orb, n_exp) bytes.
- *  n_exp <= 1024 (default used by the paper's example: 200).
+ *  n_exp <= 1024 (default used by the paper's example: 200); n_orb <= 9
+ *  (BOP_E_UNSUPPORTED beyond).
  *  mu = NULL (Lanczos form): sigma_m for every m from the chain, which equals
  *  the moment route for m <= n_max in exact arithmetic.
  * ========================================================================= */

@@ -535,62 +535,76 @@ __global__ void k_fermi_finish(FermiState *st, double *E_F)
     E_F[0] = 0.5 * (st->lo + st->hi);
 }
 
-// per-atom N, U, n(E_F); total U by fixed-order reduction
-__global__ void __launch_bounds__(DT)
+// per-atom N, U, n(E_F) and block partials of U.  One thread per orbital row
+// (EA atoms x n_orb rows per block, so the GPU has enough waves for the long
+// per-row sums); an atom's orbitals are then added in orbital order, as a
+// per-atom loop would add them.
+constexpr int EA = 64;           // atoms per block of the energy pass
+
+__global__ void __launch_bounds__(EA * 9)
 k_energy(int n_atoms, int no, int n_exp, const double *__restrict__ gs, const double *__restrict__ a_inf,
          const double *__restrict__ b_inf, const double *__restrict__ H_on, const double *__restrict__ E_F,
          double *__restrict__ N_atom, double *__restrict__ U_atom, double *__restrict__ dos_atom,
          int *__restrict__ flags, double *__restrict__ part)
 {
-    __shared__ double s_inv[1040], s_red[DT / 64];
+    __shared__ double s_inv[1040], s_red[EA * 9 / 64], s_n[EA * 9], s_u[EA * 9], s_d[EA * 9];
     for (int k = threadIdx.x; k <= n_exp + 4; k += blockDim.x) s_inv[k] = k ? 1.0 / k : 0.0;
     __syncthreads();
     const double E = E_F[0];
     const long n_rows = (long)n_atoms * no;
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const long r = (long)blockIdx.x * EA * no + threadIdx.x;
+    double N = 0.0, U = 0.0, D = 0.0;
+    if (r < n_rows) {
+        double ai = a_inf[r], bi = b_inf[r];
+        double eps = (E - ai) / (2.0 * bi);
+        double c = eps < -1.0 ? -1.0 : (eps > 1.0 ? 1.0 : eps);
+        double s = sqrt(fmax(0.0, 1.0 - c * c));
+        double phi = acos(c);
+        // sin((m+1) phi), sin((m+2) phi) and (cos, sin)((m+3) phi), advanced
+        // by unit-modulus rotation; chi^_m, chi^_(m+1) carried along
+        const double c2 = c * c - s * s, s2 = 2.0 * c * s;
+        double w1 = s, w2 = s2;
+        double c3 = c2 * c - s2 * s, w3 = s2 * c + c2 * s;
+        double chi0 = 0.0;
+        double chi1 = 1.0 - phi / M_PI + s2 / (2.0 * M_PI);
+#pragma unroll 8
+        for (int m = 0; m <= n_exp; ++m) {
+            // chi^_(m+2) = (sin((m+3) phi)/(m+3) - sin((m+1) phi)/(m+1)) / pi
+            double chi2 = (w3 * s_inv[m + 3] - w1 * s_inv[m + 1]) / M_PI;
+            double g = gs[(long)m * n_rows + r];
+            N = fma(g, chi1, N);
+            U = fma(g, chi2 + chi0, U);
+            D = fma(g, w1, D);
+            chi0 = chi1;
+            chi1 = chi2;
+            double nc = c3 * c - w3 * s, ns = w3 * c + c3 * s;
+            w1 = w2; w2 = w3; w3 = ns; c3 = nc;
+        }
+        U = bi * U + (ai - H_on[r]) * N;
+        D = (eps > -1.0 && eps < 1.0) ? D / (M_PI * bi) : 0.0;
+        if (!(eps > -1.0 && eps < 1.0)) flags[r] |= BOP_FLAG_OUTSIDE;
+    }
+    s_n[threadIdx.x] = N;
+    s_u[threadIdx.x] = U;
+    s_d[threadIdx.x] = D;
+    __syncthreads();
+    const int t = threadIdx.x;
+    const long i = (long)blockIdx.x * EA + t;
     double Ui = 0.0;
-    if (i < n_atoms) {
+    if (t < EA && i < n_atoms) {
         double sN = 0.0, sU = 0.0, sD = 0.0;
         for (int a = 0; a < no; ++a) {
-            long r = (long)i * no + a;
-            double ai = a_inf[r], bi = b_inf[r];
-            double eps = (E - ai) / (2.0 * bi);
-            double c = eps < -1.0 ? -1.0 : (eps > 1.0 ? 1.0 : eps);
-            double s = sqrt(fmax(0.0, 1.0 - c * c));
-            double phi = acos(c);
-            // sin((m+1) phi), sin((m+2) phi) and (cos, sin)((m+3) phi), advanced
-            // by unit-modulus rotation; chi^_m, chi^_(m+1) carried along
-            const double c2 = c * c - s * s, s2 = 2.0 * c * s;
-            double w1 = s, w2 = s2;
-            double c3 = c2 * c - s2 * s, w3 = s2 * c + c2 * s;
-            double chi0 = 0.0;
-            double chi1 = 1.0 - phi / M_PI + s2 / (2.0 * M_PI);
-            double N = 0.0, U = 0.0, D = 0.0;
-#pragma unroll 8
-            for (int m = 0; m <= n_exp; ++m) {
-                // chi^_(m+2) = (sin((m+3) phi)/(m+3) - sin((m+1) phi)/(m+1)) / pi
-                double chi2 = (w3 * s_inv[m + 3] - w1 * s_inv[m + 1]) / M_PI;
-                double g = gs[(long)m * n_rows + r];
-                N = fma(g, chi1, N);
-                U = fma(g, chi2 + chi0, U);
-                D = fma(g, w1, D);
-                chi0 = chi1;
-                chi1 = chi2;
-                double nc = c3 * c - w3 * s, ns = w3 * c + c3 * s;
-                w1 = w2; w2 = w3; w3 = ns; c3 = nc;
-            }
-            U = bi * U + (ai - H_on[r]) * N;
-            D = (eps > -1.0 && eps < 1.0) ? D / (M_PI * bi) : 0.0;
-            if (!(eps > -1.0 && eps < 1.0)) flags[r] |= BOP_FLAG_OUTSIDE;
-            sN += N; sU += U; sD += D;
+            sN += s_n[t * no + a];
+            sU += s_u[t * no + a];
+            sD += s_d[t * no + a];
         }
         N_atom[i] = 2.0 * sN;
         U_atom[i] = 2.0 * sU;
         dos_atom[i] = 2.0 * sD;
         Ui = 2.0 * sU;
     }
-    double t = block_sum(Ui, s_red);
-    if (threadIdx.x == 0) part[blockIdx.x] = t;
+    const double tb = block_sum(Ui, s_red);
+    if (threadIdx.x == 0) part[blockIdx.x] = tb;
 }
 
 // total U from the block partials (one block, fixed order)
@@ -658,6 +672,7 @@ extern "C" int bop_energy(int n_atoms, int no, int n_max, int n_exp, const doubl
                           hipStream_t stream)
 {
     BOP_REQUIRE(n_atoms > 0 && no > 0, BOP_E_ARG, "bop_energy: n_atoms and n_orb must be > 0");
+    BOP_REQUIRE(no <= 9, BOP_E_UNSUPPORTED, "bop_energy: at most 9 orbitals per atom");
     BOP_REQUIRE(n_max >= 1 && n_max <= MAX_NMAX, BOP_E_UNSUPPORTED, "bop_energy: n_max must be 1..%d", MAX_NMAX);
     BOP_REQUIRE(n_exp >= 1 && n_exp <= 1024, BOP_E_UNSUPPORTED, "bop_energy: n_exp must be 1..1024");
     BOP_REQUIRE(ef_mode == 0 || ef_mode == 1, BOP_E_ARG, "bop_energy: ef_mode must be 0 or 1");
@@ -686,8 +701,8 @@ extern "C" int bop_energy(int n_atoms, int no, int n_max, int n_exp, const doubl
         k_fermi_finish<<<1, 1, 0, stream>>>(w.st, E_F);
         BOP_LAUNCHED();
     }
-    const unsigned ablk = (unsigned)((n_atoms + DT - 1) / DT);
-    k_energy<<<ablk, DT, 0, stream>>>(n_atoms, no, n_exp, w.gs, a_inf, b_inf, H_on, E_F, N_atom, U_atom,
+    const unsigned ablk = (unsigned)((n_atoms + EA - 1) / EA);
+    k_energy<<<ablk, EA * no, 0, stream>>>(n_atoms, no, n_exp, w.gs, a_inf, b_inf, H_on, E_F, N_atom, U_atom,
                                       dos_atom, flags, w.part);
     k_energy_total<<<1, DT, 0, stream>>>(ablk, w.part, U_total);
     BOP_LAUNCHED();
