@@ -173,6 +173,8 @@ __device__ int bfs_tile(int tile, int B, int n_atoms, int K, const int *__restri
 constexpr int PREP_REG = 24;
 
 // exclusive prefix of v over the workgroup (thread order); writes the total
+constexpr int FRONT = 1024;      // frontier rows per chunk of the bitmap search
+
 template <int WGT>
 __device__ inline int wg_scan_excl(int v, int *s_wave, int &total)
 {
@@ -208,7 +210,7 @@ template <int WGT>
 __device__ int bfs_tile_bits(int tile, int B, int n_atoms, int K, const int *__restrict__ order,
                              const int *__restrict__ row_ptr, const int *__restrict__ nbr_j, int deg_max,
                              int *g2l, int *sup, int rows_cap, int *s_size, int *s_wave, unsigned *s_vis,
-                             unsigned *s_new, int nw)
+                             unsigned *s_new, int nw, int *s_p0, int *s_deg)
 {
     const int tid = threadIdx.x;
     const int first = tile * B;
@@ -228,18 +230,28 @@ __device__ int bfs_tile_bits(int tile, int B, int n_atoms, int K, const int *__r
     const int w0 = min(tid * per, nw), w1 = min(w0 + per, nw);
     for (int k = 1; k <= K; ++k) {
         const int begin = (k >= 2) ? s_size[k - 2] : 0, end = s_size[k - 1];
-        const long nent = (long)(end - begin) * deg_max;
-        for (long e = tid; e < nent; e += WGT) {
-            const int t = begin + (int)(e / deg_max), sl = (int)(e % deg_max);
-            const int g = sup[t];
-            const int p0 = row_ptr[g], deg = row_ptr[g + 1] - p0;
-            if (sl < deg) {
-                const int j = nbr_j[p0 + sl];
-                const unsigned bit = 1u << (j & 31);
-                if (!(s_vis[j >> 5] & bit)) atomicOr(&s_new[j >> 5], bit);
+        // frontier rows in chunks of FRONT: each row's pair range is looked up
+        // once into LDS, then every (row, slot) entry needs one load
+        for (int c0 = begin; c0 < end; c0 += FRONT) {
+            const int c1 = min(end, c0 + FRONT);
+            for (int t = c0 + tid; t < c1; t += WGT) {
+                const int g = sup[t];
+                const int p0 = row_ptr[g];
+                s_p0[t - c0] = p0;
+                s_deg[t - c0] = row_ptr[g + 1] - p0;
             }
+            __syncthreads();
+            const long nent = (long)(c1 - c0) * deg_max;
+            for (long e = tid; e < nent; e += WGT) {
+                const int tl = (int)(e / deg_max), sl = (int)(e % deg_max);
+                if (sl < s_deg[tl]) {
+                    const int j = nbr_j[s_p0[tl] + sl];
+                    const unsigned bit = 1u << (j & 31);
+                    if (!(s_vis[j >> 5] & bit)) atomicOr(&s_new[j >> 5], bit);
+                }
+            }
+            __syncthreads();
         }
-        __syncthreads();
         int cnt = 0;
         for (int w = w0; w < w1; ++w) cnt += __popc(s_new[w]);
         int tot;
@@ -394,7 +406,7 @@ k_plan_bits(int n_atoms, int B, int n_tiles, int K, const int *__restrict__ orde
             int *hdr, char *scratch, size_t per_wg)
 {
     extern __shared__ unsigned s_bits[];
-    __shared__ int s_size[MAXK + 2], s_tile[1], s_cnt[1];
+    __shared__ int s_size[MAXK + 2], s_tile[1], s_cnt[1], s_p0[FRONT], s_deg[FRONT];
     const int tid = threadIdx.x, lane = tid & 63;
     const int nw = (n_atoms + 31) / 32;
     for (int i = tid; i < nw; i += PLAN_T) s_bits[i] = 0u;
@@ -413,28 +425,37 @@ k_plan_bits(int n_atoms, int B, int n_tiles, int K, const int *__restrict__ orde
         __syncthreads();
         for (int k = 1; k <= K; ++k) {
             const int begin = (k >= 2) ? s_size[k - 2] : 0, end = s_size[k - 1];
-            const long nent = (long)(end - begin) * deg_max;
-            for (long c0 = 0; c0 < nent; c0 += PLAN_T) {
-                const long e = c0 + tid;
-                int j = -1;
-                bool fresh = false;
-                if (e < nent) {
-                    const int t = begin + (int)(e / deg_max), sl = (int)(e % deg_max);
+            // frontier rows in chunks of FRONT, their pair ranges looked up once
+            for (int f0 = begin; f0 < end; f0 += FRONT) {
+                const int f1 = min(end, f0 + FRONT);
+                for (int t = f0 + tid; t < f1; t += PLAN_T) {
                     const int g = sup[t];
-                    const int p0 = row_ptr[g], deg = row_ptr[g + 1] - p0;
-                    if (sl < deg) {
-                        j = nbr_j[p0 + sl];
-                        const unsigned bit = 1u << (j & 31);
-                        fresh = !(atomicOr(&s_bits[j >> 5], bit) & bit);
-                    }
+                    const int p0 = row_ptr[g];
+                    s_p0[t - f0] = p0;
+                    s_deg[t - f0] = row_ptr[g + 1] - p0;
                 }
-                const unsigned long long m = __ballot(fresh);
-                int at = 0;
-                if (lane == 0 && m) at = atomicAdd(&s_cnt[0], (int)__popcll(m));
-                at = __shfl(at, 0);
-                if (fresh) sup[at + __popcll(m & ((1ull << lane) - 1ull))] = j;
+                __syncthreads();
+                const long nent = (long)(f1 - f0) * deg_max;
+                for (long c0 = 0; c0 < nent; c0 += PLAN_T) {
+                    const long e = c0 + tid;
+                    int j = -1;
+                    bool fresh = false;
+                    if (e < nent) {
+                        const int tl = (int)(e / deg_max), sl = (int)(e % deg_max);
+                        if (sl < s_deg[tl]) {
+                            j = nbr_j[s_p0[tl] + sl];
+                            const unsigned bit = 1u << (j & 31);
+                            fresh = !(atomicOr(&s_bits[j >> 5], bit) & bit);
+                        }
+                    }
+                    const unsigned long long m = __ballot(fresh);
+                    int at = 0;
+                    if (lane == 0 && m) at = atomicAdd(&s_cnt[0], (int)__popcll(m));
+                    at = __shfl(at, 0);
+                    if (fresh) sup[at + __popcll(m & ((1ull << lane) - 1ull))] = j;
+                }
+                __syncthreads();
             }
-            __syncthreads();
             if (tid == 0) s_size[k] = s_cnt[0];
             __syncthreads();
         }
@@ -471,6 +492,7 @@ k_prepare(int n_atoms, int B, int n_tiles, int K, const int *__restrict__ order,
           int *hdr, char *ws, Layout lay, size_t map_stride)
 {
     __shared__ int s_size[MAXK + 2], s_wave[PLAN_T / 64], s_flag[1], s_tile[1];
+    __shared__ int s_p0[BITS ? FRONT : 1], s_deg[BITS ? FRONT : 1];
     extern __shared__ unsigned s_bits2[];        // BITS: visited and layer bitmaps
     const int nw = (n_atoms + 31) / 32;
     if constexpr (BITS) {
@@ -487,7 +509,8 @@ k_prepare(int n_atoms, int B, int n_tiles, int K, const int *__restrict__ order,
         int *rinfo = sup + rows_cap;
         int *lnb = rinfo + rows_cap;
         const int rows = BITS ? bfs_tile_bits<PLAN_T>(tile, B, n_atoms, K, order, row_ptr, nbr_j, deg_max, g2l,
-                                                      sup, rows_cap, s_size, s_wave, s_bits2, s_bits2 + nw, nw)
+                                                      sup, rows_cap, s_size, s_wave, s_bits2, s_bits2 + nw, nw,
+                                                      s_p0, s_deg)
                               : bfs_tile<PLAN_T>(tile, B, n_atoms, K, order, row_ptr, nbr_j, deg_max, g2l, sup,
                                                  rows_cap, s_size, s_wave, s_flag);
         if (rows < 0) {
@@ -1500,7 +1523,7 @@ extern "C" int bop_moments_plan(int n_atoms, int n_orb, int n_max, int dtype, co
     const size_t bits_bytes = 4ull * ((n_atoms + 31) / 32);
     const int search = tuning ? tuning->plan_search : 0;
     BOP_REQUIRE(search >= 0 && search <= 2, BOP_E_ARG, "bop_moments_plan: plan_search must be 0, 1 or 2");
-    const bool fits = bits_bytes <= (size_t)device_lds_per_block() && bits_bytes <= 64 * 1024;
+    const bool fits = bits_bytes + 16 * 1024 <= (size_t)device_lds_per_block() && bits_bytes <= 64 * 1024;
     BOP_REQUIRE(search != 1 || fits, BOP_E_UNSUPPORTED, "bop_moments_plan: %d atoms too many for the LDS bitmap",
                 n_atoms);
     const bool bits = search == 1 || (search == 0 && fits);
@@ -1572,7 +1595,7 @@ extern "C" int bop_moments_prepare(const bop_plan *plan, const int *row_ptr, con
     BOP_LAUNCHED();
     // the ordered search with two LDS bitmaps where they fit a workgroup
     const size_t bits2 = 2 * 4ull * ((n + 31) / 32);
-    const bool bits = plan->search == 1 && bits2 <= (size_t)device_lds_per_block() && bits2 <= 128 * 1024;
+    const bool bits = plan->search == 1 && bits2 + 16 * 1024 <= (size_t)device_lds_per_block() && bits2 <= 128 * 1024;
     if (bits)
         k_prepare<true><<<pwg, PLAN_T, bits2, stream>>>(n, plan->tile_atoms, plan->n_tiles, plan->n_max / 2, order,
                                                         row_ptr, nbr_j, plan->deg_max, plan->rows_cap, hdr, w, lay,
