@@ -8,10 +8,13 @@
 //  * A tile is a group of B spatially adjacent atoms; the B * n_orb unit start
 //    vectors are the columns of X, one column per lane of a 64-wide wavefront.
 //  * Each tile's K-hop support is found once per neighbour list (prepare pass)
-//    by a deterministic breadth-first search: every frontier (row, slot) claims
-//    its neighbour with an atomic minimum on a per-workgroup global->local map
-//    and the owners are compacted in (row, slot) order, so local rows come out
-//    in layer order independent of scheduling.  Each local row keeps its
+//    by a deterministic breadth-first search, one workgroup per tile.  Up to
+//    524,288 atoms, two bitmaps in LDS (visited atoms, atoms of the layer being
+//    built) give each layer, listed in ascending atom index by a scan of the
+//    layer bitmap; for larger structures every frontier (row, slot) claims its
+//    neighbour with an atomic minimum on a per-workgroup global->local map and
+//    the owners are compacted in (row, slot) order.  Either way local rows come
+//    out in layer order independent of scheduling.  Each local row keeps its
 //    neighbour slots sorted by the neighbour's layer: at step k the neighbours
 //    whose X^(k-1) is non-zero form a prefix of that list.
 //  * The steps are step-synchronous launches over a batch of tiles; a
@@ -26,12 +29,11 @@
 //    order.  Their neighbours then sit in a few nearby patches of adjacent
 //    layers, and the ~15-fold reuse of every gathered row stays in the XCD's
 //    L2 instead of going to memory.
-//  * The plan pass only needs the layer sizes and finds them with a visited
-//    bitmap in LDS (unordered appends); the prepare pass does the ordered
-//    search above.
+//  * The plan pass only needs the layer sizes and finds them with one visited
+//    bitmap in LDS (unordered appends).
 //  * The moment dot products are fused into the step; per-chunk partial sums
-//    (FP64) are reduced in chunk order afterwards, so results are
-//    deterministic for a given plan.
+//    (FP64) of every step are kept and reduced in chunk order after a batch's
+//    last step, so results are deterministic for a given plan.
 #include "bop_internal.h"
 
 namespace bop {
