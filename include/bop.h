@@ -165,7 +165,8 @@ int bop_build_H(const bop_model *model /*[host]*/, int n_atoms, const int *speci
  *                       list changes; not when only H_on or H_bond change.
  *  bop_moments          the H.X steps; reads the prepared supports from `ws`.
  * `order` (may be NULL = input order) groups atoms into tiles.  A tile whose
- * support outgrows the plan (neighbour list changed without re-planning) gets
+ * support outgrows the plan, or whose support holds a row with more neighbours
+ * than the plan's deg_max (neighbour list changed without re-planning), gets
  * NaN moments.
  * ========================================================================= */
 typedef struct bop_tuning {

@@ -171,6 +171,11 @@ __device__ int bfs_tile(int tile, int B, int n_atoms, int K, const int *__restri
     return s_size[K];
 }
 
+// the plan's largest support per step (the moment launches are sized by it)
+struct RowsK {
+    int r[MAXK + 1];
+};
+
 // rows with at most this many neighbours classify their slots in one sweep
 constexpr int PREP_REG = 24;
 
@@ -491,7 +496,7 @@ template <bool BITS>
 __global__ void __launch_bounds__(PLAN_T)
 k_prepare(int n_atoms, int B, int n_tiles, int K, const int *__restrict__ order,
           const int *__restrict__ row_ptr, const int *__restrict__ nbr_j, int deg_max, int rows_cap,
-          int *hdr, char *ws, Layout lay, size_t map_stride)
+          RowsK rows_k, int *hdr, char *ws, Layout lay, size_t map_stride)
 {
     __shared__ int s_size[MAXK + 2], s_wave[PLAN_T / 64], s_flag[1], s_tile[1];
     __shared__ int s_p0[BITS ? FRONT : 1], s_deg[BITS ? FRONT : 1];
@@ -527,6 +532,14 @@ k_prepare(int n_atoms, int B, int n_tiles, int K, const int *__restrict__ order,
             continue;
         }
         if (threadIdx.x <= K) sizes[tile * (MAXK + 2) + threadIdx.x] = s_size[threadIdx.x];
+        // a support larger at some step than the plan's largest (the launches
+        // are sized by those) also fails the tile
+        if (threadIdx.x == 0) {
+            int over = 0;
+            for (int k = 0; k <= K; ++k) over |= s_size[k] > rows_k.r[k];
+            s_flag[0] = over;
+        }
+        __syncthreads();
         // per row: neighbour slots by class (0: layer < L, 1: layer L, 2: layer
         // L + 1, 3: outside the support), stable in slot order within a class;
         // one sweep counts, a second places, slot loads issued eight at a time
@@ -538,6 +551,10 @@ k_prepare(int n_atoms, int B, int n_tiles, int K, const int *__restrict__ order,
             const int endL = s_size[L];
             const int endL1 = (L + 1 <= K) ? s_size[L + 1] : s_size[K];
             const int p0 = row_ptr[g], deg = row_ptr[g + 1] - p0;
+            if (deg > deg_max) {        // more neighbours than planned: the tile fails
+                s_flag[0] = 1;
+                continue;
+            }
             int *dst = lnb + (long)l * deg_max;
             int cnt[3] = {0, 0, 0};
             if (deg <= PREP_REG) {
@@ -585,6 +602,11 @@ k_prepare(int n_atoms, int B, int n_tiles, int K, const int *__restrict__ order,
             rinfo[l] = L | (n1 << 8) | (n2 << 16) | (c << 24);
         }
         __syncthreads();
+        if (s_flag[0] && threadIdx.x == 0) {
+            sizes[tile * (MAXK + 2)] = -1;
+            sizes[tile * (MAXK + 2) + 1] = min(min(B, n_atoms - tile * B), rows_cap);
+            atomicOr(&hdr[1], 1);
+        }
         reset_map<PLAN_T>(g2l, sup, rows);
     }
 }
@@ -1601,17 +1623,19 @@ extern "C" int bop_moments_prepare(const bop_plan *plan, const int *row_ptr, con
     long nmap = (long)pwg * (long)(map_stride / 4);
     k_init<<<(unsigned)((nmap + 255) / 256), 256, 0, stream>>>(hdr, 8, (int *)(w + lay.x), nmap);
     BOP_LAUNCHED();
+    RowsK rk{};
+    for (int k = 0; k <= plan->n_max / 2; ++k) rk.r[k] = plan->rows_k[k];
     // the ordered search with two LDS bitmaps where they fit a workgroup
     const size_t bits2 = 2 * 4ull * ((n + 31) / 32);
     const bool bits = plan->search == 1 && bits2 + 16 * 1024 <= (size_t)device_lds_per_block() && bits2 <= 128 * 1024;
     if (bits)
         k_prepare<true><<<pwg, PLAN_T, bits2, stream>>>(n, plan->tile_atoms, plan->n_tiles, plan->n_max / 2, order,
-                                                        row_ptr, nbr_j, plan->deg_max, plan->rows_cap, hdr, w, lay,
-                                                        map_stride);
+                                                        row_ptr, nbr_j, plan->deg_max, plan->rows_cap, rk, hdr, w,
+                                                        lay, map_stride);
     else
         k_prepare<false><<<pwg, PLAN_T, 0, stream>>>(n, plan->tile_atoms, plan->n_tiles, plan->n_max / 2, order,
-                                                     row_ptr, nbr_j, plan->deg_max, plan->rows_cap, hdr, w, lay,
-                                                     map_stride);
+                                                     row_ptr, nbr_j, plan->deg_max, plan->rows_cap, rk, hdr, w,
+                                                     lay, map_stride);
     BOP_LAUNCHED();
     return BOP_OK;
 }

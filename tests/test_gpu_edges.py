@@ -97,3 +97,39 @@ def test_recursion_register_and_generic_kernels(bop):
         assert np.array_equal(got[n_max]["flags"] & 0xff, ref["flags"] & 0xff)
     assert np.array_equal(got[21]["a"][:, :10], got[20]["a"])
     assert np.array_equal(got[21]["b"][:, :11], got[20]["b"])
+
+
+@pytest.mark.parametrize("search", [1, 2])
+def test_plan_outgrown_by_neighbour_list(bop, search):
+    """A plan made for one neighbour list and used with another whose rows
+    have more neighbours than the plan's deg_max: the tiles that meet such a
+    row get NaN moments (the documented failure), nothing is written past the
+    planned rows, and the atoms of every other tile still match the oracle.
+    Two 16-atom bcc blocks far apart (at most 11 neighbours) are the planned
+    structure; the same blocks joined face to face (12 at the junction) the
+    used one."""
+    import torch
+    a = 2.87
+    blk, _ = W.cubic_lattice("bcc", a, 2)
+    box = np.eye(3) * 40.0
+    apart = np.vstack([blk + 2.0, blk + 20.0])
+    joined = np.vstack([blk + 2.0, blk + 2.0 + np.array([2 * a, 0.0, 0.0])])
+    m = W.canonical_d_model(3.5)
+    spc = np.zeros(32, np.int32)
+    species = torch.as_tensor(spc, device="cuda")
+    nl_a = bop.build_neighbours(torch.as_tensor(apart, device="cuda"), box, 3.5)
+    nl_b = bop.build_neighbours(torch.as_tensor(joined, device="cuda"), box, 3.5)
+    plan = bop.moments_plan(32, 5, 6, "f64", nl_a, {"plan_search": search})
+    deg_b = np.diff(_np(nl_b.row_ptr))
+    assert plan.deg_max == 11 and deg_b.max() == 12
+    H_on, H_b = bop.build_H(m, species, nl_b, dtype="f64")
+    ws = bop.moments_prepare(plan, nl_b)
+    mu = _np(bop.moments(plan, nl_b, H_on, H_b, ws=ws))
+    bad = np.isnan(mu).all(axis=(1, 2))
+    assert bad.any()
+    assert np.isfinite(mu[~bad]).all()
+    ref_nl = O.neighbours(joined, box, 3.5)
+    ref = O.moments(ref_nl, *O.build_H(m, spc, ref_nl), 6)
+    if (~bad).any():
+        from test_gpu_parity import _mu_err
+        assert _mu_err(mu[~bad], ref[~bad]) < 1e-10
