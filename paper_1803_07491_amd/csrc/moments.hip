@@ -694,7 +694,7 @@ __host__ __device__ inline int h_slice(int deg_max, int nb) { return (deg_max * 
 // that); the update kernel then forms r_k = y' - a_(k-1) u_(k-1).
 template <typename T, int NO, int WGT, int LANCZOS, typename S = T, bool HS = false>
 __global__ void __launch_bounds__(WGT)
-k_step(Batch bt, int k, int K, int last, int nch, int chunk_rows, int deg_max, int rows_cap,
+k_step(Batch bt, int k, int K, int last, int keep, int nch, int chunk_rows, int deg_max, int rows_cap,
        const int *__restrict__ row_ptr, const double *__restrict__ H_on, const T *__restrict__ H,
        const int *__restrict__ sizes_, const char *tiles_base, size_t tile_stride, char *xbase,
        size_t x_stride, double *__restrict__ part, const double *__restrict__ lc)
@@ -858,7 +858,7 @@ k_step(Batch bt, int k, int K, int last, int nch, int chunk_rows, int deg_max, i
                 acc[a] = acc[a] * ls - lbeta * xm;
             }
         }
-        if (!last) {
+        if (keep) {
 #pragma unroll
             for (int a = 0; a < NO; ++a) __builtin_nontemporal_store((S)acc[a], &xo[a * 64]);
         }
@@ -982,7 +982,7 @@ __global__ void k_x0_bf16(Batch bt, int n_max, const int *__restrict__ sizes_, c
 // r_(k-2) read from the BF16 buffer that y' replaces.
 template <int NO, int WGT, int LANCZOS>
 __global__ void __launch_bounds__(WGT)
-k_step_bf16(Batch bt, int k, int K, int last, int nch, int chunk_rows, int deg_max, int rows_cap,
+k_step_bf16(Batch bt, int k, int K, int last, int keep, int nch, int chunk_rows, int deg_max, int rows_cap,
             const int *__restrict__ row_ptr, const double *__restrict__ H_on,
             const unsigned short *__restrict__ H, const int *__restrict__ sizes_, const char *tiles_base,
             size_t tile_stride, char *xbase, size_t x_stride, double *__restrict__ part,
@@ -1087,7 +1087,7 @@ k_step_bf16(Batch bt, int k, int K, int last, int nch, int chunk_rows, int deg_m
                 if (!LANCZOS) se[cb] = fma((double)v, (double)v, se[cb]);
                 outv |= (unsigned long long)f32_to_bf16(v) << (16 * j);
             }
-            if (!last && 4 * g < SW) *(unsigned long long *)(Xc + off) = outv;
+            if (keep && 4 * g < SW) *(unsigned long long *)(Xc + off) = outv;
         }
     }
     // sum over the four alpha groups, then over wavefronts in a fixed order
@@ -1137,12 +1137,15 @@ int run_moments_bf16(const bop_plan &p, const int *row_ptr, const double *H_on, 
         const int nb8 = (bt.count + 7) / 8;
         for (int k = 1; k <= steps; ++k) {
             const int last = k > K;
+            // X^K is read again only by the extra step of an odd n_max; for an
+            // even n_max its moments come from this step's partial sums
+            const int keep = !last && (k < K || (p.n_max & 1));
             const int rows_k = last ? p.rows_k[K] : p.rows_k[k];
             const int nch = (rows_k + p.chunk_rows - 1) / p.chunk_rows;
             if (nch <= 0) continue;
             dim3 grid((unsigned)(nb8 * nch * 8));
 #define BOP_STEP16(W)                                                                                    \
-    k_step_bf16<NO, W, 0><<<grid, W, 0, st>>>(bt, k, K, last, nch, p.chunk_rows, p.deg_max, p.rows_cap,       \
+    k_step_bf16<NO, W, 0><<<grid, W, 0, st>>>(bt, k, K, last, keep, nch, p.chunk_rows, p.deg_max, p.rows_cap, \
                                               row_ptr, H_on, H, sizes, tiles, lay.tile_stride, xb, lay.x_stride, \
                                               part + sp.off[k], nullptr)
             if (p.block_threads == 256) BOP_STEP16(256);
@@ -1181,12 +1184,15 @@ int run_moments(const bop_plan &p, const int *row_ptr, const double *H_on, const
         const int nb8 = (bt.count + 7) / 8;
         for (int k = 1; k <= steps; ++k) {
             const int last = k > K;
+            // X^K is read again only by the extra step of an odd n_max; for an
+            // even n_max its moments come from this step's partial sums
+            const int keep = !last && (k < K || (p.n_max & 1));
             const int rows_k = last ? p.rows_k[K] : p.rows_k[k];
             const int nch = (rows_k + p.chunk_rows - 1) / p.chunk_rows;
             if (nch <= 0) continue;
             dim3 grid((unsigned)(nb8 * nch * 8));
 #define BOP_STEP_ARGS                                                                                 \
-    bt, k, K, last, nch, p.chunk_rows, p.deg_max, p.rows_cap, row_ptr, H_on, H, sizes, tiles,           \
+    bt, k, K, last, keep, nch, p.chunk_rows, p.deg_max, p.rows_cap, row_ptr, H_on, H, sizes, tiles,     \
         lay.tile_stride, xb, lay.x_stride, part + sp.off[k], nullptr
 #define BOP_STEP(W)                                                                                   \
     do {                                                                                              \
@@ -1439,7 +1445,8 @@ int run_lanczos(const bop_plan &p, const int *row_ptr, const double *H_on, const
             dim3 grid((unsigned)(nb8 * nch * 8));
             if (bf) {
 #define BOP_LSTEP16(W)                                                                                   \
-    k_step_bf16<NO, W, 1><<<grid, W, 0, st>>>(bt, k, K, last, nch, p.chunk_rows, p.deg_max, p.rows_cap, \
+    k_step_bf16<NO, W, 1><<<grid, W, 0, st>>>(bt, k, K, last, !last, nch, p.chunk_rows, p.deg_max,      \
+                                              p.rows_cap,                                                \
                                               row_ptr, H_on, (const unsigned short *)Hv, sizes, tiles,   \
                                               lay.tile_stride, xb, lay.x_stride, part, lc)
                 if (p.block_threads == 256) BOP_LSTEP16(256);
@@ -1448,7 +1455,8 @@ int run_lanczos(const bop_plan &p, const int *row_ptr, const double *H_on, const
 #undef BOP_LSTEP16
             } else {
 #define BOP_LSTEP_ARGS                                                                                \
-    bt, k, K, last, nch, p.chunk_rows, p.deg_max, p.rows_cap, row_ptr, H_on, (const T *)Hv, sizes,      \
+    bt, k, K, last, !last, nch, p.chunk_rows, p.deg_max, p.rows_cap, row_ptr, H_on, (const T *)Hv,      \
+        sizes,                                                                                        \
         tiles, lay.tile_stride, xb, lay.x_stride, part, lc
 #define BOP_LSTEP(W)                                                                                  \
     do {                                                                                              \
