@@ -114,8 +114,12 @@ def cpu_baseline(wl, target_s=12.0):
         O.energy(gs, rec["a_inf"], rec["b_inf"], H_on[sel], 0.0)
         return time.perf_counter() - t
 
+    # two probes: the first (16 atoms) is dominated by start-up costs, so the
+    # second, sized to about a tenth of the target, sets the sample
     t_probe = run(16)
-    m = int(max(16, min(wl.n_atoms, 16 * target_s / max(t_probe, 1e-3))))
+    m1 = int(max(16, min(wl.n_atoms, 16 * 0.1 * target_s / max(t_probe, 1e-3))))
+    t_probe = run(m1)
+    m = int(max(16, min(wl.n_atoms, m1 * target_s / max(t_probe, 1e-3))))
     t_s = run(m)
     t_tot = t_s + t_nlh * m / wl.n_atoms
     return {"value": m * wl.n_max / t_tot, "unit": "atom-moments/s", "cores": O.num_threads(),
