@@ -7,7 +7,7 @@ contributes its moment traces mu_1..mu_6 at zero shift (features) and its
 converged, gauge-fixed onsite shift (target).  The network is trained with
 the library's MLP kernels.  A warm start then costs one cheap 6-moment pass,
 the feature kernel and one forward pass; the plain cycle continues from the
-predicted shifts and remains the judge of convergence.
+predicted shifts and still decides when it has converged.
 
 Precision ladder: with FP32 H.X products the per-atom electron counts carry
 noise of order 1e-4..1e-3 electrons at 16 moments (the moments-to-recursion
