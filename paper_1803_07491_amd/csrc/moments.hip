@@ -1282,12 +1282,13 @@ __global__ void k_l0(Batch bt, int n_max, const int *__restrict__ sizes_, const 
 }
 
 // r_k = y' - a_(k-1) s_(k-1) r_(k-1) on the rows of the support of X^k (k is
-// the moment-step index, level k - 1), in place of y'; partial sums of |r_k|^2.
-// A thread owns one column of a row: n_orb values in the [n_orb][64] layout,
+// the moment-step index, level k - 1), in place of y'; partial sums of |r_k|^2
+// (of r_k rounded to the storage type, also when keep = 0 leaves y' in place
+// because no later level reads r_k).  A thread owns one column of a row: n_orb values in the [n_orb][64] layout,
 // or the slot-width vector in the BF16 [64][slot width] layout.
 template <typename T, int NO, int WGT, int BF, typename S = T>
 __global__ void __launch_bounds__(WGT)
-k_lupdate(Batch bt, int k, int nch, int chunk_rows, int rows_cap, const int *__restrict__ sizes_,
+k_lupdate(Batch bt, int k, int keep, int nch, int chunk_rows, int rows_cap, const int *__restrict__ sizes_,
           const char *tiles_base, size_t tile_stride, char *xbase, size_t x_stride,
           const double *__restrict__ lc, double *__restrict__ part)
 {
@@ -1322,7 +1323,7 @@ k_lupdate(Batch bt, int k, int nch, int chunk_rows, int rows_cap, const int *__r
                 const float x = hp ? bf16_to_f32(Xp[off + al]) : 0.f;
                 const float r = fmaf(-asf, x, y);
                 const unsigned short rb = f32_to_bf16(r);
-                Xc[off + al] = rb;
+                if (keep) Xc[off + al] = rb;
                 const double rd = (double)bf16_to_f32(rb);
                 se = fma(rd, rd, se);
             }
@@ -1338,7 +1339,7 @@ k_lupdate(Batch bt, int k, int nch, int chunk_rows, int rows_cap, const int *__r
             for (int al = 0; al < NO; ++al) {
                 const T x = hp ? (T)Xp[off + al * 64] : T(0);
                 const S rs = (S)((T)Xc[off + al * 64] - ast * x);
-                Xc[off + al * 64] = rs;
+                if (keep) Xc[off + al * 64] = rs;
                 const double r = (double)(T)rs;          // the norm of the vector as stored
                 se = fma(r, r, se);
             }
@@ -1479,11 +1480,16 @@ int run_lanczos(const bop_plan &p, const int *row_ptr, const double *H_on, const
                                                lay.tile_stride, part, lc, a, b, flags);
             BOP_LAUNCHED();
             if (last) continue;
+            // r_K is read again only by the extra level of an odd n_max; for an
+            // even n_max only its norm (b_K) is needed
+            const int keep = k < K || (p.n_max & 1);
 #define BOP_LUPD(W)                                                                                        \
     do {                                                                                                   \
-        if (bf) k_lupdate<T, NO, W, 1><<<grid, W, 0, st>>>(bt, k, nch, p.chunk_rows, p.rows_cap, sizes, tiles, \
+        if (bf) k_lupdate<T, NO, W, 1><<<grid, W, 0, st>>>(bt, k, keep, nch, p.chunk_rows, p.rows_cap, sizes,    \
+                                                           tiles,                                          \
                                                            lay.tile_stride, xb, lay.x_stride, lc, part);   \
-        else k_lupdate<T, NO, W, 0, S><<<grid, W, 0, st>>>(bt, k, nch, p.chunk_rows, p.rows_cap, sizes, tiles, \
+        else k_lupdate<T, NO, W, 0, S><<<grid, W, 0, st>>>(bt, k, keep, nch, p.chunk_rows, p.rows_cap, sizes, \
+                                                        tiles,                                             \
                                                         lay.tile_stride, xb, lay.x_stride, lc, part);      \
     } while (0)
             if (p.block_threads == 256) BOP_LUPD(256);
