@@ -368,11 +368,12 @@ __host__ __device__ inline Layout make_layout(const bop_plan &p, int n_prep_wg)
     size_t xb = L.x_stride * 2 * p.batch_tiles;
     size_t maps = (size_t)n_prep_wg * ((4ull * p.n_atoms + 255) / 256 * 256);
     L.x = take(xb > maps ? xb : maps);
-    // chunk partials: one step's worth for the Lanczos form, every step's for
-    // the moment form (reduced after the batch's last step)
+    // chunk partials: one step's worth for the Lanczos form (three per chunk at
+    // its last level), every step's for the moment form (two per chunk,
+    // reduced after the batch's last step)
     const size_t nch = (p.rows_cap + p.chunk_rows - 1) / p.chunk_rows;
     const size_t nch_all = step_parts(p).total_chunks;
-    L.part = take(8ull * 2 * 64 * (nch > nch_all ? nch : nch_all) * p.batch_tiles);
+    L.part = take(8ull * 64 * (3 * nch > 2 * nch_all ? 3 * nch : 2 * nch_all) * p.batch_tiles);
     L.lc = take(8ull * 4 * 64 * p.batch_tiles);
     L.bytes = o;
     return L;
@@ -694,7 +695,7 @@ __host__ __device__ inline int h_slice(int deg_max, int nb) { return (deg_max * 
 // that); the update kernel then forms r_k = y' - a_(k-1) u_(k-1).
 template <typename T, int NO, int WGT, int LANCZOS, typename S = T, bool HS = false>
 __global__ void __launch_bounds__(WGT)
-k_step(Batch bt, int k, int K, int last, int keep, int nch, int chunk_rows, int deg_max, int rows_cap,
+k_step(Batch bt, int k, int K, int last, int keep, int fin, int nch, int chunk_rows, int deg_max, int rows_cap,
        const int *__restrict__ row_ptr, const double *__restrict__ H_on, const T *__restrict__ H,
        const int *__restrict__ sizes_, const char *tiles_base, size_t tile_stride, char *xbase,
        size_t x_stride, double *__restrict__ part, const double *__restrict__ lc)
@@ -712,7 +713,7 @@ k_step(Batch bt, int k, int K, int last, int keep, int nch, int chunk_rows, int 
     // 1 (s,p,d) slots measured fastest there.
     constexpr bool PIPE = sizeof(T) == 4;
     constexpr int G = sizeof(T) == 8 ? (NO <= 5 ? 2 : 1) : 2;
-    __shared__ double s_red[2][NW][64];
+    __shared__ double s_red[LANCZOS ? 3 : 2][NW][64];
     extern __shared__ char s_dyn[];
     // XCD-aware numbering: block b runs on XCD b % 8; the other factor walks
     // tile-major through (tile, chunk)
@@ -736,7 +737,7 @@ k_step(Batch bt, int k, int K, int last, int keep, int nch, int chunk_rows, int 
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     T *sH = (T *)s_dyn + (size_t)w * h_slice(deg_max, NB);  // this wave's H blocks
     constexpr int stride_row = NO * 64;
-    double so = 0.0, se = 0.0;
+    double so = 0.0, se = 0.0, sx = 0.0;
     T ls = T(1), lbeta = T(0);
     if (LANCZOS) {
         ls = (T)lc[((size_t)t * 4 + 0) * 64 + lane];
@@ -865,19 +866,27 @@ k_step(Batch bt, int k, int K, int last, int keep, int nch, int chunk_rows, int 
 #pragma unroll
         for (int a = 0; a < NO; ++a) {
             so = fma((double)xs[a], (double)acc[a], so);
-            if (!LANCZOS) se = fma((double)acc[a], (double)acc[a], se);
+            if (!LANCZOS || fin) se = fma((double)acc[a], (double)acc[a], se);
+            if (LANCZOS && fin) sx = fma((double)xs[a], (double)xs[a], sx);
         }
     }
     s_red[0][w][lane] = so;
     s_red[1][w][lane] = se;
+    if constexpr (LANCZOS) s_red[2][w][lane] = sx;
     __syncthreads();
     if (threadIdx.x < 64) {
-        double to = 0.0, te = 0.0;
+        double to = 0.0, te = 0.0, tx = 0.0;
 #pragma unroll
-        for (int q2 = 0; q2 < NW; ++q2) { to += s_red[0][q2][threadIdx.x]; te += s_red[1][q2][threadIdx.x]; }
-        double *pp = part + (((size_t)t * nch + chunk) * 2) * 64;
+        for (int q2 = 0; q2 < NW; ++q2) {
+            to += s_red[0][q2][threadIdx.x];
+            te += s_red[1][q2][threadIdx.x];
+            if constexpr (LANCZOS) tx += s_red[2][q2][threadIdx.x];
+        }
+        const int ns = LANCZOS && fin ? 3 : 2;
+        double *pp = part + (((size_t)t * nch + chunk) * ns) * 64;
         pp[threadIdx.x] = to;
         pp[64 + threadIdx.x] = te;
+        if (LANCZOS && fin) pp[128 + threadIdx.x] = tx;
     }
 }
 
@@ -1118,6 +1127,10 @@ static inline size_t h_lds_bytes(const bop_plan &p, int wgt, size_t elem)
     return (size_t)(wgt / 64) * h_slice(p.deg_max, p.n_orb == 5 ? BOP_D_PACKED : p.n_orb * p.n_orb) * elem;
 }
 
+// static LDS of k_step (its per-wave partial sums), which the H slices share
+// the workgroup's LDS with
+static inline size_t step_static_lds(int wgt, int lanczos) { return (size_t)(lanczos ? 3 : 2) * wgt * 8; }
+
 template <int NO>
 int run_moments_bf16(const bop_plan &p, const int *row_ptr, const double *H_on, const void *Hv, double *mu,
                      char *ws, const Layout &lay, hipStream_t st)
@@ -1192,7 +1205,7 @@ int run_moments(const bop_plan &p, const int *row_ptr, const double *H_on, const
             if (nch <= 0) continue;
             dim3 grid((unsigned)(nb8 * nch * 8));
 #define BOP_STEP_ARGS                                                                                 \
-    bt, k, K, last, keep, nch, p.chunk_rows, p.deg_max, p.rows_cap, row_ptr, H_on, H, sizes, tiles,     \
+    bt, k, K, last, keep, 0, nch, p.chunk_rows, p.deg_max, p.rows_cap, row_ptr, H_on, H, sizes, tiles,  \
         lay.tile_stride, xb, lay.x_stride, part + sp.off[k], nullptr
 #define BOP_STEP(W)                                                                                   \
     do {                                                                                              \
@@ -1200,7 +1213,8 @@ int run_moments(const bop_plan &p, const int *row_ptr, const double *H_on, const
         if constexpr (sizeof(T) == 8) {                                                               \
             k_step<T, NO, W, 0, T, true><<<grid, W, 0, st>>>(BOP_STEP_ARGS);                          \
         } else {                                                                                      \
-            if (lds > lds_max) k_step<T, NO, W, 0, T, true><<<grid, W, 0, st>>>(BOP_STEP_ARGS);       \
+            if (lds + step_static_lds(W, 0) > lds_max)                                                \
+                k_step<T, NO, W, 0, T, true><<<grid, W, 0, st>>>(BOP_STEP_ARGS);                      \
             else k_step<T, NO, W, 0, T, false><<<grid, W, lds, st>>>(BOP_STEP_ARGS);                  \
         }                                                                                             \
     } while (0)
@@ -1358,7 +1372,8 @@ k_lupdate(Batch bt, int k, int keep, int nch, int chunk_rows, int rows_cap, cons
 // Per-column reduction of level k - 1 in chunk order.  which = 0: a_(k-1) from
 // the product pass (slot 0); which = 1: b_k from the update pass (slot 1), with
 // the breakdown test of the moment route (b_k^2 <= thr * b_1^2 ends the chain,
-// later a repeat the last one and later b are zero).
+// later a repeat the last one and later b are zero); which = 2: both, from the
+// three partials of a last product pass (<r_(k-1), y'>, |y'|^2, |r_(k-1)|^2).
 __global__ void k_lreduce(Batch bt, int k, int K, int last, int which, int n_max, int no, int nch,
                           int chunk_rows, int nw, double thr, const int *__restrict__ sizes_, const char *tiles_base,
                           size_t tile_stride, const double *__restrict__ part, double *__restrict__ lc,
@@ -1373,16 +1388,21 @@ __global__ void k_lreduce(Batch bt, int k, int K, int last, int which, int n_max
     if (c >= sizes[0] * no) return;
     const int nrow = last ? sizes[K] : sizes[k];
     const int used = tile_chunks(nrow, chunk_rows, nw);
-    double sum = 0.0;
+    const int ns = which == 2 ? 3 : 2;
     // eight chunks' loads in flight, added in chunk order
-    for (int q0 = 0; q0 < used; q0 += 8) {
-        double v[8];
+    auto chunk_sum = [&](int slot) {
+        double sum = 0.0;
+        for (int q0 = 0; q0 < used; q0 += 8) {
+            double v[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = part[(((size_t)t * nch + min(q0 + u, used - 1)) * 2 + which) * 64 + c];
+            for (int u = 0; u < 8; ++u) v[u] = part[(((size_t)t * nch + min(q0 + u, used - 1)) * ns + slot) * 64 + c];
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
-            if (q0 + u < used) sum += v[u];
-    }
+            for (int u = 0; u < 8; ++u)
+                if (q0 + u < used) sum += v[u];
+        }
+        return sum;
+    };
+    double sum = chunk_sum(which == 1 ? 1 : 0);
     const int *sup = (const int *)(tiles_base + tile_stride * tile);
     const long gr = (long)sup[c / no] * no + c % no;
     const int na = n_max >= 1 ? (n_max - 1) / 2 + 1 : 0, nb = n_max / 2;
@@ -1391,12 +1411,19 @@ __global__ void k_lreduce(Batch bt, int k, int K, int last, int which, int n_max
     int fl = flags[gr];
     const bool broke = fl & BOP_FLAG_BREAKDOWN;
     if (!isfinite(sum)) fl |= BOP_FLAG_NONFINITE;
-    if (which == 0) {
+    if (which != 1) {
         const double s = l[c];
         const double av = broke ? a[gr * na + lev - 1] : s * sum;
         a[gr * na + lev] = av;
         l[128 + c] = broke ? 0.0 : av * s;
-    } else {
+        if (which == 2) {
+            // |r_k|^2 = |y'|^2 - 2 a <u, y'> + a^2 |u|^2 with u = s r_(k-1), <u, y'> = a
+            const double yy = chunk_sum(1), xx = chunk_sum(2);
+            if (!isfinite(yy) || !isfinite(xx)) fl |= BOP_FLAG_NONFINITE;
+            sum = yy - 2.0 * av * av + av * av * s * s * xx;
+        }
+    }
+    if (which != 0) {
         if (!broke) {
             const double var = lev == 0 ? sum : b[gr * (nb + 1) + 1] * b[gr * (nb + 1) + 1];
             if (!(sum > thr * var) || !(sum > 0.0)) {
@@ -1443,6 +1470,10 @@ int run_lanczos(const bop_plan &p, const int *row_ptr, const double *H_on, const
             const int rows_k = last ? p.rows_k[K] : p.rows_k[k];
             const int nch = (rows_k + p.chunk_rows - 1) / p.chunk_rows;
             if (nch <= 0) continue;
+            // the last level of an even n_max: b_K from the product's partials
+            // (|r_K|^2 = |y'|^2 - 2 a^2 + a^2 s^2 |r_(K-1)|^2), so y' is not stored
+            // and no update pass follows (FP32/FP64 vectors)
+            const int fin = !bf && !last && k == K && !(p.n_max & 1);
             dim3 grid((unsigned)(nb8 * nch * 8));
             if (bf) {
 #define BOP_LSTEP16(W)                                                                                   \
@@ -1456,7 +1487,8 @@ int run_lanczos(const bop_plan &p, const int *row_ptr, const double *H_on, const
 #undef BOP_LSTEP16
             } else {
 #define BOP_LSTEP_ARGS                                                                                \
-    bt, k, K, last, !last, nch, p.chunk_rows, p.deg_max, p.rows_cap, row_ptr, H_on, (const T *)Hv,      \
+    bt, k, K, last, !last && !fin, fin, nch, p.chunk_rows, p.deg_max, p.rows_cap, row_ptr, H_on,        \
+        (const T *)Hv,                                                                                \
         sizes,                                                                                        \
         tiles, lay.tile_stride, xb, lay.x_stride, part, lc
 #define BOP_LSTEP(W)                                                                                  \
@@ -1465,7 +1497,8 @@ int run_lanczos(const bop_plan &p, const int *row_ptr, const double *H_on, const
         if constexpr (sizeof(T) == 8) {                                                               \
             k_step<T, NO, W, 1, S, true><<<grid, W, 0, st>>>(BOP_LSTEP_ARGS);                         \
         } else {                                                                                      \
-            if (lds > lds_max) k_step<T, NO, W, 1, S, true><<<grid, W, 0, st>>>(BOP_LSTEP_ARGS);      \
+            if (lds + step_static_lds(W, 1) > lds_max)                                                \
+                k_step<T, NO, W, 1, S, true><<<grid, W, 0, st>>>(BOP_LSTEP_ARGS);                     \
             else k_step<T, NO, W, 1, S, false><<<grid, W, lds, st>>>(BOP_LSTEP_ARGS);                 \
         }                                                                                             \
     } while (0)
@@ -1476,10 +1509,11 @@ int run_lanczos(const bop_plan &p, const int *row_ptr, const double *H_on, const
 #undef BOP_LSTEP_ARGS
             }
             BOP_LAUNCHED();
-            k_lreduce<<<bt.count, 64, 0, st>>>(bt, k, K, last, 0, p.n_max, NO, nch, p.chunk_rows, p.block_threads / 64, thr, sizes, tiles,
-                                               lay.tile_stride, part, lc, a, b, flags);
+            k_lreduce<<<bt.count, 64, 0, st>>>(bt, k, K, last, fin ? 2 : 0, p.n_max, NO, nch, p.chunk_rows,
+                                               p.block_threads / 64, thr, sizes, tiles, lay.tile_stride, part, lc,
+                                               a, b, flags);
             BOP_LAUNCHED();
-            if (last) continue;
+            if (last || fin) continue;
             // r_K is read again only by the extra level of an odd n_max; for an
             // even n_max only its norm (b_K) is needed
             const int keep = k < K || (p.n_max & 1);
