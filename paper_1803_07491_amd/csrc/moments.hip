@@ -991,7 +991,8 @@ __global__ void k_x0_bf16(Batch bt, int n_max, const int *__restrict__ sizes_, c
 // r_(k-2) read from the BF16 buffer that y' replaces.
 template <int NO, int WGT, int LANCZOS>
 __global__ void __launch_bounds__(WGT)
-k_step_bf16(Batch bt, int k, int K, int last, int keep, int nch, int chunk_rows, int deg_max, int rows_cap,
+k_step_bf16(Batch bt, int k, int K, int last, int keep, int fin, int nch, int chunk_rows, int deg_max,
+            int rows_cap,
             const int *__restrict__ row_ptr, const double *__restrict__ H_on,
             const unsigned short *__restrict__ H, const int *__restrict__ sizes_, const char *tiles_base,
             size_t tile_stride, char *xbase, size_t x_stride, double *__restrict__ part,
@@ -1000,7 +1001,7 @@ k_step_bf16(Batch bt, int k, int K, int last, int keep, int nch, int chunk_rows,
     constexpr int NW = WGT / 64;
     constexpr int SW = NO <= 8 ? 8 : 16;
     constexpr int SPC = 32 / SW;                 // slots per K = 32 chunk
-    __shared__ double s_red[2][NW][64];
+    __shared__ double s_red[LANCZOS ? 3 : 2][NW][64];
     const int xcd = blockIdx.x & 7, q = blockIdx.x >> 3;
     const int t = (q / nch) * 8 + xcd, chunk = q % nch;
     if (t >= bt.count) return;
@@ -1020,7 +1021,7 @@ k_step_bf16(Batch bt, int k, int K, int last, int keep, int nch, int chunk_rows,
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int gslot = (SW == 8) ? g : (g >> 1);  // slot of this lane group within a chunk
     const int boff = (SW == 8) ? 0 : 8 * (g & 1);
-    double so[4] = {0, 0, 0, 0}, se[4] = {0, 0, 0, 0};
+    double so[4] = {0, 0, 0, 0}, se[4] = {0, 0, 0, 0}, sx[4] = {0, 0, 0, 0};
     float ls[4] = {1.f, 1.f, 1.f, 1.f}, lbeta[4] = {0.f, 0.f, 0.f, 0.f};
     if (LANCZOS) {
 #pragma unroll
@@ -1093,7 +1094,8 @@ k_step_bf16(Batch bt, int k, int K, int last, int keep, int nch, int chunk_rows,
                 float v = fmaf(e[j], xp[j], acc[cb][j]);
                 if (LANCZOS) v = v * ls[cb] - lbeta[cb] * xm[j];
                 so[cb] = fma((double)xp[j], (double)v, so[cb]);
-                if (!LANCZOS) se[cb] = fma((double)v, (double)v, se[cb]);
+                if (!LANCZOS || fin) se[cb] = fma((double)v, (double)v, se[cb]);
+                if (LANCZOS && fin) sx[cb] = fma((double)xp[j], (double)xp[j], sx[cb]);
                 outv |= (unsigned long long)f32_to_bf16(v) << (16 * j);
             }
             if (keep && 4 * g < SW) *(unsigned long long *)(Xc + off) = outv;
@@ -1104,19 +1106,30 @@ k_step_bf16(Batch bt, int k, int K, int last, int keep, int nch, int chunk_rows,
     for (int cb = 0; cb < 4; ++cb) {
         so[cb] += __shfl_xor(so[cb], 16); so[cb] += __shfl_xor(so[cb], 32);
         se[cb] += __shfl_xor(se[cb], 16); se[cb] += __shfl_xor(se[cb], 32);
+        if constexpr (LANCZOS) { sx[cb] += __shfl_xor(sx[cb], 16); sx[cb] += __shfl_xor(sx[cb], 32); }
     }
     if (g == 0) {
 #pragma unroll
-        for (int cb = 0; cb < 4; ++cb) { s_red[0][w][cb * 16 + n] = so[cb]; s_red[1][w][cb * 16 + n] = se[cb]; }
+        for (int cb = 0; cb < 4; ++cb) {
+            s_red[0][w][cb * 16 + n] = so[cb];
+            s_red[1][w][cb * 16 + n] = se[cb];
+            if constexpr (LANCZOS) s_red[2][w][cb * 16 + n] = sx[cb];
+        }
     }
     __syncthreads();
     if (threadIdx.x < 64) {
-        double to = 0.0, te = 0.0;
+        double to = 0.0, te = 0.0, tx = 0.0;
 #pragma unroll
-        for (int q2 = 0; q2 < NW; ++q2) { to += s_red[0][q2][threadIdx.x]; te += s_red[1][q2][threadIdx.x]; }
-        double *pp = part + (((size_t)t * nch + chunk) * 2) * 64;
+        for (int q2 = 0; q2 < NW; ++q2) {
+            to += s_red[0][q2][threadIdx.x];
+            te += s_red[1][q2][threadIdx.x];
+            if constexpr (LANCZOS) tx += s_red[2][q2][threadIdx.x];
+        }
+        const int ns = LANCZOS && fin ? 3 : 2;
+        double *pp = part + (((size_t)t * nch + chunk) * ns) * 64;
         pp[threadIdx.x] = to;
         pp[64 + threadIdx.x] = te;
+        if (LANCZOS && fin) pp[128 + threadIdx.x] = tx;
     }
 }
 
@@ -1158,7 +1171,8 @@ int run_moments_bf16(const bop_plan &p, const int *row_ptr, const double *H_on, 
             if (nch <= 0) continue;
             dim3 grid((unsigned)(nb8 * nch * 8));
 #define BOP_STEP16(W)                                                                                    \
-    k_step_bf16<NO, W, 0><<<grid, W, 0, st>>>(bt, k, K, last, keep, nch, p.chunk_rows, p.deg_max, p.rows_cap, \
+    k_step_bf16<NO, W, 0><<<grid, W, 0, st>>>(bt, k, K, last, keep, 0, nch, p.chunk_rows, p.deg_max,          \
+                                              p.rows_cap,                                                    \
                                               row_ptr, H_on, H, sizes, tiles, lay.tile_stride, xb, lay.x_stride, \
                                               part + sp.off[k], nullptr)
             if (p.block_threads == 256) BOP_STEP16(256);
@@ -1472,12 +1486,13 @@ int run_lanczos(const bop_plan &p, const int *row_ptr, const double *H_on, const
             if (nch <= 0) continue;
             // the last level of an even n_max: b_K from the product's partials
             // (|r_K|^2 = |y'|^2 - 2 a^2 + a^2 s^2 |r_(K-1)|^2), so y' is not stored
-            // and no update pass follows (FP32/FP64 vectors)
-            const int fin = !bf && !last && k == K && !(p.n_max & 1);
+            // and no update pass follows
+            const int fin = !last && k == K && !(p.n_max & 1);
             dim3 grid((unsigned)(nb8 * nch * 8));
             if (bf) {
 #define BOP_LSTEP16(W)                                                                                   \
-    k_step_bf16<NO, W, 1><<<grid, W, 0, st>>>(bt, k, K, last, !last, nch, p.chunk_rows, p.deg_max,      \
+    k_step_bf16<NO, W, 1><<<grid, W, 0, st>>>(bt, k, K, last, !last && !fin, fin, nch, p.chunk_rows,    \
+                                              p.deg_max,                                                 \
                                               p.rows_cap,                                                \
                                               row_ptr, H_on, (const unsigned short *)Hv, sizes, tiles,   \
                                               lay.tile_stride, xb, lay.x_stride, part, lc)
