@@ -175,3 +175,34 @@ def test_fp32_wide_rows_read_h_with_scalar_loads(bop):
     m.run_moments()
     from test_gpu_parity import _mu_err
     assert _mu_err(_np(m.mu), O.moments(ref_nl, *O.build_H(model, spc, ref_nl), wl.n_max)) < 1e-5
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("n_max", [2, 4])
+def test_lanczos_breakdown_at_last_level(bop, dtype, n_max):
+    """A dimer along z with onsite level e: each d orbital couples only to the
+    same orbital of the other atom, so every chain spans two states: a_0 = a_1
+    = e, b_1 = |hopping| and b_2 = 0 exactly.  For an even n_max the last
+    level's b_K comes from the product pass's partial sums (|r|^2 = |y'|^2 -
+    2a^2 + a^2 s^2 |r_prev|^2): n_max = 4 puts the breakdown on that level
+    (every orbital flagged at level 2), n_max = 2 takes b_1 from it.  The
+    oracle's moment route is used for a and b_1 only: at b_2 it stops at its
+    rounding level (6e-8 on the weak delta bonds), which the closed form
+    replaces."""
+    e = 0.7
+    d = W.dimer(2.6, direction=(0.0, 0.0, 1.0))
+    wl = W.Workload("dimer_z", d.pos, d.cell, d.species, W.canonical_d_model(3.5, onsite_d=(e,)), n_max, 200,
+                    d.n_elec)
+    ref = O.energy_pipeline(wl)
+    p = bop.EnergyPath(wl.pos, wl.cell, wl.species, wl.model, n_max, wl.n_exp, dtype, method="lanczos")
+    p.run(float(np.sum(wl.n_elec)))
+    tol = {"f64": 1e-12, "f32": 1e-5, "bf16": 0.1}[dtype]
+    a, b, fl = _np(p.rec["a"]), _np(p.rec["b"]), _np(p.rec["flags"])
+    np.testing.assert_allclose(a, e, atol=tol)
+    np.testing.assert_allclose(b[:, 1], ref["rec"]["b"][:, 1], atol=tol)
+    assert np.all(b[:, 1] > 0.1)
+    if n_max == 4:
+        assert np.all(b[:, 2] == 0.0)
+        assert np.all((fl & 0xff01) == 0x201)
+    else:
+        assert np.all((fl & 0xff01) == 0)
