@@ -1259,7 +1259,10 @@ int run_moments(const bop_plan &p, const int *row_ptr, const double *H_on, const
 // amplified by the ill-conditioned moments-to-coefficients map.  Vectors are
 // stored unnormalised (r_k = |r_k| u_k) and scaled by the per-column factor
 // when read, so a level costs one product pass, one elementwise update pass and
-// two per-column reductions.
+// two per-column reductions.  The last level of an even n_max needs only b_K, the
+// norm of r_K: its product pass also sums |y'|^2 and |r_(K-1)|^2, which give
+// |r_K|^2 = |y'|^2 - 2 a^2 + a^2 s^2 |r_(K-1)|^2 with a = <u_(K-1), y'>, so that
+// level has no update pass and stores no vector.
 //
 // Column coefficients lc[t][.][c]: [0] s_k = 1/|r_k|, [1] beta_k = b_k s_(k-1),
 // [2] a_k s_k, [3] s_(k-1).
