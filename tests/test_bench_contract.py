@@ -1,0 +1,39 @@
+"""CPU-side checks of bench.py's contract: it refuses more than one GPU with a
+message, and the committed bench line for the headline workload carries every
+field of the JSON line, the roofline object and the timed oracle baseline.
+No kernel is launched."""
+import json
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_bench_refuses_several_gpus():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], cwd=ROOT,
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode != 0
+    assert "one GPU" in (r.stdout + r.stderr)
+    assert r.stdout.strip() == ""          # no JSON line for a configuration it does not run
+
+
+def test_committed_bench_line_has_every_field():
+    j = json.load(open(os.path.join(ROOT, "profiles", "bench_bcc_large_f32.json")))
+    for key in ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better",
+                "scaling", "vs_baseline", "dtype", "data", "config", "roofline", "cpu_baseline"):
+        assert key in j, key
+    assert j["metric"] == j["unit"] == "atom-moments/s"
+    assert j["n_gpus"] == 1 and j["higher_is_better"] is True and j["data"] == "synthetic"
+    assert "workload" in j["config"] and j["config"]["n_atoms"] == 128000 and j["config"]["n_max"] == 18
+    # value is atom-moments per second of one whole step
+    assert abs(j["value"] - 128000 * 18 / (j["ms_per_step"] * 1e-3)) < 1e-6 * j["value"]
+    r = j["roofline"]
+    for key in ("bound", "achieved", "peak", "unit", "frac", "traffic"):
+        assert key in r, key
+    assert abs(r["frac"] - r["achieved"] / r["peak"]) < 1e-12
+    assert abs(r["achieved"] - r["algorithmic_flops_per_launch"] / (r["kernel_ms"] * 1e-3) / 1e12) < 1e-9 * r["achieved"]
+    c = j["cpu_baseline"]
+    for key in ("value", "unit", "cores", "kind", "sample"):
+        assert key in c, key
+    assert c["kind"] == "oracle" and c["cores"] >= 1 and c["unit"] == j["unit"]
