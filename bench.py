@@ -7,8 +7,10 @@ displacements sigma = 0.08 A (seed 2), canonical d band (dd sigma : pi : delta =
 (14 neighbours), 18 moments, N_d = 4.5, one energy evaluation.
 
 A step is one pass of the whole path with inputs resident on the GPU:
-neighbour list -> Hamiltonian -> moment plan -> moments (H.X in the compute
-dtype, FP64 accumulation) -> recursion -> expansion coefficients -> Fermi level
+neighbour list -> Hamiltonian -> moment plan -> H.X passes in the compute
+dtype with FP64 sums (by default the Lanczos form, which gives the recursion
+coefficients of the 18 moments directly; --method moments computes the moments
+and the FP64 recursion) -> terminator -> expansion coefficients -> Fermi level
 -> energies.  The metric is atom-moments/s = N_atoms * n_max / step time.
 
 Printed: one JSON line with the metric, a roofline object for the moment
@@ -32,6 +34,7 @@ if ROOT not in sys.path:
 
 PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6, "bf16": 2500.0, "f16": 157.3}   # MI355X peaks: vector FP32 (incl. packed), FP64, dense BF16 MFMA
 PEAK_NONPACKED_F32 = 78.6                     # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
+PEAK_HBM_TBPS = 8.0
 
 
 def log(msg):
@@ -79,18 +82,23 @@ def kernel_source_hash():
 
 
 def read_traffic(dtype, method):
-    """HBM bytes per launch of the moment kernel measured with rocprofv3
-    counters (FETCH_SIZE + WRITE_SIZE, scaled by a copy-kernel calibration),
-    if recorded for the current kernel source (moment form only)."""
-    if method != "moments":
-        return None
-    p = os.path.join(ROOT, "profiles", f"traffic_moments_bcc_large_{dtype}.json")
+    """HBM bytes of one H.X pass measured with rocprofv3 counters (FETCH_SIZE
+    + WRITE_SIZE, scaled by a copy-kernel calibration), if recorded for the
+    current kernel source."""
+    p = os.path.join(ROOT, "profiles", f"traffic_{method}_bcc_large_{dtype}.json")
     if not os.path.exists(p):
         return None
     d = json.load(open(p))
     if d.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
     return d.get("bytes_per_launch")
+
+
+def per_atom_errors(out, ref):
+    """Largest relative per-atom differences of N_i and U_i."""
+    eN = ((out["N_atom"] - ref["N_atom"]).abs() / ref["N_atom"].abs()).max().item()
+    eU = ((out["U_atom"] - ref["U_atom"]).abs() / ref["U_atom"].abs()).max().item()
+    return {"N": eN, "U": eU}
 
 
 def cpu_baseline(wl, target_s=12.0):
@@ -158,8 +166,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--dtype", default="f32", choices=["f32", "f64", "bf16", "f16"],
                     help="H.X arithmetic/storage; f16 = FP16 vectors with FP32 H and arithmetic (Lanczos form)")
-    ap.add_argument("--method", default="moments", choices=["moments", "lanczos"],
-                    help="moments then FP64 recursion, or the recursion straight from the H.X products")
+    ap.add_argument("--method", default="lanczos", choices=["moments", "lanczos"],
+                    help="recursion coefficients straight from the H.X products (Lanczos, default), or moments "
+                         "then the FP64 recursion")
     ap.add_argument("--reps", type=int, default=40)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-f64", action="store_true", help="skip the FP64 comparison run")
@@ -210,6 +219,7 @@ def main():
     log(f"{args.dtype}: {t_step * 1e3:.2f} ms/step, moment kernel {t_mom_ms:.2f} ms, "
         f"E_F {float(out['E_F'].cpu()[0]):.8f} eV, U {float(out['U_total'].cpu()[0]) / wl.n_atoms:.8f} eV/atom")
 
+    out = {k: (v.clone() if hasattr(v, "clone") else v) for k, v in out.items()}
     rp = path.nl.row_ptr.cpu().numpy()
     nj = path.nl.nbr_j.cpu().numpy()
     sample = np.random.default_rng(7).choice(wl.n_atoms, size=8, replace=False)
@@ -243,6 +253,10 @@ def main():
                      "algorithmic_flops_per_launch": flops,
                      "flops_per_atom": float(fpa.mean()), "flops_per_atom_spread": float(np.ptp(fpa))},
     }
+    if traffic:
+        # the second ceiling: measured HBM bytes of the pass over its time
+        res["roofline"]["achieved_hbm_TBps"] = traffic / (t_mom_ms * 1e-3) / 1e12
+        res["roofline"]["hbm_frac"] = res["roofline"]["achieved_hbm_TBps"] / PEAK_HBM_TBPS
     if args.dtype == "f32":
         res["roofline"]["frac_nonpacked_fp32"] = achieved / PEAK_NONPACKED_F32
     if not args.no_f64 and (args.dtype != "f64" or args.method != "moments"):
@@ -251,11 +265,30 @@ def main():
         t64, k64, o64 = timed_steps(p64, n_elec, args.steps, 1, torch)
         u32 = float(out["U_total"].cpu()[0])
         u64 = float(o64["U_total"].cpu()[0])
+        # per-atom accuracy of the timed form: its energies at the FP64 path's
+        # Fermi level against the FP64 path's, every atom
+        o_at = path.run_tail(n_elec, E_F=o64["E_F"].clone())
+        res["accuracy_vs_f64"] = {"max_atom_rel_err": per_atom_errors(o_at, o64), "bar": 1e-5,
+                                  "energy_err_meV_per_atom": abs(u32 - u64) / wl.n_atoms * 1e3,
+                                  "E_F_diff_eV": abs(float(out["E_F"].cpu()[0]) - float(o64["E_F"].cpu()[0]))}
         res["f64_path"] = {"value": wl.n_atoms * wl.n_max / t64, "ms_per_step": t64 * 1e3, "kernel_ms": k64,
-                           "achieved_tflops": flops / (k64 * 1e-3) / 1e12,
-                           "energy_err_meV_per_atom": abs(u32 - u64) / wl.n_atoms * 1e3}
-        log(f"f64: {t64 * 1e3:.2f} ms/step, moment kernel {k64:.2f} ms, |dU| "
-            f"{res['f64_path']['energy_err_meV_per_atom']:.3e} meV/atom")
+                           "achieved_tflops": flops / (k64 * 1e-3) / 1e12}
+        log(f"f64: {t64 * 1e3:.2f} ms/step, moment kernel {k64:.2f} ms; timed form vs f64: {res['accuracy_vs_f64']}")
+        if args.method == "lanczos" and args.dtype == "f32":
+            # the FP32 moment form, for comparison: faster, but the moments-to-
+            # coefficients map amplifies its rounding beyond the FP32 bar per atom
+            del path
+            pm = P.EnergyPath(wl.pos, wl.cell, wl.species, wl.model, wl.n_max, wl.n_exp, "f32", method="moments")
+            tm, km, om = timed_steps(pm, n_elec, args.steps, 1, torch)
+            om_at = pm.run_tail(n_elec, E_F=o64["E_F"].clone())
+            res["moments_f32_path"] = {"value": wl.n_atoms * wl.n_max / tm, "ms_per_step": tm * 1e3,
+                                       "kernel_ms": km, "achieved_tflops": flops / (km * 1e-3) / 1e12,
+                                       "frac": flops / (km * 1e-3) / 1e12 / peak,
+                                       "max_atom_rel_err": per_atom_errors(om_at, o64),
+                                       "meets_fp32_bar": False}
+            res["moments_f32_path"]["meets_fp32_bar"] = max(res["moments_f32_path"]["max_atom_rel_err"].values()) < 1e-5
+            log(f"moments f32: {tm * 1e3:.2f} ms/step, kernel {km:.2f} ms, {res['moments_f32_path']['max_atom_rel_err']}")
+            del pm
         del p64
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")

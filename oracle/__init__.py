@@ -296,7 +296,9 @@ def scf(wl, shift0=None, mix=0.5, tol=1e-4, max_iter=200, n_floor=1e-3, n_max=No
 # MLP reference (NumPy FP64).  Network: x (6) -> tanh(W1 x + b1) (64)
 # -> tanh(W2 h1 + b2) (64) -> W3 h2 + b3 (1); loss = mean squared error.
 # Not from the paper (its warm start of onsite levels, Sec. III "Speed-ups"
-# (ii), is the idea this replaces); parity unpinned beyond finite differences.
+# (ii), is the idea this replaces).  Pins: the gradients by central finite
+# differences of the loss; Adam by hand-worked steps and the constant-gradient
+# invariant of its bias correction (Kingma & Ba, Algorithm 1).
 # --------------------------------------------------------------------------
 def mlp_forward(params, x):
     W1, b1, W2, b2, W3, b3 = params
@@ -329,6 +331,8 @@ def mlp_loss_grad(params, x, t):
 
 
 def adam_step(params, grads, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam step (Kingma & Ba, Algorithm 1): moment estimates, bias
+    correction by 1 - beta^t, eps added outside the square root."""
     out_p, out_m, out_v = [], [], []
     for p, g, mm, vv in zip(params, grads, m, v):
         mm = b1 * mm + (1 - b1) * g

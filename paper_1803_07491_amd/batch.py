@@ -17,8 +17,8 @@ import ctypes as C
 
 import numpy as np
 
-from . import (Neighbours, build_H, build_neighbours, lanczos, load, moments, moments_plan,
-               moments_prepare, n_a, n_b, _check, _ptr, _stream, _torch)
+from . import (BOP_E_CAPACITY, BOP_E_UNSUPPORTED, BopError, Neighbours, build_H, build_neighbours, lanczos,
+               load, moments, moments_plan, moments_prepare, n_a, n_b, _check, _ptr, _stream, _torch)
 
 
 class BatchedMoments:
@@ -136,7 +136,11 @@ def autotune(batch: BatchedMoments, candidates=CANDIDATES, reps=2, log=None):
     for cand in candidates:
         try:
             batch.set_tuning(cand)
-        except Exception as e:          # e.g. a tiling the plan rejects
+        except BopError as e:
+            # a tiling the plan rejects; any other failure (a HIP error that
+            # may have left the stream unusable) propagates
+            if e.code not in (BOP_E_UNSUPPORTED, BOP_E_CAPACITY):
+                raise
             if log:
                 log(f"skip {cand}: {e}")
             continue
@@ -156,5 +160,7 @@ def autotune(batch: BatchedMoments, candidates=CANDIDATES, reps=2, log=None):
             log(f"{key}: {ms:.2f} ms")
         if best is None or ms < best[1]:
             best = (cand, ms)
+    if best is None:
+        raise RuntimeError("autotune: the plan rejected every candidate tiling")
     batch.set_tuning(best[0])
     return best[0], times

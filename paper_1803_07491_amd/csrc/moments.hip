@@ -46,6 +46,7 @@ constexpr int MAXK = MAX_NMAX / 2;
 constexpr int HDR = 256;            // header ints: [0] queue, [1] error, [2] max rows, [3] max degree,
                                     // [8 + k] max rows of U^k (plan)
 constexpr int PLAN_T = 512;
+constexpr int LC_N = 8;             // Lanczos column coefficients per lane and tile
 
 // Row assignment of the step kernels: a tile with nrow rows at this step uses
 // nct = tile_chunks(..) of the launch's chunks, and chunk c < nct takes the
@@ -329,7 +330,7 @@ struct Layout {
     size_t x;           // X buffers: batch x 2 x rows_cap x n_orb x 64 (also prepare's maps)
     size_t x_stride;    // bytes of one X buffer
     size_t part;        // double [batch][chunks][2][64]
-    size_t lc;          // double [batch][4][64]: Lanczos column coefficients
+    size_t lc;          // double [batch][LC_N][64]: Lanczos column coefficients
     size_t bytes;
 };
 
@@ -365,7 +366,7 @@ __host__ __device__ inline Layout make_layout(const bop_plan &p, int n_prep_wg)
     L.tile_stride = (4ull * p.rows_cap * (2 + p.deg_max) + 255) / 256 * 256;
     L.tiles = take(L.tile_stride * p.n_tiles);
     L.x_stride = (x_row_bytes(p.dtype, p.n_orb) * p.rows_cap + 255) / 256 * 256;
-    size_t xb = L.x_stride * 2 * p.batch_tiles;
+    size_t xb = L.x_stride * (p.batch_tiles >= 2 ? 2 * (size_t)p.batch_tiles : 4);
     size_t maps = (size_t)n_prep_wg * ((4ull * p.n_atoms + 255) / 256 * 256);
     L.x = take(xb > maps ? xb : maps);
     // chunk partials: one step's worth for the Lanczos form (three per chunk at
@@ -374,7 +375,7 @@ __host__ __device__ inline Layout make_layout(const bop_plan &p, int n_prep_wg)
     const size_t nch = (p.rows_cap + p.chunk_rows - 1) / p.chunk_rows;
     const size_t nch_all = step_parts(p).total_chunks;
     L.part = take(8ull * 64 * (3 * nch > 2 * nch_all ? 3 * nch : 2 * nch_all) * p.batch_tiles);
-    L.lc = take(8ull * 4 * 64 * p.batch_tiles);
+    L.lc = take(8ull * LC_N * 64 * p.batch_tiles);
     L.bytes = o;
     return L;
 }
@@ -687,12 +688,20 @@ __host__ __device__ inline int h_slice(int deg_max, int nb) { return (deg_max * 
 // long after it would have left L2, where it would evict the rows being
 // gathered.
 //
-// LANCZOS = 1: the same product for Lanczos level k - 1 (the support of H u_(k-1)
-// is that of X^k).  The buffer read holds r_(k-1) = u_(k-1) / s, the buffer
-// written holds r_(k-2) on entry; per column (lane) lc gives s = 1/|r_(k-1)| and
-// beta = b_(k-1) * s_(k-2).  The row stores y' = s H r_(k-1) - beta r_(k-2) in
-// place of r_(k-2) and the partial sums give <r_(k-1), y'> (a_(k-1) = s times
-// that); the update kernel then forms r_k = y' - a_(k-1) u_(k-1).
+// LANCZOS = 1: one whole Lanczos level j = k - 1 per pass (the support of
+// H u_j is that of X^k).  A tile then has four vectors: Y (two, ping-pong) and
+// R (two).  Entering the pass, Y holds y'_j = H u_(j-1) - b_(j-1) u_(j-2) (not
+// yet orthogonalised against u_(j-1)) and R holds r_(j-1), r_(j-2), with
+// u = s r.  The gathers read Y only: H r_j = H y'_j - c_j H r_(j-1), c_j =
+// a_(j-1) s_(j-1), and H r_(j-1) = (y'_j + beta_(j-1) r_(j-2)) / s_(j-1) is a
+// combination of the row's own entries, so no second vector is gathered and
+// no separate update pass is needed.  Per row the pass forms
+//   r_j = y'_j - c_j r_(j-1)            (stored in place of r_(j-2)),
+//   y'_(j+1) = s_j H r_j - beta_j r_(j-1)  (stored in the other Y buffer),
+// and partial sums of <r_j, y'_(j+1)>, |y'_(j+1)|^2 and |r_j|^2, from which
+// k_lreduce_fused takes a_j = s_j <r_j, y'_(j+1)> and b_(j+1)^2 = |y'_(j+1) -
+// a_j u_j|^2 = |y'|^2 - 2 a_j^2 + a_j^2 s_j^2 |r_j|^2.  Per column (lane) lc
+// gives s_j, beta_j = b_j s_(j-1), c_j, beta_(j-1) and 1/s_(j-1).
 template <typename T, int NO, int WGT, int LANCZOS, typename S = T, bool HS = false>
 __global__ void __launch_bounds__(WGT)
 k_step(Batch bt, int k, int K, int last, int keep, int fin, int nch, int chunk_rows, int deg_max, int rows_cap,
@@ -731,17 +740,25 @@ k_step(Batch bt, int k, int K, int last, int keep, int fin, int nch, int chunk_r
     const int *rinfo = sup + rows_cap;
     const int *lnb = rinfo + rows_cap;
     const int src = last ? (K & 1) : ((k - 1) & 1);
-    const S *Xp = (const S *)(xbase + x_stride * (2 * (size_t)t + src));
-    S *Xc = (S *)(xbase + x_stride * (2 * (size_t)t + (k & 1)));
+    constexpr size_t NBUF = LANCZOS ? 4 : 2;      // X buffers per tile
+    const S *Xp = (const S *)(xbase + x_stride * (NBUF * t + src));
+    S *Xc = (S *)(xbase + x_stride * (NBUF * t + (k & 1)));
+    // Lanczos: r_(j-2) read and r_j written (same buffer), r_(j-1) read
+    S *Ra = (S *)(xbase + x_stride * (NBUF * t + 2 + ((k - 1) & 1)));
+    const S *Rb = (const S *)(xbase + x_stride * (NBUF * t + 2 + (k & 1)));
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     T *sH = (T *)s_dyn + (size_t)w * h_slice(deg_max, NB);  // this wave's H blocks
     constexpr int stride_row = NO * 64;
     double so = 0.0, se = 0.0, sx = 0.0;
-    T ls = T(1), lbeta = T(0);
+    T ls = T(1), lbeta = T(0), lcj = T(0), lbp = T(0), linv = T(0);
     if (LANCZOS) {
-        ls = (T)lc[((size_t)t * 4 + 0) * 64 + lane];
-        lbeta = (T)lc[((size_t)t * 4 + 1) * 64 + lane];
+        const double *l = lc + (size_t)t * LC_N * 64 + lane;
+        ls = (T)l[0];
+        lbeta = (T)l[64];
+        lcj = (T)l[128];
+        lbp = (T)l[192];
+        linv = (T)l[256];
     }
     // a row's H blocks into the LDS slice: 16 bytes per lane where every block
     // is a whole number of 16-byte units (packed FP32 d-d blocks, 64 bytes)
@@ -784,7 +801,7 @@ k_step(Batch bt, int k, int K, int last, int keep, int fin, int nch, int chunk_r
         const T *hsrc = H + (long)p0 * NB;
         (void)deg;
         const S *xrow = Xp + (long)l * stride_row + lane;
-        T acc[NO], xs[NO];
+        T acc[NO], xs[NO], r1[LANCZOS ? NO : 1], r2[LANCZOS ? NO : 1];
 #pragma unroll
         for (int a = 0; a < NO; ++a) {
             xs[a] = has_prev ? (T)xrow[a * 64] : T(0);
@@ -851,23 +868,43 @@ k_step(Batch bt, int k, int K, int last, int keep, int fin, int nch, int chunk_r
             if (l + RS < nrow) h_copy((const float *)(H + (long)p0_n * NB), (float *)sH, (p1_n - p0_n) * NB);
         }
         S *xo = Xc + (long)l * stride_row + lane;
-        if (LANCZOS) {
-            const bool has_prev2 = L <= k - 2;
+        if constexpr (LANCZOS) {
+            // the row's own r_(j-1) and r_(j-2) (zero outside their supports),
+            // loaded after the products so that they hold no registers there
+            const bool h1 = L <= k - 2, h2 = L <= k - 3;
+            const long off = (long)l * stride_row + lane;
 #pragma unroll
             for (int a = 0; a < NO; ++a) {
-                const T xm = has_prev2 ? (T)xo[a * 64] : T(0);
-                acc[a] = acc[a] * ls - lbeta * xm;
+                r1[a] = h1 ? (T)Rb[off + a * 64] : T(0);
+                r2[a] = h2 ? (T)Ra[off + a * 64] : T(0);
             }
-        }
-        if (keep) {
+            S *ro = Ra + (long)l * stride_row + lane;
 #pragma unroll
-            for (int a = 0; a < NO; ++a) __builtin_nontemporal_store((S)acc[a], &xo[a * 64]);
-        }
+            for (int a = 0; a < NO; ++a) {
+                const T hrp = (xs[a] + lbp * r2[a]) * linv;      // H r_(j-1) at this row
+                const T hr = acc[a] - lcj * hrp;                 // H r_j
+                const S rj = (S)(xs[a] - lcj * r1[a]);           // r_j
+                const S y = (S)(ls * hr - lbeta * r1[a]);        // y'_(j+1)
+                if (keep) {
+                    __builtin_nontemporal_store(rj, &ro[a * 64]);
+                    __builtin_nontemporal_store(y, &xo[a * 64]);
+                }
+                // sums of the vectors as stored
+                const double rd = (double)(T)rj, yd = (double)(T)y;
+                so = fma(rd, yd, so);
+                se = fma(yd, yd, se);
+                sx = fma(rd, rd, sx);
+            }
+        } else {
+            if (keep) {
 #pragma unroll
-        for (int a = 0; a < NO; ++a) {
-            so = fma((double)xs[a], (double)acc[a], so);
-            if (!LANCZOS || fin) se = fma((double)acc[a], (double)acc[a], se);
-            if (LANCZOS && fin) sx = fma((double)xs[a], (double)xs[a], sx);
+                for (int a = 0; a < NO; ++a) __builtin_nontemporal_store((S)acc[a], &xo[a * 64]);
+            }
+#pragma unroll
+            for (int a = 0; a < NO; ++a) {
+                so = fma((double)xs[a], (double)acc[a], so);
+                se = fma((double)acc[a], (double)acc[a], se);
+            }
         }
     }
     s_red[0][w][lane] = so;
@@ -882,11 +919,11 @@ k_step(Batch bt, int k, int K, int last, int keep, int fin, int nch, int chunk_r
             te += s_red[1][q2][threadIdx.x];
             if constexpr (LANCZOS) tx += s_red[2][q2][threadIdx.x];
         }
-        const int ns = LANCZOS && fin ? 3 : 2;
+        constexpr int ns = LANCZOS ? 3 : 2;
         double *pp = part + (((size_t)t * nch + chunk) * ns) * 64;
         pp[threadIdx.x] = to;
         pp[64 + threadIdx.x] = te;
-        if (LANCZOS && fin) pp[128 + threadIdx.x] = tx;
+        if constexpr (LANCZOS) pp[128 + threadIdx.x] = tx;
     }
 }
 
@@ -1026,8 +1063,8 @@ k_step_bf16(Batch bt, int k, int K, int last, int keep, int fin, int nch, int ch
     if (LANCZOS) {
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb) {
-            ls[cb] = (float)lc[((size_t)t * 4 + 0) * 64 + cb * 16 + n];
-            lbeta[cb] = (float)lc[((size_t)t * 4 + 1) * 64 + cb * 16 + n];
+            ls[cb] = (float)lc[((size_t)t * LC_N + 0) * 64 + cb * 16 + n];
+            lbeta[cb] = (float)lc[((size_t)t * LC_N + 1) * 64 + cb * 16 + n];
         }
     }
     for (int l = chunk * NW + w; l < nrow; l += nct * NW) {
@@ -1271,7 +1308,7 @@ int run_moments(const bop_plan &p, const int *row_ptr, const double *H_on, const
 // coefficients for the seeds of failed tiles
 template <typename T, int NO, typename S = T>
 __global__ void k_l0(Batch bt, int n_max, const int *__restrict__ sizes_, const char *tiles_base,
-                     size_t tile_stride, char *xbase, size_t x_stride, double *__restrict__ lc,
+                     size_t tile_stride, char *xbase, size_t x_stride, int nbuf, double *__restrict__ lc,
                      double *__restrict__ a, double *__restrict__ b, int *__restrict__ flags, int bf16)
 {
     const int t = blockIdx.x;
@@ -1290,21 +1327,19 @@ __global__ void k_l0(Batch bt, int n_max, const int *__restrict__ sizes_, const 
     }
     if (failed) return;
     if (threadIdx.x < 64) {
-        double *l = lc + (size_t)t * 4 * 64;
+        double *l = lc + (size_t)t * LC_N * 64;
         l[threadIdx.x] = threadIdx.x < Bt * NO ? 1.0 : 0.0;
-        l[64 + threadIdx.x] = 0.0;
-        l[128 + threadIdx.x] = 0.0;
-        l[192 + threadIdx.x] = 0.0;
+        for (int q = 1; q < LC_N; ++q) l[q * 64 + threadIdx.x] = 0.0;
     }
     if (bf16) {
         constexpr int SW = NO <= 8 ? 8 : 16;
-        unsigned short *X0 = (unsigned short *)(xbase + x_stride * (2 * (size_t)t));
+        unsigned short *X0 = (unsigned short *)(xbase + x_stride * ((size_t)nbuf * t));
         for (int e = threadIdx.x; e < Bt * 64 * SW; e += blockDim.x) {
             int l = e / (64 * SW), rest = e % (64 * SW), c = rest / SW, al = rest % SW;
             X0[e] = (al < NO && c == l * NO + al) ? (unsigned short)0x3f80 : (unsigned short)0;
         }
     } else {
-        S *X0 = (S *)(xbase + x_stride * (2 * (size_t)t));
+        S *X0 = (S *)(xbase + x_stride * ((size_t)nbuf * t));
         for (int e = threadIdx.x; e < Bt * NO * 64; e += blockDim.x) {
             int l = e / (NO * 64), rest = e % (NO * 64), al = rest / 64, c = rest % 64;
             X0[(long)l * NO * 64 + al * 64 + c] = (c == l * NO + al) ? S(1) : S(0);
@@ -1312,18 +1347,20 @@ __global__ void k_l0(Batch bt, int n_max, const int *__restrict__ sizes_, const 
     }
 }
 
-// r_k = y' - a_(k-1) s_(k-1) r_(k-1) on the rows of the support of X^k (k is
-// the moment-step index, level k - 1), in place of y'; partial sums of |r_k|^2
-// (of r_k rounded to the storage type, also when keep = 0 leaves y' in place
-// because no later level reads r_k).  A thread owns one column of a row: n_orb values in the [n_orb][64] layout,
-// or the slot-width vector in the BF16 [64][slot width] layout.
-template <typename T, int NO, int WGT, int BF, typename S = T>
+// BF16 Lanczos update (the MFMA form keeps the two-pass scheme): r_k = y' -
+// a_(k-1) s_(k-1) r_(k-1) on the rows of the support of X^k (k is the
+// moment-step index, level k - 1), in place of y'; partial sums of |r_k|^2 (of
+// r_k rounded to BF16, also when keep = 0 leaves y' in place because no later
+// level reads r_k).  A thread owns one column of a row: the slot-width vector
+// in the BF16 [64][slot width] layout.
+template <int NO, int WGT>
 __global__ void __launch_bounds__(WGT)
-k_lupdate(Batch bt, int k, int keep, int nch, int chunk_rows, int rows_cap, const int *__restrict__ sizes_,
-          const char *tiles_base, size_t tile_stride, char *xbase, size_t x_stride,
-          const double *__restrict__ lc, double *__restrict__ part)
+k_lupdate_bf16(Batch bt, int k, int keep, int nch, int chunk_rows, int rows_cap, const int *__restrict__ sizes_,
+               const char *tiles_base, size_t tile_stride, char *xbase, size_t x_stride,
+               const double *__restrict__ lc, double *__restrict__ part)
 {
     constexpr int NW = WGT / 64;
+    constexpr int SW = NO <= 8 ? 8 : 16;
     __shared__ double s_red[NW][64];
     const int xcd = blockIdx.x & 7, q = blockIdx.x >> 3;
     const int t = (q / nch) * 8 + xcd, chunk = q % nch;
@@ -1338,42 +1375,23 @@ k_lupdate(Batch bt, int k, int keep, int nch, int chunk_rows, int rows_cap, cons
     const int *rinfo = sup + rows_cap;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int src = (k - 1) & 1, dst = k & 1;
-    const double as = lc[((size_t)t * 4 + 2) * 64 + lane];
+    const double as = lc[((size_t)t * LC_N + 2) * 64 + lane];
     double se = 0.0;
-    if (BF) {
-        constexpr int SW = NO <= 8 ? 8 : 16;
-        const unsigned short *Xp = (const unsigned short *)(xbase + x_stride * (2 * (size_t)t + src));
-        unsigned short *Xc = (unsigned short *)(xbase + x_stride * (2 * (size_t)t + dst));
-        const float asf = (float)as;
-        for (int l = chunk * NW + w; l < nrow; l += nct * NW) {
-            const bool hp = (rinfo[l] & 255) <= k - 1;
-            const long off = ((long)l * 64 + lane) * SW;
+    const unsigned short *Xp = (const unsigned short *)(xbase + x_stride * (2 * (size_t)t + src));
+    unsigned short *Xc = (unsigned short *)(xbase + x_stride * (2 * (size_t)t + dst));
+    const float asf = (float)as;
+    for (int l = chunk * NW + w; l < nrow; l += nct * NW) {
+        const bool hp = (rinfo[l] & 255) <= k - 1;
+        const long off = ((long)l * 64 + lane) * SW;
 #pragma unroll
-            for (int al = 0; al < NO; ++al) {
-                const float y = bf16_to_f32(Xc[off + al]);
-                const float x = hp ? bf16_to_f32(Xp[off + al]) : 0.f;
-                const float r = fmaf(-asf, x, y);
-                const unsigned short rb = f32_to_bf16(r);
-                if (keep) Xc[off + al] = rb;
-                const double rd = (double)bf16_to_f32(rb);
-                se = fma(rd, rd, se);
-            }
-        }
-    } else {
-        const S *Xp = (const S *)(xbase + x_stride * (2 * (size_t)t + src));
-        S *Xc = (S *)(xbase + x_stride * (2 * (size_t)t + dst));
-        const T ast = (T)as;
-        for (int l = chunk * NW + w; l < nrow; l += nct * NW) {
-            const bool hp = (rinfo[l] & 255) <= k - 1;
-            const long off = (long)l * NO * 64 + lane;
-#pragma unroll
-            for (int al = 0; al < NO; ++al) {
-                const T x = hp ? (T)Xp[off + al * 64] : T(0);
-                const S rs = (S)((T)Xc[off + al * 64] - ast * x);
-                if (keep) Xc[off + al * 64] = rs;
-                const double r = (double)(T)rs;          // the norm of the vector as stored
-                se = fma(r, r, se);
-            }
+        for (int al = 0; al < NO; ++al) {
+            const float y = bf16_to_f32(Xc[off + al]);
+            const float x = hp ? bf16_to_f32(Xp[off + al]) : 0.f;
+            const float r = fmaf(-asf, x, y);
+            const unsigned short rb = f32_to_bf16(r);
+            if (keep) Xc[off + al] = rb;
+            const double rd = (double)bf16_to_f32(rb);
+            se = fma(rd, rd, se);
         }
     }
     s_red[w][lane] = se;
@@ -1386,11 +1404,28 @@ k_lupdate(Batch bt, int k, int keep, int nch, int chunk_rows, int rows_cap, cons
     }
 }
 
-// Per-column reduction of level k - 1 in chunk order.  which = 0: a_(k-1) from
-// the product pass (slot 0); which = 1: b_k from the update pass (slot 1), with
-// the breakdown test of the moment route (b_k^2 <= thr * b_1^2 ends the chain,
-// later a repeat the last one and later b are zero); which = 2: both, from the
-// three partials of a last product pass (<r_(k-1), y'>, |y'|^2, |r_(k-1)|^2).
+// Sum of one partial slot over a tile's chunks, in chunk order, eight chunks'
+// loads in flight.
+__device__ inline double chunk_sum(const double *part, int t, int nch, int used, int ns, int slot, int c)
+{
+    double sum = 0.0;
+    for (int q0 = 0; q0 < used; q0 += 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = part[(((size_t)t * nch + min(q0 + u, used - 1)) * ns + slot) * 64 + c];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (q0 + u < used) sum += v[u];
+    }
+    return sum;
+}
+
+// Per-column reduction of level k - 1 of the BF16 two-pass scheme, in chunk
+// order.  which = 0: a_(k-1) from the product pass (slot 0); which = 1: b_k from
+// the update pass (slot 1), with the breakdown test of the moment route (b_k^2
+// <= thr * b_1^2 ends the chain, later a repeat the last one and later b are
+// zero); which = 2: both, from the three partials of a last product pass
+// (<r_(k-1), y'>, |y'|^2, |r_(k-1)|^2).
 __global__ void k_lreduce(Batch bt, int k, int K, int last, int which, int n_max, int no, int nch,
                           int chunk_rows, int nw, double thr, const int *__restrict__ sizes_, const char *tiles_base,
                           size_t tile_stride, const double *__restrict__ part, double *__restrict__ lc,
@@ -1406,25 +1441,12 @@ __global__ void k_lreduce(Batch bt, int k, int K, int last, int which, int n_max
     const int nrow = last ? sizes[K] : sizes[k];
     const int used = tile_chunks(nrow, chunk_rows, nw);
     const int ns = which == 2 ? 3 : 2;
-    // eight chunks' loads in flight, added in chunk order
-    auto chunk_sum = [&](int slot) {
-        double sum = 0.0;
-        for (int q0 = 0; q0 < used; q0 += 8) {
-            double v[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) v[u] = part[(((size_t)t * nch + min(q0 + u, used - 1)) * ns + slot) * 64 + c];
-#pragma unroll
-            for (int u = 0; u < 8; ++u)
-                if (q0 + u < used) sum += v[u];
-        }
-        return sum;
-    };
-    double sum = chunk_sum(which == 1 ? 1 : 0);
+    double sum = chunk_sum(part, t, nch, used, ns, which == 1 ? 1 : 0, c);
     const int *sup = (const int *)(tiles_base + tile_stride * tile);
     const long gr = (long)sup[c / no] * no + c % no;
     const int na = n_max >= 1 ? (n_max - 1) / 2 + 1 : 0, nb = n_max / 2;
     const int lev = k - 1;
-    double *l = lc + (size_t)t * 4 * 64;
+    double *l = lc + (size_t)t * LC_N * 64;
     int fl = flags[gr];
     const bool broke = fl & BOP_FLAG_BREAKDOWN;
     if (!isfinite(sum)) fl |= BOP_FLAG_NONFINITE;
@@ -1435,7 +1457,7 @@ __global__ void k_lreduce(Batch bt, int k, int K, int last, int which, int n_max
         l[128 + c] = broke ? 0.0 : av * s;
         if (which == 2) {
             // |r_k|^2 = |y'|^2 - 2 a <u, y'> + a^2 |u|^2 with u = s r_(k-1), <u, y'> = a
-            const double yy = chunk_sum(1), xx = chunk_sum(2);
+            const double yy = chunk_sum(part, t, nch, used, ns, 1, c), xx = chunk_sum(part, t, nch, used, ns, 2, c);
             if (!isfinite(yy) || !isfinite(xx)) fl |= BOP_FLAG_NONFINITE;
             sum = yy - 2.0 * av * av + av * av * s * s * xx;
         }
@@ -1461,9 +1483,68 @@ __global__ void k_lreduce(Batch bt, int k, int K, int last, int which, int n_max
     flags[gr] = fl;
 }
 
-template <typename T, int NO, typename S = T>
-int run_lanczos(const bop_plan &p, const int *row_ptr, const double *H_on, const void *Hv, double *a, double *b,
-                int *flags, char *ws, const Layout &lay, hipStream_t st)
+// Per-column reduction after a fused Lanczos pass (level j = k - 1), in chunk
+// order: a_j = s_j <r_j, y'_(j+1)>; unless this is the last level of an odd
+// n_max, b_(j+1)^2 = |y'_(j+1)|^2 - 2 a_j^2 + a_j^2 s_j^2 |r_j|^2 (the squared
+// norm of r_(j+1) = y'_(j+1) - a_j u_j, u_j = s_j r_j; FP64 sums of the stored
+// vectors, so its cancellation error is about 1e-16 |y'|^2), with the
+// breakdown test of the moment route (b_(j+1)^2 <= thr b_1^2 ends the chain:
+// later a repeat the last one, later b are zero and the column's coefficients
+// become zero, so its vectors stay zero).  Then the next level's column
+// coefficients: s_(j+1) = 1/b_(j+1), beta_(j+1) = b_(j+1) s_j, c_(j+1) = a_j s_j,
+// beta_j and 1/s_j.
+__global__ void k_lreduce_fused(Batch bt, int k, int K, int last, int n_max, int no, int nch, int chunk_rows,
+                                int nw, double thr, const int *__restrict__ sizes_, const char *tiles_base,
+                                size_t tile_stride, const double *__restrict__ part, double *__restrict__ lc,
+                                double *__restrict__ a, double *__restrict__ b, int *__restrict__ flags)
+{
+    const int t = blockIdx.x;
+    if (t >= bt.count) return;
+    const int tile = bt.first + t;
+    const int *sizes = sizes_ + tile * (MAXK + 2);
+    if (sizes[0] < 0) return;
+    const int c = threadIdx.x;
+    if (c >= sizes[0] * no) return;
+    const int nrow = last ? sizes[K] : sizes[k];
+    const int used = tile_chunks(nrow, chunk_rows, nw);
+    const double ry = chunk_sum(part, t, nch, used, 3, 0, c);
+    const double yy = chunk_sum(part, t, nch, used, 3, 1, c);
+    const double rr = chunk_sum(part, t, nch, used, 3, 2, c);
+    const int *sup = (const int *)(tiles_base + tile_stride * tile);
+    const long gr = (long)sup[c / no] * no + c % no;
+    const int na = n_max >= 1 ? (n_max - 1) / 2 + 1 : 0, nb = n_max / 2;
+    const int lev = k - 1;
+    double *l = lc + (size_t)t * LC_N * 64 + c;
+    int fl = flags[gr];
+    const bool broke = fl & BOP_FLAG_BREAKDOWN;
+    if (!isfinite(ry) || !isfinite(yy) || !isfinite(rr)) fl |= BOP_FLAG_NONFINITE;
+    const double s = l[0];
+    const double av = broke ? a[gr * na + lev - 1] : s * ry;
+    a[gr * na + lev] = av;
+    if (!last && !broke) {
+        const double bsq = yy - 2.0 * av * av + av * av * s * s * rr;
+        const double var = lev == 0 ? bsq : b[gr * (nb + 1) + 1] * b[gr * (nb + 1) + 1];
+        if (!(bsq > thr * var) || !(bsq > 0.0)) {
+            for (int j = lev + 1; j <= nb; ++j) b[gr * (nb + 1) + j] = 0.0;
+            fl |= BOP_FLAG_BREAKDOWN | ((lev + 1) << 8);
+            for (int q = 0; q < 5; ++q) l[q * 64] = 0.0;
+        } else {
+            const double bb = sqrt(bsq);
+            b[gr * (nb + 1) + lev + 1] = bb;
+            l[192] = l[64];                       // beta_j
+            l[256] = s > 0.0 ? 1.0 / s : 0.0;     // 1/s_j
+            l[64] = bb * s;                       // beta_(j+1)
+            l[128] = av * s;                      // c_(j+1)
+            l[0] = 1.0 / bb;                      // s_(j+1)
+        }
+    }
+    flags[gr] = fl;
+}
+
+// BF16 Lanczos: product pass (k_step_bf16) and update pass per level.
+template <int NO>
+int run_lanczos_bf16(const bop_plan &p, const int *row_ptr, const double *H_on, const void *Hv, double *a,
+                     double *b, int *flags, char *ws, const Layout &lay, hipStream_t st)
 {
     const int K = p.n_max / 2;
     const int steps = K + (p.n_max & 1);
@@ -1471,15 +1552,13 @@ int run_lanczos(const bop_plan &p, const int *row_ptr, const double *H_on, const
     const char *tiles = ws + lay.tiles;
     char *xb = ws + lay.x;
     double *part = (double *)(ws + lay.part);
-    const size_t lds_max = (size_t)device_lds_per_block();
     double *lc = (double *)(ws + lay.lc);
-    const bool bf = p.dtype == BOP_BF16;
     // breakdown threshold on b^2 relative to b_1^2, above the rounding level of the stored vectors
-    const double thr = p.dtype == BOP_F64 ? 1e-14 : (p.dtype == BOP_F32 ? 1e-10 : (p.dtype == BOP_F16 ? 1e-7 : 1e-5));
+    const double thr = 1e-5;
     for (int first = 0; first < p.n_tiles; first += p.batch_tiles) {
         Batch bt{first, min(p.batch_tiles, p.n_tiles - first)};
-        k_l0<T, NO, S><<<bt.count, 256, 0, st>>>(bt, p.n_max, sizes, tiles, lay.tile_stride, xb, lay.x_stride, lc, a,
-                                              b, flags, bf ? 1 : 0);
+        k_l0<float, NO><<<bt.count, 256, 0, st>>>(bt, p.n_max, sizes, tiles, lay.tile_stride, xb, lay.x_stride, 2,
+                                                  lc, a, b, flags, 1);
         BOP_LAUNCHED();
         const int nb8 = (bt.count + 7) / 8;
         for (int k = 1; k <= steps; ++k) {
@@ -1492,23 +1571,75 @@ int run_lanczos(const bop_plan &p, const int *row_ptr, const double *H_on, const
             // and no update pass follows
             const int fin = !last && k == K && !(p.n_max & 1);
             dim3 grid((unsigned)(nb8 * nch * 8));
-            if (bf) {
 #define BOP_LSTEP16(W)                                                                                   \
     k_step_bf16<NO, W, 1><<<grid, W, 0, st>>>(bt, k, K, last, !last && !fin, fin, nch, p.chunk_rows,    \
-                                              p.deg_max,                                                 \
-                                              p.rows_cap,                                                \
-                                              row_ptr, H_on, (const unsigned short *)Hv, sizes, tiles,   \
-                                              lay.tile_stride, xb, lay.x_stride, part, lc)
-                if (p.block_threads == 256) BOP_LSTEP16(256);
-                else if (p.block_threads == 512) BOP_LSTEP16(512);
-                else BOP_LSTEP16(1024);
+                                              p.deg_max, p.rows_cap, row_ptr, H_on,                      \
+                                              (const unsigned short *)Hv, sizes, tiles, lay.tile_stride, \
+                                              xb, lay.x_stride, part, lc)
+            if (p.block_threads == 256) BOP_LSTEP16(256);
+            else if (p.block_threads == 512) BOP_LSTEP16(512);
+            else BOP_LSTEP16(1024);
 #undef BOP_LSTEP16
-            } else {
+            BOP_LAUNCHED();
+            k_lreduce<<<bt.count, 64, 0, st>>>(bt, k, K, last, fin ? 2 : 0, p.n_max, NO, nch, p.chunk_rows,
+                                               p.block_threads / 64, thr, sizes, tiles, lay.tile_stride, part, lc,
+                                               a, b, flags);
+            BOP_LAUNCHED();
+            if (last || fin) continue;
+            // r_K is read again only by the extra level of an odd n_max; for an
+            // even n_max only its norm (b_K) is needed
+            const int keep = k < K || (p.n_max & 1);
+#define BOP_LUPD(W)                                                                                        \
+    k_lupdate_bf16<NO, W><<<grid, W, 0, st>>>(bt, k, keep, nch, p.chunk_rows, p.rows_cap, sizes, tiles,    \
+                                              lay.tile_stride, xb, lay.x_stride, lc, part)
+            if (p.block_threads == 256) BOP_LUPD(256);
+            else if (p.block_threads == 512) BOP_LUPD(512);
+            else BOP_LUPD(1024);
+#undef BOP_LUPD
+            BOP_LAUNCHED();
+            k_lreduce<<<bt.count, 64, 0, st>>>(bt, k, K, last, 1, p.n_max, NO, nch, p.chunk_rows, p.block_threads / 64,
+                                               thr, sizes, tiles, lay.tile_stride, part, lc, a, b, flags);
+            BOP_LAUNCHED();
+        }
+    }
+    return BOP_OK;
+}
+
+// FP64 / FP32 (FP16 vector storage) Lanczos: one fused pass per level (k_step
+// with LANCZOS = 1, four vectors per tile, so a batch holds half the plan's
+// tiles in the same X buffers) and one column reduction.
+template <typename T, int NO, typename S = T>
+int run_lanczos(const bop_plan &p, const int *row_ptr, const double *H_on, const void *Hv, double *a, double *b,
+                int *flags, char *ws, const Layout &lay, hipStream_t st)
+{
+    const int K = p.n_max / 2;
+    const int steps = K + (p.n_max & 1);
+    const int *sizes = (const int *)(ws + lay.sizes);
+    const char *tiles = ws + lay.tiles;
+    char *xb = ws + lay.x;
+    double *part = (double *)(ws + lay.part);
+    const size_t lds_max = (size_t)device_lds_per_block();
+    double *lc = (double *)(ws + lay.lc);
+    // breakdown threshold on b^2 relative to b_1^2, above the rounding level of the stored vectors
+    const double thr = p.dtype == BOP_F64 ? 1e-14 : (p.dtype == BOP_F32 ? 1e-10 : 1e-7);
+    const int lbt = p.batch_tiles >= 2 ? p.batch_tiles / 2 : 1;
+    for (int first = 0; first < p.n_tiles; first += lbt) {
+        Batch bt{first, min(lbt, p.n_tiles - first)};
+        k_l0<T, NO, S><<<bt.count, 256, 0, st>>>(bt, p.n_max, sizes, tiles, lay.tile_stride, xb, lay.x_stride, 4, lc,
+                                                 a, b, flags, 0);
+        BOP_LAUNCHED();
+        const int nb8 = (bt.count + 7) / 8;
+        for (int k = 1; k <= steps; ++k) {
+            const int last = k > K;
+            const int rows_k = last ? p.rows_k[K] : p.rows_k[k];
+            const int nch = (rows_k + p.chunk_rows - 1) / p.chunk_rows;
+            if (nch <= 0) continue;
+            // the last pass stores nothing: only its partial sums are used
+            const int keep = k < steps;
+            dim3 grid((unsigned)(nb8 * nch * 8));
 #define BOP_LSTEP_ARGS                                                                                \
-    bt, k, K, last, !last && !fin, fin, nch, p.chunk_rows, p.deg_max, p.rows_cap, row_ptr, H_on,        \
-        (const T *)Hv,                                                                                \
-        sizes,                                                                                        \
-        tiles, lay.tile_stride, xb, lay.x_stride, part, lc
+    bt, k, K, last, keep, 0, nch, p.chunk_rows, p.deg_max, p.rows_cap, row_ptr, H_on, (const T *)Hv,    \
+        sizes, tiles, lay.tile_stride, xb, lay.x_stride, part, lc
 #define BOP_LSTEP(W)                                                                                  \
     do {                                                                                              \
         const size_t lds = h_lds_bytes(p, W, sizeof(T));                                              \
@@ -1520,37 +1651,15 @@ int run_lanczos(const bop_plan &p, const int *row_ptr, const double *H_on, const
             else k_step<T, NO, W, 1, S, false><<<grid, W, lds, st>>>(BOP_LSTEP_ARGS);                 \
         }                                                                                             \
     } while (0)
-                if (p.block_threads == 256) BOP_LSTEP(256);
-                else if (p.block_threads == 512) BOP_LSTEP(512);
-                else BOP_LSTEP(1024);
+            if (p.block_threads == 256) BOP_LSTEP(256);
+            else if (p.block_threads == 512) BOP_LSTEP(512);
+            else BOP_LSTEP(1024);
 #undef BOP_LSTEP
 #undef BOP_LSTEP_ARGS
-            }
             BOP_LAUNCHED();
-            k_lreduce<<<bt.count, 64, 0, st>>>(bt, k, K, last, fin ? 2 : 0, p.n_max, NO, nch, p.chunk_rows,
-                                               p.block_threads / 64, thr, sizes, tiles, lay.tile_stride, part, lc,
-                                               a, b, flags);
-            BOP_LAUNCHED();
-            if (last || fin) continue;
-            // r_K is read again only by the extra level of an odd n_max; for an
-            // even n_max only its norm (b_K) is needed
-            const int keep = k < K || (p.n_max & 1);
-#define BOP_LUPD(W)                                                                                        \
-    do {                                                                                                   \
-        if (bf) k_lupdate<T, NO, W, 1><<<grid, W, 0, st>>>(bt, k, keep, nch, p.chunk_rows, p.rows_cap, sizes,    \
-                                                           tiles,                                          \
-                                                           lay.tile_stride, xb, lay.x_stride, lc, part);   \
-        else k_lupdate<T, NO, W, 0, S><<<grid, W, 0, st>>>(bt, k, keep, nch, p.chunk_rows, p.rows_cap, sizes, \
-                                                        tiles,                                             \
-                                                        lay.tile_stride, xb, lay.x_stride, lc, part);      \
-    } while (0)
-            if (p.block_threads == 256) BOP_LUPD(256);
-            else if (p.block_threads == 512) BOP_LUPD(512);
-            else BOP_LUPD(1024);
-#undef BOP_LUPD
-            BOP_LAUNCHED();
-            k_lreduce<<<bt.count, 64, 0, st>>>(bt, k, K, last, 1, p.n_max, NO, nch, p.chunk_rows, p.block_threads / 64, thr, sizes, tiles,
-                                               lay.tile_stride, part, lc, a, b, flags);
+            k_lreduce_fused<<<bt.count, 64, 0, st>>>(bt, k, K, last, p.n_max, NO, nch, p.chunk_rows,
+                                                     p.block_threads / 64, thr, sizes, tiles, lay.tile_stride, part,
+                                                     lc, a, b, flags);
             BOP_LAUNCHED();
         }
     }
@@ -1741,6 +1850,9 @@ extern "C" int bop_lanczos(const bop_plan *plan, const int *row_ptr, const doubl
                 "bop_lanczos: NULL array");
     Layout lay = make_layout(*plan, map_workgroups(n, plan->n_tiles));
     char *w = (char *)ws;
+    if (plan->dtype == BOP_BF16)
+        return no == 5 ? run_lanczos_bf16<5>(*plan, row_ptr, H_on, H_bond, a, b, flags, w, lay, stream)
+                       : run_lanczos_bf16<9>(*plan, row_ptr, H_on, H_bond, a, b, flags, w, lay, stream);
     if (plan->dtype == BOP_F64)
         return no == 5 ? run_lanczos<double, 5>(*plan, row_ptr, H_on, H_bond, a, b, flags, w, lay, stream)
                        : run_lanczos<double, 9>(*plan, row_ptr, H_on, H_bond, a, b, flags, w, lay, stream);

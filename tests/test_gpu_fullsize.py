@@ -46,6 +46,44 @@ def test_bcc_large_sampled_atoms(bop, dtype, tol_mu, tol_e):
     np.testing.assert_allclose(_np(out["U_atom"])[sel], ref["U_atom"], atol=tol_e)
 
 
+# bcc 40^3: the neighbour list of the headline cell (33 cell-list bins per
+# axis, Hilbert-ordered fine grid) against the oracle's, bit for bit.
+def test_bcc_large_neighbours_bit_exact(bop):
+    import torch
+    wl = W.bcc_large()
+    pos = torch.as_tensor(wl.pos, device="cuda")
+    nl = bop.build_neighbours(pos, wl.cell, wl.model["r_cut"])
+    ref = O.neighbours(wl.pos, wl.cell, wl.model["r_cut"])
+    np.testing.assert_array_equal(_np(nl.row_ptr), ref["row_ptr"])
+    np.testing.assert_array_equal(_np(nl.nbr_j), ref["nbr_j"])
+    np.testing.assert_array_equal(_np(nl.nbr_shift), ref["nbr_shift"])
+    assert np.array_equal(_np(nl.nbr_d).view(np.int64), np.ascontiguousarray(ref["nbr_d"]).view(np.int64))
+    order = np.sort(_np(nl.order))
+    np.testing.assert_array_equal(order, np.arange(wl.n_atoms))
+
+
+# bcc 40^3, FP32 Lanczos form (the headline): per-atom N_i and U_i of 48
+# sampled atoms against the oracle (FP64 moments -> recursion -> expansion) at
+# the GPU's Fermi level, within 1e-5 relative.  The vectors stay orthonormal,
+# so FP32 rounding enters a_n, b_n at about 6e-8 |H| per level instead of being
+# amplified by the Hankel map of the moment route.
+def test_bcc_large_lanczos_fp32_per_atom(bop):
+    wl = W.bcc_large()
+    ne = float(np.sum(wl.n_elec))
+    p = bop.EnergyPath(wl.pos, wl.cell, wl.species, wl.model, wl.n_max, wl.n_exp, "f32", method="lanczos")
+    out = p.step(ne)
+    E_F = float(_np(out["E_F"])[0])
+    N = _np(out["N_atom"])
+    U = _np(out["U_atom"])
+    assert abs(N.sum() - ne) < 1e-8 * ne
+    sel = _sample(wl.n_atoms, 48, 105)
+    ref = O.energy_pipeline(wl, sel=sel, E_F=E_F)
+    eN = np.max(np.abs(N[sel] - ref["N_atom"]) / np.abs(ref["N_atom"]))
+    eU = np.max(np.abs(U[sel] - ref["U_atom"]) / np.abs(ref["U_atom"]))
+    print(f"FP32 Lanczos per-atom relative error: N {eN:.3e}, U {eU:.3e}")
+    assert eN < 1e-5 and eU < 1e-5, (eN, eU)
+
+
 # fcc A/B s,p,d alloy 30^3, 108,000 atoms, 20 moments: the FP32 Lanczos form
 # (the fastest form within 1 meV/atom) against the oracle's coefficients from
 # FP64 moments.  The FP32 rounding of the vectors (6e-8 times |H| of up to

@@ -129,7 +129,12 @@ def test_lanczos_scf_fp32_matches_oracle(bop):
 
 # FP16 storage of the Lanczos vectors (FP32 H and arithmetic): unit roundoff
 # 2^-11 per stored value times the spectral radius of these Hamiltonians
-# (about 10 eV) bounds a_n, b_n by 5e-3 eV; U within 1e-4 relative.
+# (about 10 eV) bounds a_n, b_n by 5e-3 eV.  A coefficient error d moves the
+# band by at most d, so U_ia by at most about N_ia d: 5e-3 relative in the
+# worst case; errors of different levels and orbitals largely cancel, and U is
+# held to 2e-4 relative (measured up to 1.1e-4 on the alloy: the fused level
+# pass rebuilds H r_(j-1) from the stored y'_j, one more FP16 rounding per
+# level than a separate update pass, which measured 1.0e-4).
 @pytest.mark.parametrize("name", ["bcc_small", "bcc_alloy", "fcc_spd", "hcp"])
 def test_lanczos_fp16_storage_bound(bop, name):
     wl = _wl(name)
@@ -141,7 +146,7 @@ def test_lanczos_fp16_storage_bound(bop, name):
     eu = abs(u - ref["U_total"]) / abs(ref["U_total"])
     print(f"{name}: f16 a {ea:.2e} b {eb:.2e} U rel {eu:.2e} ({abs(u - ref['U_total']) / wl.n_atoms * 1e3:.4f} meV/atom)")
     assert ea < 5e-3 and eb < 5e-3
-    assert eu < 1e-4
+    assert eu < 2e-4
 
 
 def test_moments_reject_fp16_storage(bop):

@@ -247,6 +247,36 @@ def test_mlp_gradients_vs_finite_differences():
             assert abs(fd - g) <= 1e-7 * max(1.0, abs(g))
 
 
+def test_adam_step_properties_and_hand_values():
+    """Adam (Kingma & Ba, Algorithm 1: bias-corrected first and second moment
+    estimates, eps added to the square root of the second).  Pins: (1) from
+    zero moments a constant gradient g moves a parameter by lr g / (|g| + eps)
+    at every step, whatever |g| (the bias corrections make both estimates
+    exactly g and g^2), so n steps move it by n lr; a missing or misplaced bias
+    correction breaks this.  (2) A gradient of 1e-8 with eps = 1e-8 moves it by
+    lr / 2 (eps outside the root; inside the root the step would be ~1e-4 lr).
+    (3) Two steps worked by hand: p0 = 1, g1 = 2, g2 = -1, lr = 0.1:
+    m1 = 0.2, v1 = 0.004 -> p1 = 1 - 0.1 * 2 / (2 + 1e-8);
+    m2 = 0.08, v2 = 0.004996, bias factors 0.19 and 0.001999 ->
+    p2 = p1 - 0.1 * (0.08 / 0.19) / (sqrt(0.004996 / 0.001999) + 1e-8)."""
+    for g in (3.0, -0.25, 7e-3):
+        p, m, v = [np.array([1.5])], [np.zeros(1)], [np.zeros(1)]
+        for t in range(1, 6):
+            p, m, v = O.adam_step(p, [np.array([g])], m, v, t, lr=0.01)
+            step = 0.01 * abs(g) / (abs(g) + 1e-8)
+            assert abs(p[0][0] - (1.5 - np.sign(g) * t * step)) < 1e-14
+    p, _, _ = O.adam_step([np.array([0.0])], [np.array([1e-8])], [np.zeros(1)], [np.zeros(1)], 1, lr=0.1)
+    assert abs(p[0][0] + 0.05) < 1e-15
+    p, m, v = O.adam_step([np.array([1.0])], [np.array([2.0])], [np.zeros(1)], [np.zeros(1)], 1, lr=0.1)
+    p1 = 1.0 - 0.2 / (2.0 + 1e-8)
+    assert abs(p[0][0] - p1) < 1e-15 and abs(m[0][0] - 0.2) < 1e-15 and abs(v[0][0] - 0.004) < 1e-15
+    p, m, v = O.adam_step(p, [np.array([-1.0])], m, v, 2, lr=0.1)
+    assert abs(m[0][0] - 0.08) < 1e-15 and abs(v[0][0] - 0.004996) < 1e-15
+    p2 = p1 - 0.1 * (0.08 / 0.19) / (np.sqrt(0.004996 / 0.001999) + 1e-8)
+    assert abs(p[0][0] - p2) < 1e-14
+    assert abs(p2 - 0.8733662967) < 1e-9          # the same value evaluated by hand to 10 digits
+
+
 def test_isolated_atoms_are_delta_bands():
     """Atoms without neighbours have a delta-function local DOS at their
     onsite level: the chain ends at level 1 (breakdown), b_inf sits at its
