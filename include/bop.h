@@ -19,7 +19,8 @@
  *  - Array arguments are device pointers to caller-owned, contiguous, row-major
  *    memory unless marked [host].  The library allocates no device memory; any
  *    scratch comes from a caller buffer whose size a *_workspace_size /
- *    *_plan call reports.
+ *    *_plan call reports (bop_energy_noalloc instead uses a fixed device
+ *    array of the library).
  *  - Every call takes the HIP stream last, only enqueues work on it and returns;
  *    exceptions (documented per call) read a count back to the host.
  *    Buffers must stay alive until the stream's work has completed.
@@ -314,6 +315,25 @@ int bop_energy(int n_atoms, int n_orb, int n_max, int n_exp, const double *mu,
                int ef_mode, double *E_F, double *N_atom, double *U_atom,
                double *dos_atom, double *U_total, int *flags,
                void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* =========================================================================
+ * bop_energy without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation).  Same arguments, kernels and results as bop_energy;
+ * the workspace is a fixed device array of BOP_ENERGY_NOALLOC_BYTES (64 MiB),
+ * one per GPU the library runs on, kept until the process ends.  Fits n_atoms
+ * * n_orb * (n_exp + 1) * 8 bytes plus small partials: about 8,000 d-band
+ * atoms or 4,500 s,p,d atoms at n_exp = 200.  Larger inputs: BOP_E_CAPACITY
+ * (nothing enqueued).  It calls no allocator.  All calls on one GPU share the
+ * array, which keeps the last call's contents: calls that overlap on one GPU
+ * (several streams or threads) race.
+ * ========================================================================= */
+#define BOP_ENERGY_NOALLOC_BYTES (64ull << 20)
+int bop_energy_noalloc(int n_atoms, int n_orb, int n_max, int n_exp, const double *mu,
+                       const double *a, const double *b, const double *a_inf,
+                       const double *b_inf, const double *H_on, double n_elec /*[host]*/,
+                       int ef_mode, double *E_F, double *N_atom, double *U_atom,
+                       double *dos_atom, double *U_total, int *flags, hipStream_t stream);
 
 /* =========================================================================
  * One local-charge-neutrality step (App. A.3 Eq. BOP_LCN with the linear

@@ -117,6 +117,8 @@ def load(path: str = LIB_PATH):
     lib.bop_energy_workspace_size.argtypes = [C.c_int, C.c_int, C.c_int]
     lib.bop_energy.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, P, P, P, P, P, P, C.c_double, C.c_int,
                                P, P, P, P, P, P, P, C.c_size_t, P]
+    lib.bop_energy_noalloc.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, P, P, P, P, P, P, C.c_double, C.c_int,
+                                       P, P, P, P, P, P, P]
     lib.bop_scf_step.argtypes = [C.POINTER(System), C.c_double, C.c_double, C.c_double, P, P, P, P, P]
     lib.bop_features.argtypes = [C.c_int, C.c_int, C.c_int, P, P, P, P, P]
     lib.bop_mlp_forward.argtypes = [C.c_int, P, P, P, P]
@@ -410,6 +412,35 @@ def energy(mu, rec, H_on, n_elec, n_max, n_exp=200, E_F=None, ws=None):
     out["E_F"] = ef
     out["U_total"] = ut
     return out
+
+
+def energy_noalloc(mu, rec, H_on, n_elec, n_max, n_exp=200, E_F=None, out=None):
+    """``energy`` through ``bop_energy_noalloc``: the library's fixed scratch
+    array instead of a workspace.  Output tensors may be passed in ``out``
+    (keys N_atom, U_atom, dos_atom, E_F, U_total) so that the call allocates
+    nothing."""
+    torch = _torch()
+    lib = load()
+    n, no = H_on.shape
+    dev = H_on.device
+    o = dict(out or {})
+    for k in ("N_atom", "U_atom", "dos_atom"):
+        if k not in o:
+            o[k] = torch.empty(n, dtype=torch.float64, device=dev)
+    if "U_total" not in o:
+        o["U_total"] = torch.zeros(1, dtype=torch.float64, device=dev)
+    ef_mode = 0
+    if E_F is not None:
+        ef_mode = 1
+        o["E_F"] = E_F if isinstance(E_F, torch.Tensor) else torch.tensor([float(E_F)], dtype=torch.float64,
+                                                                          device=dev)
+    elif "E_F" not in o:
+        o["E_F"] = torch.zeros(1, dtype=torch.float64, device=dev)
+    _check(lib.bop_energy_noalloc(n, no, n_max, n_exp, _ptr(mu), _ptr(rec["a"]), _ptr(rec["b"]), _ptr(rec["a_inf"]),
+                                  _ptr(rec["b_inf"]), _ptr(H_on), float(n_elec), ef_mode, _ptr(o["E_F"]),
+                                  _ptr(o["N_atom"]), _ptr(o["U_atom"]), _ptr(o["dos_atom"]), _ptr(o["U_total"]),
+                                  _ptr(rec["flags"]), _stream()))
+    return o
 
 
 class EnergyPath:

@@ -24,6 +24,7 @@
 #include "bop_internal.h"
 
 #include <cmath>
+#include <mutex>
 
 namespace bop {
 namespace {
@@ -665,11 +666,11 @@ extern "C" size_t bop_energy_workspace_size(int n_atoms, int n_orb, int n_exp)
     return carve(nullptr, (long)n_atoms * n_orb, n_exp).bytes + 256;
 }
 
-extern "C" int bop_energy(int n_atoms, int no, int n_max, int n_exp, const double *mu, const double *a,
-                          const double *b, const double *a_inf, const double *b_inf, const double *H_on,
-                          double n_elec, int ef_mode, double *E_F, double *N_atom, double *U_atom,
-                          double *dos_atom, double *U_total, int *flags, void *ws, size_t ws_bytes,
-                          hipStream_t stream)
+static int energy_impl(int n_atoms, int no, int n_max, int n_exp, const double *mu, const double *a,
+                       const double *b, const double *a_inf, const double *b_inf, const double *H_on,
+                       double n_elec, int ef_mode, double *E_F, double *N_atom, double *U_atom,
+                       double *dos_atom, double *U_total, int *flags, void *ws, size_t ws_bytes,
+                       hipStream_t stream)
 {
     BOP_REQUIRE(n_atoms > 0 && no > 0, BOP_E_ARG, "bop_energy: n_atoms and n_orb must be > 0");
     BOP_REQUIRE(no <= 9, BOP_E_UNSUPPORTED, "bop_energy: at most 9 orbitals per atom");
@@ -707,6 +708,69 @@ extern "C" int bop_energy(int n_atoms, int no, int n_max, int n_exp, const doubl
     k_energy_total<<<1, DT, 0, stream>>>(ablk, w.part, U_total);
     BOP_LAUNCHED();
     return BOP_OK;
+}
+
+extern "C" int bop_energy(int n_atoms, int no, int n_max, int n_exp, const double *mu, const double *a,
+                          const double *b, const double *a_inf, const double *b_inf, const double *H_on,
+                          double n_elec, int ef_mode, double *E_F, double *N_atom, double *U_atom,
+                          double *dos_atom, double *U_total, int *flags, void *ws, size_t ws_bytes,
+                          hipStream_t stream)
+{
+    return energy_impl(n_atoms, no, n_max, n_exp, mu, a, b, a_inf, b_inf, H_on, n_elec, ef_mode, E_F, N_atom,
+                       U_atom, dos_atom, U_total, flags, ws, ws_bytes, stream);
+}
+
+// ---------------------------------------------------------------------------
+// bop_energy without a caller workspace: the expansion coefficients, block
+// partials and Fermi state live in a fixed device array of
+// BOP_ENERGY_NOALLOC_BYTES, one copy per GPU the library runs on, held until
+// the process ends.  Nothing in it must start at zero: every kernel writes the
+// part of the workspace it reads before reading it.  Calls that overlap on one
+// GPU (several streams or threads) share the array and race.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) char scratch[BOP_ENERGY_NOALLOC_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+void *scratch_ptr[MAX_DEVICES];     // the array's device address on each GPU (NULL: not looked up yet)
+}  // namespace
+
+// The device address of `scratch` on the current GPU, looked up once per GPU
+// with that GPU current.  The array's name in host code is only a host-side
+// handle, never a device address.
+static int scratch_address(void **out)
+{
+    int dev = -1;
+    BOP_HIP(hipGetDevice(&dev));
+    BOP_REQUIRE(dev >= 0 && dev < MAX_DEVICES, BOP_E_UNSUPPORTED, "bop_energy_noalloc: device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_ptr[dev]) {
+        void *p = nullptr;
+        BOP_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        BOP_REQUIRE(p, BOP_E_HIP, "bop_energy_noalloc: no device address for the scratch array");
+        scratch_ptr[dev] = p;
+    }
+    *out = scratch_ptr[dev];
+    return BOP_OK;
+}
+
+extern "C" int bop_energy_noalloc(int n_atoms, int no, int n_max, int n_exp, const double *mu, const double *a,
+                                  const double *b, const double *a_inf, const double *b_inf, const double *H_on,
+                                  double n_elec, int ef_mode, double *E_F, double *N_atom, double *U_atom,
+                                  double *dos_atom, double *U_total, int *flags, hipStream_t stream)
+{
+    BOP_REQUIRE(n_atoms > 0 && no > 0 && n_exp >= 0, BOP_E_ARG, "bop_energy_noalloc: n_atoms and n_orb must be > 0");
+    const size_t need = carve(nullptr, (long)n_atoms * no, n_exp).bytes;
+    BOP_REQUIRE(need <= BOP_ENERGY_NOALLOC_BYTES, BOP_E_CAPACITY,
+                "bop_energy_noalloc: %d atoms x %d orbitals at n_exp %d need %zu bytes of scratch, more than its "
+                "fixed %llu; use bop_energy with a caller workspace",
+                n_atoms, no, n_exp, need, (unsigned long long)BOP_ENERGY_NOALLOC_BYTES);
+    void *ws = nullptr;
+    const int rc = scratch_address(&ws);
+    if (rc != BOP_OK) return rc;
+    return energy_impl(n_atoms, no, n_max, n_exp, mu, a, b, a_inf, b_inf, H_on, n_elec, ef_mode, E_F, N_atom,
+                       U_atom, dos_atom, U_total, flags, ws, BOP_ENERGY_NOALLOC_BYTES, stream);
 }
 
 namespace bop {
