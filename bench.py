@@ -433,7 +433,7 @@ def bench_scf(args, torch, P, W):
     model = WS.fit(x[:rows_fit], t[:rows_fit], epochs=args.epochs, batch=4096, lr=1e-3)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t1
-    xv = (x[rows_fit:] - model.mean) / model.std
+    xv = P.standardise(x[rows_fit:].contiguous(), model.mean, model.std)
     yv = model.predict(xv).double()
     # gauge: compare mean-free predictions per validation structure
     off = rows_fit

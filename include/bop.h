@@ -266,15 +266,38 @@ int bop_lanczos(const bop_plan *plan /*[host]*/, const int *row_ptr, const doubl
  * unnormalised Lanczos vector (the printed Eq. momtob needs c^n before b_n
  * is known).  Breakdown (b_(n+1)^2 <= 1e-14 (mu_2 - mu_1^2)) sets b_(n+1) = 0,
  * repeats a_n, and flags BOP_FLAG_BREAKDOWN | level << 8.
- * bw_mode 0: Gershgorin band edges Eq. (gershogorin) over rows n < n_a (b_0 = 0,
- * b_(n_a) used only if computed); a_inf = (top + bottom)/2, b_inf =
- * (top - bottom)/4.  bw_mode 1: the given global a_glob, b_glob (option viii).
+ * bw_mode (App. B.5 estimates of the centre a_inf = A and width b_inf = B):
+ *  BOP_BW_GERSHGORIN (vii)  band edges of Eq. (gershogorin) over rows n < n_a
+ *                       (b_0 = 0, b_(n_a) used only if computed); A = (top +
+ *                       bottom)/2, B = (top - bottom)/4.  The default.
+ *  BOP_BW_GLOBAL (viii) the given a_glob, b_glob for every row.
+ *  BOP_BW_LOWEST (i)    A = a_0, B = b_1.
+ *  BOP_BW_HIGHEST (ii)  the highest computed a_n and b_n.
+ *  BOP_BW_AVERAGE (iii) A = mean a_n, B = sqrt(mean b_n^2).
+ *  BOP_BW_AVERAGE_HIGHEST (iv)  A = mean a_n, B = highest computed b_n.
+ *  BOP_BW_MINMAX (v)    A = (max a + min a)/2, B = (max a - min a + 4 max b)/4,
+ *                       Eq. (findeminemax).
+ *  BOP_BW_WEIGHTED      the weighted-average terminator of App. B.1 Eq.
+ *                       (weighted), beta = a_glob >= 0: w_m = 1/(beta (M - m) +
+ *                       1), m = 0..M for a and 1..M for b, M the highest
+ *                       computed level; the averages serve as the constant
+ *                       tail and as the expansion's centre and width.
+ *  Options i-v and the weighted average use the levels computed before a
+ *  breakdown only (flag level L: a_0..a_(L-1), b_1..b_(L-1)).
  *
  *  mu [n_rows][n_max+1] -> a [n_rows][n_a], b [n_rows][n_b+1],
  *  a_inf, b_inf, flags [n_rows].   n_max <= 40.
  *  mu = NULL: a, b (and flags) are inputs from bop_lanczos; only a_inf, b_inf
  *  and the flags the terminator adds are written.
  * ========================================================================= */
+#define BOP_BW_GERSHGORIN      0
+#define BOP_BW_GLOBAL          1
+#define BOP_BW_LOWEST          2
+#define BOP_BW_HIGHEST         3
+#define BOP_BW_AVERAGE         4
+#define BOP_BW_AVERAGE_HIGHEST 5
+#define BOP_BW_MINMAX          6
+#define BOP_BW_WEIGHTED        7
 int bop_recursion(int n_rows, int n_max, const double *mu, int bw_mode,
                   double a_glob, double b_glob, double *a, double *b,
                   double *a_inf, double *b_inf, int *flags, hipStream_t stream);
@@ -369,6 +392,26 @@ int bop_scf_step(const bop_system *sys /*[host]*/, double mix, double n_floor,
                  int *converged, hipStream_t stream);
 
 /* =========================================================================
+ * The same step with Broyden mixing (Sec. II "Self-consistency", mixer (ii):
+ * Broyden's second method, updating an approximation H of the inverse
+ * Jacobian of the residual).  Residual F_i = q_i / max(n_i(E_F), n_floor), the
+ * linear mixer's output step; H_0 = -mix I, so a step from H_0 is linear
+ * mixing.  With s = shift_n - shift_(n-1), y = F_n - F_(n-1):
+ *   H_n = H_(n-1) + (s - H_(n-1) y) y^T / (y.y),  shift_(n+1) = shift_n - H_n F_n,
+ * then the mean shift is removed.  `iter` is the caller's 0-based iteration
+ * count of this cycle: position j = iter % (hist + 1) in the history, j = 0
+ * (the first step and every hist + 1 steps) starting again from H_0.  The
+ * history lives in `ws` (bop_broyden_workspace_size(n_atoms, hist) bytes,
+ * hist <= 64) and must be kept between the steps of one cycle.  Converged
+ * (max |q_i| < tol): nothing changes.
+ * ========================================================================= */
+size_t bop_broyden_workspace_size(int n_atoms, int hist);
+int bop_scf_step_broyden(const bop_system *sys /*[host]*/, double mix, double n_floor,
+                         double tol, int iter, int hist, double *shift, double *q,
+                         double *max_dq, int *converged, void *ws, size_t ws_bytes,
+                         hipStream_t stream);
+
+/* =========================================================================
  * Learned warm start (not in the paper: its Sec. III speed-up (ii), starting
  * the self-consistency from earlier onsite levels, generalised to a learned
  * map from an atom's lowest moments to its converged onsite shift).  FP32.
@@ -392,6 +435,19 @@ int bop_features(int n_atoms, int n_orb, int n_max, const double *mu, const floa
                  const float *std, float *x, hipStream_t stream);
 int bop_mlp_forward(int n_rows, const float *params, const float *x, float *y,
                     hipStream_t stream);
+/*  bop_feature_stats   mean[6] and std[6] (n - 1 normalisation, floored at
+ *                      1e-12) of the columns of x[n_rows][6]; FP64 sums in a
+ *                      fixed order.
+ *  bop_standardise     out[r][f] = (x[r][f] - mean[f]) / std[f] (may alias x).
+ *  bop_mlp_shift       the warm-start shifts: y = network(x[r]) in FP64, minus
+ *                      their mean (the gauge of the charge-neutrality cycle: a
+ *                      shift common to all atoms moves E_F with it and changes
+ *                      nothing else). */
+int bop_feature_stats(int n_rows, const float *x, float *mean, float *std, hipStream_t stream);
+int bop_standardise(int n_rows, const float *x, const float *mean, const float *std, float *out,
+                    hipStream_t stream);
+int bop_mlp_shift(int n_rows, const float *params, const float *x, double *shift,
+                  hipStream_t stream);
 size_t bop_mlp_train_workspace_size(int batch);
 int bop_mlp_train_step(int batch, const int *idx, const float *x, const float *t,
                        float *params, float *adam_m, float *adam_v, int step, float lr,

@@ -172,9 +172,15 @@ def n_b(n_max):
     return int(lib().or_n_b(n_max))
 
 
-def recursion(mu_rows, n_max, global_ab=None):
-    """Recursion coefficients and Gershgorin terminator per row (orbital).
-    ``mu_rows`` [R, n_max+1].  Returns dict(a, b, a_inf, b_inf, flags)."""
+BW_MODES = {"gershgorin": 0, "global": 1, "lowest": 2, "highest": 3, "average": 4, "average_highest": 5,
+            "minmax": 6, "weighted": 7}
+
+
+def recursion(mu_rows, n_max, global_ab=None, bw="gershgorin", beta=1.0):
+    """Recursion coefficients and terminator per row (orbital).  ``mu_rows``
+    [R, n_max+1]; ``bw`` one of BW_MODES (App. B.5 options i-v, vii, viii and
+    the weighted average of Eq. weighted with ``beta``).  Returns dict(a, b,
+    a_inf, b_inf, flags)."""
     mu_rows = _c(mu_rows, np.float64).reshape(-1, n_max + 1)
     R = mu_rows.shape[0]
     a = np.zeros((R, n_a(n_max)))
@@ -182,8 +188,11 @@ def recursion(mu_rows, n_max, global_ab=None):
     ai = np.zeros(R)
     bi = np.zeros(R)
     fl = np.zeros(R, np.int32)
-    mode, ag, bg = (0, 0.0, 0.0) if global_ab is None else (1, global_ab[0], global_ab[1])
-    lib().or_recursion(R, n_max, _p(mu_rows), mode, ag, bg, _p(a), _p(b), _p(ai), _p(bi), _p(fl))
+    if global_ab is not None:
+        mode, p1, p2 = 1, global_ab[0], global_ab[1]
+    else:
+        mode, p1, p2 = BW_MODES[bw], (beta if bw == "weighted" else 0.0), 0.0
+    lib().or_recursion(R, n_max, _p(mu_rows), mode, p1, p2, _p(a), _p(b), _p(ai), _p(bi), _p(fl))
     return {"a": a, "b": b, "a_inf": ai, "b_inf": bi, "flags": fl}
 
 
@@ -252,7 +261,8 @@ def rotation(u):
 
 
 # --------------------------------------------------------------------------
-def energy_pipeline(wl, shift=None, sel=None, n_max=None, n_exp=None, E_F=None, nl=None):
+def energy_pipeline(wl, shift=None, sel=None, n_max=None, n_exp=None, E_F=None, nl=None, bw="gershgorin",
+                    beta=1.0):
     """Whole path for a workload: neighbours -> H -> moments -> recursion ->
     DOS coefficients -> Fermi level (unless given) -> energies.  With ``sel``
     only those atoms' moments and energies are computed and ``E_F`` must be
@@ -265,7 +275,7 @@ def energy_pipeline(wl, shift=None, sel=None, n_max=None, n_exp=None, E_F=None, 
     mu = moments(nl, H_on, H_bond, n_max, sel)
     no = H_on.shape[1]
     rows = mu.reshape(-1, n_max + 1)
-    rec = recursion(rows, n_max)
+    rec = recursion(rows, n_max, bw=bw, beta=beta)
     gs = dos_coeffs(rows, rec, n_max, n_exp)
     Hs = H_on if sel is None else H_on[np.asarray(sel)]
     if E_F is None:
@@ -290,6 +300,72 @@ def scf(wl, shift0=None, mix=0.5, tol=1e-4, max_iter=200, n_floor=1e-3, n_max=No
             return shift, hist, r
         shift = shift_new
     return shift, hist, r
+
+
+class Broyden:
+    """Broyden's second method (Broyden 1965, the update of the inverse
+    Jacobian) for F(x) = 0, as a mixer of the self-consistency cycle (Sec. II
+    "Self-consistency", mixer (ii)).
+
+    H_0 = -eta I, so the first step x + eta F is linear mixing.  With s =
+    x_n - x_(n-1) and y = F_n - F_(n-1):
+        H_n = H_(n-1) + (s - H_(n-1) y) y^T / (y^T y),
+        x_(n+1) = x_n - H_n F_n.
+    H is kept as -eta I + sum_k u_k y_k^T with u_k = (s - H_(k-1) y) / (y^T y).
+    After ``hist`` updates the history is cleared (a restart from H_0).
+    Readings (the paper names the method only): F is the Newton-like output
+    step q_i / max(n_i(E_F), n_floor) of the linear mixer, and the mean of x
+    is removed after each step (the gauge of the charge-neutrality cycle)."""
+
+    def __init__(self, eta=0.5, hist=20, gauge=True):
+        self.eta, self.hist, self.gauge = float(eta), int(hist), gauge
+        self.u, self.y = [], []
+        self.x_prev = self.F_prev = None
+
+    def apply_H(self, v):
+        out = -self.eta * v
+        for u, y in zip(self.u, self.y):
+            out = out + u * np.dot(y, v)
+        return out
+
+    def step(self, x, F):
+        x = np.asarray(x, np.float64)
+        F = np.asarray(F, np.float64)
+        if self.x_prev is not None and len(self.u) >= self.hist:
+            self.u, self.y, self.x_prev, self.F_prev = [], [], None, None     # restart
+        if self.x_prev is not None:
+            s = x - self.x_prev
+            y = F - self.F_prev
+            yy = np.dot(y, y)
+            # an unchanged F (y = 0) gives no information: a zero update
+            self.u.append((s - self.apply_H(y)) / yy if yy > 0.0 else np.zeros_like(x))
+            self.y.append(y)
+        self.x_prev, self.F_prev = x.copy(), F.copy()
+        xn = x - self.apply_H(F)
+        if self.gauge:
+            xn = xn - xn.mean()
+        return xn
+
+
+def scf_broyden(wl, shift0=None, mix=0.5, tol=1e-4, max_iter=200, n_floor=1e-3, n_max=None, hist=20):
+    """Charge-neutrality cycle with Broyden mixing; returns (shift, history,
+    last pipeline result).  Convergence test as in the linear cycle: stop,
+    with the shifts unchanged, once max |q_i| < tol."""
+    n = wl.n_atoms
+    shift = np.zeros(n) if shift0 is None else np.array(shift0, float)
+    nl = neighbours(wl.pos, wl.cell, wl.model["r_cut"])
+    mixer = Broyden(mix, hist)
+    hist_out = []
+    for it in range(max_iter):
+        r = energy_pipeline(wl, shift=shift, nl=nl, n_max=n_max)
+        q = r["N_atom"] - wl.n_elec
+        mq = float(np.max(np.abs(q)))
+        hist_out.append({"it": it, "max_dq": mq, "U_total": r["U_total"], "E_F": r["E_F"]})
+        if mq < tol:
+            return shift, hist_out, r
+        F = q / np.maximum(r["dos_atom"], n_floor)
+        shift = mixer.step(shift, F)
+    return shift, hist_out, r
 
 
 # --------------------------------------------------------------------------
@@ -328,6 +404,20 @@ def mlp_loss_grad(params, x, t):
     gW1 = gz1.T @ x
     gb1 = gz1.sum(0)
     return loss, [gW1, gb1, gW2, gb2, gW3, gb3]
+
+
+def feature_stats(x):
+    """Column means and standard deviations (n - 1 normalisation, floored at
+    1e-12) of the feature rows x [n, 6]."""
+    x = np.asarray(x, np.float64)
+    return x.mean(0), np.maximum(x.std(0, ddof=1), 1e-12)
+
+
+def mlp_shift(params, x):
+    """Warm-start shifts: the network's outputs minus their mean (the gauge of
+    the charge-neutrality cycle)."""
+    y, _ = mlp_forward(params, x)
+    return y - y.mean()
 
 
 def adam_step(params, grads, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):

@@ -537,9 +537,90 @@ int or_n_b(int n_max) { return n_max / 2; }
  * Band edges: Gershgorin circles Eq. (gershogorin) over the computed rows
  * n = 0..n_a-1, with b_0 = 0 and b_(n_a) included only if it was computed;
  * a_inf = (E_top + E_bot)/2, b_inf = (E_top - E_bot)/4.  bw_mode 1 uses the
- * given global values instead (App. B.5 option (viii)).  b_inf below 1e-6 eV
- * is raised to 1e-6 eV (flag bit 8 = value 8).
+ * given global values instead (App. B.5 option (viii)); modes 2-7 are the
+ * other estimates of or_band_centre_width.  b_inf below 1e-6 eV is raised to
+ * 1e-6 eV (flag bit 8 = value 8).
  */
+/*
+ * Centre a_inf = A and half-width parameter b_inf = B of the terminator from
+ * the computed chain a[0..na-1], b[1..nb] (App. B.5; App. B.1 Eq. weighted).
+ *   0  Gershgorin circles, Eq. (gershogorin) (option vii)
+ *   1  the given global A = p1, B = p2 (option viii)
+ *   2  lowest computed coefficients (option i): A = a_0, B = b_1
+ *   3  highest computed coefficients (option ii)
+ *   4  averages (option iii): A = mean a_n, B = sqrt(mean b_n^2)
+ *   5  average centre, highest width (option iv): A = mean a_n, B = b_top
+ *   6  lowest band bottom and highest top (option v, Eq. findeminemax):
+ *      A = (max a + min a)/2, B = (max a - min a + 4 max b)/4
+ *   7  weighted averages, Eq. (weighted), with beta = p1:
+ *      w_m = 1/(beta (M - m) + 1) over m = 0..M for a, 1..M for b
+ * Readings: "lowest computed" a is a_0 (the printed a^(1) is the second
+ * level of a chain that starts at a^(0), Eq. DOS-G).  The sums and extremes
+ * of options i-v and the weighted average run over the levels the chain
+ * really computed: up to level L-1 if it broke down at level L (b_L = 0, the
+ * later a repeat a_(L-1)); M is the highest such level, separately for a and
+ * b.  The weighted average is used as the constant terminator of the tail
+ * (Eq. abinf with these values), which also centres and scales the Chebyshev
+ * expansion.  Option vi (Beer et al.) and the oscillating terminator need
+ * methods the paper only cites and are not provided.
+ */
+static void or_band_centre_width(int mode, double p1, double p2, const double *ar, const double *br, int na,
+                                 int nb, int fl, double *A, double *B)
+{
+    if (mode == 1) { *A = p1; *B = p2; return; }
+    if (mode == 0) {
+        double lo = 0.0, hi = 0.0;
+        for (int n = 0; n < na; ++n) {
+            double bl = (n >= 1 && n <= nb) ? br[n] : 0.0;
+            double bh = (n + 1 <= nb) ? br[n + 1] : 0.0;
+            double e0 = ar[n] - bl - bh, e1 = ar[n] + bl + bh;
+            if (n == 0 || e0 < lo) lo = e0;
+            if (n == 0 || e1 > hi) hi = e1;
+        }
+        *A = 0.5 * (hi + lo);
+        *B = 0.25 * (hi - lo);
+        return;
+    }
+    int nav = na, nbv = nb;            /* levels the chain computed */
+    if (fl & 1) {
+        int L = fl >> 8;
+        if (L < nav) nav = L;
+        if (L - 1 < nbv) nbv = L - 1;
+    }
+    double asum = 0.0, amax = 0.0, amin = 0.0, b2sum = 0.0, bmax = 0.0;
+    for (int n = 0; n < nav; ++n) {
+        asum += ar[n];
+        if (n == 0 || ar[n] > amax) amax = ar[n];
+        if (n == 0 || ar[n] < amin) amin = ar[n];
+    }
+    for (int n = 1; n <= nbv; ++n) {
+        b2sum += br[n] * br[n];
+        if (br[n] > bmax) bmax = br[n];
+    }
+    double amean = nav > 0 ? asum / nav : 0.0;
+    double blow = nbv >= 1 ? br[1] : 0.0, btop = nbv >= 1 ? br[nbv] : 0.0;
+    switch (mode) {
+    case 2: *A = nav > 0 ? ar[0] : 0.0; *B = blow; break;
+    case 3: *A = nav > 0 ? ar[nav - 1] : 0.0; *B = btop; break;
+    case 4: *A = amean; *B = nbv > 0 ? sqrt(b2sum / nbv) : 0.0; break;
+    case 5: *A = amean; *B = btop; break;
+    case 6: *A = 0.5 * (amax + amin); *B = 0.25 * (amax - amin + 4.0 * bmax); break;
+    default: {
+        double beta = p1, wa = 0.0, sa = 0.0, wb = 0.0, sb = 0.0;
+        for (int m = 0; m < nav; ++m) {
+            double w = 1.0 / (beta * (double)(nav - 1 - m) + 1.0);
+            wa += w; sa += w * ar[m];
+        }
+        for (int m = 1; m <= nbv; ++m) {
+            double w = 1.0 / (beta * (double)(nbv - m) + 1.0);
+            wb += w; sb += w * br[m];
+        }
+        *A = wa > 0.0 ? sa / wa : 0.0;
+        *B = wb > 0.0 ? sb / wb : 0.0;
+    }
+    }
+}
+
 void or_recursion(int n_rows, int n_max, const double *mu, int bw_mode,
                   double a_glob, double b_glob, double *a, double *b,
                   double *a_inf, double *b_inf, int *flags)
@@ -580,19 +661,7 @@ void or_recursion(int n_rows, int n_max, const double *mu, int bw_mode,
             for (int j = 0; j <= n + 1; ++j) { cprev[j] = ccur[j]; ccur[j] = d[j] / br[n + 1]; }
         }
         double ai, bi;
-        if (bw_mode == 1) { ai = a_glob; bi = b_glob; }
-        else {
-            double lo = 0.0, hi = 0.0;
-            for (int n = 0; n < na; ++n) {
-                double bl = (n >= 1 && n <= nb) ? br[n] : 0.0;
-                double bh = (n + 1 <= nb) ? br[n + 1] : 0.0;
-                double e0 = ar[n] - bl - bh, e1 = ar[n] + bl + bh;
-                if (n == 0 || e0 < lo) lo = e0;
-                if (n == 0 || e1 > hi) hi = e1;
-            }
-            ai = 0.5 * (hi + lo);
-            bi = 0.25 * (hi - lo);
-        }
+        or_band_centre_width(bw_mode, a_glob, b_glob, ar, br, na, nb, fl, &ai, &bi);
         if (bi < 1e-6) { bi = 1e-6; fl |= 8; }
         a_inf[r] = ai;
         b_inf[r] = bi;

@@ -120,8 +120,15 @@ def load(path: str = LIB_PATH):
     lib.bop_energy_noalloc.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, P, P, P, P, P, P, C.c_double, C.c_int,
                                        P, P, P, P, P, P, P]
     lib.bop_scf_step.argtypes = [C.POINTER(System), C.c_double, C.c_double, C.c_double, P, P, P, P, P]
+    lib.bop_broyden_workspace_size.restype = C.c_size_t
+    lib.bop_broyden_workspace_size.argtypes = [C.c_int, C.c_int]
+    lib.bop_scf_step_broyden.argtypes = [C.POINTER(System), C.c_double, C.c_double, C.c_double, C.c_int, C.c_int,
+                                         P, P, P, P, P, C.c_size_t, P]
     lib.bop_features.argtypes = [C.c_int, C.c_int, C.c_int, P, P, P, P, P]
     lib.bop_mlp_forward.argtypes = [C.c_int, P, P, P, P]
+    lib.bop_feature_stats.argtypes = [C.c_int, P, P, P, P]
+    lib.bop_standardise.argtypes = [C.c_int, P, P, P, P, P]
+    lib.bop_mlp_shift.argtypes = [C.c_int, P, P, P, P]
     lib.bop_mlp_train_workspace_size.restype = C.c_size_t
     lib.bop_mlp_train_workspace_size.argtypes = [C.c_int]
     lib.bop_mlp_train_step.argtypes = [C.c_int, P, P, P, P, P, P, C.c_int, C.c_float, P, P, P, C.c_size_t, P]
@@ -344,7 +351,17 @@ def lanczos(plan: Plan, nl: Neighbours, H_on, H_bond, out=None, ws=None, use_ord
     return {"a": a, "b": b, "flags": fl}
 
 
-def terminator(rec, n_max, global_ab=None):
+BW_MODES = {"gershgorin": 0, "global": 1, "lowest": 2, "highest": 3, "average": 4, "average_highest": 5,
+            "minmax": 6, "weighted": 7}
+
+
+def _bw_args(global_ab, bw, beta):
+    if global_ab is not None:
+        return 1, float(global_ab[0]), float(global_ab[1])
+    return BW_MODES[bw], (float(beta) if bw == "weighted" else 0.0), 0.0
+
+
+def terminator(rec, n_max, global_ab=None, bw="gershgorin", beta=1.0):
     """a_inf, b_inf (and terminator flags) for coefficients from ``lanczos``
     (``bop_recursion`` with mu = NULL); updates and returns ``rec``."""
     torch = _torch()
@@ -353,7 +370,7 @@ def terminator(rec, n_max, global_ab=None):
     for k in ("a_inf", "b_inf"):
         if k not in rec:
             rec[k] = torch.empty(R, dtype=torch.float64, device=dev)
-    mode, ag, bg = (0, 0.0, 0.0) if global_ab is None else (1, float(global_ab[0]), float(global_ab[1]))
+    mode, ag, bg = _bw_args(global_ab, bw, beta)
     _check(load().bop_recursion(R, n_max, None, mode, ag, bg, _ptr(rec["a"]), _ptr(rec["b"]), _ptr(rec["a_inf"]),
                                 _ptr(rec["b_inf"]), _ptr(rec["flags"]), _stream()))
     return rec
@@ -367,9 +384,9 @@ def n_b(n_max):
     return n_max // 2
 
 
-def recursion(mu_rows, n_max, global_ab=None, out=None):
+def recursion(mu_rows, n_max, global_ab=None, out=None, bw="gershgorin", beta=1.0):
     """Recursion coefficients a [R, n_a], b [R, n_b+1], a_inf, b_inf, flags
-    (``bop_recursion``)."""
+    (``bop_recursion``); ``bw`` selects the band centre/width estimate."""
     torch = _torch()
     lib = load()
     mu_rows = _dev(mu_rows.reshape(-1, n_max + 1), torch.float64, "mu")
@@ -381,7 +398,7 @@ def recursion(mu_rows, n_max, global_ab=None, out=None):
     ai = o.get("a_inf", torch.empty(R, dtype=torch.float64, device=dev))
     bi = o.get("b_inf", torch.empty(R, dtype=torch.float64, device=dev))
     fl = o.get("flags", torch.empty(R, dtype=torch.int32, device=dev))
-    mode, ag, bg = (0, 0.0, 0.0) if global_ab is None else (1, float(global_ab[0]), float(global_ab[1]))
+    mode, ag, bg = _bw_args(global_ab, bw, beta)
     _check(lib.bop_recursion(R, n_max, _ptr(mu_rows), mode, ag, bg, _ptr(a), _ptr(b), _ptr(ai), _ptr(bi),
                              _ptr(fl), _stream()))
     return {"a": a, "b": b, "a_inf": ai, "b_inf": bi, "flags": fl}
@@ -448,9 +465,12 @@ class EnergyPath:
     with every buffer allocated once (device tensors) and reused."""
 
     def __init__(self, pos, cell, species, model: dict, n_max: int, n_exp: int = 200, dtype: str = "f64",
-                 tuning=None, device="cuda", method: str = "moments"):
+                 tuning=None, device="cuda", method: str = "moments", bw: str = "gershgorin", beta: float = 1.0):
         torch = _torch()
         load()
+        if bw not in BW_MODES or bw == "global":
+            raise ValueError(f"bw must be one of {sorted(k for k in BW_MODES if k != 'global')}")
+        self.bw, self.beta = bw, float(beta)
         if method not in ("moments", "lanczos"):
             raise ValueError("method must be 'moments' or 'lanczos'")
         self.method = method
@@ -503,9 +523,9 @@ class EnergyPath:
 
     def run_tail(self, n_elec, E_F=None):
         if self.method == "lanczos":
-            terminator(self.rec, self.n_max)
+            terminator(self.rec, self.n_max, bw=self.bw, beta=self.beta)
             return energy(None, self.rec, self.H_on, n_elec, self.n_max, self.n_exp, E_F=E_F, ws=self.ews)
-        recursion(self.mu, self.n_max, out=self.rec)
+        recursion(self.mu, self.n_max, out=self.rec, bw=self.bw, beta=self.beta)
         return energy(self.mu, self.rec, self.H_on, n_elec, self.n_max, self.n_exp, E_F=E_F, ws=self.ews)
 
     def run(self, n_elec, E_F=None):
@@ -518,9 +538,14 @@ class SCFPath(EnergyPath):
     shift per atom, updated on the device until max |N_i - n0_i| < tol."""
 
     def __init__(self, pos, cell, species, model, n_max, n0, n_exp=200, dtype="f64", tuning=None, device="cuda",
-                 method="moments"):
+                 method="moments", mixer="linear", hist=20):
         super().__init__(pos, cell, species, model, n_max, n_exp, dtype, tuning, device, method)
         torch = _torch()
+        if mixer not in ("linear", "broyden"):
+            raise ValueError("mixer must be 'linear' or 'broyden'")
+        self.mixer, self.hist, self.iter = mixer, int(hist), 0
+        self.bws = _bytes(load().bop_broyden_workspace_size(self.n, self.hist), self.device) \
+            if mixer == "broyden" else None
         self.n0 = torch.as_tensor(np.ascontiguousarray(n0, np.float64), device=self.device)
         self.n_elec = float(np.sum(n0))
         self.shift = torch.zeros(self.n, dtype=torch.float64, device=self.device)
@@ -551,14 +576,24 @@ class SCFPath(EnergyPath):
         self.sys = s
 
     def set_shift(self, shift):
+        """Start a new cycle from ``shift`` (the Broyden history starts again)."""
         self.shift.copy_(_torch().as_tensor(shift, dtype=_torch().float64, device=self.device))
+        self.iter = 0
 
     def step(self, mix=0.5, n_floor=1e-3, tol=1e-4):
-        _check(load().bop_scf_step(C.byref(self.sys), float(mix), float(n_floor), float(tol), _ptr(self.shift),
-                                   _ptr(self.q), _ptr(self.max_dq), _ptr(self.converged), _stream()))
+        if self.mixer == "broyden":
+            _check(load().bop_scf_step_broyden(C.byref(self.sys), float(mix), float(n_floor), float(tol), self.iter,
+                                               self.hist, _ptr(self.shift), _ptr(self.q), _ptr(self.max_dq),
+                                               _ptr(self.converged), _ptr(self.bws), self.bws.numel(), _stream()))
+        else:
+            _check(load().bop_scf_step(C.byref(self.sys), float(mix), float(n_floor), float(tol), _ptr(self.shift),
+                                       _ptr(self.q), _ptr(self.max_dq), _ptr(self.converged), _stream()))
+        self.iter += 1
 
     def run_scf(self, mix=0.5, n_floor=1e-3, tol=1e-4, max_iter=200):
-        """Iterate until converged; returns (iterations, history of max|q|)."""
+        """Iterate from the current shifts until converged (a new cycle: the
+        Broyden history starts again); returns (iterations, history of max|q|)."""
+        self.iter = 0
         hist = []
         for it in range(max_iter):
             self.step(mix, n_floor, tol)
@@ -586,6 +621,35 @@ def mlp_forward(params, x):
     torch = _torch()
     y = torch.empty(x.shape[0], dtype=torch.float32, device=x.device)
     _check(load().bop_mlp_forward(x.shape[0], _ptr(params), _ptr(x), _ptr(y), _stream()))
+    return y
+
+
+def feature_stats(x):
+    """Column mean and std (n - 1) of the features x [n, 6] (``bop_feature_stats``)."""
+    torch = _torch()
+    mean = torch.empty(6, dtype=torch.float32, device=x.device)
+    std = torch.empty(6, dtype=torch.float32, device=x.device)
+    _check(load().bop_feature_stats(x.shape[0], _ptr(_dev(x, torch.float32, "x")), _ptr(mean), _ptr(std),
+                                    _stream()))
+    return mean, std
+
+
+def standardise(x, mean, std, out=None):
+    """(x - mean) / std per feature column (``bop_standardise``)."""
+    torch = _torch()
+    if out is None:
+        out = torch.empty_like(x)
+    _check(load().bop_standardise(x.shape[0], _ptr(_dev(x, torch.float32, "x")), _ptr(mean), _ptr(std), _ptr(out),
+                                  _stream()))
+    return out
+
+
+def mlp_shift(params, x):
+    """Gauge-fixed warm-start shifts (FP64, mean removed) for standardised
+    features x (``bop_mlp_shift``)."""
+    torch = _torch()
+    y = torch.empty(x.shape[0], dtype=torch.float64, device=x.device)
+    _check(load().bop_mlp_shift(x.shape[0], _ptr(params), _ptr(_dev(x, torch.float32, "x")), _ptr(y), _stream()))
     return y
 
 

@@ -38,6 +38,59 @@ __device__ inline int n_b_of(int n_max) { return n_max / 2; }
 // ---------------------------------------------------------------------------
 // recursion coefficients and band edges
 // ---------------------------------------------------------------------------
+// Centre and width of the terminator from a row's stored chain a[0..na-1],
+// b[1..nb] for the estimates of App. B.5 other than Gershgorin and the global
+// values: (i) lowest, (ii) highest computed levels, (iii) averages, (iv)
+// average centre with the highest width, (v) extreme a with the largest b
+// (Eq. findeminemax), and the weighted averages of Eq. (weighted) with
+// w_m = 1 / (beta (M - m) + 1).  Only the levels the chain computed count: up
+// to level L - 1 when it broke down at level L (flag level L).
+__device__ inline void band_estimate(int mode, double beta, const double *ar, const double *br, int na, int nb,
+                                     int fl, double &A, double &B)
+{
+    int nav = na, nbv = nb;
+    if (fl & BOP_FLAG_BREAKDOWN) {
+        const int L = fl >> 8;
+        nav = min(nav, L);
+        nbv = min(nbv, L - 1);
+    }
+    double asum = 0.0, amax = 0.0, amin = 0.0, b2sum = 0.0, bmax = 0.0;
+    for (int n = 0; n < nav; ++n) {
+        const double v = ar[n];
+        asum += v;
+        amax = n == 0 ? v : fmax(amax, v);
+        amin = n == 0 ? v : fmin(amin, v);
+    }
+    for (int n = 1; n <= nbv; ++n) {
+        const double v = br[n];
+        b2sum += v * v;
+        bmax = fmax(bmax, v);
+    }
+    const double amean = nav > 0 ? asum / nav : 0.0;
+    const double blow = nbv >= 1 ? br[1] : 0.0, btop = nbv >= 1 ? br[nbv] : 0.0;
+    switch (mode) {
+    case BOP_BW_LOWEST: A = nav > 0 ? ar[0] : 0.0; B = blow; break;
+    case BOP_BW_HIGHEST: A = nav > 0 ? ar[nav - 1] : 0.0; B = btop; break;
+    case BOP_BW_AVERAGE: A = amean; B = nbv > 0 ? sqrt(b2sum / nbv) : 0.0; break;
+    case BOP_BW_AVERAGE_HIGHEST: A = amean; B = btop; break;
+    case BOP_BW_MINMAX: A = 0.5 * (amax + amin); B = 0.25 * (amax - amin + 4.0 * bmax); break;
+    default: {
+        double wa = 0.0, sa = 0.0, wb = 0.0, sb = 0.0;
+        for (int m = 0; m < nav; ++m) {
+            const double w = 1.0 / (beta * (double)(nav - 1 - m) + 1.0);
+            wa += w;
+            sa += w * ar[m];
+        }
+        for (int m = 1; m <= nbv; ++m) {
+            const double w = 1.0 / (beta * (double)(nbv - m) + 1.0);
+            wb += w;
+            sb += w * br[m];
+        }
+        A = wa > 0.0 ? sa / wa : 0.0;
+        B = wb > 0.0 ? sb / wb : 0.0;
+    }
+    }
+}
 __global__ void __launch_bounds__(DT)
 k_recursion(int n_rows, int n_max, const double *__restrict__ mu, int bw_mode, double a_glob,
             double b_glob, double *__restrict__ a, double *__restrict__ b, double *__restrict__ a_inf,
@@ -93,7 +146,8 @@ k_recursion(int n_rows, int n_max, const double *__restrict__ mu, int bw_mode, d
     }
 terminator:
     double ai, bi;
-    if (bw_mode == 1) { ai = a_glob; bi = b_glob; }
+    if (bw_mode == BOP_BW_GLOBAL) { ai = a_glob; bi = b_glob; }
+    else if (bw_mode != BOP_BW_GERSHGORIN) band_estimate(bw_mode, a_glob, ar, br, na, nb, fl, ai, bi);
     else {
         double lo = 0.0, hi = 0.0;
         for (int n = 0; n < na; ++n) {
@@ -647,10 +701,14 @@ extern "C" int bop_recursion(int n_rows, int n_max, const double *mu, int bw_mod
 {
     BOP_REQUIRE(n_rows >= 0, BOP_E_ARG, "bop_recursion: n_rows < 0");
     BOP_REQUIRE(n_max >= 1 && n_max <= MAX_NMAX, BOP_E_UNSUPPORTED, "bop_recursion: n_max must be 1..%d", MAX_NMAX);
-    BOP_REQUIRE(bw_mode == 0 || bw_mode == 1, BOP_E_ARG, "bop_recursion: bw_mode must be 0 or 1");
+    BOP_REQUIRE(bw_mode >= BOP_BW_GERSHGORIN && bw_mode <= BOP_BW_WEIGHTED, BOP_E_ARG,
+                "bop_recursion: bw_mode must be %d..%d", BOP_BW_GERSHGORIN, BOP_BW_WEIGHTED);
+    BOP_REQUIRE(bw_mode != BOP_BW_WEIGHTED || a_glob >= 0.0, BOP_E_ARG, "bop_recursion: weighted beta must be >= 0");
     if (n_rows == 0) return BOP_OK;
     BOP_REQUIRE(a && b && a_inf && b_inf && flags, BOP_E_ARG, "bop_recursion: NULL array");
-    if (mu && n_max <= 20)
+    // the register kernel covers Gershgorin and the global values; the other
+    // estimates read the chain back from a and b in the generic kernel
+    if (mu && n_max <= 20 && bw_mode <= BOP_BW_GLOBAL)
         k_recursion_reg<20><<<(n_rows + DT - 1) / DT, DT, 0, stream>>>(n_rows, n_max, mu, bw_mode, a_glob, b_glob,
                                                                        a, b, a_inf, b_inf, flags);
     else

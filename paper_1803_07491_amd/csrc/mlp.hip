@@ -63,8 +63,9 @@ __device__ inline float forward_row(const float *s, const float *xr, float *h1, 
     return y;
 }
 
+template <typename Y>
 __global__ void __launch_bounds__(MT)
-k_mlp_forward(int n, const float *__restrict__ params, const float *__restrict__ x, float *__restrict__ y)
+k_mlp_forward(int n, const float *__restrict__ params, const float *__restrict__ x, Y *__restrict__ y)
 {
     __shared__ float s[NPARAM];
     load_params(params, s);
@@ -73,7 +74,60 @@ k_mlp_forward(int n, const float *__restrict__ params, const float *__restrict__
     float xr[NX], h1[NH], h2[NH];
 #pragma unroll
     for (int c = 0; c < NX; ++c) xr[c] = x[(long)r * NX + c];
-    y[r] = forward_row(s, xr, h1, h2);
+    y[r] = (Y)forward_row(s, xr, h1, h2);
+}
+
+// Column statistics of the features x[n][NX]: block f computes feature f's
+// mean and its standard deviation with the n - 1 normalisation (two passes,
+// FP64 sums in a fixed order), the deviation floored at 1e-12.
+__global__ void __launch_bounds__(MT)
+k_feature_stats(int n, const float *__restrict__ x, float *__restrict__ mean, float *__restrict__ stdv)
+{
+    __shared__ double s_red[MT / 64];
+    __shared__ double s_mean;
+    const int f = blockIdx.x;
+    double v = 0.0;
+    for (long r = threadIdx.x; r < n; r += MT) v += (double)x[r * NX + f];
+    v = block_combine(v, 0, s_red);
+    if (threadIdx.x == 0) s_mean = v / (double)n;
+    __syncthreads();
+    const double m = s_mean;
+    double q = 0.0;
+    for (long r = threadIdx.x; r < n; r += MT) {
+        const double d = (double)x[r * NX + f] - m;
+        q = fma(d, d, q);
+    }
+    q = block_combine(q, 0, s_red);
+    if (threadIdx.x == 0) {
+        mean[f] = (float)m;
+        const double sd = n > 1 ? sqrt(q / (double)(n - 1)) : 0.0;
+        stdv[f] = (float)fmax(sd, 1e-12);
+    }
+}
+
+__global__ void k_standardise(long n, const float *__restrict__ x, const float *__restrict__ mean,
+                              const float *__restrict__ stdv, float *__restrict__ out)
+{
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * NX) return;
+    const int f = (int)(e % NX);
+    out[e] = (x[e] - mean[f]) / stdv[f];
+}
+
+// Gauge fix of predicted shifts: y -= mean(y), one block, FP64 sum in a fixed
+// order (a shift common to all atoms moves E_F by the same amount and changes
+// nothing else, so predictions are compared and used mean-free).
+__global__ void __launch_bounds__(1024) k_remove_mean(int n, double *__restrict__ y)
+{
+    __shared__ double s_red[1024 / 64];
+    __shared__ double s_mean;
+    double v = 0.0;
+    for (int r = threadIdx.x; r < n; r += blockDim.x) v += y[r];
+    v = block_combine(v, 0, s_red);
+    if (threadIdx.x == 0) s_mean = v / (double)n;
+    __syncthreads();
+    const double m = s_mean;
+    for (int r = threadIdx.x; r < n; r += blockDim.x) y[r] -= m;
 }
 
 // per row: activations and back-propagated pre-activation gradients
@@ -234,7 +288,40 @@ extern "C" int bop_mlp_forward(int n_rows, const float *params, const float *x, 
     BOP_REQUIRE(n_rows >= 0, BOP_E_ARG, "bop_mlp_forward: n_rows < 0");
     if (n_rows == 0) return BOP_OK;
     BOP_REQUIRE(params && x && y, BOP_E_ARG, "bop_mlp_forward: NULL array");
-    k_mlp_forward<<<(n_rows + MT - 1) / MT, MT, 0, stream>>>(n_rows, params, x, y);
+    k_mlp_forward<float><<<(n_rows + MT - 1) / MT, MT, 0, stream>>>(n_rows, params, x, y);
+    BOP_LAUNCHED();
+    return BOP_OK;
+}
+
+extern "C" int bop_feature_stats(int n_rows, const float *x, float *mean, float *stdv, hipStream_t stream)
+{
+    BOP_REQUIRE(n_rows > 0, BOP_E_ARG, "bop_feature_stats: n_rows must be > 0");
+    BOP_REQUIRE(x && mean && stdv, BOP_E_ARG, "bop_feature_stats: NULL array");
+    k_feature_stats<<<NX, MT, 0, stream>>>(n_rows, x, mean, stdv);
+    BOP_LAUNCHED();
+    return BOP_OK;
+}
+
+extern "C" int bop_standardise(int n_rows, const float *x, const float *mean, const float *stdv, float *out,
+                               hipStream_t stream)
+{
+    BOP_REQUIRE(n_rows >= 0, BOP_E_ARG, "bop_standardise: n_rows < 0");
+    if (n_rows == 0) return BOP_OK;
+    BOP_REQUIRE(x && mean && stdv && out, BOP_E_ARG, "bop_standardise: NULL array");
+    const long ne = (long)n_rows * NX;
+    k_standardise<<<(unsigned)((ne + 255) / 256), 256, 0, stream>>>(n_rows, x, mean, stdv, out);
+    BOP_LAUNCHED();
+    return BOP_OK;
+}
+
+extern "C" int bop_mlp_shift(int n_rows, const float *params, const float *x, double *shift, hipStream_t stream)
+{
+    BOP_REQUIRE(n_rows >= 0, BOP_E_ARG, "bop_mlp_shift: n_rows < 0");
+    if (n_rows == 0) return BOP_OK;
+    BOP_REQUIRE(params && x && shift, BOP_E_ARG, "bop_mlp_shift: NULL array");
+    k_mlp_forward<double><<<(n_rows + MT - 1) / MT, MT, 0, stream>>>(n_rows, params, x, shift);
+    BOP_LAUNCHED();
+    k_remove_mean<<<1, 1024, 0, stream>>>(n_rows, shift);
     BOP_LAUNCHED();
     return BOP_OK;
 }

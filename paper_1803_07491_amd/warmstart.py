@@ -24,7 +24,8 @@ from __future__ import annotations
 import time
 from dataclasses import dataclass
 
-from . import EnergyPath, MLP, SCFPath, BopError, BOP_E_NOT_CONVERGED, features, _torch
+from . import (EnergyPath, MLP, SCFPath, BopError, BOP_E_NOT_CONVERGED, feature_stats, features, mlp_shift,
+               standardise, _torch)
 
 N_FEAT_MOMENTS = 6
 
@@ -116,20 +117,21 @@ def training_set(structures, log=None):
 
 
 def fit(x, t, epochs=50, batch=4096, lr=1e-3, seed=0):
-    """Standardise the features and train the network; returns the model."""
+    """Standardise the features (``bop_feature_stats``, ``bop_standardise``)
+    and train the network; returns the model."""
     m = MLP(seed=seed, device=x.device)
-    mean = x.mean(0)
-    std = x.std(0).clamp_min(1e-12)
+    mean, std = feature_stats(x)
     m.mean.copy_(mean)
     m.std.copy_(std)
-    m.train((x - mean) / std, t, epochs=epochs, batch=batch, lr=lr, seed=seed)
+    m.train(standardise(x, mean, std), t, epochs=epochs, batch=batch, lr=lr, seed=seed)
     return m
 
 
 def predict_shift(model, wl):
-    """Warm-start shifts for a structure (gauge-fixed: mean removed)."""
+    """Warm-start shifts for a structure: features of a 6-moment pass,
+    standardised with the training statistics, then ``bop_mlp_shift``
+    (network output with its mean removed)."""
     p = EnergyPath(wl.pos, wl.cell, wl.species, wl.model, N_FEAT_MOMENTS, wl.n_exp, "f64")
     p.run_moments()
     x = features(p.mu, p.no, N_FEAT_MOMENTS, model.mean, model.std)
-    y = model.predict(x).double()
-    return y - y.mean()
+    return mlp_shift(model.params, x)

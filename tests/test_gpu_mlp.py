@@ -71,3 +71,30 @@ def test_training_reduces_loss(bop):
     m.train(xd, td, epochs=20, batch=1024, lr=3e-3)
     l1, _ = m.grad(xd, td)
     assert float(l1.item()) < 0.1 * float(l0.item())
+
+
+def test_feature_stats_standardise_and_shift_match_oracle(bop):
+    """Feature statistics (FP64 sums of FP32 values: 1e-6 relative), the
+    standardisation (FP32, 1e-5) and the gauge-fixed shifts (the forward bound,
+    2e-5 of the output scale) against the oracle; 300,001 rows span many
+    reduction strides."""
+    import torch
+    rng = np.random.default_rng(4)
+    x = rng.normal(loc=[0.0, 1.0, -2.0, 5.0, 0.1, 30.0], scale=[1.0, 0.5, 3.0, 0.01, 2.0, 7.0], size=(300001, 6))
+    x32 = x.astype(np.float32)
+    xd = torch.tensor(x32, device="cuda")
+    mean, std = bop.feature_stats(xd)
+    m_ref, s_ref = O.feature_stats(x32.astype(np.float64))
+    assert np.max(np.abs(mean.cpu().numpy() - m_ref) / np.maximum(np.abs(m_ref), s_ref)) < 1e-6
+    assert np.max(np.abs(std.cpu().numpy() - s_ref) / s_ref) < 1e-6
+    # both sides standardise with the oracle's statistics (rounded to FP32)
+    m32, s32 = m_ref.astype(np.float32), s_ref.astype(np.float32)
+    z = bop.standardise(xd, torch.tensor(m32, device="cuda"), torch.tensor(s32, device="cuda")).cpu().numpy()
+    z_ref = (x32.astype(np.float64) - m32.astype(np.float64)) / s32.astype(np.float64)
+    assert np.max(np.abs(z - z_ref)) < 1e-5 * max(1.0, np.abs(z_ref).max())
+    arrs, _, _, p, _, _ = _setup(bop)
+    zd = torch.tensor(z_ref[:5000].astype(np.float32), device="cuda")
+    sh = bop.mlp_shift(p, zd).cpu().numpy()
+    sh_ref = O.mlp_shift(arrs, z_ref[:5000].astype(np.float32).astype(np.float64))
+    assert np.max(np.abs(sh - sh_ref)) < 2e-5 * max(1.0, np.abs(sh_ref).max())
+    assert abs(sh.sum()) < 1e-9 * 5000

@@ -225,6 +225,23 @@ def test_scf_fixed_point_and_invariants():
     assert np.mean(shift[spc == 1]) < np.mean(shift[spc == 0])
 
 
+def test_scf_broyden_reaches_the_linear_fixed_point():
+    """The Broyden cycle converges (max |q| < 1e-4) in fewer iterations than
+    linear mixing on the 54-atom alloy, to the same fixed point: shifts agree
+    within 1e-3 eV (both stop within 1e-4 electrons of charge neutrality; the
+    per-atom DOS at E_F is ~1 state/eV)."""
+    rng = np.random.default_rng(5)
+    pos, cell = W.cubic_lattice("bcc", 2.87, 3)
+    spc = W.random_species(54, [27, 27], rng)
+    wl = W.Workload("a", W.wrap(pos, cell), cell, spc, W.canonical_d_model(3.5, onsite_d=(0.0, 0.8)),
+                    8, 200, np.where(spc == 0, 6.0, 5.0))
+    s_lin, h_lin, _ = O.scf(wl, mix=0.5, tol=1e-4, max_iter=100)
+    s_bro, h_bro, r = O.scf_broyden(wl, mix=0.5, tol=1e-4, max_iter=100)
+    assert h_bro[-1]["max_dq"] < 1e-4 and len(h_bro) < len(h_lin)
+    assert abs(np.mean(s_bro)) < 1e-12
+    assert np.max(np.abs(s_bro - s_lin)) < 1e-3
+
+
 def test_mlp_gradients_vs_finite_differences():
     rng = np.random.default_rng(0)
     sizes = [(64, 6), (64,), (64, 64), (64,), (1, 64), (1,)]
@@ -275,6 +292,106 @@ def test_adam_step_properties_and_hand_values():
     p2 = p1 - 0.1 * (0.08 / 0.19) / (np.sqrt(0.004996 / 0.001999) + 1e-8)
     assert abs(p[0][0] - p2) < 1e-14
     assert abs(p2 - 0.8733662967) < 1e-9          # the same value evaluated by hand to 10 digits
+
+
+def test_feature_stats_and_gauge_closed_forms():
+    """Column statistics of 0, 1, ..., n-1 (scaled per column): mean (n-1)/2 and
+    sample variance n (n+1) / 12.  The gauge-fixed shifts sum to zero and keep
+    every difference of the network's outputs."""
+    n = 1001
+    x = np.arange(n, dtype=np.float64)[:, None] * np.array([1.0, 2.0, -0.5, 3.0, 0.25, 10.0])[None, :]
+    mean, std = O.feature_stats(x)
+    scale = np.array([1.0, 2.0, 0.5, 3.0, 0.25, 10.0])
+    assert np.allclose(mean, (n - 1) / 2 * np.array([1.0, 2.0, -0.5, 3.0, 0.25, 10.0]), rtol=1e-14)
+    assert np.allclose(std, np.sqrt(n * (n + 1) / 12.0) * scale, rtol=1e-13)
+    mean1, std1 = O.feature_stats(np.ones((5, 6)))
+    assert np.all(std1 == 1e-12) and np.all(mean1 == 1.0)
+    rng = np.random.default_rng(1)
+    params = [rng.normal(scale=0.3, size=sh) for sh in [(64, 6), (64,), (64, 64), (64,), (1, 64), (1,)]]
+    xs = rng.normal(size=(50, 6))
+    y, _ = O.mlp_forward(params, xs)
+    d = O.mlp_shift(params, xs)
+    assert abs(d.sum()) < 1e-12
+    assert np.allclose(d[1:] - d[:-1], y[1:] - y[:-1], atol=1e-14)
+
+
+def _chain_moments(a, b, n_max):
+    """Site-0 moments of a finite tridiagonal chain (a_0.., b_1..)."""
+    J = np.diag(a) + np.diag(b, 1) + np.diag(b, -1)
+    return np.array([np.linalg.matrix_power(J, n)[0, 0] for n in range(n_max + 1)])
+
+
+def test_band_centre_and_width_options_hand_values():
+    """App. B.5 options i-v, vii and the weighted average of Eq. (weighted) on a
+    chain with a = (0.5, -1, 2, 0.25), b = (1, 2, 0.5, 1.5), 8 moments (four
+    levels of each), worked by hand:
+      (i)   a_0, b_1                            -> 0.5, 1
+      (ii)  a_3, b_4                            -> 0.25, 1.5
+      (iii) mean a = 1.75/4, sqrt(mean b^2) = sqrt(7.5/4)
+      (iv)  mean a, b_4                         -> 0.4375, 1.5
+      (v)   (2 - 1)/2, (2 + 1 + 4*2)/4          -> 0.5, 2.75
+      (vii) edges -4 and 4.5 (rows 1 and 2)     -> 0.25, 2.125
+      weighted, beta = 1: w = 1/4, 1/3, 1/2, 1 for both a and b:
+            (0.125 - 1/3 + 1 + 0.25) / (25/12) = 0.5,
+            (0.25 + 2/3 + 0.25 + 1.5) / (25/12) = 1.28."""
+    a = [0.5, -1.0, 2.0, 0.25, 0.7]          # a_4 does not enter 8 moments
+    b = [1.0, 2.0, 0.5, 1.5]
+    mu = _chain_moments(a, b, 8)[None, :]
+    want = {"lowest": (0.5, 1.0), "highest": (0.25, 1.5), "average": (0.4375, math.sqrt(1.875)),
+            "average_highest": (0.4375, 1.5), "minmax": (0.5, 2.75), "gershgorin": (0.25, 2.125),
+            "weighted": (0.5, 1.28)}
+    for mode, (A, B) in want.items():
+        r = O.recursion(mu, 8, bw=mode, beta=1.0)
+        assert np.allclose(r["a"][0], a[:4], atol=1e-12) and np.allclose(r["b"][0, 1:], b, atol=1e-12)
+        assert abs(r["a_inf"][0] - A) < 1e-12 and abs(r["b_inf"][0] - B) < 1e-12, mode
+    # weighted with beta = 0: plain averages of a and of b
+    r = O.recursion(mu, 8, bw="weighted", beta=0.0)
+    assert abs(r["a_inf"][0] - 0.4375) < 1e-12 and abs(r["b_inf"][0] - 1.25) < 1e-12
+
+
+def test_band_options_use_only_levels_before_a_breakdown():
+    """A two-level chain (a = (1, -0.5), b_1 = 2, nothing beyond) at 6 moments:
+    the recursion breaks down at level 2; options i-v and the weighted average
+    see a_0, a_1, b_1 only: (ii) gives a_1 = -0.5 and b_1 = 2, (iii) gives 0.25
+    and 2, (v) gives 0.25 and (1.5 + 8)/4."""
+    mu = _chain_moments([1.0, -0.5], [2.0], 6)[None, :]
+    r = O.recursion(mu, 6, bw="highest")
+    assert r["flags"][0] & 1 and (r["flags"][0] >> 8) == 2
+    assert abs(r["a_inf"][0] + 0.5) < 1e-12 and abs(r["b_inf"][0] - 2.0) < 1e-12
+    r = O.recursion(mu, 6, bw="average")
+    assert abs(r["a_inf"][0] - 0.25) < 1e-12 and abs(r["b_inf"][0] - 2.0) < 1e-12
+    r = O.recursion(mu, 6, bw="minmax")
+    assert abs(r["a_inf"][0] - 0.25) < 1e-12 and abs(r["b_inf"][0] - 9.5 / 4) < 1e-12
+
+
+def test_broyden_linear_system_secant_and_linear_limit():
+    """Broyden's second method on F(x) = b - A x (A symmetric positive definite,
+    6 x 6): (1) it reaches A^-1 b within 2n = 12 steps (Gay 1979: Broyden's
+    updates terminate on linear systems in at most 2n steps); (2) after every
+    update the secant condition H_n y_n = s_n holds; (3) with no history it is
+    linear mixing, x + eta F."""
+    rng = np.random.default_rng(0)
+    Q, _ = np.linalg.qr(rng.normal(size=(6, 6)))
+    A = Q @ np.diag([0.5, 0.8, 1.0, 1.7, 2.5, 3.0]) @ Q.T
+    bvec = rng.normal(size=6)
+    x_star = np.linalg.solve(A, bvec)
+    m = O.Broyden(eta=0.3, hist=50, gauge=False)
+    x = np.zeros(6)
+    for it in range(13):
+        F = bvec - A @ x
+        x_new = m.step(x, F)
+        if m.u:
+            assert np.allclose(m.apply_H(m.y[-1]), x - m_prev, atol=1e-12)
+        m_prev = x.copy()
+        x = x_new
+    assert np.max(np.abs(x - x_star)) < 1e-8
+    lin = O.Broyden(eta=0.3, hist=0, gauge=False)
+    x = np.zeros(6)
+    for it in range(5):
+        F = bvec - A @ x
+        xn = lin.step(x, F)
+        assert np.allclose(xn, x + 0.3 * F, atol=1e-15)
+        x = xn
 
 
 def test_isolated_atoms_are_delta_bands():
