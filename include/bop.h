@@ -412,6 +412,52 @@ int bop_scf_step_broyden(const bop_system *sys /*[host]*/, double mix, double n_
                          hipStream_t stream);
 
 /* =========================================================================
+ * Collinear magnetism (Sec. II "Hamiltonian": the up and down channels are
+ * computed one after the other, each like a non-magnetic calculation; App.
+ * A.2.2 collinear onsite levels; App. A.1 Eq. TB-UX).
+ *
+ * Channel onsite levels E_iav = H0_ia + shift_i - (-1)^v B_z
+ * + (1/2) (-1)^v I_i m_i, with (-1)^v = -1 for the up channel (a positive
+ * moment lowers the up levels by I_i m_i / 2).  The channels share H_bond.
+ *
+ *  bop_spin_shifts   shift_spin[2][N]: the per-atom onsite shifts of the up
+ *                    and down channels (shift, moment may be NULL = 0).
+ *  bop_mag_energy    both channels through the energy path with one Fermi
+ *                    level: sum over channels, orbitals, atoms of N_iav = N_e
+ *                    (sys->n_elec).  The bop_system buffers hold both channels
+ *                    stacked, up atoms then down atoms: H_on [2N][n_orb], mu
+ *                    [2N][n_orb][n_max+1] (method 0) or a, b, flags for 2N
+ *                    n_orb rows (method 1), a_inf, b_inf, flags [2N n_orb],
+ *                    N_atom, U_atom, dos_atom [2N] and energy_ws sized for 2N
+ *                    atoms.  Outputs per channel (no spin factor): N_atom[v N
+ *                    + i] = N_iv, U_atom[v N + i] = sum_a int^E_F (E - E_iav)
+ *                    n_iav dE, dos_atom[v N + i] = n_iv(E_F); U_total = bond
+ *                    energy of both channels; m_out[N] = N_iup - N_idown;
+ *                    U_X[1] = -1/4 sum_i I_i m_out_i^2 (Eq. TB-UX).
+ *  bop_mag_scf_step  bop_mag_energy, then q_i = N_iup + N_idown - n0_i and
+ *                    dm_i = m_out_i - moment_i; converged (*converged = 1,
+ *                    nothing updated) if max |q| < tol and max |dm| < tol_m;
+ *                    else shift_i += mix q_i / max(n_i(E_F), n_floor) (total
+ *                    DOS), minus the mean, and moment_i += mix_m dm_i.
+ *                    max_d[2] = max |q|, max |dm|.
+ * ========================================================================= */
+typedef struct bop_magnetism {
+    double stoner[BOP_MAX_SPECIES];   /* Stoner exchange integral I per species (eV) */
+    double B_z;                       /* field term of the onsite levels (eV) */
+} bop_magnetism;
+
+int bop_spin_shifts(int n_atoms, const int *species, const bop_magnetism *mag /*[host]*/,
+                    const double *shift, const double *moment, double *shift_spin,
+                    hipStream_t stream);
+int bop_mag_energy(const bop_system *sys /*[host]*/, const bop_magnetism *mag /*[host]*/,
+                   const double *shift, const double *moment, double *m_out, double *U_X,
+                   hipStream_t stream);
+int bop_mag_scf_step(const bop_system *sys /*[host]*/, const bop_magnetism *mag /*[host]*/,
+                     double mix, double mix_m, double n_floor, double tol, double tol_m,
+                     double *shift, double *moment, double *m_out, double *q, double *U_X,
+                     double *max_d, int *converged, hipStream_t stream);
+
+/* =========================================================================
  * Learned warm start (not in the paper: its Sec. III speed-up (ii), starting
  * the self-consistency from earlier onsite levels, generalised to a learned
  * map from an atom's lowest moments to its converged onsite shift).  FP32.

@@ -302,6 +302,85 @@ def scf(wl, shift0=None, mix=0.5, tol=1e-4, max_iter=200, n_floor=1e-3, n_max=No
     return shift, hist, r
 
 
+# --------------------------------------------------------------------------
+# Collinear magnetism (Sec. II "Hamiltonian": one loop over the two spin
+# channels; App. A.2.2 collinear onsite levels; App. A.1 Eq. TB-UX).
+# --------------------------------------------------------------------------
+def spin_shifts(shift, moment, species, stoner, B_z=0.0):
+    """Onsite shifts of the two spin channels (collinear form of the onsite
+    levels, App. A.2.2): E_iav = H0 + shift_i - (-1)^v B_z + (1/2) (-1)^v I_i m_i.
+    Reading: (-1)^v = -1 for the up channel, so that the majority channel
+    (m_i > 0 means more up electrons) is lowered by I_i m_i / 2 (Stoner)."""
+    I = np.asarray(stoner, np.float64)[np.asarray(species)]
+    shift = np.asarray(shift, np.float64)
+    moment = np.asarray(moment, np.float64)
+    return shift + B_z - 0.5 * I * moment, shift - B_z + 0.5 * I * moment
+
+
+def energy_pipeline_mag(wl, stoner, shift=None, moment=None, B_z=0.0, n_max=None, n_exp=None, nl=None):
+    """Collinear-magnetic energy path: both spin channels share the bonds and
+    differ in their onsite levels; one Fermi level with sum over channels,
+    orbitals and atoms of N_iav = N_e; per channel N_iv = sum_a N_iav and the
+    onsite bond energy U_iv = sum_a int^E_F (E - E_iav) n_iav dE (Eq.
+    TB-Ubond with the spin index); moments m_i = N_iup - N_idown; exchange
+    energy U_X = -1/4 sum_i I_i m_i^2 (Eq. TB-UX) of these moments.
+    The channels' rows are stacked (up atoms then down atoms) and handed to
+    the non-magnetic count and energy routines, which count both spins of a
+    row (factor 2): the Fermi level of the stacked rows for 2 N_e electrons is
+    the one of the channels for N_e, and their per-atom outputs are halved."""
+    n = wl.n_atoms
+    n_max = wl.n_max if n_max is None else n_max
+    n_exp = wl.n_exp if n_exp is None else n_exp
+    shift = np.zeros(n) if shift is None else np.asarray(shift, np.float64)
+    moment = np.zeros(n) if moment is None else np.asarray(moment, np.float64)
+    if nl is None:
+        nl = neighbours(wl.pos, wl.cell, wl.model["r_cut"])
+    s_up, s_dn = spin_shifts(shift, moment, wl.species, stoner, B_z)
+    H_up, H_bond = build_H(wl.model, wl.species, nl, s_up)
+    H_dn, _ = build_H(wl.model, wl.species, nl, s_dn)
+    mu = np.concatenate([moments(nl, H_up, H_bond, n_max), moments(nl, H_dn, H_bond, n_max)])
+    rows = mu.reshape(-1, n_max + 1)
+    rec = recursion(rows, n_max)
+    gs = dos_coeffs(rows, rec, n_max, n_exp)
+    n_e = float(np.sum(wl.n_elec))
+    E_F = fermi(gs, rec["a_inf"], rec["b_inf"], 2.0 * n_e)
+    en = energy(gs, rec["a_inf"], rec["b_inf"], np.concatenate([H_up, H_dn]), E_F)
+    N_sp = en["N_atom"].reshape(2, n) / 2.0
+    U_sp = en["U_atom"].reshape(2, n) / 2.0
+    D_sp = en["dos_atom"].reshape(2, n) / 2.0
+    m_out = N_sp[0] - N_sp[1]
+    I = np.asarray(stoner, np.float64)[np.asarray(wl.species)]
+    return {"E_F": E_F, "N_spin": N_sp, "U_spin": U_sp, "dos_spin": D_sp, "N_atom": N_sp.sum(0),
+            "U_atom": U_sp.sum(0), "dos_atom": D_sp.sum(0), "moment": m_out,
+            "U_bond": float(U_sp.sum()), "U_X": float(-0.25 * np.sum(I * m_out * m_out)), "mu": mu, "rec": rec}
+
+
+def scf_mag(wl, stoner, moment0, shift0=None, B_z=0.0, mix=0.5, mix_m=0.5, tol=1e-4, tol_m=1e-4, max_iter=200,
+            n_floor=1e-3, n_max=None):
+    """Self-consistent collinear magnetism with local charge neutrality: the
+    shifts follow the linear charge-neutrality cycle (total DOS at E_F), the
+    moments are mixed linearly, m_i <- m_i + mix_m (m_i^out - m_i) (a Stoner
+    cycle).  Converged when max |q_i| < tol and max |m_i^out - m_i| < tol_m;
+    then nothing is updated.  Returns (shift, moment, history, last result)."""
+    n = wl.n_atoms
+    shift = np.zeros(n) if shift0 is None else np.array(shift0, float)
+    m = np.array(moment0, float) * np.ones(n)
+    nl = neighbours(wl.pos, wl.cell, wl.model["r_cut"])
+    hist = []
+    for it in range(max_iter):
+        r = energy_pipeline_mag(wl, stoner, shift, m, B_z, n_max=n_max, nl=nl)
+        q = r["N_atom"] - wl.n_elec
+        dm = r["moment"] - m
+        mq, mdm = float(np.max(np.abs(q))), float(np.max(np.abs(dm)))
+        hist.append({"it": it, "max_dq": mq, "max_dm": mdm, "m_mean": float(r["moment"].mean())})
+        if mq < tol and mdm < tol_m:
+            return shift, m, hist, r
+        shift = shift + mix * q / np.maximum(r["dos_atom"], n_floor)
+        shift = shift - shift.mean()
+        m = m + mix_m * dm
+    return shift, m, hist, r
+
+
 class Broyden:
     """Broyden's second method (Broyden 1965, the update of the inverse
     Jacobian) for F(x) = 0, as a mixer of the self-consistency cycle (Sec. II

@@ -88,6 +88,10 @@ class System(C.Structure):
     ]
 
 
+class Magnetism(C.Structure):
+    _fields_ = [("stoner", C.c_double * MAX_SPECIES), ("B_z", C.c_double)]
+
+
 _lib = None
 
 
@@ -124,6 +128,10 @@ def load(path: str = LIB_PATH):
     lib.bop_broyden_workspace_size.argtypes = [C.c_int, C.c_int]
     lib.bop_scf_step_broyden.argtypes = [C.POINTER(System), C.c_double, C.c_double, C.c_double, C.c_int, C.c_int,
                                          P, P, P, P, P, C.c_size_t, P]
+    lib.bop_spin_shifts.argtypes = [C.c_int, P, C.POINTER(Magnetism), P, P, P, P]
+    lib.bop_mag_energy.argtypes = [C.POINTER(System), C.POINTER(Magnetism), P, P, P, P, P]
+    lib.bop_mag_scf_step.argtypes = [C.POINTER(System), C.POINTER(Magnetism), C.c_double, C.c_double, C.c_double,
+                                     C.c_double, C.c_double, P, P, P, P, P, P, P, P]
     lib.bop_features.argtypes = [C.c_int, C.c_int, C.c_int, P, P, P, P, P]
     lib.bop_mlp_forward.argtypes = [C.c_int, P, P, P, P]
     lib.bop_feature_stats.argtypes = [C.c_int, P, P, P, P]
@@ -602,6 +610,103 @@ class SCFPath(EnergyPath):
             if int(self.converged.item()):
                 return it + 1, hist
         raise BopError(BOP_E_NOT_CONVERGED, f"SCF not converged in {max_iter} iterations (max|q| {hist[-1]:.3e})")
+
+
+class MagneticPath:
+    """Collinear-magnetic energy path and Stoner / charge-neutrality cycle
+    (``bop_mag_energy``, ``bop_mag_scf_step``): both spin channels share the
+    neighbour list, bonds and moment plan; every per-row and per-atom buffer
+    holds the up channel's atoms followed by the down channel's."""
+
+    def __init__(self, pos, cell, species, model, n_max, n0, stoner, B_z=0.0, n_exp=200, dtype="f64",
+                 method="moments", tuning=None, device="cuda"):
+        torch = _torch()
+        lib = load()
+        if method not in ("moments", "lanczos"):
+            raise ValueError("method must be 'moments' or 'lanczos'")
+        self.device = torch.device(device)
+        self.model, self.n_max, self.n_exp, self.dtype, self.method = model, int(n_max), int(n_exp), dtype, method
+        self.pos = torch.as_tensor(np.ascontiguousarray(pos, np.float64), device=self.device)
+        self.cell = np.ascontiguousarray(cell, np.float64)
+        self.species = torch.as_tensor(np.ascontiguousarray(species, np.int32), device=self.device)
+        n = self.n = self.pos.shape[0]
+        no = self.no = model["n_orb"]
+        self.mag = Magnetism()
+        st = list(stoner) if np.ndim(stoner) else [float(stoner)] * model["n_species"]
+        for k, v in enumerate(st):
+            self.mag.stoner[k] = float(v)
+        self.mag.B_z = float(B_z)
+        self.nl = build_neighbours(self.pos, self.cell, model["r_cut"])
+        self.H_on1, self.H_bond = build_H(model, self.species, self.nl, dtype=dtype)
+        self.plan = moments_plan(n, no, self.n_max, dtype, self.nl, tuning)
+        self.mws = moments_prepare(self.plan, self.nl)
+        f64 = dict(dtype=torch.float64, device=self.device)
+        R2 = 2 * n * no
+        self.H_on = torch.empty((2 * n, no), **f64)
+        self.mu = torch.empty((2 * n, no, self.n_max + 1), **f64)
+        self.rec = {"a": torch.empty((R2, n_a(self.n_max)), **f64), "b": torch.empty((R2, n_b(self.n_max) + 1), **f64),
+                    "a_inf": torch.empty(R2, **f64), "b_inf": torch.empty(R2, **f64),
+                    "flags": torch.empty(R2, dtype=torch.int32, device=self.device)}
+        self.ews = _bytes(lib.bop_energy_workspace_size(2 * n, no, self.n_exp), self.device)
+        self.out = {k: torch.zeros(2 * n, **f64) for k in ("N_atom", "U_atom", "dos_atom")}
+        self.out["E_F"] = torch.zeros(1, **f64)
+        self.out["U_total"] = torch.zeros(1, **f64)
+        self.n0 = torch.as_tensor(np.ascontiguousarray(n0, np.float64) * np.ones(n), device=self.device)
+        self.shift = torch.zeros(n, **f64)
+        self.moment = torch.zeros(n, **f64)
+        self.m_out = torch.zeros(n, **f64)
+        self.q = torch.zeros(n, **f64)
+        self.U_X = torch.zeros(1, **f64)
+        self.max_d = torch.zeros(2, **f64)
+        self.converged = torch.zeros(1, dtype=torch.int32, device=self.device)
+        sy = System()
+        sy.model = model_struct(model)
+        sy.n_atoms, sy.n_max, sy.n_exp, sy.dtype = n, self.n_max, self.n_exp, DTYPES[dtype]
+        sy.method = 1 if method == "lanczos" else 0
+        sy.species, sy.n0 = _ptr(self.species), _ptr(self.n0)
+        sy.row_ptr, sy.nbr_j, sy.order = _ptr(self.nl.row_ptr), _ptr(self.nl.nbr_j), _ptr(self.nl.order)
+        sy.n_pairs = self.nl.n_pairs
+        sy.H_on, sy.H_bond = _ptr(self.H_on), _ptr(self.H_bond)
+        sy.plan = self.plan
+        sy.moments_ws, sy.moments_ws_bytes = _ptr(self.mws), self.mws.numel()
+        sy.mu = _ptr(self.mu)
+        for k in ("a", "b", "a_inf", "b_inf", "flags"):
+            setattr(sy, k, _ptr(self.rec[k]))
+        sy.energy_ws, sy.energy_ws_bytes = _ptr(self.ews), self.ews.numel()
+        sy.n_elec = float(self.n0.sum().item())
+        for k in ("E_F", "N_atom", "U_atom", "dos_atom", "U_total"):
+            setattr(sy, k, _ptr(self.out[k]))
+        self.sys = sy
+
+    def set_state(self, shift=None, moment=None):
+        torch = _torch()
+        if shift is not None:
+            self.shift.copy_(torch.as_tensor(shift, dtype=torch.float64, device=self.device))
+        if moment is not None:
+            self.moment.copy_(torch.as_tensor(moment, dtype=torch.float64, device=self.device))
+
+    def energy(self):
+        """Both channels at the current shifts and moments (``bop_mag_energy``);
+        returns the output dict (per-channel rows in N_atom, U_atom, dos_atom)."""
+        _check(load().bop_mag_energy(C.byref(self.sys), C.byref(self.mag), _ptr(self.shift), _ptr(self.moment),
+                                     _ptr(self.m_out), _ptr(self.U_X), _stream()))
+        return self.out
+
+    def step(self, mix=0.5, mix_m=0.5, n_floor=1e-3, tol=1e-4, tol_m=1e-4):
+        _check(load().bop_mag_scf_step(C.byref(self.sys), C.byref(self.mag), float(mix), float(mix_m),
+                                       float(n_floor), float(tol), float(tol_m), _ptr(self.shift),
+                                       _ptr(self.moment), _ptr(self.m_out), _ptr(self.q), _ptr(self.U_X),
+                                       _ptr(self.max_d), _ptr(self.converged), _stream()))
+
+    def run_scf(self, mix=0.5, mix_m=0.5, n_floor=1e-3, tol=1e-4, tol_m=1e-4, max_iter=300):
+        """Iterate until converged; returns (iterations, history of (max|q|, max|dm|))."""
+        hist = []
+        for it in range(max_iter):
+            self.step(mix, mix_m, n_floor, tol, tol_m)
+            hist.append(tuple(self.max_d.cpu().numpy().tolist()))
+            if int(self.converged.item()):
+                return it + 1, hist
+        raise BopError(BOP_E_NOT_CONVERGED, f"magnetic SCF not converged in {max_iter} iterations ({hist[-1]})")
 
 
 MLP_NPARAM = 4673

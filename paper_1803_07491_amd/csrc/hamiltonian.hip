@@ -81,10 +81,15 @@ k_bonds_d(bop_model m, int n, long P, const int *__restrict__ species, const int
     double l = dx / r, mm = dy / r, nn = dz / r;
     double st = sqrt(l * l + mm * mm), ct = nn, cp = 1.0, sp = 0.0;
     if (st > 0.0) { cp = l / st; sp = mm / st; }
-    int pr = species[i] * m.n_species + species[j];
+    // a species outside the model gives NaN blocks (never an index past its tables)
+    const int si = species[i], sj = species[j];
+    const bool ok = si >= 0 && si < m.n_species && sj >= 0 && sj < m.n_species;
+    int pr = ok ? si * m.n_species + sj : 0;
     double D[5] = { bond_integral(m, pr, BOP_DDS, r), bond_integral(m, pr, BOP_DDP, r),
                     bond_integral(m, pr, BOP_DDP, r), bond_integral(m, pr, BOP_DDD, r),
                     bond_integral(m, pr, BOP_DDD, r) };
+    if (!ok)
+        for (int c = 0; c < 5; ++c) D[c] = __builtin_nan("");
     double R[5][5];
     rot_d(ct, st, cp, sp, R);
     if constexpr (sizeof(T) >= 4) {
@@ -129,10 +134,12 @@ k_bonds_spd(bop_model m, int n, long P, const int *__restrict__ species, const i
     double l = dx / r, mm = dy / r, nn = dz / r;
     double st = sqrt(l * l + mm * mm), ct = nn, cp = 1.0, sp = 0.0;
     if (st > 0.0) { cp = l / st; sp = mm / st; }
-    int pr = species[i] * m.n_species + species[j];
+    const int si = species[i], sj = species[j];
+    const bool ok = si >= 0 && si < m.n_species && sj >= 0 && sj < m.n_species;
+    int pr = ok ? si * m.n_species + sj : 0;
     double v[BOP_N_CHANNELS];
 #pragma unroll
-    for (int c = 0; c < BOP_N_CHANNELS; ++c) v[c] = bond_integral(m, pr, c, r);
+    for (int c = 0; c < BOP_N_CHANNELS; ++c) v[c] = ok ? bond_integral(m, pr, c, r) : __builtin_nan("");
     // block-diagonal rotation (1, R_p, R_d) as a full 9x9
     double Rp[3][3], Rd[5][5], R[9][9];
     rot_p(ct, st, cp, sp, Rp);
@@ -177,11 +184,12 @@ __global__ void k_onsite(bop_model m, int n, const int *__restrict__ species, co
 {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    int s = species[i], no = m.n_orb;
+    const int s = species[i], no = m.n_orb;
+    const bool ok = s >= 0 && s < m.n_species;
     double sh = shift ? shift[i] : 0.0;
     for (int a = 0; a < no; ++a) {
         int lq = (no == 5) ? 2 : (a == 0 ? 0 : (a < 4 ? 1 : 2));
-        H_on[(long)i * no + a] = m.onsite[s][lq] + sh;
+        H_on[(long)i * no + a] = ok ? m.onsite[s][lq] + sh : __builtin_nan("");
     }
 }
 

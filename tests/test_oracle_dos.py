@@ -411,3 +411,46 @@ def test_isolated_atoms_are_delta_bands():
     np.testing.assert_allclose(r["N_atom"], [10.0, 1.0], atol=1e-6)
     np.testing.assert_allclose(r["U_atom"], [0.0, 0.0], atol=1e-6)
     assert abs(r["E_F"] - 0.8) < 1e-5
+
+
+def test_magnetic_channels_reduce_to_the_non_magnetic_path():
+    """With no exchange (I = 0) and no field both spin channels are the
+    non-magnetic problem: same Fermi level, N_i, U_i, and zero moments."""
+    wl = W.bcc_small()
+    r0 = O.energy_pipeline(wl)
+    rm = O.energy_pipeline_mag(wl, [0.0], moment=np.linspace(-1, 1, wl.n_atoms))
+    assert abs(rm["E_F"] - r0["E_F"]) < 1e-12
+    np.testing.assert_allclose(rm["N_atom"], r0["N_atom"], atol=1e-12)
+    np.testing.assert_allclose(rm["U_atom"], r0["U_atom"], atol=1e-12)
+    assert np.max(np.abs(rm["moment"])) < 1e-12 and rm["U_X"] == 0.0
+
+
+def test_magnetic_linear_response_is_the_stoner_factor():
+    """A small uniform moment m splits the channels by I m; at fixed E_F
+    (unchanged to first order by symmetry) the output moment is
+    m_out = I n_sigma(E_F) m, n_sigma the non-magnetic DOS per spin and atom at
+    E_F: the Stoner enhancement.  It pins the sign and the factor 1/2 of the
+    spin splitting."""
+    wl = W.bcc_small()
+    r0 = O.energy_pipeline(wl)
+    m0 = 1e-5
+    rm = O.energy_pipeline_mag(wl, [0.8], moment=np.full(wl.n_atoms, m0))
+    want = 0.8 * r0["dos_atom"] / 2.0
+    np.testing.assert_allclose(rm["moment"] / m0, want, rtol=1e-4)
+
+
+def test_magnetic_isolated_atoms_closed_form():
+    """Isolated atoms with 6.5 d electrons and exchange splitting I m = 1 eV:
+    the lowered (up) shell fills (5 electrons), the down shell holds 1.5, so
+    m_out = 3.5 whatever the input moment's size, U_X = -1/4 I m_out^2, and
+    the Fermi level sits on the down level, H0 + I m / 2."""
+    pos = np.array([[1.0, 1.0, 1.0], [9.0, 9.0, 9.0]])
+    cell = np.eye(3) * 20.0
+    wl = W.Workload("iso", pos, cell, np.zeros(2, np.int32), W.canonical_d_model(3.5), 6, 200,
+                    np.array([6.5, 6.5]))
+    rm = O.energy_pipeline_mag(wl, [1.0], moment=np.array([1.0, 1.0]))
+    np.testing.assert_allclose(rm["N_spin"][0], [5.0, 5.0], atol=1e-6)
+    np.testing.assert_allclose(rm["N_spin"][1], [1.5, 1.5], atol=1e-6)
+    np.testing.assert_allclose(rm["moment"], [3.5, 3.5], atol=1e-6)
+    assert abs(rm["U_X"] + 0.25 * 2 * 3.5 ** 2) < 1e-5
+    assert abs(rm["E_F"] - 0.5) < 1e-5
