@@ -37,3 +37,19 @@ def test_committed_bench_line_has_every_field():
     for key in ("value", "unit", "cores", "kind", "sample"):
         assert key in c, key
     assert c["kind"] == "oracle" and c["cores"] >= 1 and c["unit"] == j["unit"]
+
+
+def test_committed_bench_line_states_its_accuracy():
+    """The headline form carries its own per-atom accuracy against the FP64
+    path, and it meets the FP32 bar (1e-5 relative on every atom's N and U);
+    the faster FP32 moment form is reported beside it with its own error."""
+    j = json.load(open(os.path.join(ROOT, "profiles", "bench_bcc_large_f32.json")))
+    acc = j["accuracy_vs_f64"]
+    assert acc["bar"] == 1e-5
+    assert max(acc["max_atom_rel_err"].values()) < acc["bar"]
+    assert j["config"]["method"] == "lanczos" and j["dtype"] == "f32"
+    m = j["moments_f32_path"]
+    assert m["meets_fp32_bar"] == (max(m["max_atom_rel_err"].values()) < 1e-5)
+    r = j["roofline"]
+    if r["traffic"]:
+        assert abs(r["achieved_hbm_TBps"] - r["traffic"] / (r["kernel_ms"] * 1e-3) / 1e12) < 1e-9
