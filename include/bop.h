@@ -183,6 +183,21 @@ typedef struct bop_tuning {
 } bop_tuning;
 
 #define BOP_MAX_NMAX 40
+/* Maximum radius of the interference paths (Sec. III "Speed-ups" (iii), an
+ * additional approximation): with r_max > 0 the moments of atom i keep only the
+ * paths whose every atom lies within r_max of atom i (minimum-image distance
+ * from the positions).  Needs r_max + r_cut below half the smallest height of
+ * the cell (then each atom within r_max has one image there), else BOP_E_ARG;
+ * FP64/FP32/FP16 forms only (BF16: BOP_E_UNSUPPORTED).  The tiles' supports
+ * then hold only atoms within r_max of one of their atoms, and each column
+ * keeps the rows within r_max of its own atom. */
+typedef struct bop_path_radius {
+    double r_max;          /* > 0 */
+    double r_cut;          /* the neighbour list's cutoff */
+    double cell[9];        /* rows a1, a2, a3 */
+    const double *pos;     /* [N][3] device positions (those of the neighbour list) */
+} bop_path_radius;
+
 typedef struct bop_plan {
     int n_atoms, n_orb, n_max, dtype;
     int tile_atoms, n_tiles, block_threads, batch_tiles, chunk_rows;
@@ -193,17 +208,20 @@ typedef struct bop_plan {
                             1 = bitmaps in LDS (rows of a layer in ascending atom index),
                             2 = per-workgroup map (rows in order of discovery) */
     size_t ws_bytes;     /* workspace bop_moments_prepare / bop_moments need */
+    double r_max;        /* path radius of the plan (0: none) */
 } bop_plan;
 
 size_t bop_moments_plan_scratch_size(int n_atoms);
 int bop_moments_plan(int n_atoms, int n_orb, int n_max, int dtype,
                      const int *row_ptr, const int *nbr_j, const int *order,
                      const bop_tuning *tuning /*[host] or NULL*/,
+                     const bop_path_radius *radius /*[host] or NULL = all paths*/,
                      void *scratch, size_t scratch_bytes,
                      bop_plan *plan /*[host] out*/, hipStream_t stream);
 int bop_moments_prepare(const bop_plan *plan /*[host]*/, const int *row_ptr,
-                        const int *nbr_j, const int *order, void *ws, size_t ws_bytes,
-                        hipStream_t stream);
+                        const int *nbr_j, const int *order,
+                        const bop_path_radius *radius /*[host]; the plan's, or NULL if it has none*/,
+                        void *ws, size_t ws_bytes, hipStream_t stream);
 int bop_moments(const bop_plan *plan /*[host]*/, const int *row_ptr, const double *H_on,
                 const void *H_bond, double *mu, void *ws, size_t ws_bytes,
                 hipStream_t stream);

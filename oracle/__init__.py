@@ -64,6 +64,7 @@ def lib():
         _lib.or_neighbours.argtypes = [C.c_int, P, P, C.c_double, C.c_int, C.c_long, P, P, P, P]
         _lib.or_build_H.argtypes = [P, C.c_int, P, P, P, P, P, P, P]
         _lib.or_moments.argtypes = [C.c_int, C.c_int, C.c_int, P, P, P, P, C.c_int, P, P]
+        _lib.or_moments_radius.argtypes = [C.c_int, C.c_int, C.c_int, P, P, P, C.c_double, P, P, C.c_int, P, P]
         _lib.or_recursion.argtypes = [C.c_int, C.c_int, P, C.c_int, C.c_double, C.c_double, P, P, P, P, P]
         _lib.or_jackson.argtypes = [C.c_int, P]
         _lib.or_dos_coeffs.argtypes = [C.c_int, C.c_int, C.c_int, P, P, P, P, P, P, P]
@@ -154,13 +155,20 @@ def build_H(model, species, nl, shift=None):
     return H_on, H_bond
 
 
-def moments(nl, H_on, H_bond, n_max, sel=None):
-    """Orbital moments mu[s, a, n] = <i a|H^n|i a> for i = sel[s]."""
+def moments(nl, H_on, H_bond, n_max, sel=None, r_max=0.0):
+    """Orbital moments mu[s, a, n] = <i a|H^n|i a> for i = sel[s]; with
+    r_max > 0 only paths that stay within r_max of atom i (Sec. III
+    "Speed-ups" (iii))."""
     n, no = H_on.shape
     sel = np.arange(n, dtype=np.int32) if sel is None else _c(sel, np.int32)
     mu = np.zeros((sel.shape[0], no, n_max + 1))
-    lib().or_moments(n, no, n_max, _p(nl["row_ptr"]), _p(nl["nbr_j"]), _p(_c(H_on, np.float64)),
-                     _p(_c(H_bond, np.float64)), sel.shape[0], _p(sel), _p(mu))
+    if r_max > 0.0:
+        lib().or_moments_radius(n, no, n_max, _p(nl["row_ptr"]), _p(nl["nbr_j"]), _p(_c(nl["nbr_d"], np.float64)),
+                                float(r_max), _p(_c(H_on, np.float64)), _p(_c(H_bond, np.float64)), sel.shape[0],
+                                _p(sel), _p(mu))
+    else:
+        lib().or_moments(n, no, n_max, _p(nl["row_ptr"]), _p(nl["nbr_j"]), _p(_c(H_on, np.float64)),
+                         _p(_c(H_bond, np.float64)), sel.shape[0], _p(sel), _p(mu))
     return mu
 
 
@@ -262,7 +270,7 @@ def rotation(u):
 
 # --------------------------------------------------------------------------
 def energy_pipeline(wl, shift=None, sel=None, n_max=None, n_exp=None, E_F=None, nl=None, bw="gershgorin",
-                    beta=1.0):
+                    beta=1.0, r_max=0.0):
     """Whole path for a workload: neighbours -> H -> moments -> recursion ->
     DOS coefficients -> Fermi level (unless given) -> energies.  With ``sel``
     only those atoms' moments and energies are computed and ``E_F`` must be
@@ -272,7 +280,7 @@ def energy_pipeline(wl, shift=None, sel=None, n_max=None, n_exp=None, E_F=None, 
     if nl is None:
         nl = neighbours(wl.pos, wl.cell, wl.model["r_cut"])
     H_on, H_bond = build_H(wl.model, wl.species, nl, shift)
-    mu = moments(nl, H_on, H_bond, n_max, sel)
+    mu = moments(nl, H_on, H_bond, n_max, sel, r_max=r_max)
     no = H_on.shape[1]
     rows = mu.reshape(-1, n_max + 1)
     rec = recursion(rows, n_max, bw=bw, beta=beta)

@@ -419,10 +419,32 @@ void or_build_H(const or_model *m, int n, const int *species, const double *shif
  *   mu(2k)   = <X^k, X^k>,   mu(2k-1) = <X^(k-1), X^k>,
  *   mu(2K+1) = <X^K, H X^K>  (odd n_max, K = floor(n_max/2)).
  */
+int or_moments_radius(int n, int n_orb, int n_max, const int *row_ptr, const int *nbr_j,
+                      const double *nbr_d, double r_max, const double *H_on, const double *H_bond,
+                      int n_sel, const int *sel, double *mu);
+
 int or_moments(int n, int n_orb, int n_max, const int *row_ptr, const int *nbr_j,
                const double *H_on, const double *H_bond, int n_sel, const int *sel,
                double *mu)
 {
+    return or_moments_radius(n, n_orb, n_max, row_ptr, nbr_j, NULL, 0.0, H_on, H_bond, n_sel, sel, mu);
+}
+
+/*
+ * The same with a maximum path radius (Sec. III "Speed-ups" (iii)): when
+ * r_max > 0, only interference paths that stay within r_max of their start
+ * atom are kept.  The position of a path's end relative to the start atom is
+ * the sum of the bond vectors nbr_d along it; a row enters the support only
+ * through a bond that ends within r_max, and a bond adds to a row's product
+ * only if its target lies within r_max.  (For r_max + r_cut below half the
+ * shortest cell height every atom within r_max has one such position.)
+ */
+int or_moments_radius(int n, int n_orb, int n_max, const int *row_ptr, const int *nbr_j,
+                      const double *nbr_d, double r_max, const double *H_on, const double *H_bond,
+                      int n_sel, const int *sel, double *mu)
+{
+    const int trunc = r_max > 0.0 && nbr_d != NULL;
+    const double r2max = r_max * r_max;
     int K = n_max / 2, no = n_orb, nb2 = no * no;
 
 #pragma omp parallel
@@ -434,12 +456,15 @@ int or_moments(int n, int n_orb, int n_max, const int *row_ptr, const int *nbr_j
         double *X0 = NULL, *X1 = NULL;
         int xcap = 0;
         int *size = (int *)malloc(sizeof(int) * (K + 2));
+        double *rel = (double *)malloc(sizeof(double) * 3 * cap);   /* row position - start position */
 #pragma omp for schedule(dynamic, 1)
         for (int s = 0; s < n_sel; ++s) {
             int i = sel[s];
             /* breadth-first layers: size[k] = |support of X^k| */
             int cnt = 0;
-            sup[cnt] = i; loc[i] = cnt; ++cnt;
+            sup[cnt] = i; loc[i] = cnt;
+            rel[0] = rel[1] = rel[2] = 0.0;
+            ++cnt;
             size[0] = 1;
             for (int k = 1; k <= K; ++k) {
                 int begin = (k >= 2) ? size[k - 2] : 0, end = size[k - 1];
@@ -448,8 +473,18 @@ int or_moments(int n, int n_orb, int n_max, const int *row_ptr, const int *nbr_j
                     for (int p = row_ptr[g]; p < row_ptr[g + 1]; ++p) {
                         int j = nbr_j[p];
                         if (loc[j] >= 0) continue;
-                        if (cnt == cap) { cap *= 2; sup = (int *)realloc(sup, sizeof(int) * cap); }
+                        double v[3] = {0.0, 0.0, 0.0};
+                        if (trunc) {
+                            for (int c = 0; c < 3; ++c) v[c] = rel[3 * t + c] + nbr_d[3 * p + c];
+                            if ((v[0] * v[0] + v[1] * v[1]) + v[2] * v[2] > r2max) continue;
+                        }
+                        if (cnt == cap) {
+                            cap *= 2;
+                            sup = (int *)realloc(sup, sizeof(int) * cap);
+                            rel = (double *)realloc(rel, sizeof(double) * 3 * cap);
+                        }
                         loc[j] = cnt;
+                        for (int c = 0; c < 3; ++c) rel[3 * cnt + c] = v[c];
                         sup[cnt++] = j;
                     }
                 }
@@ -482,6 +517,11 @@ int or_moments(int n, int n_orb, int n_max, const int *row_ptr, const int *nbr_j
                     for (int p = row_ptr[g]; p < row_ptr[g + 1]; ++p) {
                         int lj = loc[nbr_j[p]];
                         if (lj < 0 || lj >= prev) continue;
+                        if (trunc) {
+                            double v[3];
+                            for (int c = 0; c < 3; ++c) v[c] = rel[3 * r + c] + nbr_d[3 * p + c];
+                            if ((v[0] * v[0] + v[1] * v[1]) + v[2] * v[2] > r2max) continue;
+                        }
                         const double *H = &H_bond[(long)p * nb2];
                         const double *x = &Xp[(long)lj * nb2];
                         for (int b = 0; b < no; ++b)
@@ -509,7 +549,7 @@ int or_moments(int n, int n_orb, int n_max, const int *row_ptr, const int *nbr_j
             }
             for (int t = 0; t < cnt; ++t) loc[sup[t]] = -1;
         }
-        free(loc); free(sup); free(X0); free(X1); free(size);
+        free(loc); free(sup); free(X0); free(X1); free(size); free(rel);
     }
     return 0;
 }

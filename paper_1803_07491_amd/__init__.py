@@ -65,7 +65,24 @@ class Plan(C.Structure):
                 ("tile_atoms", C.c_int), ("n_tiles", C.c_int), ("block_threads", C.c_int),
                 ("batch_tiles", C.c_int), ("chunk_rows", C.c_int), ("deg_max", C.c_int),
                 ("rows_cap", C.c_int), ("rows_k", C.c_int * (MAX_NMAX // 2 + 1)),
-                ("search", C.c_int), ("ws_bytes", C.c_size_t)]
+                ("search", C.c_int), ("ws_bytes", C.c_size_t), ("r_max", C.c_double)]
+
+
+class PathRadius(C.Structure):
+    _fields_ = [("r_max", C.c_double), ("r_cut", C.c_double), ("cell", C.c_double * 9), ("pos", C.c_void_p)]
+
+
+def path_radius(r_max, r_cut, cell, pos):
+    """The ABI's path-radius struct (``pos`` a device tensor that must stay
+    alive while the plan is used), or None for r_max <= 0."""
+    if not r_max or r_max <= 0:
+        return None
+    r = PathRadius()
+    r.r_max, r.r_cut = float(r_max), float(r_cut)
+    for e, v in enumerate(np.ascontiguousarray(cell, np.float64).reshape(9)):
+        r.cell[e] = float(v)
+    r.pos = pos.data_ptr()
+    return r
 
 
 P = C.c_void_p
@@ -113,8 +130,8 @@ def load(path: str = LIB_PATH):
     lib.bop_moments_plan_scratch_size.restype = C.c_size_t
     lib.bop_moments_plan_scratch_size.argtypes = [C.c_int]
     lib.bop_moments_plan.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, P, P, P, C.POINTER(Tuning),
-                                     P, C.c_size_t, C.POINTER(Plan), P]
-    lib.bop_moments_prepare.argtypes = [C.POINTER(Plan), P, P, P, P, C.c_size_t, P]
+                                     C.POINTER(PathRadius), P, C.c_size_t, C.POINTER(Plan), P]
+    lib.bop_moments_prepare.argtypes = [C.POINTER(Plan), P, P, P, C.POINTER(PathRadius), P, C.c_size_t, P]
     lib.bop_moments.argtypes = [C.POINTER(Plan), P, P, P, P, P, C.c_size_t, P]
     lib.bop_recursion.argtypes = [C.c_int, C.c_int, P, C.c_int, C.c_double, C.c_double, P, P, P, P, P, P]
     lib.bop_energy_workspace_size.restype = C.c_size_t
@@ -295,8 +312,9 @@ def build_H(model: dict, species, nl: Neighbours, shift=None, dtype="f64", H_on=
     return H_on, H_bond
 
 
-def moments_plan(n_atoms, n_orb, n_max, dtype, nl: Neighbours, tuning=None, use_order=True) -> Plan:
-    """Breadth-first sizing of the moment tiles (``bop_moments_plan``)."""
+def moments_plan(n_atoms, n_orb, n_max, dtype, nl: Neighbours, tuning=None, use_order=True, radius=None) -> Plan:
+    """Breadth-first sizing of the moment tiles (``bop_moments_plan``);
+    ``radius`` a ``PathRadius`` (maximum path radius) or None."""
     torch = _torch()
     lib = load()
     dev = nl.row_ptr.device
@@ -310,19 +328,20 @@ def moments_plan(n_atoms, n_orb, n_max, dtype, nl: Neighbours, tuning=None, use_
                    int(tuning.get("plan_search", 0)))
     _check(lib.bop_moments_plan(n_atoms, n_orb, n_max, DTYPES[dtype], _ptr(nl.row_ptr), _ptr(nl.nbr_j),
                                 _ptr(nl.order) if use_order else None, C.byref(t) if t else None,
-                                _ptr(scratch), sb, C.byref(plan), _stream()))
+                                C.byref(radius) if radius else None, _ptr(scratch), sb, C.byref(plan), _stream()))
     del scratch
     return plan
 
 
-def moments_prepare(plan: Plan, nl: Neighbours, ws=None, use_order=True):
+def moments_prepare(plan: Plan, nl: Neighbours, ws=None, use_order=True, radius=None):
     """Store every tile's support in the moment workspace
     (``bop_moments_prepare``); returns the workspace tensor."""
     lib = load()
     if ws is None:
         ws = _bytes(plan.ws_bytes, nl.row_ptr.device)
     _check(lib.bop_moments_prepare(C.byref(plan), _ptr(nl.row_ptr), _ptr(nl.nbr_j),
-                                   _ptr(nl.order) if use_order else None, _ptr(ws), ws.numel(), _stream()))
+                                   _ptr(nl.order) if use_order else None, C.byref(radius) if radius else None,
+                                   _ptr(ws), ws.numel(), _stream()))
     return ws
 
 
@@ -473,9 +492,11 @@ class EnergyPath:
     with every buffer allocated once (device tensors) and reused."""
 
     def __init__(self, pos, cell, species, model: dict, n_max: int, n_exp: int = 200, dtype: str = "f64",
-                 tuning=None, device="cuda", method: str = "moments", bw: str = "gershgorin", beta: float = 1.0):
+                 tuning=None, device="cuda", method: str = "moments", bw: str = "gershgorin", beta: float = 1.0,
+                 r_max: float = 0.0):
         torch = _torch()
         load()
+        self.r_max = float(r_max)
         if bw not in BW_MODES or bw == "global":
             raise ValueError(f"bw must be one of {sorted(k for k in BW_MODES if k != 'global')}")
         self.bw, self.beta = bw, float(beta)
@@ -493,8 +514,9 @@ class EnergyPath:
         self.tuning = tuning
         self.nl = build_neighbours(self.pos, self.cell, model["r_cut"])
         self.H_on, self.H_bond = build_H(model, self.species, self.nl, dtype=dtype)
-        self.plan = moments_plan(self.n, self.no, self.n_max, dtype, self.nl, tuning)
-        self.mws = moments_prepare(self.plan, self.nl)
+        self.radius = path_radius(self.r_max, model["r_cut"], self.cell, self.pos)
+        self.plan = moments_plan(self.n, self.no, self.n_max, dtype, self.nl, tuning, radius=self.radius)
+        self.mws = moments_prepare(self.plan, self.nl, radius=self.radius)
         self.mu = torch.empty((self.n, self.no, self.n_max + 1), dtype=torch.float64, device=self.device)
         R = self.n * self.no
         self.rec = {"a": torch.empty((R, n_a(self.n_max)), dtype=torch.float64, device=self.device),
@@ -511,10 +533,10 @@ class EnergyPath:
             self.H_bond = None
         self.H_on, self.H_bond = build_H(self.model, self.species, self.nl, shift=shift, dtype=self.dtype,
                                          H_on=self.H_on, H_bond=self.H_bond)
-        self.plan = moments_plan(self.n, self.no, self.n_max, self.dtype, self.nl, self.tuning)
+        self.plan = moments_plan(self.n, self.no, self.n_max, self.dtype, self.nl, self.tuning, radius=self.radius)
         if self.plan.ws_bytes > self.mws.numel():
             self.mws = None
-        self.mws = moments_prepare(self.plan, self.nl, ws=self.mws)
+        self.mws = moments_prepare(self.plan, self.nl, ws=self.mws, radius=self.radius)
 
     def step(self, n_elec, E_F=None):
         """The whole path for the structure: neighbours, H, plan, moments,

@@ -69,6 +69,54 @@ __device__ inline void wg_min(int *p, int v)
     __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// Maximum path radius: an atom belongs to a tile's support only if it lies
+// within r_max of one of the tile's atoms, and a column keeps only the rows
+// within r_max of its own atom.  Distances are minimum-image distances from
+// the positions: fractional offsets rounded to the nearest integer, which is
+// exact for offsets shorter than half the smallest cell height (the plan
+// requires r_max below that).
+struct Radius {
+    int on;
+    double r2;
+    double A[9], Ai[9];          // cell rows a1, a2, a3 and the inverse
+    const double *pos;
+};
+
+__device__ inline bool within(const Radius &R, const double *pj, const double *pt)
+{
+    const double d0 = pj[0] - pt[0], d1 = pj[1] - pt[1], d2 = pj[2] - pt[2];
+    double f[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        f[a] = d0 * R.Ai[a] + d1 * R.Ai[3 + a] + d2 * R.Ai[6 + a];
+        f[a] -= rint(f[a]);
+    }
+    double q = 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double v = f[0] * R.A[c] + f[1] * R.A[3 + c] + f[2] * R.A[6 + c];
+        q += v * v;
+    }
+    return q <= R.r2;
+}
+
+// whether atom j lies within r_max of any of the tile's Bt atoms (positions in tp)
+__device__ inline bool inside_any(const Radius &R, int j, const double *tp, int Bt)
+{
+    if (!R.on) return true;
+    const double pj[3] = {R.pos[3 * (long)j], R.pos[3 * (long)j + 1], R.pos[3 * (long)j + 2]};
+    for (int t = 0; t < Bt; ++t)
+        if (within(R, pj, tp + 3 * t)) return true;
+    return false;
+}
+
+// the tile atoms' positions into LDS (tp: 3 doubles per atom, at most 64 atoms)
+__device__ inline void tile_positions(const Radius &R, const int *sup, int Bt, double *tp)
+{
+    if (R.on)
+        for (int e = threadIdx.x; e < 3 * Bt; e += blockDim.x) tp[e] = R.pos[3 * (long)sup[e / 3] + e % 3];
+}
+
 // exclusive prefix of a 0/1 flag over the workgroup; returns the position and
 // writes the workgroup total
 template <int WGT>
@@ -104,7 +152,8 @@ __device__ inline int wg_scan01(int own, int *s_wave, int &total)
 template <int WGT>
 __device__ int bfs_tile(int tile, int B, int n_atoms, int K, const int *__restrict__ order,
                         const int *__restrict__ row_ptr, const int *__restrict__ nbr_j, int deg_max,
-                        int *g2l, int *sup, int rows_cap, int *s_size, int *s_wave, int *s_flag)
+                        int *g2l, int *sup, int rows_cap, int *s_size, int *s_wave, int *s_flag,
+                        const Radius &rad, double *s_tp)
 {
     const int tid = threadIdx.x;
     const int first = tile * B;
@@ -121,6 +170,8 @@ __device__ int bfs_tile(int tile, int B, int n_atoms, int K, const int *__restri
         __syncthreads();
         return -1;
     }
+    tile_positions(rad, sup, Bt, s_tp);
+    __syncthreads();
     for (int k = 1; k <= K; ++k) {
         const int begin = (k >= 2) ? s_size[k - 2] : 0, end = s_size[k - 1];
         const long nent = (long)(end - begin) * deg_max;
@@ -128,7 +179,10 @@ __device__ int bfs_tile(int tile, int B, int n_atoms, int K, const int *__restri
             int t = begin + (int)(e / deg_max), s = (int)(e % deg_max);
             int g = sup[t];
             int p0 = row_ptr[g], deg = row_ptr[g + 1] - p0;
-            if (s < deg) wg_min(&g2l[nbr_j[p0 + s]], CLAIM + (int)e);
+            if (s < deg) {
+                const int j = nbr_j[p0 + s];
+                if (inside_any(rad, j, s_tp, Bt)) wg_min(&g2l[j], CLAIM + (int)e);
+            }
         }
         __syncthreads();
         int base = end;
@@ -218,7 +272,7 @@ template <int WGT>
 __device__ int bfs_tile_bits(int tile, int B, int n_atoms, int K, const int *__restrict__ order,
                              const int *__restrict__ row_ptr, const int *__restrict__ nbr_j, int deg_max,
                              int *g2l, int *sup, int rows_cap, int *s_size, int *s_wave, unsigned *s_vis,
-                             unsigned *s_new, int nw, int *s_p0, int *s_deg)
+                             unsigned *s_new, int nw, int *s_p0, int *s_deg, const Radius &rad, double *s_tp)
 {
     const int tid = threadIdx.x;
     const int first = tile * B;
@@ -234,6 +288,8 @@ __device__ int bfs_tile_bits(int tile, int B, int n_atoms, int K, const int *__r
     if (tid == 0) s_size[0] = Bt;
     __syncthreads();
     if (Bt > rows_cap) return -1;
+    tile_positions(rad, sup, Bt, s_tp);
+    __syncthreads();
     const int per = (nw + WGT - 1) / WGT;
     const int w0 = min(tid * per, nw), w1 = min(w0 + per, nw);
     for (int k = 1; k <= K; ++k) {
@@ -255,7 +311,7 @@ __device__ int bfs_tile_bits(int tile, int B, int n_atoms, int K, const int *__r
                 if (sl < s_deg[tl]) {
                     const int j = nbr_j[s_p0[tl] + sl];
                     const unsigned bit = 1u << (j & 31);
-                    if (!(s_vis[j >> 5] & bit)) atomicOr(&s_new[j >> 5], bit);
+                    if (!(s_vis[j >> 5] & bit) && inside_any(rad, j, s_tp, Bt)) atomicOr(&s_new[j >> 5], bit);
                 }
             }
             __syncthreads();
@@ -325,7 +381,7 @@ __host__ __device__ inline size_t x_row_bytes(int dtype, int n_orb)
 
 struct Layout {
     size_t sizes;       // int [n_tiles][MAXK + 2]: rows of U^k per tile; [0] = -1 marks a failed tile
-    size_t tiles;       // per tile: sup[rows_cap], rinfo[rows_cap], lnb[rows_cap * deg_max]
+    size_t tiles;       // per tile: sup[rows_cap], rinfo[rows_cap], lnb[rows_cap * deg_max], rmask[rows_cap]
     size_t tile_stride;
     size_t x;           // X buffers: batch x 2 x rows_cap x n_orb x 64 (also prepare's maps)
     size_t x_stride;    // bytes of one X buffer
@@ -363,7 +419,7 @@ __host__ __device__ inline Layout make_layout(const bop_plan &p, int n_prep_wg)
     size_t o = HDR;
     auto take = [&](size_t b) { size_t r = o; o += (b + 255) / 256 * 256; return r; };
     L.sizes = take(4ull * p.n_tiles * (MAXK + 2));
-    L.tile_stride = (4ull * p.rows_cap * (2 + p.deg_max) + 255) / 256 * 256;
+    L.tile_stride = (4ull * p.rows_cap * (3 + p.deg_max) + 255) / 256 * 256;   // sup, rinfo, lnb, row masks
     L.tiles = take(L.tile_stride * p.n_tiles);
     L.x_stride = (x_row_bytes(p.dtype, p.n_orb) * p.rows_cap + 255) / 256 * 256;
     size_t xb = L.x_stride * (p.batch_tiles >= 2 ? 2 * (size_t)p.batch_tiles : 4);
@@ -386,9 +442,10 @@ __host__ __device__ inline Layout make_layout(const bop_plan &p, int n_prep_wg)
 __global__ void __launch_bounds__(PLAN_T)
 k_plan(int n_atoms, int B, int n_tiles, int K, const int *__restrict__ order,
        const int *__restrict__ row_ptr, const int *__restrict__ nbr_j, int deg_max,
-       int *hdr, char *scratch, size_t per_wg)
+       int *hdr, char *scratch, size_t per_wg, Radius rad)
 {
     __shared__ int s_size[MAXK + 2], s_wave[PLAN_T / 64], s_flag[1], s_tile[1];
+    __shared__ double s_tp[3 * 64];
     char *mine = scratch + per_wg * blockIdx.x;
     int *g2l = (int *)mine;
     int *sup = (int *)(mine + align_up(4ull * n_atoms, 256));
@@ -396,7 +453,7 @@ k_plan(int n_atoms, int B, int n_tiles, int K, const int *__restrict__ order,
         int tile = next_tile(&hdr[0], s_tile);
         if (tile >= n_tiles) break;
         int rows = bfs_tile<PLAN_T>(tile, B, n_atoms, K, order, row_ptr, nbr_j, deg_max, g2l, sup,
-                                    n_atoms, s_size, s_wave, s_flag);
+                                    n_atoms, s_size, s_wave, s_flag, rad, s_tp);
         if (threadIdx.x <= K) atomicMax(&hdr[8 + threadIdx.x], s_size[threadIdx.x]);
         if (threadIdx.x == 0) atomicMax(&hdr[2], rows);
         reset_map<PLAN_T>(g2l, sup, rows);
@@ -412,10 +469,11 @@ k_plan(int n_atoms, int B, int n_tiles, int K, const int *__restrict__ order,
 __global__ void __launch_bounds__(PLAN_T)
 k_plan_bits(int n_atoms, int B, int n_tiles, int K, const int *__restrict__ order,
             const int *__restrict__ row_ptr, const int *__restrict__ nbr_j, int deg_max,
-            int *hdr, char *scratch, size_t per_wg)
+            int *hdr, char *scratch, size_t per_wg, Radius rad)
 {
     extern __shared__ unsigned s_bits[];
     __shared__ int s_size[MAXK + 2], s_tile[1], s_cnt[1], s_p0[FRONT], s_deg[FRONT];
+    __shared__ double s_tp[3 * 64];
     const int tid = threadIdx.x, lane = tid & 63;
     const int nw = (n_atoms + 31) / 32;
     for (int i = tid; i < nw; i += PLAN_T) s_bits[i] = 0u;
@@ -431,6 +489,8 @@ k_plan_bits(int n_atoms, int B, int n_tiles, int K, const int *__restrict__ orde
             atomicOr(&s_bits[g >> 5], 1u << (g & 31));
         }
         if (tid == 0) { s_size[0] = Bt; s_cnt[0] = Bt; }
+        __syncthreads();
+        tile_positions(rad, sup, Bt, s_tp);
         __syncthreads();
         for (int k = 1; k <= K; ++k) {
             const int begin = (k >= 2) ? s_size[k - 2] : 0, end = s_size[k - 1];
@@ -454,7 +514,8 @@ k_plan_bits(int n_atoms, int B, int n_tiles, int K, const int *__restrict__ orde
                         if (sl < s_deg[tl]) {
                             j = nbr_j[s_p0[tl] + sl];
                             const unsigned bit = 1u << (j & 31);
-                            fresh = !(atomicOr(&s_bits[j >> 5], bit) & bit);
+                            if (!(s_bits[j >> 5] & bit) && inside_any(rad, j, s_tp, Bt))
+                                fresh = !(atomicOr(&s_bits[j >> 5], bit) & bit);
                         }
                     }
                     const unsigned long long m = __ballot(fresh);
@@ -498,9 +559,10 @@ template <bool BITS>
 __global__ void __launch_bounds__(PLAN_T)
 k_prepare(int n_atoms, int B, int n_tiles, int K, const int *__restrict__ order,
           const int *__restrict__ row_ptr, const int *__restrict__ nbr_j, int deg_max, int rows_cap,
-          RowsK rows_k, int *hdr, char *ws, Layout lay, size_t map_stride)
+          RowsK rows_k, int *hdr, char *ws, Layout lay, size_t map_stride, Radius rad)
 {
     __shared__ int s_size[MAXK + 2], s_wave[PLAN_T / 64], s_flag[1], s_tile[1];
+    __shared__ double s_tp[3 * 64];
     __shared__ int s_p0[BITS ? FRONT : 1], s_deg[BITS ? FRONT : 1];
     extern __shared__ unsigned s_bits2[];        // BITS: visited and layer bitmaps
     const int nw = (n_atoms + 31) / 32;
@@ -519,9 +581,9 @@ k_prepare(int n_atoms, int B, int n_tiles, int K, const int *__restrict__ order,
         int *lnb = rinfo + rows_cap;
         const int rows = BITS ? bfs_tile_bits<PLAN_T>(tile, B, n_atoms, K, order, row_ptr, nbr_j, deg_max, g2l,
                                                       sup, rows_cap, s_size, s_wave, s_bits2, s_bits2 + nw, nw,
-                                                      s_p0, s_deg)
+                                                      s_p0, s_deg, rad, s_tp)
                               : bfs_tile<PLAN_T>(tile, B, n_atoms, K, order, row_ptr, nbr_j, deg_max, g2l, sup,
-                                                 rows_cap, s_size, s_wave, s_flag);
+                                                 rows_cap, s_size, s_wave, s_flag, rad, s_tp);
         if (rows < 0) {
             // support larger than planned: keep the seeds so that their moments
             // can be marked NaN, and raise the error flag
@@ -602,6 +664,16 @@ k_prepare(int n_atoms, int B, int n_tiles, int K, const int *__restrict__ order,
             }
             const int n1 = cnt[0], n2 = cnt[0] + cnt[1], c = n2 + cnt[2];
             rinfo[l] = L | (n1 << 8) | (n2 << 16) | (c << 24);
+            if (rad.on) {
+                // the columns of tile atom t keep this row if it lies within r_max of t
+                int *rmask = lnb + (long)rows_cap * deg_max;
+                const int Bt = s_size[0];
+                const double pj[3] = {rad.pos[3 * (long)g], rad.pos[3 * (long)g + 1], rad.pos[3 * (long)g + 2]};
+                int bits = 0;
+                for (int t = 0; t < Bt; ++t)
+                    if (within(rad, pj, s_tp + 3 * t)) bits |= 1 << t;
+                rmask[l] = bits;
+            }
         }
         __syncthreads();
         if (s_flag[0] && threadIdx.x == 0) {
@@ -702,7 +774,7 @@ __host__ __device__ inline int h_slice(int deg_max, int nb) { return (deg_max * 
 // k_lreduce_fused takes a_j = s_j <r_j, y'_(j+1)> and b_(j+1)^2 = |y'_(j+1) -
 // a_j u_j|^2 = |y'|^2 - 2 a_j^2 + a_j^2 s_j^2 |r_j|^2.  Per column (lane) lc
 // gives s_j, beta_j = b_j s_(j-1), c_j, beta_(j-1) and 1/s_(j-1).
-template <typename T, int NO, int WGT, int LANCZOS, typename S = T, bool HS = false>
+template <typename T, int NO, int WGT, int LANCZOS, typename S = T, bool HS = false, bool TR = false>
 __global__ void __launch_bounds__(WGT)
 k_step(Batch bt, int k, int K, int last, int keep, int fin, int nch, int chunk_rows, int deg_max, int rows_cap,
        const int *__restrict__ row_ptr, const double *__restrict__ H_on, const T *__restrict__ H,
@@ -739,6 +811,7 @@ k_step(Batch bt, int k, int K, int last, int keep, int fin, int nch, int chunk_r
     const int *sup = (const int *)(tiles_base + tile_stride * tile);
     const int *rinfo = sup + rows_cap;
     const int *lnb = rinfo + rows_cap;
+    const int *rmask = lnb + (long)rows_cap * deg_max;   // path radius: tile atoms that keep the row
     const int src = last ? (K & 1) : ((k - 1) & 1);
     constexpr size_t NBUF = LANCZOS ? 4 : 2;      // X buffers per tile
     const S *Xp = (const S *)(xbase + x_stride * (NBUF * t + src));
@@ -770,20 +843,22 @@ k_step(Batch bt, int k, int K, int last, int keep, int fin, int nch, int chunk_r
     // the current row computes, which takes their dependent loads off the
     // critical path
     int l = chunk * NW + w;
-    int g_n = 0, info_n = 0, slots_n = 0, p0_n = 0, p1_n = 0;
+    int g_n = 0, info_n = 0, slots_n = 0, p0_n = 0, p1_n = 0, tm_n = -1;
     if (l < nrow) {
         g_n = __builtin_amdgcn_readfirstlane(sup[l]);
         info_n = __builtin_amdgcn_readfirstlane(rinfo[l]);
+        if constexpr (TR) tm_n = __builtin_amdgcn_readfirstlane(rmask[l]);
         slots_n = lane < deg_max ? lnb[(long)l * deg_max + lane] : 0;
         p0_n = row_ptr[g_n];
         p1_n = row_ptr[g_n + 1];
         if constexpr (!HS) h_copy((const float *)(H + (long)p0_n * NB), (float *)sH, (p1_n - p0_n) * NB);
     }
     for (; l < nrow; l += RS) {
-        const int g = g_n, info = info_n, slots_all = slots_n, p0 = p0_n, deg = p1_n - p0_n;
+        const int g = g_n, info = info_n, slots_all = slots_n, p0 = p0_n, deg = p1_n - p0_n, tm = tm_n;
         if (l + RS < nrow) {
             g_n = __builtin_amdgcn_readfirstlane(sup[l + RS]);
             info_n = __builtin_amdgcn_readfirstlane(rinfo[l + RS]);
+            if constexpr (TR) tm_n = __builtin_amdgcn_readfirstlane(rmask[l + RS]);
             slots_n = lane < deg_max ? lnb[(long)(l + RS) * deg_max + lane] : 0;
             p0_n = row_ptr[g_n];
             p1_n = row_ptr[g_n + 1];
@@ -862,6 +937,14 @@ k_step(Batch bt, int k, int K, int last, int keep, int fin, int nch, int chunk_r
                 product(s0, x, hoff);
             }
         }
+        // path radius: a column keeps the row only within r_max of its atom
+        if constexpr (TR) {
+            if (!((tm >> (lane / NO)) & 1)) {
+#pragma unroll
+                for (int a = 0; a < NO; ++a) acc[a] = T(0);
+            }
+        }
+        (void)tm;
         __builtin_amdgcn_wave_barrier();   // all lanes done with sH before the next row's copy
         if constexpr (!HS) {
             if (nval == 0) __builtin_amdgcn_s_waitcnt(0);   // this row's copy (unused) has landed
@@ -1258,21 +1341,27 @@ int run_moments(const bop_plan &p, const int *row_ptr, const double *H_on, const
 #define BOP_STEP_ARGS                                                                                 \
     bt, k, K, last, keep, 0, nch, p.chunk_rows, p.deg_max, p.rows_cap, row_ptr, H_on, H, sizes, tiles,  \
         lay.tile_stride, xb, lay.x_stride, part + sp.off[k], nullptr
-#define BOP_STEP(W)                                                                                   \
+#define BOP_STEP_TR(W, TR)                                                                            \
     do {                                                                                              \
         const size_t lds = h_lds_bytes(p, W, sizeof(T));                                              \
         if constexpr (sizeof(T) == 8) {                                                               \
-            k_step<T, NO, W, 0, T, true><<<grid, W, 0, st>>>(BOP_STEP_ARGS);                          \
+            k_step<T, NO, W, 0, T, true, TR><<<grid, W, 0, st>>>(BOP_STEP_ARGS);                      \
         } else {                                                                                      \
             if (lds + step_static_lds(W, 0) > lds_max)                                                \
-                k_step<T, NO, W, 0, T, true><<<grid, W, 0, st>>>(BOP_STEP_ARGS);                      \
-            else k_step<T, NO, W, 0, T, false><<<grid, W, lds, st>>>(BOP_STEP_ARGS);                  \
+                k_step<T, NO, W, 0, T, true, TR><<<grid, W, 0, st>>>(BOP_STEP_ARGS);                  \
+            else k_step<T, NO, W, 0, T, false, TR><<<grid, W, lds, st>>>(BOP_STEP_ARGS);              \
         }                                                                                             \
+    } while (0)
+#define BOP_STEP(W)                                                                                   \
+    do {                                                                                              \
+        if (p.r_max > 0.0) BOP_STEP_TR(W, true);                                                      \
+        else BOP_STEP_TR(W, false);                                                                   \
     } while (0)
             if (p.block_threads == 256) BOP_STEP(256);
             else if (p.block_threads == 512) BOP_STEP(512);
             else BOP_STEP(1024);
 #undef BOP_STEP
+#undef BOP_STEP_TR
 #undef BOP_STEP_ARGS
             BOP_LAUNCHED();
         }
@@ -1640,21 +1729,27 @@ int run_lanczos(const bop_plan &p, const int *row_ptr, const double *H_on, const
 #define BOP_LSTEP_ARGS                                                                                \
     bt, k, K, last, keep, 0, nch, p.chunk_rows, p.deg_max, p.rows_cap, row_ptr, H_on, (const T *)Hv,    \
         sizes, tiles, lay.tile_stride, xb, lay.x_stride, part, lc
-#define BOP_LSTEP(W)                                                                                  \
+#define BOP_LSTEP_TR(W, TR)                                                                           \
     do {                                                                                              \
         const size_t lds = h_lds_bytes(p, W, sizeof(T));                                              \
         if constexpr (sizeof(T) == 8) {                                                               \
-            k_step<T, NO, W, 1, S, true><<<grid, W, 0, st>>>(BOP_LSTEP_ARGS);                         \
+            k_step<T, NO, W, 1, S, true, TR><<<grid, W, 0, st>>>(BOP_LSTEP_ARGS);                     \
         } else {                                                                                      \
             if (lds + step_static_lds(W, 1) > lds_max)                                                \
-                k_step<T, NO, W, 1, S, true><<<grid, W, 0, st>>>(BOP_LSTEP_ARGS);                     \
-            else k_step<T, NO, W, 1, S, false><<<grid, W, lds, st>>>(BOP_LSTEP_ARGS);                 \
+                k_step<T, NO, W, 1, S, true, TR><<<grid, W, 0, st>>>(BOP_LSTEP_ARGS);                 \
+            else k_step<T, NO, W, 1, S, false, TR><<<grid, W, lds, st>>>(BOP_LSTEP_ARGS);             \
         }                                                                                             \
+    } while (0)
+#define BOP_LSTEP(W)                                                                                  \
+    do {                                                                                              \
+        if (p.r_max > 0.0) BOP_LSTEP_TR(W, true);                                                     \
+        else BOP_LSTEP_TR(W, false);                                                                  \
     } while (0)
             if (p.block_threads == 256) BOP_LSTEP(256);
             else if (p.block_threads == 512) BOP_LSTEP(512);
             else BOP_LSTEP(1024);
 #undef BOP_LSTEP
+#undef BOP_LSTEP_TR
 #undef BOP_LSTEP_ARGS
             BOP_LAUNCHED();
             k_lreduce_fused<<<bt.count, 64, 0, st>>>(bt, k, K, last, p.n_max, NO, nch, p.chunk_rows,
@@ -1685,6 +1780,46 @@ static int map_workgroups(int n_atoms, int n_tiles)
     return w < 1 ? 1 : (int)w;
 }
 
+// Device form of a path radius; checks that r_max + r_cut is below half the
+// smallest cell height (where the minimum image of every atom within r_max is
+// unique and the fractional rounding finds it).
+static int make_radius(const bop_path_radius *r, Radius *out, const char *who)
+{
+    *out = Radius{};
+    if (!r) return BOP_OK;
+    BOP_REQUIRE(r->r_max > 0.0 && r->r_cut >= 0.0 && r->pos, BOP_E_ARG, "%s: path radius needs r_max > 0 and positions",
+                who);
+    const double *A = r->cell;
+    auto cross = [](const double *u, const double *v, double *w) {
+        w[0] = u[1] * v[2] - u[2] * v[1];
+        w[1] = u[2] * v[0] - u[0] * v[2];
+        w[2] = u[0] * v[1] - u[1] * v[0];
+    };
+    double c23[3], c31[3], c12[3];
+    cross(A + 3, A + 6, c23);
+    cross(A + 6, A + 0, c31);
+    cross(A + 0, A + 3, c12);
+    const double V = A[0] * c23[0] + A[1] * c23[1] + A[2] * c23[2];
+    BOP_REQUIRE(std::fabs(V) > 0.0, BOP_E_ARG, "%s: singular cell", who);
+    const double *cs[3] = {c23, c31, c12};
+    double hmin = INFINITY;
+    for (int a = 0; a < 3; ++a) {
+        const double nrm = std::sqrt(cs[a][0] * cs[a][0] + cs[a][1] * cs[a][1] + cs[a][2] * cs[a][2]);
+        hmin = std::fmin(hmin, std::fabs(V) / nrm);
+    }
+    BOP_REQUIRE(r->r_max + r->r_cut < 0.5 * hmin, BOP_E_ARG,
+                "%s: r_max + r_cut = %g must be below half the smallest cell height (%g)", who, r->r_max + r->r_cut,
+                0.5 * hmin);
+    out->on = 1;
+    out->r2 = r->r_max * r->r_max;
+    for (int e = 0; e < 9; ++e) out->A[e] = A[e];
+    // inverse of the row-vector cell matrix: column a of it is (a_b x a_c) / V
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) out->Ai[b * 3 + a] = cs[a][b] / V;
+    out->pos = r->pos;
+    return BOP_OK;
+}
+
 extern "C" size_t bop_moments_plan_scratch_size(int n_atoms)
 {
     if (n_atoms < 0) return 0;
@@ -1694,7 +1829,8 @@ extern "C" size_t bop_moments_plan_scratch_size(int n_atoms)
 
 extern "C" int bop_moments_plan(int n_atoms, int n_orb, int n_max, int dtype, const int *row_ptr,
                                 const int *nbr_j, const int *order, const bop_tuning *tuning,
-                                void *scratch, size_t scratch_bytes, bop_plan *plan, hipStream_t stream)
+                                const bop_path_radius *radius, void *scratch, size_t scratch_bytes, bop_plan *plan,
+                                hipStream_t stream)
 {
     BOP_REQUIRE(plan && n_atoms >= 0, BOP_E_ARG, "bop_moments_plan: bad arguments");
     BOP_REQUIRE(n_orb == 5 || n_orb == 9, BOP_E_UNSUPPORTED, "bop_moments_plan: n_orb must be 5 or 9");
@@ -1702,6 +1838,10 @@ extern "C" int bop_moments_plan(int n_atoms, int n_orb, int n_max, int dtype, co
     BOP_REQUIRE(dtype == BOP_F64 || dtype == BOP_F32 || dtype == BOP_BF16 || dtype == BOP_F16, BOP_E_UNSUPPORTED,
                 "bop_moments_plan: unknown dtype %d", dtype);
     BOP_REQUIRE(n_atoms == 0 || (row_ptr && nbr_j), BOP_E_ARG, "bop_moments_plan: neighbour arrays NULL");
+    BOP_REQUIRE(!radius || dtype != BOP_BF16, BOP_E_UNSUPPORTED,
+                "bop_moments_plan: a path radius is not supported with BF16 H.X");
+    Radius rad;
+    if (int rc = make_radius(radius, &rad, "bop_moments_plan")) return rc;
     size_t need = bop_moments_plan_scratch_size(n_atoms);
     BOP_REQUIRE(scratch && scratch_bytes >= need, BOP_E_CAPACITY,
                 "bop_moments_plan: scratch of %zu bytes needed", need);
@@ -1744,9 +1884,10 @@ extern "C" int bop_moments_plan(int n_atoms, int n_orb, int n_max, int dtype, co
                     dmax);
         if (bits)
             k_plan_bits<<<pwg, PLAN_T, bits_bytes, stream>>>(n_atoms, B, n_tiles, K, order, row_ptr, nbr_j, dmax,
-                                                            hdr, base, per);
+                                                            hdr, base, per, rad);
         else
-            k_plan<<<pwg, PLAN_T, 0, stream>>>(n_atoms, B, n_tiles, K, order, row_ptr, nbr_j, dmax, hdr, base, per);
+            k_plan<<<pwg, PLAN_T, 0, stream>>>(n_atoms, B, n_tiles, K, order, row_ptr, nbr_j, dmax, hdr, base, per,
+                                               rad);
         BOP_LAUNCHED();
         BOP_HIP(hipMemcpyAsync(hv, hdr, sizeof hv, hipMemcpyDeviceToHost, stream));
         BOP_HIP(hipStreamSynchronize(stream));
@@ -1764,6 +1905,7 @@ extern "C" int bop_moments_plan(int n_atoms, int n_orb, int n_max, int dtype, co
     plan->rows_cap = hv[2] > 0 ? hv[2] : 1;
     for (int k = 0; k <= K; ++k) plan->rows_k[k] = hv[8 + k];
     plan->search = bits ? 1 : 2;
+    plan->r_max = radius ? radius->r_max : 0.0;
     BOP_REQUIRE(plan->rows_cap < (1 << 23), BOP_E_UNSUPPORTED, "bop_moments_plan: tile support too large");
     const size_t x_tile = 2 * align_up(x_row_bytes(dtype, n_orb) * plan->rows_cap, 256);
     // default batch: 24 GiB of X buffers, at most a quarter of the free device
@@ -1782,9 +1924,13 @@ extern "C" int bop_moments_plan(int n_atoms, int n_orb, int n_max, int dtype, co
 }
 
 extern "C" int bop_moments_prepare(const bop_plan *plan, const int *row_ptr, const int *nbr_j, const int *order,
-                                   void *ws, size_t ws_bytes, hipStream_t stream)
+                                   const bop_path_radius *radius, void *ws, size_t ws_bytes, hipStream_t stream)
 {
     BOP_REQUIRE(plan, BOP_E_ARG, "bop_moments_prepare: plan is NULL");
+    BOP_REQUIRE((plan->r_max > 0.0) == (radius != nullptr) && (!radius || radius->r_max == plan->r_max), BOP_E_ARG,
+                "bop_moments_prepare: give the plan's path radius (and none if the plan has none)");
+    Radius rad;
+    if (int rc = make_radius(radius, &rad, "bop_moments_prepare")) return rc;
     BOP_REQUIRE(ws && ws_bytes >= plan->ws_bytes, BOP_E_CAPACITY,
                 "bop_moments_prepare: workspace of %zu bytes needed, %zu given", plan->ws_bytes, ws_bytes);
     const int n = plan->n_atoms;
@@ -1806,11 +1952,11 @@ extern "C" int bop_moments_prepare(const bop_plan *plan, const int *row_ptr, con
     if (bits)
         k_prepare<true><<<pwg, PLAN_T, bits2, stream>>>(n, plan->tile_atoms, plan->n_tiles, plan->n_max / 2, order,
                                                         row_ptr, nbr_j, plan->deg_max, plan->rows_cap, rk, hdr, w,
-                                                        lay, map_stride);
+                                                        lay, map_stride, rad);
     else
         k_prepare<false><<<pwg, PLAN_T, 0, stream>>>(n, plan->tile_atoms, plan->n_tiles, plan->n_max / 2, order,
                                                      row_ptr, nbr_j, plan->deg_max, plan->rows_cap, rk, hdr, w,
-                                                     lay, map_stride);
+                                                     lay, map_stride, rad);
     BOP_LAUNCHED();
     return BOP_OK;
 }

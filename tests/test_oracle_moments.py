@@ -142,3 +142,64 @@ def test_dimer_moments():
     np.testing.assert_allclose(rec["b"][:, 1], np.abs(V), rtol=1e-13)
     assert np.all(rec["flags"] & 1)
     assert np.all((rec["flags"] >> 8) == 2)
+
+
+def _bcc6():
+    rng = np.random.default_rng(12)
+    pos, cell = W.cubic_lattice("bcc", 2.87, 6)              # 432 atoms, L = 17.22 A
+    return W.displace(pos, cell, 0.05, rng), cell
+
+
+def test_path_radius_large_and_tiny_limits():
+    """A radius beyond every path's reach changes nothing (4 moments: two hops
+    of at most 3.5 A each, r_max = 7.5 A); a radius below the nearest-neighbour
+    distance leaves the start atom alone: mu_n = E^n."""
+    pos, cell = _bcc6()
+    model = W.canonical_d_model(3.5, onsite_d=(0.3,))
+    spc = np.zeros(len(pos), np.int32)
+    nl = O.neighbours(pos, cell, 3.5)
+    H_on, H_b = O.build_H(model, spc, nl)
+    sel = np.array([0, 17, 431], np.int32)
+    full = O.moments(nl, H_on, H_b, 4, sel)
+    np.testing.assert_allclose(O.moments(nl, H_on, H_b, 4, sel, r_max=7.5), full, rtol=1e-15, atol=1e-15)
+    tiny = O.moments(nl, H_on, H_b, 6, sel, r_max=2.0)
+    np.testing.assert_allclose(tiny, np.broadcast_to(0.3 ** np.arange(7), tiny.shape), rtol=1e-14)
+
+
+def test_path_radius_matches_cluster_matrix_powers():
+    """Brute force: the atoms within r_max of the start atom (minimum image)
+    form a cluster; its dense Hamiltonian keeps the bonds whose target lies
+    within r_max; the truncated moments are the diagonal of its matrix powers.
+    r_max = 4.45 A sits in the gap between the third and fourth bcc shells
+    (4.06 and 4.76 A, broadened by the displacements), asserted here."""
+    pos, cell = _bcc6()
+    model = W.canonical_d_model(3.5)
+    spc = np.zeros(len(pos), np.int32)
+    nl = O.neighbours(pos, cell, 3.5)
+    H_on, H_b = O.build_H(model, spc, nl)
+    r_max, n_max = 4.45, 9
+    inv = np.linalg.inv(cell)
+    for i in (0, 101, 250):
+        d = pos - pos[i]
+        f = d @ inv
+        f -= np.rint(f)
+        dist = np.linalg.norm(f @ cell, axis=1)
+        assert np.min(np.abs(dist - r_max)) > 0.05
+        inside = np.nonzero(dist <= r_max)[0]
+        rel = (f @ cell)[inside]
+        idx = {a: k for k, a in enumerate(inside)}
+        Hc = np.zeros((5 * len(inside), 5 * len(inside)))
+        for k, a in enumerate(inside):
+            Hc[5 * k:5 * k + 5, 5 * k:5 * k + 5] = np.diag(H_on[a])
+            for p in range(nl["row_ptr"][a], nl["row_ptr"][a + 1]):
+                j = nl["nbr_j"][p]
+                if j in idx and np.linalg.norm(rel[k] + nl["nbr_d"][p]) <= r_max:
+                    kj = idx[j]
+                    Hc[5 * k:5 * k + 5, 5 * kj:5 * kj + 5] += H_b[p]
+        s = idx[i]
+        want = np.array([[np.linalg.matrix_power(Hc, n)[5 * s + al, 5 * s + al] for n in range(n_max + 1)]
+                         for al in range(5)])
+        got = O.moments(nl, H_on, H_b, n_max, np.array([i], np.int32), r_max=r_max)[0]
+        np.testing.assert_allclose(got, want, rtol=1e-11, atol=1e-13)
+        full = O.moments(nl, H_on, H_b, n_max, np.array([i], np.int32))[0]
+        assert np.max(np.abs(got - full)[:, 2::2] / full[:, 2::2]) > 1e-3    # the truncation does bite
