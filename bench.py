@@ -172,9 +172,15 @@ def main():
     ap.add_argument("--reps", type=int, default=40)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-f64", action="store_true", help="skip the FP64 comparison run")
-    ap.add_argument("--workload", default="energy", choices=["energy", "batch", "scf", "precision"],
+    ap.add_argument("--workload", default="energy",
+                    choices=["energy", "batch", "scf", "precision", "radius", "md", "magnetic"],
                     help="energy: bcc 40^3 single energy (default); batch: 512 ragged structures; "
-                         "scf: 250,000-atom alloy SCF with MLP warm start; precision: s,p,d alloy, 20 moments")
+                         "scf: 250,000-atom alloy SCF with MLP warm start (and Broyden mixing); precision: s,p,d "
+                         "alloy, 20 moments; radius: bcc 40^3 with maximum path radii; md: alloy SCF along a "
+                         "trajectory, warm against cold starts; magnetic: collinear ferromagnetic bcc Stoner cycle")
+    ap.add_argument("--md-steps", type=int, default=5)
+    ap.add_argument("--reps-md", type=int, default=30)
+    ap.add_argument("--reps-mag", type=int, default=12)
     ap.add_argument("--n-structs", type=int, default=512)
     ap.add_argument("--n-train", type=int, default=200)
     ap.add_argument("--epochs", type=int, default=50)
@@ -205,7 +211,8 @@ def main():
     import workloads as W
     P.load()
     if args.workload != "energy":
-        {"batch": bench_batch, "scf": bench_scf, "precision": bench_precision}[args.workload](args, torch, P, W)
+        {"batch": bench_batch, "scf": bench_scf, "precision": bench_precision, "radius": bench_radius,
+         "md": bench_md, "magnetic": bench_magnetic}[args.workload](args, torch, P, W)
         return
     wl = W.bcc_large(reps=args.reps)
     n_elec = float(wl.n_elec.sum())
@@ -453,6 +460,15 @@ def bench_scf(args, torch, P, W):
     plain, it_p, t_p, _ = WS.converge(wl, dtype="f64")
     u_p = float(plain.out["U_total"].item())
     log(f"plain FP64: {it_p} iterations, {t_p:.2f} s")
+    bro = P.SCFPath(wl.pos, wl.cell, wl.species, wl.model, wl.n_max, wl.n_elec, wl.n_exp, "f64", mixer="broyden")
+    torch.cuda.synchronize()
+    tb0 = time.perf_counter()
+    it_b, _ = bro.run_scf(tol=1e-4, max_iter=300)
+    torch.cuda.synchronize()
+    broyden = {"iterations": it_b, "seconds": time.perf_counter() - tb0,
+               "energy_diff_meV_per_atom": abs(float(bro.out["U_total"].item()) - u_p) / wl.n_atoms * 1e3}
+    log(f"Broyden FP64: {broyden}")
+    del bro
     shift_p = plain.shift.clone()
     del plain
 
@@ -490,7 +506,7 @@ def bench_scf(args, torch, P, W):
                                f"eps_B=0.8 eV, N_d 6/5, d band cutoff 3.5 A, 16 moments, LCN SCF to max|q|<1e-4, "
                                f"MLP warm start",
                    "n_atoms": wl.n_atoms, "n_max": wl.n_max, "mix": 0.5},
-        "plain_fp64": {"iterations": it_p, "seconds": t_p},
+        "plain_fp64": {"iterations": it_p, "seconds": t_p}, "broyden_fp64": broyden,
         "warm_fp64": w64, "warm_fp32_lanczos": w32,
         "speedup_vs_plain": t_p / best["seconds"],
         "mlp": {"train_structures": n_fit, "val_structures": len(train) - n_fit, "rows": int(x.shape[0]),
@@ -550,6 +566,142 @@ def bench_precision(args, torch, P, W):
         "cpu_baseline": {"value": 64 * wl.n_max / t_o, "unit": "atom-moments/s", "cores": O.num_threads(),
                          "kind": "oracle", "sample": "64 seeded atoms, FP64 moments only"},
     }
+    print(json.dumps(res), flush=True)
+
+
+def bench_radius(args, torch, P, W):
+    """Maximum path radius (Sec. III "Speed-ups" (iii)) on the headline
+    workload, FP32 Lanczos: step time and energy error against the paths of
+    every length, per radius."""
+    wl = W.bcc_large(reps=args.reps)
+    ne = float(wl.n_elec.sum())
+    full = P.EnergyPath(wl.pos, wl.cell, wl.species, wl.model, wl.n_max, wl.n_exp, "f32", method="lanczos")
+    t0, k0, o0 = timed_steps(full, ne, args.steps, 1, torch)
+    ref = {k: v.clone() for k, v in o0.items()}
+    rows0 = full.plan.rows_cap
+    del full
+    forms = {}
+    for r_max in (7.0, 10.0, 13.0, 16.0, 19.0):
+        p = P.EnergyPath(wl.pos, wl.cell, wl.species, wl.model, wl.n_max, wl.n_exp, "f32", method="lanczos",
+                         r_max=r_max)
+        t, k, o = timed_steps(p, ne, args.steps, 1, torch)
+        du = abs(float(o["U_total"].item()) - float(ref["U_total"].item())) / wl.n_atoms * 1e3
+        forms[f"{r_max:g}"] = {"ms_per_step": t * 1e3, "hx_ms": k, "rows_cap": p.plan.rows_cap,
+                               "energy_diff_meV_per_atom": du,
+                               "max_atom_U_diff_eV": float((o["U_atom"] - ref["U_atom"]).abs().max()),
+                               "atom_moments_per_s": wl.n_atoms * wl.n_max / t,
+                               "diverging_rows": int(((p.rec["flags"] & 16) != 0).sum().item())}
+        log(f"r_max {r_max}: {forms[f'{r_max:g}']}")
+        del p
+    within = [kv for kv in forms.items() if kv[1]["energy_diff_meV_per_atom"] <= 1.0]
+    # the fastest radius within 1 meV/atom of all paths, else the widest one
+    best = min(within, key=lambda kv: kv[1]["ms_per_step"]) if within else list(forms.items())[-1]
+    res = {"metric": "atom-moments/s", "value": best[1]["atom_moments_per_s"], "unit": "atom-moments/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": best[1]["ms_per_step"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": (f"bcc {args.reps}^3 ({wl.n_atoms} atoms), 18 moments, FP32 Lanczos, maximum "
+                                   f"path radius {best[0]} A ("
+                                   + ("the fastest within 1 meV/atom of all paths)" if within else
+                                      "none tested is within 1 meV/atom of all paths; the widest)")),
+                      "n_atoms": wl.n_atoms, "n_max": wl.n_max},
+           "all_paths": {"ms_per_step": t0 * 1e3, "hx_ms": k0, "rows_cap": rows0}, "radii": forms}
+    print(json.dumps(res), flush=True)
+
+
+def bench_md(args, torch, P, W):
+    """Sec. III "Speed-ups" (ii): the alloy's charge-neutrality cycle along a
+    seeded trajectory, each step started from the previous converged shifts
+    (warm) or from zero (cold); linear and Broyden mixing, FP64."""
+    wl = W.bcc_alloy_scf(reps=args.reps_md)
+    traj = W.md_trajectory(wl, args.md_steps, step_sigma=0.02)
+    res_m = {}
+    for mixer in ("linear", "broyden"):
+        out = {}
+        for mode in ("cold", "warm"):
+            s = P.SCFPath(wl.pos, wl.cell, wl.species, wl.model, wl.n_max, wl.n_elec, wl.n_exp, "f64", mixer=mixer)
+            its, secs = [], []
+            for t, pos in enumerate(traj):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                if t > 0:
+                    s.set_positions(pos)
+                if mode == "cold":
+                    s.set_shift(np.zeros(wl.n_atoms))
+                it, _ = s.run_scf(tol=1e-4, max_iter=300)
+                torch.cuda.synchronize()
+                its.append(it)
+                secs.append(time.perf_counter() - t0)
+            out[mode] = {"iterations": its, "seconds": secs, "total_s": float(np.sum(secs)),
+                         "U_last_eV_per_atom": float(s.out["U_total"].item()) / wl.n_atoms}
+            log(f"{mixer} {mode}: {out[mode]['iterations']} iterations, {out[mode]['total_s']:.2f} s")
+            del s
+        res_m[mixer] = out
+    best = min((m for m in res_m), key=lambda m: res_m[m]["warm"]["total_s"])
+    res = {"metric": "s per converged SCF", "value": res_m[best]["warm"]["total_s"] / args.md_steps, "unit": "s",
+           "n_gpus": 1, "steps": args.md_steps, "warmup": 0,
+           "ms_per_step": res_m[best]["warm"]["total_s"] / args.md_steps * 1e3, "higher_is_better": False,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"bcc A/B alloy {args.reps_md}^3 cells ({wl.n_atoms} atoms), 16 moments, LCN SCF "
+                                  f"to max|q|<1e-4 along {args.md_steps} seeded MD-like steps (0.02 A per step), "
+                                  f"warm start from the previous step; {best} mixing",
+                      "n_atoms": wl.n_atoms, "n_max": wl.n_max},
+           "mixers": res_m,
+           "speedup_warm_vs_cold": res_m[best]["cold"]["total_s"] / res_m[best]["warm"]["total_s"]}
+    print(json.dumps(res), flush=True)
+
+
+def bench_magnetic(args, torch, P, W):
+    """Collinear magnetism: ferromagnetic bcc (a = 2.87 A, 6.5 d electrons,
+    Stoner I = 0.8 eV), 16 moments; the Stoner / charge-neutrality cycle from
+    m = 1, with the FP64 moment route and the FP32 Lanczos form, which is
+    judged by the FP64 path's energies at its converged state."""
+    import workloads as W_
+    rng = np.random.default_rng(9)
+    pos, cell = W_.cubic_lattice("bcc", 2.87, args.reps_mag)
+    pos = W_.displace(pos, cell, 0.03, rng)
+    n = pos.shape[0]
+    model = W_.canonical_d_model(3.5)
+    spc = np.zeros(n, np.int32)
+    n0 = np.full(n, 6.5)
+    out = {}
+    for method, dtype in (("moments", "f64"), ("lanczos", "f32")):
+        p = P.MagneticPath(pos, cell, spc, model, 16, n0, [0.8], dtype=dtype, method=method)
+        p.set_state(np.zeros(n), np.ones(n))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        it, hist = p.run_scf(mix=0.5, mix_m=0.8, max_iter=800)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        rec = {"iterations": it, "seconds": sec, "ms_per_iteration": sec / it * 1e3,
+               "m_mean": float(p.moment.mean().item()), "U_bond_eV_per_atom": float(p.out["U_total"].item()) / n,
+               "U_X_eV_per_atom": float(p.U_X.item()) / n, "shift": p.shift.clone(), "moment": p.moment.clone()}
+        out[f"{method}_{dtype}"] = rec
+        log(f"{method} {dtype}: {it} iterations, {sec:.2f} s, m {rec['m_mean']:.4f}")
+        del p
+    # the FP64 path at the FP32 cycle's converged state judges it
+    r32 = out["lanczos_f32"]
+    chk = P.MagneticPath(pos, cell, spc, model, 16, n0, [0.8], dtype="f64", method="moments")
+    chk.set_state(r32["shift"], r32["moment"])
+    chk.energy()
+    e64 = (float(chk.out["U_total"].item()) + float(chk.U_X.item())) / n
+    e32 = r32["U_bond_eV_per_atom"] + r32["U_X_eV_per_atom"]
+    r32["energy_err_meV_per_atom"] = abs(e64 - e32) * 1e3
+    ref = out["moments_f64"]
+    r32["energy_diff_vs_f64_cycle_meV_per_atom"] = abs(
+        (ref["U_bond_eV_per_atom"] + ref["U_X_eV_per_atom"]) - e32) * 1e3
+    for v in out.values():
+        v.pop("shift")
+        v.pop("moment")
+    best = "lanczos_f32" if (r32["seconds"] < ref["seconds"] and r32["energy_err_meV_per_atom"] <= 1.0) \
+        else "moments_f64"
+    res = {"metric": "s per converged SCF", "value": out[best]["seconds"], "unit": "s", "n_gpus": 1, "steps": 1,
+           "warmup": 0, "ms_per_step": out[best]["seconds"] * 1e3, "higher_is_better": False, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32" if best == "lanczos_f32" else "f64", "data": "synthetic",
+           "config": {"workload": f"collinear ferromagnetic bcc {args.reps_mag}^3 ({n} atoms), a=2.87 A, sigma=0.03 A, "
+                                  f"canonical d band, 6.5 d electrons, Stoner I=0.8 eV, 16 moments, Stoner/LCN cycle "
+                                  f"from m=1 to max|q|,|dm|<1e-4",
+                      "n_atoms": n, "n_max": 16},
+           "forms": out}
     print(json.dumps(res), flush=True)
 
 

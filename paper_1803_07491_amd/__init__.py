@@ -591,11 +591,6 @@ class SCFPath(EnergyPath):
         s.n_atoms, s.n_max, s.n_exp, s.dtype = self.n, self.n_max, self.n_exp, DTYPES[dtype]
         s.method = 1 if method == "lanczos" else 0
         s.species, s.n0 = _ptr(self.species), _ptr(self.n0)
-        s.row_ptr, s.nbr_j, s.order = _ptr(self.nl.row_ptr), _ptr(self.nl.nbr_j), _ptr(self.nl.order)
-        s.n_pairs = self.nl.n_pairs
-        s.H_on, s.H_bond = _ptr(self.H_on), _ptr(self.H_bond)
-        s.plan = self.plan
-        s.moments_ws, s.moments_ws_bytes = _ptr(self.mws), self.mws.numel()
         s.mu = _ptr(self.mu)
         for k in ("a", "b", "a_inf", "b_inf", "flags"):
             setattr(s, k, _ptr(self.rec[k]))
@@ -604,6 +599,25 @@ class SCFPath(EnergyPath):
         for k in ("E_F", "N_atom", "U_atom", "dos_atom", "U_total"):
             setattr(s, k, _ptr(self.out[k]))
         self.sys = s
+        self._point_at_structure()
+
+    def _point_at_structure(self):
+        """The system's neighbour list, H and moment plan (after a rebuild)."""
+        s = self.sys
+        s.row_ptr, s.nbr_j, s.order = _ptr(self.nl.row_ptr), _ptr(self.nl.nbr_j), _ptr(self.nl.order)
+        s.n_pairs = self.nl.n_pairs
+        s.H_on, s.H_bond = _ptr(self.H_on), _ptr(self.H_bond)
+        s.plan = self.plan
+        s.moments_ws, s.moments_ws_bytes = _ptr(self.mws), self.mws.numel()
+
+    def set_positions(self, pos):
+        """Move the atoms (an MD or relaxation step): neighbour list, bonds and
+        moment plan are rebuilt; the shifts stay, so the next cycle starts from
+        the previous step's converged onsite levels (Sec. III "Speed-ups" (ii))."""
+        torch = _torch()
+        self.pos.copy_(torch.as_tensor(np.ascontiguousarray(pos, np.float64), device=self.device))
+        self.rebuild()
+        self._point_at_structure()
 
     def set_shift(self, shift):
         """Start a new cycle from ``shift`` (the Broyden history starts again)."""

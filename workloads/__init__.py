@@ -438,3 +438,15 @@ NAMED = {
     "fcc_alloy_spd": fcc_alloy_spd,
     "bcc_alloy_scf": bcc_alloy_scf,
 }
+
+
+def md_trajectory(wl: Workload, n_steps: int, step_sigma: float = 0.02, seed: int = 6000) -> list:
+    """A seeded stand-in for the positions of successive MD steps: each step
+    adds i.i.d. normal displacements (step_sigma per component, Angstrom) to
+    the previous positions, wrapped into the cell.  Returns n_steps position
+    arrays, the first being the workload's own."""
+    rng = _rng(seed)
+    out = [np.array(wl.pos, np.float64)]
+    for _ in range(n_steps - 1):
+        out.append(wrap(out[-1] + rng.normal(scale=step_sigma, size=out[-1].shape), wl.cell))
+    return out
