@@ -520,3 +520,264 @@ def adam_step(params, grads, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
         out_m.append(mm)
         out_v.append(vv)
     return out_p, out_m, out_v
+
+
+# --------------------------------------------------------------------------
+# Forces of the bond energy (App. C.1-C.2: dU/dLambda through the weights
+# w = dU/dmu, Eq. weights; the bond-order-like Theta~ = dU/dH, Eq.
+# Theta_tilde_BOP; F_k = -sum Theta~ grad_k H, Eq. F_k), for the d band.
+#
+# Written out from the definitions, for cells small enough for dense matrices:
+#  * the weights are the exact derivatives of the bond energy with respect to
+#    every orbital's moments at the self-determined Fermi level.  The
+#    per-orbital part (recursion, terminator, expansion with its chain,
+#    damping, N and U at E_F) is evaluated here in complex arithmetic and
+#    differentiated by the complex step (Squire & Trapp 1998: f'(x) =
+#    Im f(x + ih)/h, exact to rounding for h = 1e-30).  The Fermi level
+#    moves with the moments so that the electron count stays N_e, which adds
+#    -(E_F - E_bar) dN/dmu with E_bar = sum E_r n_r(E_F) / sum n_r(E_F);
+#  * Theta~ = sum_n sum_(l=0..n-1) H^l diag(w_n) H^(n-1-l), the derivative of
+#    mu_n = diag(H^n) with respect to the folded Hamiltonian H, by dense
+#    matrix powers;
+#  * the bond blocks' derivatives with respect to the bond vector are complex
+#    steps through the direction-cosine form of the two-centre blocks (the
+#    same blocks as App. D's rotation, without its polar singularity);
+#  * F_k = -sum over directed pairs p = (i -> j) of Theta~_(i a, j b)
+#    dH_p,ab/dd (d_p = r_j + S - r_i, so +1 for k = j and -1 for k = i).
+# Onsite levels do not depend on positions, and no repulsive term is modelled.
+# Pinned by central finite differences of the bond energy.
+# --------------------------------------------------------------------------
+def _sk_dd(l, m, n, Vs, Vp, Vd):
+    """d-d bond block from the direction cosines (l, m, n) of the bond and its
+    three bond integrals, the two-centre table of Slater & Koster (Phys. Rev.
+    94, 1498 (1954), Table I), in the orbital order z2, zx, yz, x2-y2, xy of
+    App. D.  Polynomial in l, m, n, so it is smooth for every direction
+    (including the polar axis, where the angle form of App. D is singular) and
+    takes complex arrays for the complex step."""
+    s3 = np.sqrt(3.0)
+    l2, m2, n2 = l * l, m * m, n * n
+    dlm = l2 - m2
+    E = {}
+    E[4, 4] = 3 * l2 * m2 * Vs + (l2 + m2 - 4 * l2 * m2) * Vp + (n2 + l2 * m2) * Vd
+    E[2, 2] = 3 * m2 * n2 * Vs + (m2 + n2 - 4 * m2 * n2) * Vp + (l2 + m2 * n2) * Vd
+    E[1, 1] = 3 * n2 * l2 * Vs + (n2 + l2 - 4 * n2 * l2) * Vp + (m2 + n2 * l2) * Vd
+    E[4, 2] = 3 * l * m2 * n * Vs + l * n * (1 - 4 * m2) * Vp + l * n * (m2 - 1) * Vd
+    E[2, 1] = 3 * m * n2 * l * Vs + m * l * (1 - 4 * n2) * Vp + m * l * (n2 - 1) * Vd
+    E[4, 1] = 3 * l2 * m * n * Vs + m * n * (1 - 4 * l2) * Vp + m * n * (l2 - 1) * Vd
+    E[4, 3] = 1.5 * l * m * dlm * Vs - 2 * l * m * dlm * Vp + 0.5 * l * m * dlm * Vd
+    E[2, 3] = 1.5 * m * n * dlm * Vs - m * n * (1 + 2 * dlm) * Vp + m * n * (1 + 0.5 * dlm) * Vd
+    E[1, 3] = 1.5 * n * l * dlm * Vs + n * l * (1 - 2 * dlm) * Vp - n * l * (1 - 0.5 * dlm) * Vd
+    zz = n2 - 0.5 * (l2 + m2)
+    E[4, 0] = s3 * l * m * zz * Vs - 2 * s3 * l * m * n2 * Vp + 0.5 * s3 * l * m * (1 + n2) * Vd
+    E[2, 0] = s3 * m * n * zz * Vs + s3 * m * n * (l2 + m2 - n2) * Vp - 0.5 * s3 * m * n * (l2 + m2) * Vd
+    E[1, 0] = s3 * l * n * zz * Vs + s3 * l * n * (l2 + m2 - n2) * Vp - 0.5 * s3 * l * n * (l2 + m2) * Vd
+    E[3, 3] = 0.75 * dlm * dlm * Vs + (l2 + m2 - dlm * dlm) * Vp + (n2 + 0.25 * dlm * dlm) * Vd
+    E[3, 0] = 0.5 * s3 * dlm * zz * Vs - s3 * n2 * dlm * Vp + 0.25 * s3 * (1 + n2) * dlm * Vd
+    E[0, 0] = zz * zz * Vs + 3 * n2 * (l2 + m2) * Vp + 0.75 * (l2 + m2) ** 2 * Vd
+    B = np.empty(np.shape(l) + (5, 5), dtype=np.result_type(l, Vs, 1.0))
+    for (a, b), v in E.items():
+        B[..., a, b] = v
+        B[..., b, a] = v
+    return B
+
+
+def _dd_blocks(model, species, nl, d):
+    """d-d bond blocks of the directed pairs of ``nl`` for bond vectors d [P, 3]
+    (complex allowed), by the direction-cosine table."""
+    ns = model["n_species"]
+    i_of = np.repeat(np.arange(len(nl["row_ptr"]) - 1), np.diff(nl["row_ptr"]))
+    pair = species[i_of] * ns + species[nl["nbr_j"]]
+    r = np.sqrt(d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1] + d[:, 2] * d[:, 2])
+    V = np.zeros((d.shape[0], 3), dtype=r.dtype)
+    for k, ch in enumerate(("dds", "ddp", "ddd")):
+        for (si, sj), chans in model["bonds"].items():
+            if ch not in chans:
+                continue
+            f, b0, r0, q = chans[ch]
+            sel = pair == si * ns + sj
+            v = b0 * (r0 / r[sel]) ** q if f == 0 else b0 * np.exp(-q * (r[sel] - r0))
+            V[sel, k] = v
+    assert model.get("d_cut", 0.0) == 0.0, "forces: hard cutoff only"
+    u = d / r[:, None]
+    return _sk_dd(u[:, 0], u[:, 1], u[:, 2], V[:, 0], V[:, 1], V[:, 2])
+
+
+def _tail_c(mu, n_max, n_exp, E_F, e_on):
+    """Per-orbital energy path in complex arithmetic, the steps of the C
+    oracle's recursion, Gershgorin terminator, expansion coefficients (moment
+    route and chain) and N, U at the given E_F.  mu [R, n_max+1] complex.
+    Returns (N, U, n(E_F)) [R] complex."""
+    R = mu.shape[0]
+    na, nb = n_a(n_max), n_b(n_max)
+    m = mu / mu[:, :1]
+    a = np.zeros((R, na), complex)
+    b = np.zeros((R, nb + 1), complex)
+    var = (m[:, 2] - m[:, 1] ** 2).real if n_max >= 2 else np.zeros(R)
+    for r in range(R):
+        cprev = np.zeros(n_max + 2, complex)
+        ccur = np.zeros(n_max + 2, complex)
+        ccur[0] = 1.0
+        broke = False
+        for n in range(na):
+            if broke:
+                a[r, n] = a[r, n - 1]
+                continue
+            idx = np.add.outer(np.arange(n + 1), np.arange(n + 1)) + 1
+            a[r, n] = np.sum(np.outer(ccur[:n + 1], ccur[:n + 1]) * m[r][idx])
+            if n + 1 > nb:
+                break
+            dv = np.zeros(n + 2, complex)
+            dv[1:] += ccur[:n + 1]
+            dv[:n + 1] -= a[r, n] * ccur[:n + 1] + b[r, n] * cprev[:n + 1]
+            idx2 = np.add.outer(np.arange(n + 2), np.arange(n + 2))
+            b2 = np.sum(np.outer(dv, dv) * m[r][idx2])
+            if b2.real <= 1e-14 * var[r]:
+                b[r, n + 1:] = 0.0
+                broke = True
+                continue
+            b[r, n + 1] = np.sqrt(b2)
+            cprev[:n + 2] = ccur[:n + 2]
+            ccur[:n + 2] = dv / b[r, n + 1]
+    # Gershgorin terminator (values decide the extremes)
+    lo = np.zeros(R, complex)
+    hi = np.zeros(R, complex)
+    for n in range(na):
+        bl = b[:, n] if 1 <= n <= nb else np.zeros(R)
+        bh = b[:, n + 1] if n + 1 <= nb else np.zeros(R)
+        e0, e1 = a[:, n] - bl - bh, a[:, n] + bl + bh
+        if n == 0:
+            lo, hi = e0.copy(), e1.copy()
+        else:
+            lo = np.where(e0.real < lo.real, e0, lo)
+            hi = np.where(e1.real > hi.real, e1, hi)
+    ai = 0.5 * (hi + lo)
+    bi = 0.25 * (hi - lo)
+    bi = np.where(bi.real < 1e-6, 1e-6 + 0j, bi)
+    # expansion coefficients
+    g = jackson(n_exp)
+    M = n_max + 1
+    p = np.zeros((M, M))
+    p[0, 0] = 1.0
+    if M > 1:
+        p[1, 1] = 2.0
+    for mm in range(1, M - 1):
+        for n in range(mm + 2):
+            p[mm + 1, n] = (2.0 * p[mm, n - 1] if n >= 1 else 0.0) - (p[mm - 1, n] if n <= mm - 1 else 0.0)
+    from math import comb
+    gs = np.zeros((R, n_exp + 1), complex)
+    mh = np.zeros((R, M), complex)
+    for n in range(M):
+        s = sum(comb(n, l) * (-ai) ** l * m[:, n - l] for l in range(n + 1))
+        mh[:, n] = s / (2.0 * bi) ** n
+    n_mom = np.where(bi.real > 1e-6, n_max, 0)
+    gs[:, 0] = 1.0
+    for mm in range(min(n_max, n_exp) + 1):
+        val = mh[:, :mm + 1] @ p[mm, :mm + 1]
+        gs[:, mm] = np.where(mm <= n_mom, val, gs[:, mm])
+    depth = n_exp + 3
+    ah = np.zeros((R, depth), complex)
+    bh = np.zeros((R, depth), complex)
+    for k in range(depth):
+        if k < na:
+            ah[:, k] = (a[:, k] - ai) / (2.0 * bi)
+        bh[:, k] = 0.0 if k == 0 else (b[:, k] / (2.0 * bi) if k <= nb else 0.5)
+    z0 = np.zeros((R, depth), complex)
+    z1 = np.zeros((R, depth), complex)
+    z1[:, 0] = 1.0
+    for mm in range(n_exp):
+        zm = np.zeros_like(z1)
+        zm[:, 1:] = z1[:, :-1]
+        zp = np.zeros_like(z1)
+        zp[:, :-1] = z1[:, 1:]
+        bh1 = np.zeros_like(bh)
+        bh1[:, :-1] = bh[:, 1:]
+        z2 = 2.0 * (ah * z1 + bh * zm + bh1 * zp) - z0
+        z0, z1 = z1, z2
+        k = mm + 1
+        gs[:, k] = np.where(k > n_mom, z1[:, 0], gs[:, k])
+    gs = gs * g[None, :]
+    # N, U and the DOS at E_F
+    eps = (E_F - ai) / (2.0 * bi)
+    inside = (eps.real > -1.0) & (eps.real < 1.0)
+    c = np.where(inside, eps, np.where(eps.real <= -1.0, -1.0 + 0j, 1.0 + 0j))
+    phi = np.arccos(c)
+
+    def chi(k):
+        if k == 0:
+            return np.zeros(R, complex)
+        if k == 1:
+            return 1.0 - phi / np.pi + np.sin(2.0 * phi) / (2.0 * np.pi)
+        return (np.sin((k + 1) * phi) / (k + 1) - np.sin((k - 1) * phi) / (k - 1)) / np.pi
+
+    chis = [chi(k) for k in range(n_exp + 3)]
+    N = sum(gs[:, k] * chis[k + 1] for k in range(n_exp + 1))
+    U = bi * sum(gs[:, k] * (chis[k + 2] + chis[k]) for k in range(n_exp + 1)) + (ai - e_on) * N
+    D = sum(gs[:, k] * np.sin((k + 1) * phi) for k in range(n_exp + 1))
+    D = np.where(inside, D / (np.pi * bi), 0.0)
+    return N, U, D
+
+
+def weights(mu_rows, n_max, n_exp, E_F, e_on, h=1e-30):
+    """w[r, n] = dU_total/dmu_(r,n) (both spins) at the self-determined Fermi
+    level, by the complex step; also returns (dU/dmu, dN/dmu) per spin."""
+    mu_rows = np.asarray(mu_rows, np.float64)
+    R = mu_rows.shape[0]
+    N0, U0, D0 = _tail_c(mu_rows.astype(complex), n_max, n_exp, E_F, e_on)
+    dU = np.zeros((R, n_max + 1))
+    dN = np.zeros((R, n_max + 1))
+    for n in range(1, n_max + 1):
+        muc = mu_rows.astype(complex)
+        muc[:, n] += 1j * h
+        Nc, Uc, _ = _tail_c(muc, n_max, n_exp, E_F, e_on)
+        dU[:, n] = Uc.imag / h
+        dN[:, n] = Nc.imag / h
+    D = D0.real
+    E_bar = float(np.sum(e_on * D) / np.sum(D))
+    w = 2.0 * (dU - (E_F - E_bar) * dN)
+    return w, dU, dN
+
+
+def forces(wl, nl=None, n_max=None, n_exp=None):
+    """Forces F [N, 3] (eV/A) on every atom from the bond energy of the
+    non-magnetic d-band path, and the energy pipeline's result."""
+    n_max = wl.n_max if n_max is None else n_max
+    n_exp = wl.n_exp if n_exp is None else n_exp
+    assert wl.model["n_orb"] == 5, "forces: d band only"
+    if nl is None:
+        nl = neighbours(wl.pos, wl.cell, wl.model["r_cut"])
+    r = energy_pipeline(wl, nl=nl, n_max=n_max, n_exp=n_exp)
+    H_on, H_b = r["H_on"], r["H_bond"]
+    n = wl.n_atoms
+    no = 5
+    rows = r["mu"].reshape(-1, n_max + 1)
+    w, _, _ = weights(rows, n_max, n_exp, r["E_F"], H_on.reshape(-1))
+    # dense folded H and Theta~
+    H = np.diag(H_on.reshape(-1)).astype(np.float64)
+    i_of = np.repeat(np.arange(n), np.diff(nl["row_ptr"]))
+    for p in range(len(nl["nbr_j"])):
+        i, j = i_of[p], nl["nbr_j"][p]
+        H[no * i:no * i + no, no * j:no * j + no] += H_b[p]
+    powers = [np.eye(n * no)]
+    for l in range(1, n_max):
+        powers.append(powers[-1] @ H)
+    Theta = np.zeros_like(H)
+    for l in range(n_max):
+        Q = np.zeros_like(H)
+        for lp in range(n_max - l):
+            Q += w[:, l + lp + 1][:, None] * powers[lp]
+        Theta += powers[l] @ Q
+    # block derivatives by the complex step in each Cartesian direction
+    spc = np.asarray(wl.species)
+    dH = np.zeros((len(nl["nbr_j"]), 3, no, no))
+    for c in range(3):
+        d = nl["nbr_d"].astype(complex)
+        d[:, c] += 1e-30j
+        dH[:, c] = _dd_blocks(wl.model, spc, nl, d).imag / 1e-30
+    F = np.zeros((n, 3))
+    for p in range(len(nl["nbr_j"])):
+        i, j = i_of[p], nl["nbr_j"][p]
+        T = Theta[no * i:no * i + no, no * j:no * j + no]
+        gp = np.einsum("ab,cab->c", T, dH[p])
+        F[j] -= gp
+        F[i] += gp
+    return F, r, w

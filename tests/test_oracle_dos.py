@@ -454,3 +454,90 @@ def test_magnetic_isolated_atoms_closed_form():
     np.testing.assert_allclose(rm["moment"], [3.5, 3.5], atol=1e-6)
     assert abs(rm["U_X"] + 0.25 * 2 * 3.5 ** 2) < 1e-5
     assert abs(rm["E_F"] - 0.5) < 1e-5
+
+
+def _bcc54(sigma=0.05, n_max=8):
+    rng = np.random.default_rng(14)
+    pos, cell = W.cubic_lattice("bcc", 2.87, 3)
+    if sigma:
+        pos = W.displace(pos, cell, sigma, rng)
+    return W.Workload("b54", pos, cell, np.zeros(54, np.int32), W.canonical_d_model(3.5), n_max, 200,
+                      np.full(54, 6.5))
+
+
+def test_direction_cosine_blocks_match_rotation_blocks_and_invariants():
+    """The direction-cosine d-d blocks the force oracle differentiates: equal to
+    the C oracle's App. D rotation blocks for generic bonds (1e-13), equal to
+    diag(Vs, Vp, Vp, Vd, Vd) for a bond along z (the bond frame itself), with
+    eigenvalues {Vs, Vp, Vp, Vd, Vd} in every direction, including the polar
+    axis where the angle form is singular."""
+    rng = np.random.default_rng(0)
+    model = W.canonical_d_model(10.0)
+    for _ in range(6):
+        d = rng.normal(size=3)
+        d *= 2.6 / np.linalg.norm(d)
+        pos = np.array([[5.0, 5.0, 5.0], [5.0, 5.0, 5.0] + d])
+        nl = O.neighbours(pos, np.eye(3) * 30.0, 3.0)
+        _, Hb = O.build_H(model, np.zeros(2, np.int32), nl)
+        B = O._dd_blocks(model, np.zeros(2, np.int32), nl, nl["nbr_d"])
+        assert np.max(np.abs(B - Hb)) < 1e-13 * np.max(np.abs(Hb))
+    Vs, Vp, Vd = -1.3, 0.7, -0.2
+    B = O._sk_dd(np.array(0.0), np.array(0.0), np.array(1.0), Vs, Vp, Vd)
+    np.testing.assert_allclose(B, np.diag([Vs, Vp, Vp, Vd, Vd]), atol=1e-15)
+    for u in [np.array([0.0, 0.0, -1.0]), np.array([1.0, 0.0, 0.0]), rng.normal(size=3)]:
+        u = u / np.linalg.norm(u)
+        B = O._sk_dd(u[0], u[1], u[2], Vs, Vp, Vd)
+        np.testing.assert_allclose(B, B.T, atol=0)
+        np.testing.assert_allclose(np.linalg.eigvalsh(B), np.sort([Vs, Vp, Vp, Vd, Vd]), atol=1e-14)
+
+
+def test_forces_match_finite_differences_of_the_energy():
+    """The oracle's analytic forces (weights, Theta~, block derivatives)
+    against central differences of its own bond energy (neighbours, H,
+    moments, recursion, expansion and the Fermi bisection redone at r +- h,
+    h = 1e-4 A; truncation error ~h^2 F''' ~ 1e-8 eV/A), for even and odd
+    n_max (odd 5: at 7, 9 and 11 some orbitals' Gershgorin-terminated
+    expansions diverge on this cell); the forces sum to zero."""
+    for n_max in (8, 5):
+        wl = _bcc54(n_max=n_max)
+        F, r, _ = O.forces(wl)
+        assert np.max(np.abs(F.sum(axis=0))) < 1e-10
+        h = 1e-4
+        rng = np.random.default_rng(n_max)
+        for _ in range(4):
+            k, c = int(rng.integers(54)), int(rng.integers(3))
+            pp, pm = wl.pos.copy(), wl.pos.copy()
+            pp[k, c] += h
+            pm[k, c] -= h
+            up = O.energy_pipeline(W.Workload("p", pp, wl.cell, wl.species, wl.model, n_max, 200, wl.n_elec))
+            um = O.energy_pipeline(W.Workload("m", pm, wl.cell, wl.species, wl.model, n_max, 200, wl.n_elec))
+            fd = -(up["U_total"] - um["U_total"]) / (2 * h)
+            assert abs(F[k, c] - fd) < 1e-6 * max(1.0, abs(fd)), (n_max, k, c, F[k, c], fd)
+
+
+def test_forces_vanish_on_a_perfect_lattice_and_weights_match_differences():
+    """Every atom of a perfect bcc lattice is a centre of inversion: F = 0.
+    The weights dU/dmu (complex step, with the Fermi level's response) match
+    central differences of the oracle's energy in one orbital's moment."""
+    wl = _bcc54(sigma=0.0)
+    F, _, _ = O.forces(wl)
+    assert np.max(np.abs(F)) < 1e-10
+    wl = _bcc54()
+    nl = O.neighbours(wl.pos, wl.cell, 3.5)
+    r = O.energy_pipeline(wl, nl=nl)
+    rows = r["mu"].reshape(-1, 9)
+    w, _, _ = O.weights(rows, 8, 200, r["E_F"], r["H_on"].reshape(-1))
+
+    def U_of(rows_):
+        rec = O.recursion(rows_, 8)
+        gs = O.dos_coeffs(rows_, rec, 8, 200)
+        ef = O.fermi(gs, rec["a_inf"], rec["b_inf"], float(np.sum(wl.n_elec)))
+        return O.energy(gs, rec["a_inf"], rec["b_inf"], r["H_on"], ef)["U_total"]
+
+    for (row, n) in ((3, 2), (40, 5), (200, 8)):
+        h = 1e-6 * abs(rows[row, n]) + 1e-7
+        p, m = rows.copy(), rows.copy()
+        p[row, n] += h
+        m[row, n] -= h
+        fd = (U_of(p) - U_of(m)) / (2 * h)
+        assert abs(w[row, n] - fd) < 1e-5 * max(1e-3, abs(fd)), (row, n, w[row, n], fd)
