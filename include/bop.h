@@ -518,6 +518,51 @@ int bop_mlp_train_step(int batch, const int *idx, const float *x, const float *t
                        float *loss, float *grad, void *ws, size_t ws_bytes,
                        hipStream_t stream);
 
+/* =========================================================================
+ * Forces of the d-band bond energy (App. C.1-C.2: Eqs. dUdLambda, weights,
+ * theta-tilde, Theta_tilde_BOP, F_k), non-magnetic, Gershgorin terminator,
+ * no path radius, n_max <= 20.
+ *
+ * bop_weights   w[r][n] = dU_bond/dmu_r^(n) (Eq. weights, both spins) of
+ *               every orbital row r at the self-determined Fermi level: the
+ *               partial derivative of the row's U at E_F plus the Fermi
+ *               level's response, -(E_F - E_bar) dN_r/dmu with E_bar the
+ *               DOS-weighted mean onsite level at E_F.  mu [n_rows][n_max+1]
+ *               (bop_moments), H_on [n_rows], E_F [1] device (bop_energy's).
+ *               w [n_rows][n_max+1], w[r][0] = 0.  n_exp as in bop_energy.
+ * bop_bond_derivatives
+ *               dH[p][x][16] = d H_p / d d_p,x for every directed pair p
+ *               (d_p = nbr_d[p]), packed like the FP64 d-d blocks of
+ *               bop_build_H (upper triangle row-major, entry 15 = 0).
+ *               A species outside the model gives NaN.
+ * bop_forces    F[k][3] = -dU_bond/dr_k (eV/A) from Theta~ = dU/dH (Eq.
+ *               Theta_tilde_BOP) and the block derivatives (Eq. F_k):
+ *               F_k = sum over k's pairs p of g_p - g_reverse(p), g_p =
+ *               sum_ab Theta~_p,ab dH_p,ab/dd_p.  `plan` and `moments_ws` are
+ *               the ones bop_moments used (plan dtype FP64 or FP32: the
+ *               vectors' precision; H_bond in that dtype), after
+ *               bop_moments_prepare; w from bop_weights.  nbr_shift locates
+ *               each pair's reverse.  batch_tiles: tiles whose vectors are
+ *               live at once (0: a default of at most 8 GiB); pass the same
+ *               value to bop_forces_workspace_size.  Errors: BOP_E_UNSUPPORTED
+ *               (not d band, BF16/FP16, path radius, n_max > 20),
+ *               BOP_E_CAPACITY (workspace too small).  Tiles whose support
+ *               did not fit the plan give NaN forces on their atoms and
+ *               neighbours.  The pair gradients are summed with FP64
+ *               atomics: results can differ in the last bits between runs.
+ * ========================================================================= */
+size_t bop_weights_workspace_size(int n_rows, int n_max);
+int bop_weights(int n_rows, int n_max, int n_exp, const double *mu, const double *H_on,
+                const double *E_F, double *w, void *ws, size_t ws_bytes, hipStream_t stream);
+int bop_bond_derivatives(const bop_model *model, int n_atoms, const int *species,
+                         const int *row_ptr, const int *nbr_j, const double *nbr_d, long n_pairs,
+                         double *dH, hipStream_t stream);
+size_t bop_forces_workspace_size(const bop_plan *plan, long n_pairs, int batch_tiles);
+int bop_forces(const bop_plan *plan, const void *moments_ws, const int *row_ptr,
+               const int *nbr_j, const int *nbr_shift, long n_pairs, const double *H_on,
+               const void *H_bond, const double *dH, const double *w, int batch_tiles,
+               double *F, void *ws, size_t ws_bytes, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

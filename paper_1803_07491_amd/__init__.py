@@ -157,6 +157,13 @@ def load(path: str = LIB_PATH):
     lib.bop_mlp_train_workspace_size.restype = C.c_size_t
     lib.bop_mlp_train_workspace_size.argtypes = [C.c_int]
     lib.bop_mlp_train_step.argtypes = [C.c_int, P, P, P, P, P, P, C.c_int, C.c_float, P, P, P, C.c_size_t, P]
+    lib.bop_weights_workspace_size.restype = C.c_size_t
+    lib.bop_weights_workspace_size.argtypes = [C.c_int, C.c_int]
+    lib.bop_weights.argtypes = [C.c_int, C.c_int, C.c_int, P, P, P, P, P, C.c_size_t, P]
+    lib.bop_bond_derivatives.argtypes = [C.POINTER(Model), C.c_int, P, P, P, P, C.c_long, P, P]
+    lib.bop_forces_workspace_size.restype = C.c_size_t
+    lib.bop_forces_workspace_size.argtypes = [C.POINTER(Plan), C.c_long, C.c_int]
+    lib.bop_forces.argtypes = [C.POINTER(Plan), P, P, P, P, C.c_long, P, P, P, P, C.c_int, P, P, C.c_size_t, P]
     _lib = lib
     return lib
 
@@ -487,6 +494,54 @@ def energy_noalloc(mu, rec, H_on, n_elec, n_max, n_exp=200, E_F=None, out=None):
     return o
 
 
+def weights(mu, H_on, E_F, n_max, n_exp=200, out=None, ws=None):
+    """w [R, n_max+1] = dU_bond/dmu (both spins) at the self-determined Fermi
+    level ``E_F`` (1-element device tensor), ``bop_weights``."""
+    torch = _torch()
+    lib = load()
+    mu_rows = _dev(mu.reshape(-1, n_max + 1), torch.float64, "mu")
+    R = mu_rows.shape[0]
+    dev = mu_rows.device
+    if out is None:
+        out = torch.empty((R, n_max + 1), dtype=torch.float64, device=dev)
+    if ws is None:
+        ws = _bytes(lib.bop_weights_workspace_size(R, n_max), dev)
+    _check(lib.bop_weights(R, n_max, n_exp, _ptr(mu_rows), _ptr(H_on), _ptr(E_F), _ptr(out), _ptr(ws), ws.numel(),
+                           _stream()))
+    return out
+
+
+def bond_derivatives(model: dict, species, nl: Neighbours, out=None):
+    """dH [P, 3, 16]: derivatives of the packed d-d blocks with respect to the
+    bond vector (``bop_bond_derivatives``)."""
+    torch = _torch()
+    lib = load()
+    dev = species.device
+    if out is None:
+        out = torch.empty((max(nl.n_pairs, 1), 3, D_PACKED), dtype=torch.float64, device=dev)[: nl.n_pairs]
+    m = model_struct(model)
+    _check(lib.bop_bond_derivatives(C.byref(m), species.shape[0], _ptr(species), _ptr(nl.row_ptr), _ptr(nl.nbr_j),
+                                    _ptr(nl.nbr_d), nl.n_pairs, _ptr(out), _stream()))
+    return out
+
+
+def forces(plan: Plan, mws, nl: Neighbours, H_on, H_bond, dH, w, batch_tiles=0, F=None, ws=None):
+    """F [N, 3] = -dU_bond/dr (``bop_forces``) from the moment plan and its
+    prepared workspace ``mws``, the blocks in the plan's dtype, their
+    derivatives and the weights."""
+    torch = _torch()
+    lib = load()
+    dev = H_on.device
+    if F is None:
+        F = torch.empty((plan.n_atoms, 3), dtype=torch.float64, device=dev)
+    if ws is None:
+        ws = _bytes(lib.bop_forces_workspace_size(C.byref(plan), nl.n_pairs, int(batch_tiles)), dev)
+    _check(lib.bop_forces(C.byref(plan), _ptr(mws), _ptr(nl.row_ptr), _ptr(nl.nbr_j), _ptr(nl.nbr_shift), nl.n_pairs,
+                          _ptr(H_on), _ptr(H_bond), _ptr(dH), _ptr(w), int(batch_tiles), _ptr(F), _ptr(ws),
+                          ws.numel(), _stream()))
+    return F
+
+
 class EnergyPath:
     """Neighbours -> H -> moments -> recursion -> energy for one structure,
     with every buffer allocated once (device tensors) and reused."""
@@ -561,6 +616,19 @@ class EnergyPath:
     def run(self, n_elec, E_F=None):
         self.run_moments()
         return self.run_tail(n_elec, E_F)
+
+    def forces(self, n_elec, batch_tiles=0):
+        """Energy and forces of the current structure: the moment form of the
+        path (FP64 or FP32 vectors as the path's dtype), then the weights at
+        its Fermi level, the block derivatives and F = -dU_bond/dr [N, 3]."""
+        if self.method != "moments":
+            raise ValueError("forces need the moment form")
+        out = self.run(n_elec)
+        self.w = weights(self.mu, self.H_on, out["E_F"], self.n_max, self.n_exp)
+        self.dH = bond_derivatives(self.model, self.species, self.nl)
+        out["F"] = forces(self.plan, self.mws, self.nl, self.H_on, self.H_bond, self.dH, self.w,
+                          batch_tiles=batch_tiles)
+        return out
 
 
 class SCFPath(EnergyPath):

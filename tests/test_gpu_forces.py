@@ -1,0 +1,126 @@
+"""GPU forces of the d-band bond energy (weights, block derivatives, Theta~
+passes and the force sum, through the C ABI) against the oracle's
+(complex-step weights, dense Theta~, direction-cosine block derivatives),
+which is pinned on the CPU by finite differences of its own energy.
+
+Bars: FP64 forces within 1e-10 of max(1, max|F|) eV/A; FP32 vectors (weights
+and block derivatives FP64) within 1e-5 of it.  Weights: every moment order's
+column within 1e-9 of its largest entry (both sides exact derivatives; the
+difference is the rounding of two moment computations carried through the
+recursion, up to the Hankel conditioning of the 9-moment map, ~1e4)."""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _bcc54(sigma=0.05, n_max=8):
+    rng = np.random.default_rng(14)
+    pos, cell = W.cubic_lattice("bcc", 2.87, 3)
+    if sigma:
+        pos = W.displace(pos, cell, sigma, rng)
+    return W.Workload("b54", pos, cell, np.zeros(54, np.int32), W.canonical_d_model(3.5), n_max, 200,
+                      np.full(54, 6.5))
+
+
+def _gpu_forces(bop, wl, dtype="f64"):
+    p = bop.EnergyPath(wl.pos, wl.cell, wl.species, wl.model, wl.n_max, wl.n_exp, "f64")
+    out = p.forces(float(np.sum(wl.n_elec)))
+    if dtype == "f64":
+        return p, out, _np(out["F"])
+    # FP32 vectors for the Theta~ passes; weights and derivatives from FP64
+    H_on, H32 = bop.build_H(wl.model, p.species, p.nl, dtype="f32")
+    plan = bop.moments_plan(p.n, 5, wl.n_max, "f32", p.nl)
+    mws = bop.moments_prepare(plan, p.nl)
+    F = bop.forces(plan, mws, p.nl, H_on, H32, p.dH, p.w)
+    return p, out, _np(F)
+
+
+@pytest.mark.parametrize("case", ["bcc54_n8", "bcc54_n5", "bcc128_n9"])
+def test_weights_match_oracle(bop, case):
+    wl = {"bcc54_n8": lambda: _bcc54(n_max=8), "bcc54_n5": lambda: _bcc54(n_max=5),
+          "bcc128_n9": W.bcc_small}[case]()
+    p = bop.EnergyPath(wl.pos, wl.cell, wl.species, wl.model, wl.n_max, wl.n_exp, "f64")
+    out = p.run(float(np.sum(wl.n_elec)))
+    E_F = float(_np(out["E_F"])[0])
+    w = _np(bop.weights(p.mu, p.H_on, out["E_F"], wl.n_max, wl.n_exp))
+    ref = O.energy_pipeline(wl, E_F=E_F)
+    w_ref, _, _ = O.weights(ref["mu"].reshape(-1, wl.n_max + 1), wl.n_max, wl.n_exp, E_F, ref["H_on"].reshape(-1))
+    assert np.all(w[:, 0] == 0.0)
+    for n in range(1, wl.n_max + 1):
+        scale = np.abs(w_ref[:, n]).max()
+        err = np.abs(w[:, n] - w_ref[:, n]).max()
+        assert err <= 1e-9 * scale, (case, n, err, scale)
+
+
+def test_bond_derivatives_match_oracle(bop):
+    """dH/dd of every pair of a displaced bcc cell and of a dimer along z (the
+    polar axis) against the complex step of the oracle's blocks (1e-12 of the
+    largest entry)."""
+    import torch
+    for wl in (_bcc54(), W.dimer(direction=(0.0, 0.0, 1.0)), W.dimer(direction=(1.0, -2.0, 0.5))):
+        pos = torch.as_tensor(wl.pos, device="cuda")
+        sp = torch.as_tensor(wl.species, device="cuda")
+        nl = bop.build_neighbours(pos, wl.cell, wl.model["r_cut"])
+        dH = _np(bop.bond_derivatives(wl.model, sp, nl))
+        onl = O.neighbours(wl.pos, wl.cell, wl.model["r_cut"])
+        ref = np.zeros((len(onl["nbr_j"]), 3, 5, 5))
+        for c in range(3):
+            d = onl["nbr_d"].astype(complex)
+            d[:, c] += 1e-30j
+            ref[:, c] = O._dd_blocks(wl.model, np.asarray(wl.species), onl, d).imag / 1e-30
+        idx = np.array([[min(a, b) * 5 - min(a, b) * (min(a, b) - 1) // 2 + abs(b - a) for b in range(5)]
+                        for a in range(5)])
+        got = dH[:, :, idx]
+        np.testing.assert_array_equal(_np(nl.nbr_j), onl["nbr_j"])
+        assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+        assert np.all(dH[:, :, 15] == 0.0)
+
+
+@pytest.mark.parametrize("case", ["bcc54_n8", "bcc54_n5", "bcc128_n9", "bcc54_n4"])
+def test_forces_match_oracle_fp64(bop, case):
+    """Displaced bcc cells: 54 atoms (four 12-atom tiles and a ragged one of 6)
+    at 8, 5 and 4 moments, 128 atoms at 9."""
+    wl = {"bcc54_n8": lambda: _bcc54(n_max=8), "bcc54_n5": lambda: _bcc54(n_max=5),
+          "bcc128_n9": W.bcc_small, "bcc54_n4": lambda: _bcc54(n_max=4)}[case]()
+    _, out, F = _gpu_forces(bop, wl)
+    F_ref, _, _ = O.forces(wl)
+    scale = max(1.0, np.abs(F_ref).max())
+    err = np.abs(F - F_ref).max()
+    print(f"{case}: max |F - F_ref| = {err:.3e} eV/A (max |F| {np.abs(F_ref).max():.3f})")
+    assert err <= 1e-10 * scale, err
+    assert np.abs(F.sum(axis=0)).max() <= 1e-10 * scale
+
+
+def test_forces_fp32_vectors_match_oracle(bop):
+    wl = _bcc54(n_max=8)
+    _, _, F = _gpu_forces(bop, wl, "f32")
+    F_ref, _, _ = O.forces(wl)
+    scale = max(1.0, np.abs(F_ref).max())
+    err = np.abs(F - F_ref).max()
+    print(f"FP32 vectors: max |F - F_ref| = {err:.3e} eV/A")
+    assert err <= 1e-5 * scale, err
+
+
+def test_forces_perfect_lattice_and_polar_dimer(bop):
+    """Every atom of the perfect bcc lattice is a centre of inversion (F = 0);
+    with one moment nothing depends on the bonds (F = 0); a dimer along z
+    (bonds on the polar axis, a recursion that breaks down) has equal and
+    opposite forces along z, equal to the oracle's."""
+    _, _, F = _gpu_forces(bop, _bcc54(sigma=0.0))
+    assert np.abs(F).max() < 1e-10
+    # one moment: mu_1 is the onsite level, which no bond changes
+    _, _, F = _gpu_forces(bop, _bcc54(n_max=1))
+    assert np.all(F == 0.0)
+    wl = W.dimer(direction=(0.0, 0.0, 1.0))
+    _, _, F = _gpu_forces(bop, wl)
+    F_ref, _, _ = O.forces(wl)
+    assert np.abs(F - F_ref).max() <= 1e-10 * max(1.0, np.abs(F_ref).max())
+    assert np.abs(F[:, :2]).max() < 1e-12 and abs(F[0, 2] + F[1, 2]) < 1e-12
