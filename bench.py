@@ -173,11 +173,12 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-f64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--workload", default="energy",
-                    choices=["energy", "batch", "scf", "precision", "radius", "md", "magnetic"],
+                    choices=["energy", "batch", "scf", "precision", "radius", "md", "magnetic", "forces"],
                     help="energy: bcc 40^3 single energy (default); batch: 512 ragged structures; "
                          "scf: 250,000-atom alloy SCF with MLP warm start (and Broyden mixing); precision: s,p,d "
                          "alloy, 20 moments; radius: bcc 40^3 with maximum path radii; md: alloy SCF along a "
-                         "trajectory, warm against cold starts; magnetic: collinear ferromagnetic bcc Stoner cycle")
+                         "trajectory, warm against cold starts; magnetic: collinear ferromagnetic bcc Stoner cycle; forces: "
+                         "energy and forces of the bcc 40^3 cell")
     ap.add_argument("--md-steps", type=int, default=5)
     ap.add_argument("--reps-md", type=int, default=30)
     ap.add_argument("--reps-mag", type=int, default=12)
@@ -212,7 +213,7 @@ def main():
     P.load()
     if args.workload != "energy":
         {"batch": bench_batch, "scf": bench_scf, "precision": bench_precision, "radius": bench_radius,
-         "md": bench_md, "magnetic": bench_magnetic}[args.workload](args, torch, P, W)
+         "md": bench_md, "magnetic": bench_magnetic, "forces": bench_forces}[args.workload](args, torch, P, W)
         return
     wl = W.bcc_large(reps=args.reps)
     n_elec = float(wl.n_elec.sum())
@@ -702,6 +703,109 @@ def bench_magnetic(args, torch, P, W):
                                   f"from m=1 to max|q|,|dm|<1e-4",
                       "n_atoms": n, "n_max": 16},
            "forms": out}
+    print(json.dumps(res), flush=True)
+
+
+def algorithmic_force_flops_per_atom(row_ptr, nbr_j, n_max, sample):
+    """Theta~ flops one atom's 5 columns need on exact supports (the
+    diamond: X^l and G^k on the atoms within min(l, n - l) hops): per level,
+    every kept row s and each neighbour t whose operand is kept costs one 5x5
+    block times a column (50 flops), plus the onsite level (10); the backward
+    passes add per (s, t) the outer product X^k[s] G^(k+1)[t] (50) contracted
+    with the three symmetric derivative blocks (90)."""
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import dijkstra
+    n = row_ptr.shape[0] - 1
+    A = sp.csr_matrix((np.ones(nbr_j.shape[0]), nbr_j, row_ptr), shape=(n, n))
+    K = n_max // 2
+    dist = dijkstra(A, indices=sample, unweighted=True, limit=K + 0.5)
+    deg = np.diff(row_ptr)
+    owner = np.repeat(np.arange(n), deg)
+    out = []
+    for d in dist:
+        keep = np.isfinite(d[owner]) & np.isfinite(d[nbr_j])
+        ds, dt = d[owner][keep], d[nbr_j][keep]
+        f = 0.0
+        for lev in range(1, n_max):           # forward X^lev
+            Lc, Lp = min(lev, n_max - lev, K), min(lev - 1, n_max - lev + 1, K)
+            f += 50 * np.count_nonzero((ds <= Lc) & (dt <= Lp)) + 10 * np.count_nonzero(d <= Lc)
+        for lev in range(n_max - 1, -1, -1):  # backward G^lev and the contraction
+            Lc, Lg = min(lev, n_max - lev, K), min(lev + 1, n_max - lev - 1, K)
+            v = np.count_nonzero((ds <= Lc) & (dt <= Lg))
+            f += 140 * v + ((50 * v + 10 * np.count_nonzero(d <= Lc)) if lev >= 1 else 0)
+        out.append(5 * f)
+    return np.asarray(out)
+
+
+def bench_forces(args, torch, P, W):
+    """Energy and forces of the headline cell: the FP64 moment path (its
+    moments feed the weights), the weights, the block derivatives and the
+    Theta~ passes with FP32 or FP64 vectors; the metric counts atoms whose
+    energy and forces one step delivers."""
+    wl = W.bcc_large(reps=args.reps)
+    ne = float(wl.n_elec.sum())
+    vec = "f32" if args.dtype in ("f32", "f16", "bf16") else "f64"
+    p = P.EnergyPath(wl.pos, wl.cell, wl.species, wl.model, wl.n_max, wl.n_exp, "f64")
+    stream = torch.cuda.current_stream()
+
+    def setup():
+        p.rebuild()
+        if vec == "f64":
+            return p.plan, p.mws, p.H_bond
+        _, H32 = P.build_H(wl.model, p.species, p.nl, dtype="f32")
+        plan32 = P.moments_plan(p.n, 5, wl.n_max, "f32", p.nl)
+        return plan32, P.moments_prepare(plan32, p.nl), H32
+
+    plan, mws, Hb = setup()
+    fws = P.forces_workspace(plan, p.nl)
+    log(f"forces bcc {args.reps}^3: {wl.n_atoms} atoms, n_max {wl.n_max}, vectors {vec}, rows_cap {plan.rows_cap}, "
+        f"force workspace {fws.numel() / 2**30:.2f} GiB")
+
+    def one():
+        out = p.run(ne)
+        w = P.weights(p.mu, p.H_on, out["E_F"], wl.n_max, wl.n_exp)
+        dH = P.bond_derivatives(wl.model, p.species, p.nl)
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        F = P.forces(plan, mws, p.nl, p.H_on, Hb, dH, w, ws=fws)
+        b.record(stream)
+        return out, F, (a, b)
+
+    for _ in range(args.warmup):
+        one()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    evs = []
+    for _ in range(args.steps):
+        out, F, ev = one()
+        evs.append(ev)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / args.steps
+    kms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    Fn = F.cpu().numpy()
+    rp = p.nl.row_ptr.cpu().numpy()
+    nj = p.nl.nbr_j.cpu().numpy()
+    sample = np.random.default_rng(7).choice(wl.n_atoms, size=4, replace=False)
+    fpa = algorithmic_force_flops_per_atom(rp, nj, wl.n_max, sample)
+    flops = float(fpa.mean()) * wl.n_atoms
+    achieved = flops / (kms * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[vec]
+    res = {"metric": "atom-forces/s", "value": wl.n_atoms / t, "unit": "atoms/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": t * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": vec, "data": "synthetic",
+           "config": {"workload": f"bcc {args.reps}^3 supercell, {wl.n_atoms} atoms, a=3.16 A, sigma=0.08 A, "
+                                  f"canonical d band, cutoff 3.8 A, {wl.n_max} moments, N_d=4.5: energy (FP64 "
+                                  f"moments) and forces ({vec} Theta~ vectors)",
+                      "n_atoms": wl.n_atoms, "n_max": wl.n_max, "rows_cap": plan.rows_cap},
+           "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                        "frac": achieved / peak, "traffic": None,
+                        "kernel": "force passes (k_finit, k_fstep forward and backward, all batches)",
+                        "kernel_ms": kms, "algorithmic_flops_per_launch": flops,
+                        "flops_per_atom": float(fpa.mean())},
+           "sum_F": float(np.abs(Fn.sum(axis=0)).max()), "max_abs_F": float(np.abs(Fn).max()),
+           "U_eV_per_atom": float(out["U_total"].item()) / wl.n_atoms}
+    log(f"forces: {t * 1e3:.1f} ms/step, force passes {kms:.1f} ms, {achieved:.2f} TFLOP/s")
     print(json.dumps(res), flush=True)
 
 

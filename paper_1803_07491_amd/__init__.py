@@ -525,6 +525,12 @@ def bond_derivatives(model: dict, species, nl: Neighbours, out=None):
     return out
 
 
+def forces_workspace(plan: Plan, nl: Neighbours, batch_tiles=0):
+    """Device workspace for ``forces`` with this plan and batch."""
+    lib = load()
+    return _bytes(lib.bop_forces_workspace_size(C.byref(plan), nl.n_pairs, int(batch_tiles)), nl.row_ptr.device)
+
+
 def forces(plan: Plan, mws, nl: Neighbours, H_on, H_bond, dH, w, batch_tiles=0, F=None, ws=None):
     """F [N, 3] = -dU_bond/dr (``bop_forces``) from the moment plan and its
     prepared workspace ``mws``, the blocks in the plan's dtype, their
@@ -535,7 +541,7 @@ def forces(plan: Plan, mws, nl: Neighbours, H_on, H_bond, dH, w, batch_tiles=0, 
     if F is None:
         F = torch.empty((plan.n_atoms, 3), dtype=torch.float64, device=dev)
     if ws is None:
-        ws = _bytes(lib.bop_forces_workspace_size(C.byref(plan), nl.n_pairs, int(batch_tiles)), dev)
+        ws = forces_workspace(plan, nl, batch_tiles)
     _check(lib.bop_forces(C.byref(plan), _ptr(mws), _ptr(nl.row_ptr), _ptr(nl.nbr_j), _ptr(nl.nbr_shift), nl.n_pairs,
                           _ptr(H_on), _ptr(H_bond), _ptr(dH), _ptr(w), int(batch_tiles), _ptr(F), _ptr(ws),
                           ws.numel(), _stream()))

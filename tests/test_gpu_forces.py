@@ -124,3 +124,51 @@ def test_forces_perfect_lattice_and_polar_dimer(bop):
     F_ref, _, _ = O.forces(wl)
     assert np.abs(F - F_ref).max() <= 1e-10 * max(1.0, np.abs(F_ref).max())
     assert np.abs(F[:, :2]).max() < 1e-12 and abs(F[0, 2] + F[1, 2]) < 1e-12
+
+
+def _fullsize(bop):
+    wl = W.bcc_large()
+    p = bop.EnergyPath(wl.pos, wl.cell, wl.species, wl.model, wl.n_max, wl.n_exp, "f64")
+    out = p.forces(float(np.sum(wl.n_elec)))
+    return wl, p, _np(out["F"])
+
+
+def test_forces_fullsize_properties(bop):
+    """bcc 40^3, 128,000 atoms, 18 moments (the bench cell), in the launch
+    configuration bench.py times: the forces sum to zero (translation
+    invariance, 1e-9 eV/A per component of the sum) and two sampled
+    components match central differences of the FP64 energy path (h = 2e-3 A:
+    truncation h^2 F'''/6 ~ 1e-5, rounding of U_total ~1e-10 eV / 4e-3 A;
+    bound 5e-5 eV/A)."""
+    wl, p, F = _fullsize(bop)
+    ne = float(np.sum(wl.n_elec))
+    assert np.isfinite(F).all()
+    assert np.abs(F.sum(axis=0)).max() < 1e-9
+    del p
+    h = 2e-3
+    rng = np.random.default_rng(31)
+    for _ in range(2):
+        k, c = int(rng.integers(wl.n_atoms)), int(rng.integers(3))
+        u = []
+        for sgn in (1.0, -1.0):
+            pos = wl.pos.copy()
+            pos[k, c] += sgn * h
+            q = bop.EnergyPath(pos, wl.cell, wl.species, wl.model, wl.n_max, wl.n_exp, "f64")
+            u.append(float(q.run(ne)["U_total"].item()))
+            del q
+        fd = -(u[0] - u[1]) / (2 * h)
+        print(f"atom {k} component {c}: F {F[k, c]:.8f}, central difference {fd:.8f}")
+        assert abs(F[k, c] - fd) < 5e-5, (k, c, F[k, c], fd)
+
+
+def test_forces_fullsize_fp32_vectors(bop):
+    """FP32 vectors in the Theta~ passes at 128,000 atoms and 18 moments
+    against the FP64 forces."""
+    wl, p, F = _fullsize(bop)
+    H_on, H32 = bop.build_H(wl.model, p.species, p.nl, dtype="f32")
+    plan = bop.moments_plan(p.n, 5, wl.n_max, "f32", p.nl)
+    mws = bop.moments_prepare(plan, p.nl)
+    F32 = _np(bop.forces(plan, mws, p.nl, H_on, H32, p.dH, p.w))
+    e32 = np.abs(F32 - F).max()
+    print(f"FP32 vectors vs FP64 at 128,000 atoms: {e32:.3e} eV/A (max |F| {np.abs(F).max():.3f})")
+    assert e32 <= 1e-5 * max(1.0, np.abs(F).max())
