@@ -34,7 +34,10 @@
 //    by a wave reduction.  A pair's partial sums live in a per-tile slot
 //    array from the row's first backward pass (k = n - L) to its last
 //    (k = L), where they are added to the pair's gradient with one FP64
-//    atomic per component.
+//    atomic per component.  Per column the sum is symmetric and the block
+//    derivatives of the two directions of a bond are transposes of opposite
+//    sign, so g_reverse(p) = -g_p: only the direction with the lower pair
+//    index is contracted, and stored doubled.
 //  * Bond-block derivatives: the d-d block as V_sigma P_sigma + V_pi P_pi +
 //    V_delta P_delta with projectors built from the real d harmonics Y(u) of
 //    the bond direction u: P_sigma = Y Y^T, P_pi = (sum_x dY/du_x dY/du_x^T -
@@ -42,7 +45,8 @@
 //    App. A.2.1 written without angles, so smooth on the polar axis), in dual
 //    numbers of the three components of the bond vector.
 //  * F_k = sum over k's pairs p of g_p - g_(reverse of p), with g_p =
-//    sum_ab Theta~_p,ab dH_p,ab/dd_p (d_p = r_j + S - r_i).
+//    sum_ab Theta~_p,ab dH_p,ab/dd_p (d_p = r_j + S - r_i); with the doubled
+//    canonical direction and a zero reverse this is the same sum.
 #include "bop_internal.h"
 #include "tiles.h"
 
@@ -526,16 +530,25 @@ __global__ void k_finit(FBatch bt, int n, const double *__restrict__ w, const in
 // G^lev = w_lev e_c + H G^(lev+1) with the Theta~ contraction against X^lev)
 // pass over a batch of tiles.  Launch numbering as in the moment passes: all
 // chunks of a tile on one XCD, rows dealt to the chunks in wave-sized groups.
+// A row's neighbour slots go in groups of GS: the group's rows of the operand
+// are gathered before any is used.  In the backward pass each lane's three
+// contraction values per slot go to the wave's LDS block [3 GS][65] and are
+// summed over the 64 columns by 48 lanes (two halves of 32 columns, then one
+// exchange), instead of a shuffle tree per value.
+constexpr int GS = 4;                         // slots per gather group
+constexpr int TSTRIDE = 65;                   // LDS row of one value (64 columns + pad)
+
 template <typename T, int NO, bool BWD>
 __global__ void __launch_bounds__(FW)
 k_fstep(FBatch bt, int lev, int n, int K, int nch, int chunk_rows, int deg_max, int rows_cap,
         const int *__restrict__ row_ptr, const double *__restrict__ H_on, const T *__restrict__ H,
-        const double *__restrict__ dH, const double *__restrict__ w, const int *__restrict__ sizes_,
-        const char *tiles_base, size_t tile_stride, T *xlev, size_t xlev_rows, LevelOffsets lo, T *gbuf,
-        size_t g_rows, double *accb, double *gpair)
+        const double *__restrict__ dH, const double *__restrict__ w, const int *__restrict__ rev,
+        const int *__restrict__ sizes_, const char *tiles_base, size_t tile_stride, T *xlev, size_t xlev_rows,
+        LevelOffsets lo, T *gbuf, size_t g_rows, double *accb, double *gpair)
 {
     constexpr int NB = BOP_D_PACKED;
     constexpr int SR = NO * 64;
+    __shared__ double s_t[BWD ? NWF : 1][BWD ? 3 * GS * TSTRIDE : 1];
     const int xcd = blockIdx.x & 7, q = blockIdx.x >> 3;
     const int t = (q / nch) * 8 + xcd, chunk = q % nch;
     if (t >= bt.count) return;
@@ -559,15 +572,19 @@ k_fstep(FBatch bt, int lev, int n, int K, int nch, int chunk_rows, int deg_max, 
     double *acc_t = accb + (size_t)t * rows_cap * deg_max * 3;
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    double *st = &s_t[BWD ? wv : 0][0];
     const int Bt = sizes[0];
     T wl = T(0);                       // the lane's column weight w_lev
     if (BWD && lev >= 1 && lane < Bt * NO) wl = (T)w[((long)sup[lane / NO] * NO + lane % NO) * (n + 1) + lev];
+    // reduction lanes: value vr of the group, half hr of the columns
+    const int vr = lane & 31, hr = lane >> 5;
     for (int l = chunk * NWF + wv; l < nrow; l += RS) {
         const int g = __builtin_amdgcn_readfirstlane(sup[l]);
         const int info = __builtin_amdgcn_readfirstlane(rinfo[l]);
         const int L = info & 255, n1 = (info >> 8) & 255, n2 = (info >> 16) & 255, n3 = (info >> 24) & 255;
         const int nval = Lp >= L + 1 ? n3 : (Lp == L ? n2 : n1);
-        const int slots = lane < deg_max ? lnb[(long)l * deg_max + lane] : 0;
+        const int *lrow = lnb + (long)l * deg_max;
+        const int slots = lane < deg_max ? lrow[lane] : 0;
         const int p0 = __builtin_amdgcn_readfirstlane(row_ptr[g]);
         const bool has_prev = L <= Lp;
         T acc[NO], xk[NO];
@@ -581,52 +598,86 @@ k_fstep(FBatch bt, int lev, int n, int K, int nch, int chunk_rows, int deg_max, 
         // most n - 1) to its last (lev = L)
         const bool first = BWD && lev == min(n - L, n - 1), last = BWD && lev == L;
         double *acc_row = acc_t + (size_t)l * deg_max * 3;
-        const int ns = BWD ? n3 : nval;
-        for (int s = 0; s < ns; ++s) {
-            const int pk = __builtin_amdgcn_readlane(slots, s);
-            const long pp = (long)p0 + (pk & 255);
-            double v = 0.0;
-            if (s < nval) {
-                const int jl = pk >> 8;
-                T xn[NO];
+        for (int s0 = 0; s0 < nval; s0 += GS) {
+            T xn[GS][NO];
 #pragma unroll
-                for (int b = 0; b < NO; ++b) xn[b] = src[(size_t)jl * SR + b * 64 + lane];
+            for (int u = 0; u < GS; ++u) {
+                const int su = s0 + u < nval ? s0 + u : s0;
+                const int jl = __builtin_amdgcn_readlane(slots, su) >> 8;
+#pragma unroll
+                for (int b = 0; b < NO; ++b) xn[u][b] = src[(size_t)jl * SR + b * 64 + lane];
+            }
+            asm volatile("" ::: "memory");    // keep the group's gathers ahead of their uses
+#pragma unroll
+            for (int u = 0; u < GS; ++u) {
+                if (s0 + u >= nval) break;
+                const long pp = (long)p0 + (__builtin_amdgcn_readlane(slots, s0 + u) & 255);
                 const T *h = H + pp * NB;
 #pragma unroll
                 for (int a = 0; a < NO; ++a)
 #pragma unroll
-                    for (int b = 0; b < NO; ++b) acc[a] = fma(h[d_packed_index(a, b)], xn[b], acc[a]);
-                if (BWD) {
+                    for (int b = 0; b < NO; ++b) acc[a] = fma(h[d_packed_index(a, b)], xn[u][b], acc[a]);
+                // the contraction of the pair's canonical direction only (the
+                // one of lower index): g_reverse(p) = -g_p
+                if (BWD && __builtin_amdgcn_readfirstlane(rev[pp]) > pp) {
                     const double *dh = dH + pp * 3 * NB;
                     double t0 = 0.0, t1 = 0.0, t2 = 0.0;
 #pragma unroll
                     for (int a = 0; a < NO; ++a)
 #pragma unroll
                         for (int b = a; b < NO; ++b) {
-                            const double sab = a == b ? (double)xk[a] * (double)xn[a]
-                                                      : (double)xk[a] * (double)xn[b] + (double)xk[b] * (double)xn[a];
+                            const double sab = a == b ? (double)xk[a] * (double)xn[u][a]
+                                                      : (double)xk[a] * (double)xn[u][b] + (double)xk[b] * (double)xn[u][a];
                             const int e = d_packed_index(a, b);
                             t0 = fma(sab, dh[e], t0);
                             t1 = fma(sab, dh[NB + e], t1);
                             t2 = fma(sab, dh[2 * NB + e], t2);
                         }
-                    t0 = wave_sum(t0);
-                    t1 = wave_sum(t1);
-                    t2 = wave_sum(t2);
-                    v = lane == 0 ? t0 : (lane == 1 ? t1 : t2);
+                    st[(3 * u) * TSTRIDE + lane] = t0;
+                    st[(3 * u + 1) * TSTRIDE + lane] = t1;
+                    st[(3 * u + 2) * TSTRIDE + lane] = t2;
+                } else if (BWD) {
+                    st[(3 * u) * TSTRIDE + lane] = 0.0;
+                    st[(3 * u + 1) * TSTRIDE + lane] = 0.0;
+                    st[(3 * u + 2) * TSTRIDE + lane] = 0.0;
                 }
             }
-            if (BWD && lane < 3) {
-                double *ap = acc_row + s * 3 + lane;
-                if (first && last) {
-                    if (s < nval) unsafeAtomicAdd(&gpair[3 * pp + lane], v);
-                } else if (first) {
-                    *ap = v;
-                } else if (last) {
-                    unsafeAtomicAdd(&gpair[3 * pp + lane], *ap + v);
-                } else if (s < nval) {
-                    *ap += v;
+            if (BWD) {
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_s_waitcnt(0xc07f);        // the group's LDS writes are done
+                __builtin_amdgcn_wave_barrier();
+                const int ng = 3 * min(GS, nval - s0);
+                double v = 0.0;
+                if (vr < ng) {
+                    const double *row = st + vr * TSTRIDE + 32 * hr;
+#pragma unroll 8
+                    for (int c = 0; c < 32; ++c) v += row[c];
                 }
+                v += __shfl_xor(v, 32);
+                if (hr == 0 && vr < ng) {
+                    const int s = s0 + vr / 3, x = vr % 3;
+                    const long pp = (long)p0 + (lrow[s] & 255);
+                    double *ap = acc_row + s * 3 + x;
+                    if (rev[pp] > pp) {
+                        if (first && last) unsafeAtomicAdd(&gpair[3 * pp + x], 2.0 * v);
+                        else if (first) *ap = v;
+                        else if (last) unsafeAtomicAdd(&gpair[3 * pp + x], 2.0 * (*ap + v));
+                        else *ap += v;
+                    }
+                }
+                __builtin_amdgcn_wave_barrier();
+            }
+        }
+        if (BWD && first != last) {
+            // slots whose operand is zero at this pass: start their sums at
+            // zero (first pass) or hand them on (last pass)
+            for (int e = lane; e < 3 * (n3 - nval); e += 64) {
+                const int s = nval + e / 3, x = e % 3;
+                const long pp = (long)p0 + (lrow[s] & 255);
+                double *ap = acc_row + s * 3 + x;
+                if (rev[pp] <= pp) continue;
+                if (first) *ap = 0.0;
+                else unsafeAtomicAdd(&gpair[3 * pp + x], 2.0 * *ap);
             }
         }
         if (BWD) {
@@ -791,14 +842,14 @@ int run_forces(const bop_plan &p, const char *mws, const int *row_ptr, const dou
         for (int l = 1; l < n; ++l) {
             const int nch = grid(l);
             k_fstep<T, NO, false><<<(unsigned)(nb8 * 8 * nch), FW, 0, st>>>(
-                bt, l, n, K, nch, p.chunk_rows, p.deg_max, p.rows_cap, row_ptr, H_on, H, dH, w, sizes, tiles,
+                bt, l, n, K, nch, p.chunk_rows, p.deg_max, p.rows_cap, row_ptr, H_on, H, dH, w, f.rev, sizes, tiles,
                 lay.tile_stride, xlev, f.xlev_rows, lo, gbuf, f.g_rows, f.accb, f.gpair);
             BOP_LAUNCHED();
         }
         for (int k = n - 1; k >= 0; --k) {
             const int nch = grid(k);
             k_fstep<T, NO, true><<<(unsigned)(nb8 * 8 * nch), FW, 0, st>>>(
-                bt, k, n, K, nch, p.chunk_rows, p.deg_max, p.rows_cap, row_ptr, H_on, H, dH, w, sizes, tiles,
+                bt, k, n, K, nch, p.chunk_rows, p.deg_max, p.rows_cap, row_ptr, H_on, H, dH, w, f.rev, sizes, tiles,
                 lay.tile_stride, xlev, f.xlev_rows, lo, gbuf, f.g_rows, f.accb, f.gpair);
             BOP_LAUNCHED();
         }
