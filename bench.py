@@ -69,10 +69,10 @@ def algorithmic_flops_per_atom(row_ptr, nbr_j, n_orb, n_max, sample):
     return np.array(out)
 
 
-def kernel_source_hash():
-    """Hash of the moment kernels' code: the source without // comments and
+def kernel_source_hash(source="moments.hip"):
+    """Hash of a kernel file's code: the source without // comments and
     blank lines, so that a change of comments keeps recorded counters valid."""
-    p = os.path.join(ROOT, "paper_1803_07491_amd", "csrc", "moments.hip")
+    p = os.path.join(ROOT, "paper_1803_07491_amd", "csrc", source)
     lines = []
     for ln in open(p, encoding="utf-8").read().splitlines():
         code = ln.split("//", 1)[0].rstrip()
@@ -81,15 +81,15 @@ def kernel_source_hash():
     return hashlib.sha256("\n".join(lines).encode()).hexdigest()[:16]
 
 
-def read_traffic(dtype, method):
-    """HBM bytes of one H.X pass measured with rocprofv3 counters (FETCH_SIZE
-    + WRITE_SIZE, scaled by a copy-kernel calibration), if recorded for the
-    current kernel source."""
+def read_traffic(dtype, method, source="moments.hip"):
+    """HBM bytes of one H.X pass (or force pass) measured with rocprofv3
+    counters (FETCH_SIZE + WRITE_SIZE, scaled by a copy-kernel calibration),
+    if recorded for the current kernel source."""
     p = os.path.join(ROOT, "profiles", f"traffic_{method}_bcc_large_{dtype}.json")
     if not os.path.exists(p):
         return None
     d = json.load(open(p))
-    if d.get("kernel_source_sha256_16") != kernel_source_hash():
+    if d.get("kernel_source_sha256_16") != kernel_source_hash(source):
         return None
     return d.get("bytes_per_launch")
 
@@ -799,12 +799,15 @@ def bench_forces(args, torch, P, W):
                                   f"moments) and forces ({vec} Theta~ vectors)",
                       "n_atoms": wl.n_atoms, "n_max": wl.n_max, "rows_cap": plan.rows_cap},
            "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                        "frac": achieved / peak, "traffic": None,
+                        "frac": achieved / peak, "traffic": read_traffic(vec, "forces", "forces.hip"),
                         "kernel": "force passes (k_finit, k_fstep forward and backward, all batches)",
                         "kernel_ms": kms, "algorithmic_flops_per_launch": flops,
                         "flops_per_atom": float(fpa.mean())},
            "sum_F": float(np.abs(Fn.sum(axis=0)).max()), "max_abs_F": float(np.abs(Fn).max()),
            "U_eV_per_atom": float(out["U_total"].item()) / wl.n_atoms}
+    if res["roofline"]["traffic"]:
+        res["roofline"]["achieved_hbm_TBps"] = res["roofline"]["traffic"] / (kms * 1e-3) / 1e12
+        res["roofline"]["hbm_frac"] = res["roofline"]["achieved_hbm_TBps"] / PEAK_HBM_TBPS
     log(f"forces: {t * 1e3:.1f} ms/step, force passes {kms:.1f} ms, {achieved:.2f} TFLOP/s")
     print(json.dumps(res), flush=True)
 
