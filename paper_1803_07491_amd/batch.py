@@ -103,10 +103,15 @@ class BatchedMoments:
 
 
 class PerStructure:
-    """One plan and one moment launch sequence per structure."""
+    """One plan and one moment launch sequence per structure.  Every
+    structure keeps its own prepared workspace, so each plan's batch is
+    capped (64 tiles unless ``tuning`` says otherwise): the 512-structure
+    workload would otherwise hold X buffers for all of its tiles at once."""
 
     def __init__(self, structures, model, n_max, dtype="f32", tuning=None, device="cuda"):
         torch = _torch()
+        tuning = dict(tuning or {})
+        tuning.setdefault("batch_tiles", 64)
         self.items = []
         for wl in structures:
             pos = torch.as_tensor(np.ascontiguousarray(wl.pos, np.float64), device=device)

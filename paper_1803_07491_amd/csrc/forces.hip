@@ -578,14 +578,27 @@ k_fstep(FBatch bt, int lev, int n, int K, int nch, int chunk_rows, int deg_max, 
     if (BWD && lev >= 1 && lane < Bt * NO) wl = (T)w[((long)sup[lane / NO] * NO + lane % NO) * (n + 1) + lev];
     // reduction lanes: value vr of the group, half hr of the columns
     const int vr = lane & 31, hr = lane >> 5;
-    for (int l = chunk * NWF + wv; l < nrow; l += RS) {
-        const int g = __builtin_amdgcn_readfirstlane(sup[l]);
-        const int info = __builtin_amdgcn_readfirstlane(rinfo[l]);
+    // the next row's atom, layer word, slot list and first pair are fetched
+    // while the current row computes
+    int l = chunk * NWF + wv;
+    int g_n = 0, info_n = 0, slots_n = 0, p0_n = 0;
+    if (l < nrow) {
+        g_n = __builtin_amdgcn_readfirstlane(sup[l]);
+        info_n = __builtin_amdgcn_readfirstlane(rinfo[l]);
+        slots_n = lane < deg_max ? lnb[(long)l * deg_max + lane] : 0;
+        p0_n = __builtin_amdgcn_readfirstlane(row_ptr[g_n]);
+    }
+    for (; l < nrow; l += RS) {
+        const int g = g_n, info = info_n, slots = slots_n, p0 = p0_n;
+        if (l + RS < nrow) {
+            g_n = __builtin_amdgcn_readfirstlane(sup[l + RS]);
+            info_n = __builtin_amdgcn_readfirstlane(rinfo[l + RS]);
+            slots_n = lane < deg_max ? lnb[(long)(l + RS) * deg_max + lane] : 0;
+            p0_n = __builtin_amdgcn_readfirstlane(row_ptr[g_n]);
+        }
         const int L = info & 255, n1 = (info >> 8) & 255, n2 = (info >> 16) & 255, n3 = (info >> 24) & 255;
         const int nval = Lp >= L + 1 ? n3 : (Lp == L ? n2 : n1);
         const int *lrow = lnb + (long)l * deg_max;
-        const int slots = lane < deg_max ? lrow[lane] : 0;
-        const int p0 = __builtin_amdgcn_readfirstlane(row_ptr[g]);
         const bool has_prev = L <= Lp;
         T acc[NO], xk[NO];
 #pragma unroll
@@ -689,7 +702,7 @@ k_fstep(FBatch bt, int lev, int n, int K, int nch, int chunk_rows, int deg_max, 
             }
         }
 #pragma unroll
-        for (int a = 0; a < NO; ++a) dst[(size_t)l * SR + a * 64 + lane] = acc[a];
+        for (int a = 0; a < NO; ++a) __builtin_nontemporal_store(acc[a], &dst[(size_t)l * SR + a * 64 + lane]);
     }
 }
 
@@ -805,10 +818,10 @@ ForcesWs carve_forces(void *base, const bop_plan &p, long P, int bt)
 
 int default_force_batch(const bop_plan &p, long P)
 {
-    // tiles whose vectors are live at once: at most 8 GiB of them (a quarter
+    // tiles whose vectors are live at once: at most 24 GiB of them (a quarter
     // of the free memory if that is less), a multiple of 8, at least 8
     const size_t one = carve_forces(nullptr, p, P, 1).bytes - carve_forces(nullptr, p, P, 0).bytes;
-    size_t budget = 8ull << 30, mem_free = 0, mem_total = 0;
+    size_t budget = 24ull << 30, mem_free = 0, mem_total = 0;
     if (hipMemGetInfo(&mem_free, &mem_total) == hipSuccess && mem_free / 4 < budget) budget = mem_free / 4;
     long bt = one ? (long)(budget / one) : 8;
     bt = bt < 8 ? 8 : (bt / 8) * 8;
