@@ -358,6 +358,31 @@ int bop_energy(int n_atoms, int n_orb, int n_max, int n_exp, const double *mu,
                void *ws, size_t ws_bytes, hipStream_t stream);
 
 /* =========================================================================
+ * Atom-averaged mode (the per-atom reading of the moments; the paper's DOS
+ * and energy are per orbital, App. B.2, and that remains the default).
+ *
+ *  bop_atom_average          mu_avg[N][n_max+1] = sum_a mu[i][a][.] / n_orb and
+ *                            H_avg[N] = the orbital-averaged onsite level.
+ *  bop_energy_atom_averaged  bop_energy on one chain per atom (a, b, a_inf,
+ *                            b_inf from bop_recursion on mu_avg with n_rows =
+ *                            N), each chain standing for n_orb orbitals: the
+ *                            Fermi level solves 2 n_orb sum_i N_i = n_elec and
+ *                            N_atom, U_atom, dos_atom, U_total are 2 n_orb
+ *                            times the chain's.  Workspace:
+ *                            bop_energy_workspace_size(N, 1, n_exp).  Where
+ *                            all orbitals of an atom share one local DOS it
+ *                            equals the orbital-resolved result.
+ * ========================================================================= */
+int bop_atom_average(int n_atoms, int n_orb, int n_max, const double *mu, const double *H_on,
+                     double *mu_avg, double *H_avg, hipStream_t stream);
+int bop_energy_atom_averaged(int n_atoms, int n_orb, int n_max, int n_exp, const double *mu_avg,
+                             const double *a, const double *b, const double *a_inf,
+                             const double *b_inf, const double *H_avg, double n_elec /*[host]*/,
+                             int ef_mode, double *E_F, double *N_atom, double *U_atom,
+                             double *dos_atom, double *U_total, int *flags, void *ws,
+                             size_t ws_bytes, hipStream_t stream);
+
+/* =========================================================================
  * bop_energy without a workspace argument, for callers that cannot allocate
  * device memory (code under HIP graph capture, tight serving loops, harnesses
  * that forbid allocation).  Same arguments, kernels and results as bop_energy;

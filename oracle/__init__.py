@@ -294,6 +294,32 @@ def energy_pipeline(wl, shift=None, sel=None, n_max=None, n_exp=None, E_F=None, 
             "E_F": E_F, **en}
 
 
+def energy_pipeline_avg(wl, shift=None, n_max=None, n_exp=None, E_F=None, nl=None):
+    """Atom-averaged mode of the energy path (the per-atom reading of the
+    moments): one recursion chain per atom, from its orbital-averaged moments
+    mu_i / n_orb = sum_a mu_ia / n_orb and the averaged onsite level, each
+    chain standing for n_orb orbitals in the electron count and the energies
+    (N_i = 2 n_orb N_chain, U_i = 2 n_orb U_chain).  Where all orbitals of an
+    atom share one local DOS (e.g. equal bond integrals in every channel) it
+    equals the orbital-resolved path."""
+    n_max = wl.n_max if n_max is None else n_max
+    n_exp = wl.n_exp if n_exp is None else n_exp
+    if nl is None:
+        nl = neighbours(wl.pos, wl.cell, wl.model["r_cut"])
+    H_on, H_bond = build_H(wl.model, wl.species, nl, shift)
+    mu = moments(nl, H_on, H_bond, n_max)
+    n, no = H_on.shape
+    mu_avg = mu.reshape(n, no, n_max + 1).mean(axis=1)
+    e_avg = H_on.mean(axis=1)
+    rec = recursion(mu_avg, n_max)
+    gs = dos_coeffs(mu_avg, rec, n_max, n_exp)
+    if E_F is None:
+        E_F = fermi(gs, rec["a_inf"], rec["b_inf"], float(np.sum(wl.n_elec)) / no)
+    en = energy(gs, rec["a_inf"], rec["b_inf"], e_avg[:, None], E_F)
+    return {"mu_avg": mu_avg, "H_avg": e_avg, "rec": rec, "E_F": E_F, "N_atom": no * en["N_atom"],
+            "U_atom": no * en["U_atom"], "dos_atom": no * en["dos_atom"], "U_total": no * en["U_total"]}
+
+
 def scf(wl, shift0=None, mix=0.5, tol=1e-4, max_iter=200, n_floor=1e-3, n_max=None):
     """Plain local-charge-neutrality cycle; returns (shift, history)."""
     n = wl.n_atoms

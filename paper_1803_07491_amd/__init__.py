@@ -157,6 +157,9 @@ def load(path: str = LIB_PATH):
     lib.bop_mlp_train_workspace_size.restype = C.c_size_t
     lib.bop_mlp_train_workspace_size.argtypes = [C.c_int]
     lib.bop_mlp_train_step.argtypes = [C.c_int, P, P, P, P, P, P, C.c_int, C.c_float, P, P, P, C.c_size_t, P]
+    lib.bop_atom_average.argtypes = [C.c_int, C.c_int, C.c_int, P, P, P, P, P]
+    lib.bop_energy_atom_averaged.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, P, P, P, P, P, P, C.c_double,
+                                             C.c_int, P, P, P, P, P, P, P, C.c_size_t, P]
     lib.bop_weights_workspace_size.restype = C.c_size_t
     lib.bop_weights_workspace_size.argtypes = [C.c_int, C.c_int]
     lib.bop_weights.argtypes = [C.c_int, C.c_int, C.c_int, P, P, P, P, P, C.c_size_t, P]
@@ -462,6 +465,37 @@ def energy(mu, rec, H_on, n_elec, n_max, n_exp=200, E_F=None, ws=None):
                           ws.numel(), _stream()))
     out["E_F"] = ef
     out["U_total"] = ut
+    return out
+
+
+def energy_atom_averaged(mu, H_on, n_elec, n_max, n_exp=200, bw="gershgorin", beta=1.0, E_F=None, ws=None):
+    """The atom-averaged mode: one chain per atom from the orbital-averaged
+    moments (``bop_atom_average``, ``bop_recursion``,
+    ``bop_energy_atom_averaged``).  Returns the energy outputs plus the
+    averaged moments and chain coefficients."""
+    torch = _torch()
+    lib = load()
+    n, no = H_on.shape
+    dev = H_on.device
+    mu_avg = torch.empty((n, n_max + 1), dtype=torch.float64, device=dev)
+    H_avg = torch.empty(n, dtype=torch.float64, device=dev)
+    _check(lib.bop_atom_average(n, no, n_max, _ptr(mu), _ptr(H_on), _ptr(mu_avg), _ptr(H_avg), _stream()))
+    rec = recursion(mu_avg, n_max, bw=bw, beta=beta)
+    if ws is None:
+        ws = _bytes(lib.bop_energy_workspace_size(n, 1, n_exp), dev)
+    ef_mode = 0
+    if E_F is None:
+        ef = torch.zeros(1, dtype=torch.float64, device=dev)
+    else:
+        ef_mode = 1
+        ef = E_F if isinstance(E_F, torch.Tensor) else torch.tensor([float(E_F)], dtype=torch.float64, device=dev)
+    out = {k: torch.empty(n, dtype=torch.float64, device=dev) for k in ("N_atom", "U_atom", "dos_atom")}
+    ut = torch.zeros(1, dtype=torch.float64, device=dev)
+    _check(lib.bop_energy_atom_averaged(n, no, n_max, n_exp, _ptr(mu_avg), _ptr(rec["a"]), _ptr(rec["b"]),
+                                        _ptr(rec["a_inf"]), _ptr(rec["b_inf"]), _ptr(H_avg), float(n_elec), ef_mode,
+                                        _ptr(ef), _ptr(out["N_atom"]), _ptr(out["U_atom"]), _ptr(out["dos_atom"]),
+                                        _ptr(ut), _ptr(rec["flags"]), _ptr(ws), ws.numel(), _stream()))
+    out.update({"E_F": ef, "U_total": ut, "mu_avg": mu_avg, "H_avg": H_avg, "rec": rec})
     return out
 
 

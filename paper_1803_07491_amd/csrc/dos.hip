@@ -597,7 +597,7 @@ __global__ void k_fermi_finish(FermiState *st, double *E_F)
 constexpr int EA = 64;           // atoms per block of the energy pass
 
 __global__ void __launch_bounds__(EA * 9)
-k_energy(int n_atoms, int no, int n_exp, const double *__restrict__ gs, const double *__restrict__ a_inf,
+k_energy(int n_atoms, int no, int n_exp, double wt, const double *__restrict__ gs, const double *__restrict__ a_inf,
          const double *__restrict__ b_inf, const double *__restrict__ H_on, const double *__restrict__ E_F,
          double *__restrict__ N_atom, double *__restrict__ U_atom, double *__restrict__ dos_atom,
          int *__restrict__ flags, double *__restrict__ part)
@@ -653,10 +653,11 @@ k_energy(int n_atoms, int no, int n_exp, const double *__restrict__ gs, const do
             sU += s_u[t * no + a];
             sD += s_d[t * no + a];
         }
-        N_atom[i] = 2.0 * sN;
-        U_atom[i] = 2.0 * sU;
-        dos_atom[i] = 2.0 * sD;
-        Ui = 2.0 * sU;
+        // both spins; wt orbitals per row in the atom-averaged mode
+        N_atom[i] = 2.0 * wt * sN;
+        U_atom[i] = 2.0 * wt * sU;
+        dos_atom[i] = 2.0 * wt * sD;
+        Ui = 2.0 * wt * sU;
     }
     const double tb = block_sum(Ui, s_red);
     if (threadIdx.x == 0) part[blockIdx.x] = tb;
@@ -724,11 +725,14 @@ extern "C" size_t bop_energy_workspace_size(int n_atoms, int n_orb, int n_exp)
     return carve(nullptr, (long)n_atoms * n_orb, n_exp).bytes + 256;
 }
 
+// wt: orbitals each row stands for (1; n_orb in the atom-averaged mode, where
+// a row is an atom's averaged chain): the Fermi search counts wt 2 N per row
+// and the per-atom outputs are scaled by wt.
 static int energy_impl(int n_atoms, int no, int n_max, int n_exp, const double *mu, const double *a,
                        const double *b, const double *a_inf, const double *b_inf, const double *H_on,
                        double n_elec, int ef_mode, double *E_F, double *N_atom, double *U_atom,
                        double *dos_atom, double *U_total, int *flags, void *ws, size_t ws_bytes,
-                       hipStream_t stream)
+                       hipStream_t stream, double wt = 1.0)
 {
     BOP_REQUIRE(n_atoms > 0 && no > 0, BOP_E_ARG, "bop_energy: n_atoms and n_orb must be > 0");
     BOP_REQUIRE(no <= 9, BOP_E_UNSUPPORTED, "bop_energy: at most 9 orbitals per atom");
@@ -740,7 +744,7 @@ static int energy_impl(int n_atoms, int no, int n_max, int n_exp, const double *
     const long R = (long)n_atoms * no;
     EnergyWs w = carve(ws, R, n_exp);
     BOP_REQUIRE(ws && ws_bytes >= w.bytes, BOP_E_CAPACITY, "bop_energy: workspace of %zu bytes needed", w.bytes);
-    BOP_REQUIRE(ef_mode == 1 || (n_elec >= 0.0 && n_elec <= 2.0 * (double)R), BOP_E_ARG,
+    BOP_REQUIRE(ef_mode == 1 || (n_elec >= 0.0 && n_elec <= 2.0 * wt * (double)R), BOP_E_ARG,
                 "bop_energy: n_elec outside [0, 2 n_rows]");
     const unsigned nblk = (unsigned)((R + DT - 1) / DT);
     const int L = (n_max - 1) / 2 + 1 > n_max / 2 ? (n_max - 1) / 2 + 1 : n_max / 2;
@@ -754,14 +758,14 @@ static int energy_impl(int n_atoms, int no, int n_max, int n_exp, const double *
         const unsigned fblk = (unsigned)((2 * R + DT - 1) / DT);
         for (int it = 0; it < FT_PASSES; ++it) {
             k_fermi_tree<<<fblk, DT, 0, stream>>>((int)R, n_exp, w.gs, a_inf, b_inf, w.part, w.st);
-            k_fermi_pick<<<1, DT, 0, stream>>>(fblk, n_elec, w.part, w.st);
+            k_fermi_pick<<<1, DT, 0, stream>>>(fblk, n_elec / wt, w.part, w.st);
         }
         BOP_LAUNCHED();
         k_fermi_finish<<<1, 1, 0, stream>>>(w.st, E_F);
         BOP_LAUNCHED();
     }
     const unsigned ablk = (unsigned)((n_atoms + EA - 1) / EA);
-    k_energy<<<ablk, EA * no, 0, stream>>>(n_atoms, no, n_exp, w.gs, a_inf, b_inf, H_on, E_F, N_atom, U_atom,
+    k_energy<<<ablk, EA * no, 0, stream>>>(n_atoms, no, n_exp, wt, w.gs, a_inf, b_inf, H_on, E_F, N_atom, U_atom,
                                       dos_atom, flags, w.part);
     k_energy_total<<<1, DT, 0, stream>>>(ablk, w.part, U_total);
     BOP_LAUNCHED();
@@ -776,6 +780,50 @@ extern "C" int bop_energy(int n_atoms, int no, int n_max, int n_exp, const doubl
 {
     return energy_impl(n_atoms, no, n_max, n_exp, mu, a, b, a_inf, b_inf, H_on, n_elec, ef_mode, E_F, N_atom,
                        U_atom, dos_atom, U_total, flags, ws, ws_bytes, stream);
+}
+
+// Atom-averaged mode: one chain per atom from mu_i / n_orb.
+__global__ void __launch_bounds__(DT)
+k_atom_average(int n_atoms, int no, int n_max, const double *__restrict__ mu, const double *__restrict__ H_on,
+               double *__restrict__ mu_avg, double *__restrict__ H_avg)
+{
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int M = n_max + 1;
+    if (e >= (long)n_atoms * M) return;
+    const long i = e / M;
+    const int n = (int)(e % M);
+    double s = 0.0;
+    for (int a = 0; a < no; ++a) s += mu[(i * no + a) * M + n];
+    mu_avg[e] = s / no;
+    if (n == 0) {
+        double h = 0.0;
+        for (int a = 0; a < no; ++a) h += H_on[i * no + a];
+        H_avg[i] = h / no;
+    }
+}
+
+extern "C" int bop_atom_average(int n_atoms, int n_orb, int n_max, const double *mu, const double *H_on,
+                                double *mu_avg, double *H_avg, hipStream_t stream)
+{
+    BOP_REQUIRE(n_atoms >= 0 && n_orb > 0 && n_max >= 0 && n_max <= MAX_NMAX, BOP_E_ARG,
+                "bop_atom_average: bad sizes");
+    if (n_atoms == 0) return BOP_OK;
+    BOP_REQUIRE(mu && H_on && mu_avg && H_avg, BOP_E_ARG, "bop_atom_average: NULL array");
+    const long ne = (long)n_atoms * (n_max + 1);
+    k_atom_average<<<(unsigned)((ne + DT - 1) / DT), DT, 0, stream>>>(n_atoms, n_orb, n_max, mu, H_on, mu_avg, H_avg);
+    BOP_LAUNCHED();
+    return BOP_OK;
+}
+
+extern "C" int bop_energy_atom_averaged(int n_atoms, int n_orb, int n_max, int n_exp, const double *mu_avg,
+                                        const double *a, const double *b, const double *a_inf,
+                                        const double *b_inf, const double *H_avg, double n_elec, int ef_mode,
+                                        double *E_F, double *N_atom, double *U_atom, double *dos_atom,
+                                        double *U_total, int *flags, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    BOP_REQUIRE(n_orb > 0, BOP_E_ARG, "bop_energy_atom_averaged: n_orb must be > 0");
+    return energy_impl(n_atoms, 1, n_max, n_exp, mu_avg, a, b, a_inf, b_inf, H_avg, n_elec, ef_mode, E_F, N_atom,
+                       U_atom, dos_atom, U_total, flags, ws, ws_bytes, stream, (double)n_orb);
 }
 
 // ---------------------------------------------------------------------------

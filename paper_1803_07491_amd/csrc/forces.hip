@@ -535,7 +535,7 @@ __global__ void k_finit(FBatch bt, int n, const double *__restrict__ w, const in
 // contraction values per slot go to the wave's LDS block [3 GS][65] and are
 // summed over the 64 columns by 48 lanes (two halves of 32 columns, then one
 // exchange), instead of a shuffle tree per value.
-constexpr int GS = 4;                         // slots per gather group
+constexpr int GS = 2;                         // slots per gather group
 constexpr int TSTRIDE = 65;                   // LDS row of one value (64 columns + pad)
 
 template <typename T, int NO, bool BWD>

@@ -106,3 +106,27 @@ def test_broyden_beats_linear_on_large_alloy(bop):
     print(f"linear {it_l} iterations, Broyden {it_b}; dU {abs(u_b - u_l) / wl.n_atoms * 1e3:.2e} meV/atom")
     assert it_b < it_l
     assert abs(u_b - u_l) / wl.n_atoms * 1e3 < 1e-3
+
+
+@pytest.mark.parametrize("name", ["bcc_small", "fcc_spd", "hcp", "bcc_alloy"])
+def test_atom_averaged_mode_matches_oracle(bop, name):
+    """Atom-averaged mode (one chain per atom from mu_i / n_orb, each standing
+    for n_orb orbitals): averaged moments, coefficients, terminator, Fermi
+    level and per-atom energies against the oracle's averaged path, FP64
+    1e-10 (coefficients and levels in eV, N and U relative)."""
+    wl = _wl(name)
+    ref = O.energy_pipeline_avg(wl)
+    p = bop.EnergyPath(wl.pos, wl.cell, wl.species, wl.model, wl.n_max, wl.n_exp, "f64")
+    p.run_moments()
+    out = bop.energy_atom_averaged(p.mu, p.H_on, float(np.sum(wl.n_elec)), wl.n_max, wl.n_exp)
+    mu = _np(out["mu_avg"])
+    assert np.max(np.abs(mu - ref["mu_avg"]) / np.abs(ref["mu_avg"]).max(axis=1, keepdims=True)) < 1e-12
+    np.testing.assert_allclose(_np(out["H_avg"]), ref["H_avg"], atol=1e-14)
+    np.testing.assert_allclose(_np(out["rec"]["a"]), ref["rec"]["a"], atol=1e-10)
+    np.testing.assert_allclose(_np(out["rec"]["b"]), ref["rec"]["b"], atol=1e-10)
+    np.testing.assert_allclose(_np(out["rec"]["a_inf"]), ref["rec"]["a_inf"], atol=1e-10)
+    np.testing.assert_allclose(_np(out["rec"]["b_inf"]), ref["rec"]["b_inf"], atol=1e-10)
+    assert abs(float(_np(out["E_F"])[0]) - ref["E_F"]) < 1e-10
+    np.testing.assert_allclose(_np(out["N_atom"]), ref["N_atom"], rtol=1e-10, atol=1e-10)
+    np.testing.assert_allclose(_np(out["U_atom"]), ref["U_atom"], rtol=1e-10, atol=1e-10)
+    assert abs(float(_np(out["N_atom"]).sum()) - float(np.sum(wl.n_elec))) < 1e-8 * float(np.sum(wl.n_elec))

@@ -541,3 +541,30 @@ def test_forces_vanish_on_a_perfect_lattice_and_weights_match_differences():
         m[row, n] -= h
         fd = (U_of(p) - U_of(m)) / (2 * h)
         assert abs(w[row, n] - fd) < 1e-5 * max(1e-3, abs(fd)), (row, n, w[row, n], fd)
+
+
+def test_atom_averaged_mode_equals_orbital_mode_for_isotropic_bonds():
+    """With equal d-d bond integrals in every channel each bond block is V I,
+    so all five orbitals of an atom have the same local DOS and the atom-
+    averaged chain is each orbital's chain: both modes give the same E_F and
+    energies.  With the canonical channels they differ (the averaged DOS is a
+    different approximation) while the electron count stays N_e."""
+    rng = np.random.default_rng(21)
+    pos, cell = W.cubic_lattice("bcc", 2.87, 3)
+    pos = W.displace(pos, cell, 0.05, rng)
+    model = W.canonical_d_model(3.5)
+    b = dict(model["bonds"][(0, 0)])
+    b["ddp"] = b["dds"]
+    b["ddd"] = b["dds"]
+    iso = dict(model, bonds={(0, 0): b})
+    wl = W.Workload("iso", pos, cell, np.zeros(54, np.int32), iso, 8, 200, np.full(54, 6.5))
+    r = O.energy_pipeline(wl)
+    ra = O.energy_pipeline_avg(wl)
+    assert abs(ra["E_F"] - r["E_F"]) < 1e-12
+    np.testing.assert_allclose(ra["N_atom"], r["N_atom"], atol=1e-12)
+    np.testing.assert_allclose(ra["U_atom"], r["U_atom"], atol=1e-12)
+    wl2 = W.Workload("can", pos, cell, np.zeros(54, np.int32), model, 8, 200, np.full(54, 6.5))
+    r2 = O.energy_pipeline(wl2)
+    ra2 = O.energy_pipeline_avg(wl2)
+    assert abs(ra2["N_atom"].sum() - 54 * 6.5) < 1e-9
+    assert abs(ra2["U_total"] - r2["U_total"]) > 1e-3
