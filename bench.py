@@ -312,6 +312,15 @@ def _events(torch):
     return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
 
+def _launches(plan):
+    """Kernel launches in one moment launch sequence: per batch of tiles the
+    unit columns, one step per level (plus the odd pass) and the reduction."""
+    K = plan.n_max // 2
+    steps = K + (plan.n_max & 1)
+    n_batches = -(-plan.n_tiles // max(plan.batch_tiles, 1))
+    return n_batches * (steps + 2)
+
+
 def bench_batch(args, torch, P, W):
     """512 ragged structures (bcc/fcc/hcp/random dense packing, 50-5000 atoms,
     0.085 atoms/A^3), d band, cutoff 3.6 A, 14 moments, FP32 H.X: the batch as
@@ -365,9 +374,7 @@ def bench_batch(args, torch, P, W):
         sc = r_[..., :1] * rad ** nn
         err = max(err, float(((a_ - r_).abs() / sc).max()))
     del ps
-    cands = [dict(tile_atoms=ta, block_threads=bt, chunk_rows=cr)
-             for ta in (0, 6) for bt in (256, 512, 1024) for cr in (16, 64)]
-    best, times = autotune(b, cands, reps=max(1, args.steps // 2), log=log)
+    best, times = autotune(b, reps=max(1, args.steps // 2), log=log)
     b.capture()
     t_best = time_replays(args.steps)
     log(f"batched, autotuned {best}: {t_best:.2f} ms")
@@ -388,6 +395,7 @@ def bench_batch(args, torch, P, W):
                                f"50-5000 atoms log-uniform, 0.085 atoms/A^3), {N} atoms, d band, cutoff 3.6 A, "
                                f"{n_max} moments, moments only (one captured launch sequence)",
                    "n_atoms": N, "n_structs": len(structs), "n_max": n_max, "autotuned": best},
+        "launches_per_replay": _launches(b.plan),
         "batched_default_ms": t_def, "per_structure_loop_ms": t_loop,
         "speedup_vs_loop": t_loop / t_best, "autotune_gain": t_def / t_best, "autotune_ms": times,
         "batched_vs_per_structure_max_scaled_err": err,

@@ -128,44 +128,104 @@ class PerStructure:
             moments(plan, nl, H_on, H_bond, mu=mu, ws=ws)
 
 
+# the autotuner's search space: tile size (atoms per 64 columns; 0 = as many
+# as fit one wavefront), workgroup size, rows per workgroup and step, tiles
+# whose vectors are live at once (0 = the memory-sized default) and the
+# support search of the plan (0 automatic, 1 LDS bitmap, 2 global map)
+SPACE = {"tile_atoms": [0, 4, 6, 8, 10], "block_threads": [256, 512, 1024], "chunk_rows": [16, 32, 64, 128],
+         "batch_tiles": [0, 256, 1024], "plan_search": [0, 2]}
+DEFAULT = {"tile_atoms": 0, "block_threads": 512, "chunk_rows": 64, "batch_tiles": 0, "plan_search": 0}
+
+# kept for callers that time an explicit list
 CANDIDATES = [dict(tile_atoms=ta, block_threads=bt, chunk_rows=cr)
               for ta in (0, 6) for bt in (256, 512, 1024) for cr in (16, 32, 64, 128)]
 
 
-def autotune(batch: BatchedMoments, candidates=CANDIDATES, reps=2, log=None):
-    """Time each candidate tiling (graph replays) on the batch and keep the
-    fastest; returns (best tuning dict, {key: ms})."""
+def _key(cand):
+    return "_".join(f"{k}{cand.get(k, DEFAULT[k])}" for k in DEFAULT)
+
+
+def _time(batch, cand, reps, times, log):
+    """Graph-replay time of one tiling (ms), or None if the plan rejects it."""
     torch = _torch()
-    times = {}
-    best = None
-    for cand in candidates:
-        try:
-            batch.set_tuning(cand)
-        except BopError as e:
-            # a tiling the plan rejects; any other failure (a HIP error that
-            # may have left the stream unusable) propagates
-            if e.code not in (BOP_E_UNSUPPORTED, BOP_E_CAPACITY):
-                raise
-            if log:
-                log(f"skip {cand}: {e}")
-            continue
-        batch.capture()
-        batch.replay()
-        torch.cuda.synchronize()
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-        ev[0].record()
-        for _ in range(reps):
-            batch.replay()
-        ev[1].record()
-        torch.cuda.synchronize()
-        ms = ev[0].elapsed_time(ev[1]) / reps
-        key = f"tile{cand.get('tile_atoms', 0)}_wg{cand.get('block_threads', 0)}_chunk{cand.get('chunk_rows', 0)}"
-        times[key] = ms
+    key = _key(cand)
+    if key in times:
+        return times[key]
+    try:
+        batch.set_tuning(cand)
+    except BopError as e:
+        # a tiling the plan rejects; any other failure (a HIP error that may
+        # have left the stream unusable) propagates
+        if e.code not in (BOP_E_UNSUPPORTED, BOP_E_CAPACITY):
+            raise
         if log:
-            log(f"{key}: {ms:.2f} ms")
-        if best is None or ms < best[1]:
-            best = (cand, ms)
-    if best is None:
-        raise RuntimeError("autotune: the plan rejected every candidate tiling")
-    batch.set_tuning(best[0])
-    return best[0], times
+            log(f"skip {key}: {e}")
+        times[key] = None
+        return None
+    batch.capture()
+    batch.replay()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(reps):
+        batch.replay()
+    ev[1].record()
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / reps
+    times[key] = ms
+    if log:
+        log(f"{key}: {ms:.2f} ms")
+    return ms
+
+
+def autotune(batch: BatchedMoments, candidates=None, reps=2, log=None, space=None, rounds=2, cache=None):
+    """Pick the fastest tiling for this batch by timing graph replays.
+
+    With ``candidates`` (a list of tuning dicts) every one is timed.  Otherwise
+    a coordinate search over ``space`` (default SPACE): starting from the
+    default tiling, each parameter in turn is swept with the others fixed and
+    the best value kept, for ``rounds`` passes or until a pass changes
+    nothing.  ``cache`` (a JSON file path) stores the pick per workload
+    signature (atoms, pairs, moments, dtype, form) and is consulted first.
+    Returns (best tuning dict, {tiling: ms})."""
+    import json
+    import os
+    sig = f"n{batch.n}_p{batch.nl.n_pairs}_m{batch.n_max}_{batch.dtype}_{batch.method}"
+    if cache and os.path.exists(cache):
+        known = json.load(open(cache))
+        if sig in known:
+            best = known[sig]
+            batch.set_tuning(best)
+            return best, {}
+    times = {}
+    if candidates is not None:
+        scored = [(c, _time(batch, c, reps, times, log)) for c in candidates]
+        scored = [(c, t) for c, t in scored if t is not None]
+        if not scored:
+            raise RuntimeError("autotune: the plan rejected every candidate tiling")
+        best = min(scored, key=lambda ct: ct[1])[0]
+    else:
+        space = space or SPACE
+        best = dict(DEFAULT)
+        best_ms = _time(batch, best, reps, times, log)
+        if best_ms is None:
+            raise RuntimeError("autotune: the plan rejected the default tiling")
+        for _ in range(rounds):
+            changed = False
+            for name, values in space.items():
+                for v in values:
+                    if v == best[name]:
+                        continue
+                    cand = dict(best, **{name: v})
+                    ms = _time(batch, cand, reps, times, log)
+                    if ms is not None and ms < best_ms:
+                        best, best_ms, changed = cand, ms, True
+            if not changed:
+                break
+    batch.set_tuning(best)
+    if cache:
+        known = json.load(open(cache)) if os.path.exists(cache) else {}
+        known[sig] = best
+        with open(cache, "w") as f:
+            json.dump(known, f, indent=1)
+    return best, times

@@ -81,3 +81,24 @@ def test_autotune_keeps_a_valid_tiling(bop):
     assert len(times) == 2
     b.run()
     np.testing.assert_allclose(b.mu.cpu().numpy(), ref.cpu().numpy(), rtol=1e-5, atol=1e-5 * float(ref.abs().max()))
+
+
+def test_autotune_coordinate_search_and_cache(bop, tmp_path):
+    """The coordinate search starts from the default tiling, keeps a tiling
+    only when it is faster, leaves the batch on the pick (results unchanged
+    up to FP32 rounding), and a second call with the cache returns the same
+    pick without timing anything."""
+    from paper_1803_07491_amd.batch import BatchedMoments, autotune, _key, DEFAULT
+    structs = _batch()
+    b = BatchedMoments(structs, _model(), 8, "f32")
+    b.run()
+    ref = b.mu.clone()
+    cache = str(tmp_path / "tune.json")
+    space = {"tile_atoms": [0, 6], "chunk_rows": [16, 64], "plan_search": [0, 2]}
+    best, times = autotune(b, reps=1, space=space, rounds=1, cache=cache)
+    assert _key(DEFAULT) in times
+    assert times[_key(best)] <= times[_key(DEFAULT)]
+    b.run()
+    np.testing.assert_allclose(b.mu.cpu().numpy(), ref.cpu().numpy(), rtol=1e-5, atol=1e-5 * float(ref.abs().max()))
+    again, t2 = autotune(b, reps=1, space=space, rounds=1, cache=cache)
+    assert again == best and t2 == {}
