@@ -8,10 +8,12 @@
 // Parameters are one contiguous FP32 array:
 //   W1[64][6] | b1[64] | W2[64][64] | b2[64] | W3[64] | b3[1]   (4673 values)
 //
-// Kernels: features (per-atom moment traces, standardised), forward (one row
-// per thread, parameters in LDS), and a training step made of a per-row
-// forward+backward pass, a per-block gradient reduction over rows, and an
-// Adam update that sums the block partials in a fixed order (deterministic).
+// Kernels: features (per-atom moment traces, standardised), forward (row
+// tiles of 16 per wave, the 64 x 64 layer on MFMA), and a training step made
+// of a forward+backward pass over row tiles (both 64 x 64 products on MFMA),
+// a per-block gradient reduction over rows (the W2 block on MFMA, the rest on
+// the VALU), and an Adam update that sums the block partials in a fixed order
+// (deterministic).
 #include "bop_internal.h"
 
 namespace bop {
@@ -43,38 +45,6 @@ __global__ void k_features(int n, int no, int n_max, const double *__restrict__ 
         if (mean) v = (v - mean[k - 1]) / stdv[k - 1];
         x[(long)i * NX + k - 1] = v;
     }
-}
-
-__device__ inline float forward_row(const float *s, const float *xr, float *h1, float *h2)
-{
-    for (int a = 0; a < NH; ++a) {
-        float z = s[OB1 + a];
-#pragma unroll
-        for (int c = 0; c < NX; ++c) z = fmaf(s[OW1 + a * NX + c], xr[c], z);
-        h1[a] = tanhf(z);
-    }
-    for (int a = 0; a < NH; ++a) {
-        float z = s[OB2 + a];
-        for (int b = 0; b < NH; ++b) z = fmaf(s[OW2 + a * NH + b], h1[b], z);
-        h2[a] = tanhf(z);
-    }
-    float y = s[OB3];
-    for (int b = 0; b < NH; ++b) y = fmaf(s[OW3 + b], h2[b], y);
-    return y;
-}
-
-template <typename Y>
-__global__ void __launch_bounds__(MT)
-k_mlp_forward(int n, const float *__restrict__ params, const float *__restrict__ x, Y *__restrict__ y)
-{
-    __shared__ float s[NPARAM];
-    load_params(params, s);
-    int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= n) return;
-    float xr[NX], h1[NH], h2[NH];
-#pragma unroll
-    for (int c = 0; c < NX; ++c) xr[c] = x[(long)r * NX + c];
-    y[r] = (Y)forward_row(s, xr, h1, h2);
 }
 
 // Column statistics of the features x[n][NX]: block f computes feature f's
@@ -130,50 +100,9 @@ __global__ void __launch_bounds__(1024) k_remove_mean(int n, double *__restrict_
     for (int r = threadIdx.x; r < n; r += blockDim.x) y[r] -= m;
 }
 
-// per row: activations and back-propagated pre-activation gradients
-__global__ void __launch_bounds__(MT)
-k_mlp_fb(int B, const float *__restrict__ params, const float *__restrict__ x, const float *__restrict__ t,
-         float *__restrict__ H1, float *__restrict__ H2, float *__restrict__ GZ1, float *__restrict__ GZ2,
-         float *__restrict__ GY, float *__restrict__ loss_part)
-{
-    __shared__ float s[NPARAM];
-    __shared__ float s_red[MT / 64];
-    load_params(params, s);
-    int r = blockIdx.x * blockDim.x + threadIdx.x;
-    float l = 0.f;
-    if (r < B) {
-        float xr[NX], h1[NH], h2[NH], gz2[NH];
-#pragma unroll
-        for (int c = 0; c < NX; ++c) xr[c] = x[(long)r * NX + c];
-        float y = forward_row(s, xr, h1, h2);
-        float d = y - t[r];
-        l = d * d;
-        float gy = 2.f * d / (float)B;
-        GY[r] = gy;
-        for (int a = 0; a < NH; ++a) {
-            gz2[a] = gy * s[OW3 + a] * (1.f - h2[a] * h2[a]);
-            H1[(long)r * NH + a] = h1[a];
-            H2[(long)r * NH + a] = h2[a];
-            GZ2[(long)r * NH + a] = gz2[a];
-        }
-        for (int b = 0; b < NH; ++b) {
-            float g = 0.f;
-            for (int a = 0; a < NH; ++a) g = fmaf(s[OW2 + a * NH + b], gz2[a], g);
-            GZ1[(long)r * NH + b] = g * (1.f - h1[b] * h1[b]);
-        }
-    }
-    for (int o = 32; o > 0; o >>= 1) l += __shfl_xor(l, o);
-    if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = l;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        float tl = 0.f;
-        for (int w = 0; w < MT / 64; ++w) tl += s_red[w];
-        loss_part[blockIdx.x] = tl / (float)B;
-    }
-}
-
 // partial gradients over one block of rows: every thread owns a strided set
-// of parameters and sums its products over the block's rows
+// of parameters and sums its products over the block's rows (all but W2,
+// which k_mlp_grad_w2 sums on MFMA)
 __global__ void __launch_bounds__(MT)
 k_mlp_grad(int B, const float *__restrict__ x, const float *__restrict__ H1, const float *__restrict__ H2,
            const float *__restrict__ GZ1, const float *__restrict__ GZ2, const float *__restrict__ GY,
@@ -190,8 +119,7 @@ k_mlp_grad(int B, const float *__restrict__ x, const float *__restrict__ H1, con
             int a = p - OB1;
             for (int r = r0; r < r1; ++r) g += GZ1[(long)r * NH + a];
         } else if (p < OB2) {
-            int a = (p - OW2) / NH, b = (p - OW2) % NH;
-            for (int r = r0; r < r1; ++r) g = fmaf(GZ2[(long)r * NH + a], H1[(long)r * NH + b], g);
+            continue;           // W2: k_mlp_grad_w2 (MFMA)
         } else if (p < OW3) {
             int a = p - OB2;
             for (int r = r0; r < r1; ++r) g += GZ2[(long)r * NH + a];
@@ -242,6 +170,195 @@ __global__ void k_gather_rows(int B, const int *__restrict__ idx, const float *_
     tb[r] = t[s];
 }
 
+// ---------------------------------------------------------------------------
+// MFMA forms.  The two 64 x 64 products of a row tile (H1 W2^T forward,
+// GZ2 W2 backward) and the W2 gradient (sum over rows of GZ2^T H1) run on
+// v_mfma_f32_16x16x4_f32 (FP32 operands, FP32 accumulation): one wave takes
+// a tile of 16 rows; A[i][k] comes from lane i + 16 k, B[k][j] from lane
+// j + 16 k, and the 4 results of lane l are D[4 (l / 16) + r][l % 16].  The
+// 6 -> 64 and 64 -> 1 layers and the activations stay on the VALU.  W2 and
+// the tiles sit in LDS with rows padded to 65 floats (conflict-free reads
+// along either index).
+// ---------------------------------------------------------------------------
+typedef float f4 __attribute__((ext_vector_type(4)));
+constexpr int RT = 16;          // rows per wave tile
+constexpr int PS = NH + 1;      // padded LDS row
+
+__device__ inline f4 mfma4(float a, float b, f4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+
+__device__ inline void lds_sync_wave()
+{
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_s_waitcnt(0xc07f);     // this wave's LDS writes are done
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Forward (and with TRAIN the backward activations) of row tiles.  Without
+// TRAIN: y[r] = network(x[r]).  With TRAIN: H1, H2, GZ1, GZ2, GY for the
+// gradient pass and per-block partial sums of the loss.
+template <bool TRAIN, typename Y>
+__global__ void __launch_bounds__(MT)
+k_mlp_tile(int B, const float *__restrict__ params, const float *__restrict__ x, const float *__restrict__ t,
+           Y *__restrict__ y, float *__restrict__ H1, float *__restrict__ H2, float *__restrict__ GZ1,
+           float *__restrict__ GZ2, float *__restrict__ GY, float *__restrict__ loss_part)
+{
+    __shared__ float s[NPARAM];
+    __shared__ float s_w2[NH * PS];
+    __shared__ float s_h[MT / 64][RT * PS];         // the wave's H1 tile
+    __shared__ float s_g[MT / 64][RT * PS];         // the wave's GZ2 tile
+    __shared__ float s_red[MT / 64];
+    load_params(params, s);
+    for (int e = threadIdx.x; e < NH * NH; e += blockDim.x) s_w2[(e / NH) * PS + e % NH] = params[OW2 + e];
+    __syncthreads();
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    float *sh = s_h[w], *sg = s_g[w];
+    float lsum = 0.f;
+    const int tiles = (B + RT - 1) / RT;
+    for (int tile = blockIdx.x * (MT / 64) + w; tile < tiles; tile += gridDim.x * (MT / 64)) {
+        const int r0 = tile * RT;
+        // layer 1: lane a computes column a of the tile's 16 rows
+        {
+            float wr[NX];
+#pragma unroll
+            for (int c = 0; c < NX; ++c) wr[c] = s[OW1 + lane * NX + c];
+            const float b1 = s[OB1 + lane];
+#pragma unroll
+            for (int i = 0; i < RT; ++i) {
+                const int r = r0 + i;
+                float z = b1;
+                if (r < B) {
+#pragma unroll
+                    for (int c = 0; c < NX; ++c) z = fmaf(wr[c], x[(long)r * NX + c], z);
+                }
+                const float h = r < B ? tanhf(z) : 0.f;
+                sh[i * PS + lane] = h;
+                if (TRAIN && r < B) H1[(long)r * NH + lane] = h;
+            }
+        }
+        lds_sync_wave();
+        // layer 2: Z2 = H1 W2^T, four column blocks of 16
+        f4 acc[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[q] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
+        for (int k4 = 0; k4 < NH; k4 += 4) {
+            const int k = k4 + lk;
+            const float av = sh[li * PS + k];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[q] = mfma4(av, s_w2[(16 * q + li) * PS + k], acc[q]);
+        }
+        // bias, tanh, output layer partial sums per row
+        float h2v[4][4], yp[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int n = 16 * q + li;
+                const float h = tanhf(acc[q][r] + s[OB2 + n]);
+                h2v[q][r] = h;
+                yp[r] = fmaf(s[OW3 + n], h, yp[r]);
+                const int row = r0 + 4 * lk + r;
+                if (TRAIN && row < B) H2[(long)row * NH + n] = h;
+            }
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int o = 1; o < 16; o <<= 1) yp[r] += __shfl_xor(yp[r], o);
+        float gyr[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = r0 + 4 * lk + r;
+            const float yv = yp[r] + s[OB3];
+            gyr[r] = 0.f;
+            if (row < B) {
+                if (!TRAIN) {
+                    if (li == 0) y[row] = (Y)yv;
+                } else {
+                    const float d = yv - t[row];
+                    if (li == 0) {
+                        lsum += d * d;
+                        GY[row] = 2.f * d / (float)B;
+                    }
+                    gyr[r] = 2.f * d / (float)B;
+                }
+            }
+        }
+        if (TRAIN) {
+            // gz2 = gy W3 (1 - h2^2), into the LDS tile and memory
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int n = 16 * q + li, i = 4 * lk + r;
+                    const float g = gyr[r] * s[OW3 + n] * (1.f - h2v[q][r] * h2v[q][r]);
+                    sg[i * PS + n] = g;
+                    if (r0 + i < B) GZ2[(long)(r0 + i) * NH + n] = g;
+                }
+            lds_sync_wave();
+            // GH1 = GZ2 W2, then GZ1 = GH1 (1 - h1^2)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[q] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
+            for (int k4 = 0; k4 < NH; k4 += 4) {
+                const int k = k4 + lk;
+                const float av = sg[li * PS + k];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) acc[q] = mfma4(av, s_w2[k * PS + 16 * q + li], acc[q]);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int i = 4 * lk + r, b = 16 * q + li;
+                    const float hv = sh[i * PS + b];
+                    if (r0 + i < B) GZ1[(long)(r0 + i) * NH + b] = acc[q][r] * (1.f - hv * hv);
+                }
+        }
+        lds_sync_wave();         // the tiles are rewritten by the next tile
+    }
+    if (TRAIN) {
+        for (int o = 32; o > 0; o >>= 1) lsum += __shfl_xor(lsum, o);
+        if (lane == 0) s_red[w] = lsum;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            float tl = 0.f;
+            for (int q = 0; q < MT / 64; ++q) tl += s_red[q];
+            loss_part[blockIdx.x] = tl / (float)B;
+        }
+    }
+}
+
+// W2 gradient partials: block b sums over its row range (as k_mlp_grad);
+// wave w computes output rows a = 16 w .. 16 w + 15 of dW2 = sum_r GZ2[r]^T
+// H1[r], four column blocks of 16, K = 4 rows per instruction.
+__global__ void __launch_bounds__(MT)
+k_mlp_grad_w2(int B, const float *__restrict__ H1, const float *__restrict__ GZ2, float *__restrict__ part)
+{
+    const int rows_per = (B + gridDim.x - 1) / gridDim.x;
+    const int r0 = blockIdx.x * rows_per, r1 = min(B, r0 + rows_per);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    f4 acc[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[q] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int rb = r0; rb < r1; rb += 4) {
+        const int r = rb + lk;
+        const bool ok = r < r1;
+        const float av = ok ? GZ2[(long)r * NH + 16 * w + li] : 0.f;     // A[a][row]
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const float bv = ok ? H1[(long)r * NH + 16 * q + li] : 0.f;  // B[row][b]
+            acc[q] = mfma4(av, bv, acc[q]);
+        }
+    }
+    float *out = part + (size_t)blockIdx.x * NPARAM + OW2;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) out[(16 * w + 4 * lk + r) * NH + 16 * q + li] = acc[q][r];
+}
+
 struct TrainWs {
     float *H1, *H2, *GZ1, *GZ2, *GY, *loss_part, *part, *xb, *tb;
     size_t bytes;
@@ -257,7 +374,7 @@ TrainWs carve(void *base, int B)
     w.GZ1 = take(4ull * B * NH);
     w.GZ2 = take(4ull * B * NH);
     w.GY = take(4ull * B);
-    w.loss_part = take(4ull * ((B + MT - 1) / MT));
+    w.loss_part = take(4ull * ((B + RT * (MT / 64) - 1) / (RT * (MT / 64))));
     w.part = take(4ull * GRAD_BLOCKS * NPARAM);
     w.xb = take(4ull * B * NX);
     w.tb = take(4ull * B);
@@ -288,7 +405,9 @@ extern "C" int bop_mlp_forward(int n_rows, const float *params, const float *x, 
     BOP_REQUIRE(n_rows >= 0, BOP_E_ARG, "bop_mlp_forward: n_rows < 0");
     if (n_rows == 0) return BOP_OK;
     BOP_REQUIRE(params && x && y, BOP_E_ARG, "bop_mlp_forward: NULL array");
-    k_mlp_forward<float><<<(n_rows + MT - 1) / MT, MT, 0, stream>>>(n_rows, params, x, y);
+    const int tb = (n_rows + RT * (MT / 64) - 1) / (RT * (MT / 64));
+    k_mlp_tile<false, float><<<tb, MT, 0, stream>>>(n_rows, params, x, nullptr, y, nullptr, nullptr, nullptr,
+                                                   nullptr, nullptr, nullptr);
     BOP_LAUNCHED();
     return BOP_OK;
 }
@@ -319,7 +438,9 @@ extern "C" int bop_mlp_shift(int n_rows, const float *params, const float *x, do
     BOP_REQUIRE(n_rows >= 0, BOP_E_ARG, "bop_mlp_shift: n_rows < 0");
     if (n_rows == 0) return BOP_OK;
     BOP_REQUIRE(params && x && shift, BOP_E_ARG, "bop_mlp_shift: NULL array");
-    k_mlp_forward<double><<<(n_rows + MT - 1) / MT, MT, 0, stream>>>(n_rows, params, x, shift);
+    const int tb = (n_rows + RT * (MT / 64) - 1) / (RT * (MT / 64));
+    k_mlp_tile<false, double><<<tb, MT, 0, stream>>>(n_rows, params, x, nullptr, shift, nullptr, nullptr, nullptr,
+                                                    nullptr, nullptr, nullptr);
     BOP_LAUNCHED();
     k_remove_mean<<<1, 1024, 0, stream>>>(n_rows, shift);
     BOP_LAUNCHED();
@@ -348,10 +469,12 @@ extern "C" int bop_mlp_train_step(int batch, const int *idx, const float *x, con
         xb = w.xb;
         tb = w.tb;
     }
-    const int nfb = (batch + MT - 1) / MT;
-    k_mlp_fb<<<nfb, MT, 0, stream>>>(batch, params, xb, tb, w.H1, w.H2, w.GZ1, w.GZ2, w.GY, w.loss_part);
+    const int nfb = (batch + RT * (MT / 64) - 1) / (RT * (MT / 64));
+    k_mlp_tile<true, float><<<nfb, MT, 0, stream>>>(batch, params, xb, tb, nullptr, w.H1, w.H2, w.GZ1, w.GZ2, w.GY,
+                                                   w.loss_part);
     BOP_LAUNCHED();
     k_mlp_grad<<<GRAD_BLOCKS, MT, 0, stream>>>(batch, xb, w.H1, w.H2, w.GZ1, w.GZ2, w.GY, w.part);
+    k_mlp_grad_w2<<<GRAD_BLOCKS, MT, 0, stream>>>(batch, w.H1, w.GZ2, w.part);
     BOP_LAUNCHED();
     k_mlp_adam<<<(NPARAM + 255) / 256, 256, 0, stream>>>(GRAD_BLOCKS, nfb, w.part, w.loss_part, params, adam_m,
                                                         adam_v, step, lr, grad, loss);
