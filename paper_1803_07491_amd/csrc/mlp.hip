@@ -24,7 +24,7 @@ constexpr int OW1 = 0, OB1 = OW1 + NH * NX, OW2 = OB1 + NH, OB2 = OW2 + NH * NH,
               OB3 = OW3 + NH, NPARAM = OB3 + 1;
 static_assert(NPARAM == BOP_MLP_NPARAM, "parameter count");
 constexpr int MT = 256;           // threads per block
-constexpr int GRAD_BLOCKS = 128;  // row blocks of the gradient reduction
+constexpr int GRAD_BLOCKS = 32;   // row blocks of the gradient reduction
 
 __device__ inline void load_params(const float *__restrict__ p, float *s)
 {
@@ -100,36 +100,51 @@ __global__ void __launch_bounds__(1024) k_remove_mean(int n, double *__restrict_
     for (int r = threadIdx.x; r < n; r += blockDim.x) y[r] -= m;
 }
 
-// partial gradients over one block of rows: every thread owns a strided set
-// of parameters and sums its products over the block's rows (all but W2,
-// which k_mlp_grad_w2 sums on MFMA)
+// partial gradients over one block of rows of every parameter but W2 (which
+// k_mlp_grad_w2 sums on MFMA): thread (g, a) takes column a of the hidden
+// layers and row group g (rows r0 + g, r0 + g + 4, ...), and sums W1[a][.],
+// b1[a], b2[a], W3[a] (and b3 for a = 0) over them; the four row groups are
+// then added in a fixed order.
 __global__ void __launch_bounds__(MT)
 k_mlp_grad(int B, const float *__restrict__ x, const float *__restrict__ H1, const float *__restrict__ H2,
            const float *__restrict__ GZ1, const float *__restrict__ GZ2, const float *__restrict__ GY,
            float *__restrict__ part)
 {
+    constexpr int NG = MT / NH;         // row groups
+    constexpr int NV = NX + 4;          // W1 row, b1, b2, W3, b3
+    __shared__ float s_p[NG][NV][NH];
     const int rows_per = (B + gridDim.x - 1) / gridDim.x;
     const int r0 = blockIdx.x * rows_per, r1 = min(B, r0 + rows_per);
-    for (int p = threadIdx.x; p < NPARAM; p += blockDim.x) {
-        float g = 0.f;
-        if (p < OB1) {
-            int a = p / NX, c = p % NX;
-            for (int r = r0; r < r1; ++r) g = fmaf(GZ1[(long)r * NH + a], x[(long)r * NX + c], g);
-        } else if (p < OW2) {
-            int a = p - OB1;
-            for (int r = r0; r < r1; ++r) g += GZ1[(long)r * NH + a];
-        } else if (p < OB2) {
-            continue;           // W2: k_mlp_grad_w2 (MFMA)
-        } else if (p < OW3) {
-            int a = p - OB2;
-            for (int r = r0; r < r1; ++r) g += GZ2[(long)r * NH + a];
-        } else if (p < OB3) {
-            int b = p - OW3;
-            for (int r = r0; r < r1; ++r) g = fmaf(GY[r], H2[(long)r * NH + b], g);
-        } else {
-            for (int r = r0; r < r1; ++r) g += GY[r];
+    const int a = threadIdx.x % NH, g = threadIdx.x / NH;
+    float v[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = 0.f;
+    for (int r = r0 + g; r < r1; r += NG) {
+        const float g1 = GZ1[(long)r * NH + a], g2 = GZ2[(long)r * NH + a], gy = GY[r];
+#pragma unroll
+        for (int c = 0; c < NX; ++c) v[c] = fmaf(g1, x[(long)r * NX + c], v[c]);
+        v[NX] += g1;
+        v[NX + 1] += g2;
+        v[NX + 2] = fmaf(gy, H2[(long)r * NH + a], v[NX + 2]);
+        v[NX + 3] += gy;
+    }
+#pragma unroll
+    for (int k = 0; k < NV; ++k) s_p[g][k][a] = v[k];
+    __syncthreads();
+    if (g == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            float t = s_p[0][k][a];
+            for (int q = 1; q < NG; ++q) t += s_p[q][k][a];
+            v[k] = t;
         }
-        part[(size_t)blockIdx.x * NPARAM + p] = g;
+        float *out = part + (size_t)blockIdx.x * NPARAM;
+#pragma unroll
+        for (int c = 0; c < NX; ++c) out[OW1 + a * NX + c] = v[c];
+        out[OB1 + a] = v[NX];
+        out[OB2 + a] = v[NX + 1];
+        out[OW3 + a] = v[NX + 2];
+        if (a == 0) out[OB3] = v[NX + 3];
     }
 }
 
