@@ -806,4 +806,9 @@ def forces(wl, nl=None, n_max=None, n_exp=None):
         gp = np.einsum("ab,cab->c", T, dH[p])
         F[j] -= gp
         F[i] += gp
+    # onsite elements Theta~_(ia,ia) = dU/dE_ia through the moments; with the
+    # explicit -N_ia of the onsite reference they give the derivative of the
+    # bond energy with respect to an onsite level, the self-consistency
+    # target of Eq. BOP_SCF: Delta_ia = Theta~_(ia,ia) - N_ia
+    r["theta_onsite"] = np.diag(Theta).reshape(n, no).copy()
     return F, r, w

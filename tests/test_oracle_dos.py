@@ -568,3 +568,20 @@ def test_atom_averaged_mode_equals_orbital_mode_for_isotropic_bonds():
     ra2 = O.energy_pipeline_avg(wl2)
     assert abs(ra2["N_atom"].sum() - 54 * 6.5) < 1e-9
     assert abs(ra2["U_total"] - r2["U_total"]) > 1e-3
+
+
+def test_onsite_theta_is_the_onsite_derivative_of_the_energy():
+    """Eq. BOP_SCF: dU/dE_i (all orbitals of atom i shifted together) =
+    sum_a Theta~_(ia,ia) - N_i, with E_F following; central differences of the
+    oracle's energy in one atom's onsite shift (h = 1e-5 eV)."""
+    wl = _bcc54(n_max=8)
+    _, r, _ = O.forces(wl)
+    delta = r["theta_onsite"].sum(axis=1) - r["N_atom"]
+    h = 1e-5
+    for k in (0, 17, 40):
+        sp = np.zeros(54)
+        sm = np.zeros(54)
+        sp[k] = h
+        sm[k] = -h
+        fd = (O.energy_pipeline(wl, shift=sp)["U_total"] - O.energy_pipeline(wl, shift=sm)["U_total"]) / (2 * h)
+        assert abs(delta[k] - fd) < 1e-7 * max(1.0, abs(fd)), (k, delta[k], fd)
