@@ -568,13 +568,23 @@ int bop_mlp_train_step(int batch, const int *idx, const float *x, const float *t
  *               vectors' precision; H_bond in that dtype), after
  *               bop_moments_prepare; w from bop_weights.  nbr_shift locates
  *               each pair's reverse.  batch_tiles: tiles whose vectors are
- *               live at once (0: a default of at most 8 GiB); pass the same
- *               value to bop_forces_workspace_size.  Errors: BOP_E_UNSUPPORTED
+ *               live at once (0: a default of at most 24 GiB, or a quarter of
+ *               the free memory); pass the same value to
+ *               bop_forces_workspace_size.  theta_on [N*5] (device, may be
+ *               NULL): if given, also the onsite elements Theta~_(ia,ia) =
+ *               dU/dE_ia through the moments (both spins), the first term
+ *               of the self-consistency target of Eq. BOP_SCF; atoms of a
+ *               failed tile get NaN.  Errors: BOP_E_UNSUPPORTED
  *               (not d band, BF16/FP16, path radius, n_max > 20),
  *               BOP_E_CAPACITY (workspace too small).  Tiles whose support
  *               did not fit the plan give NaN forces on their atoms and
  *               neighbours.  The pair gradients are summed with FP64
  *               atomics: results can differ in the last bits between runs.
+ * bop_scf_target  Eq. BOP_SCF with one onsite shift per atom:
+ *               delta[i] = sum_a theta_on[i*n_orb + a] - N_atom[i] =
+ *               dU/d(shift_i) (eV per eV), from bop_forces' theta_on and
+ *               the N_atom of the same energy call.  All arrays device,
+ *               caller-owned.  Errors: BOP_E_ARG (NULL array, n_orb < 1).
  * ========================================================================= */
 size_t bop_weights_workspace_size(int n_rows, int n_max);
 int bop_weights(int n_rows, int n_max, int n_exp, const double *mu, const double *H_on,
@@ -586,7 +596,9 @@ size_t bop_forces_workspace_size(const bop_plan *plan, long n_pairs, int batch_t
 int bop_forces(const bop_plan *plan, const void *moments_ws, const int *row_ptr,
                const int *nbr_j, const int *nbr_shift, long n_pairs, const double *H_on,
                const void *H_bond, const double *dH, const double *w, int batch_tiles,
-               double *F, void *ws, size_t ws_bytes, hipStream_t stream);
+               double *F, double *theta_on, void *ws, size_t ws_bytes, hipStream_t stream);
+int bop_scf_target(int n_atoms, int n_orb, const double *theta_on, const double *N_atom,
+                   double *delta, hipStream_t stream);
 
 #ifdef __cplusplus
 }

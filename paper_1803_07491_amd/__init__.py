@@ -166,7 +166,8 @@ def load(path: str = LIB_PATH):
     lib.bop_bond_derivatives.argtypes = [C.POINTER(Model), C.c_int, P, P, P, P, C.c_long, P, P]
     lib.bop_forces_workspace_size.restype = C.c_size_t
     lib.bop_forces_workspace_size.argtypes = [C.POINTER(Plan), C.c_long, C.c_int]
-    lib.bop_forces.argtypes = [C.POINTER(Plan), P, P, P, P, C.c_long, P, P, P, P, C.c_int, P, P, C.c_size_t, P]
+    lib.bop_forces.argtypes = [C.POINTER(Plan), P, P, P, P, C.c_long, P, P, P, P, C.c_int, P, P, P, C.c_size_t, P]
+    lib.bop_scf_target.argtypes = [C.c_int, C.c_int, P, P, P, P]
     _lib = lib
     return lib
 
@@ -565,10 +566,11 @@ def forces_workspace(plan: Plan, nl: Neighbours, batch_tiles=0):
     return _bytes(lib.bop_forces_workspace_size(C.byref(plan), nl.n_pairs, int(batch_tiles)), nl.row_ptr.device)
 
 
-def forces(plan: Plan, mws, nl: Neighbours, H_on, H_bond, dH, w, batch_tiles=0, F=None, ws=None):
+def forces(plan: Plan, mws, nl: Neighbours, H_on, H_bond, dH, w, batch_tiles=0, F=None, ws=None, theta_on=None):
     """F [N, 3] = -dU_bond/dr (``bop_forces``) from the moment plan and its
     prepared workspace ``mws``, the blocks in the plan's dtype, their
-    derivatives and the weights."""
+    derivatives and the weights.  With ``theta_on`` (an [N, n_orb] FP64
+    device tensor) the onsite elements Theta~_(ia,ia) are written too."""
     torch = _torch()
     lib = load()
     dev = H_on.device
@@ -577,9 +579,19 @@ def forces(plan: Plan, mws, nl: Neighbours, H_on, H_bond, dH, w, batch_tiles=0, 
     if ws is None:
         ws = forces_workspace(plan, nl, batch_tiles)
     _check(lib.bop_forces(C.byref(plan), _ptr(mws), _ptr(nl.row_ptr), _ptr(nl.nbr_j), _ptr(nl.nbr_shift), nl.n_pairs,
-                          _ptr(H_on), _ptr(H_bond), _ptr(dH), _ptr(w), int(batch_tiles), _ptr(F), _ptr(ws),
-                          ws.numel(), _stream()))
+                          _ptr(H_on), _ptr(H_bond), _ptr(dH), _ptr(w), int(batch_tiles), _ptr(F), _ptr(theta_on),
+                          _ptr(ws), ws.numel(), _stream()))
     return F
+
+
+def scf_target(theta_on, N_atom, delta=None):
+    """Delta_i = sum_a Theta~_(ia,ia) - N_i = dU/d(shift_i) (``bop_scf_target``)."""
+    torch = _torch()
+    n, no = theta_on.shape
+    if delta is None:
+        delta = torch.empty(n, dtype=torch.float64, device=theta_on.device)
+    _check(load().bop_scf_target(n, no, _ptr(theta_on), _ptr(N_atom), _ptr(delta), _stream()))
+    return delta
 
 
 class EnergyPath:
@@ -657,17 +669,25 @@ class EnergyPath:
         self.run_moments()
         return self.run_tail(n_elec, E_F)
 
-    def forces(self, n_elec, batch_tiles=0):
+    def forces(self, n_elec, batch_tiles=0, scf_target=False):
         """Energy and forces of the current structure: the moment form of the
         path (FP64 or FP32 vectors as the path's dtype), then the weights at
-        its Fermi level, the block derivatives and F = -dU_bond/dr [N, 3]."""
+        its Fermi level, the block derivatives and F = -dU_bond/dr [N, 3].
+        With ``scf_target`` also the onsite Theta~ [N, n_orb] and the
+        per-atom target of Eq. BOP_SCF (out["theta_on"], out["delta"])."""
         if self.method != "moments":
             raise ValueError("forces need the moment form")
         out = self.run(n_elec)
         self.w = weights(self.mu, self.H_on, out["E_F"], self.n_max, self.n_exp)
         self.dH = bond_derivatives(self.model, self.species, self.nl)
+        th = None
+        if scf_target:
+            th = _torch().empty((self.n, self.no), dtype=_torch().float64, device=self.device)
         out["F"] = forces(self.plan, self.mws, self.nl, self.H_on, self.H_bond, self.dH, self.w,
-                          batch_tiles=batch_tiles)
+                          batch_tiles=batch_tiles, theta_on=th)
+        if scf_target:
+            out["theta_on"] = th
+            out["delta"] = globals()["scf_target"](th, out["N_atom"])
         return out
 
 

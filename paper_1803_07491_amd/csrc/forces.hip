@@ -499,7 +499,7 @@ __device__ inline double wave_sum(double v)
 template <typename T, int NO>
 __global__ void k_finit(FBatch bt, int n, const double *__restrict__ w, const int *__restrict__ sizes_,
                         const char *tiles_base, size_t tile_stride, const int *__restrict__ row_ptr, T *xlev,
-                        size_t xlev_rows, T *gbuf, size_t g_rows, double *gpair)
+                        size_t xlev_rows, T *gbuf, size_t g_rows, double *gpair, double *theta_on)
 {
     const int t = blockIdx.x;
     if (t >= bt.count) return;
@@ -512,6 +512,7 @@ __global__ void k_finit(FBatch bt, int n, const double *__restrict__ w, const in
             const int g = sup[b];
             for (long p = row_ptr[g] + threadIdx.x; p < row_ptr[g + 1]; p += blockDim.x)
                 for (int x = 0; x < 3; ++x) unsafeAtomicAdd(&gpair[3 * p + x], __builtin_nan(""));
+            if (theta_on && threadIdx.x < NO) unsafeAtomicAdd(&theta_on[(long)g * NO + threadIdx.x], __builtin_nan(""));
         }
         return;
     }
@@ -544,7 +545,8 @@ k_fstep(FBatch bt, int lev, int n, int K, int nch, int chunk_rows, int deg_max, 
         const int *__restrict__ row_ptr, const double *__restrict__ H_on, const T *__restrict__ H,
         const double *__restrict__ dH, const double *__restrict__ w, const int *__restrict__ rev,
         const int *__restrict__ sizes_, const char *tiles_base, size_t tile_stride, T *xlev, size_t xlev_rows,
-        LevelOffsets lo, T *gbuf, size_t g_rows, double *accb, double *gpair)
+        LevelOffsets lo, T *gbuf, size_t g_rows, double *accb, double *gpair, double *aonb,
+        double *theta_on)
 {
     constexpr int NB = BOP_D_PACKED;
     constexpr int SR = NO * 64;
@@ -570,6 +572,7 @@ k_fstep(FBatch bt, int lev, int n, int K, int nch, int chunk_rows, int deg_max, 
     T *dst = BWD ? Gt + (size_t)(lev & 1) * g_rows * SR : Xt + (size_t)lo.off[lev] * SR;
     const T *Xk = Xt + (size_t)lo.off[BWD ? lev : 0] * SR;
     double *acc_t = accb + (size_t)t * rows_cap * deg_max * 3;
+    double *aon_t = aonb + (size_t)t * rows_cap * NO;
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     double *st = &s_t[BWD ? wv : 0][0];
@@ -600,11 +603,11 @@ k_fstep(FBatch bt, int lev, int n, int K, int nch, int chunk_rows, int deg_max, 
         const int nval = Lp >= L + 1 ? n3 : (Lp == L ? n2 : n1);
         const int *lrow = lnb + (long)l * deg_max;
         const bool has_prev = L <= Lp;
-        T acc[NO], xk[NO];
+        T acc[NO], xk[NO], xs[NO];
 #pragma unroll
         for (int a = 0; a < NO; ++a) {
-            const T xs = has_prev ? src[(size_t)l * SR + a * 64 + lane] : T(0);
-            acc[a] = (T)H_on[(long)g * NO + a] * xs;
+            xs[a] = has_prev ? src[(size_t)l * SR + a * 64 + lane] : T(0);
+            acc[a] = (T)H_on[(long)g * NO + a] * xs[a];
             xk[a] = BWD ? Xk[(size_t)l * SR + a * 64 + lane] : T(0);
         }
         // a row's pair sums run from its first backward pass (lev = n - L, at
@@ -680,6 +683,31 @@ k_fstep(FBatch bt, int lev, int n, int K, int nch, int chunk_rows, int deg_max, 
                 }
                 __builtin_amdgcn_wave_barrier();
             }
+        }
+        if (BWD && theta_on) {
+            // onsite elements Theta~_(ia,ia): X^lev[i a] G^(lev+1)[i a] summed
+            // over the columns, kept like the pair sums from the row's first
+            // to its last pass
+#pragma unroll
+            for (int a = 0; a < NO; ++a) st[a * TSTRIDE + lane] = (double)xk[a] * (double)xs[a];
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_s_waitcnt(0xc07f);
+            __builtin_amdgcn_wave_barrier();
+            double v = 0.0;
+            if (vr < NO) {
+                const double *row = st + vr * TSTRIDE + 32 * hr;
+#pragma unroll 8
+                for (int c = 0; c < 32; ++c) v += row[c];
+            }
+            v += __shfl_xor(v, 32);
+            if (hr == 0 && vr < NO) {
+                double *ap = aon_t + (size_t)l * NO + vr;
+                if (first && last) unsafeAtomicAdd(&theta_on[(long)g * NO + vr], v);
+                else if (first) *ap = v;
+                else if (last) unsafeAtomicAdd(&theta_on[(long)g * NO + vr], *ap + v);
+                else *ap += v;
+            }
+            __builtin_amdgcn_wave_barrier();
         }
         if (BWD && first != last) {
             // slots whose operand is zero at this pass: start their sums at
@@ -791,7 +819,7 @@ LevelOffsets level_offsets(const bop_plan &p, long *total)
 
 struct ForcesWs {
     char *xlev, *gbuf;
-    double *accb, *gpair;
+    double *accb, *gpair, *aonb;
     int *rev;
     size_t xlev_rows, g_rows, bytes;
 };
@@ -810,6 +838,7 @@ ForcesWs carve_forces(void *base, const bop_plan &p, long P, int bt)
     f.gpair = (double *)take(sizeof(double) * 3 * (size_t)(P > 0 ? P : 1));
     f.rev = (int *)take(sizeof(int) * (size_t)(P > 0 ? P : 1));
     f.accb = (double *)take(sizeof(double) * 3 * (size_t)p.rows_cap * p.deg_max * bt);
+    f.aonb = (double *)take(sizeof(double) * (size_t)p.rows_cap * p.n_orb * bt);
     f.xlev = take(row_bytes * f.xlev_rows * bt);
     f.gbuf = take(row_bytes * 2 * f.g_rows * bt);
     f.bytes = (size_t)(c - (char *)base);
@@ -831,7 +860,7 @@ int default_force_batch(const bop_plan &p, long P)
 
 template <typename T>
 int run_forces(const bop_plan &p, const char *mws, const int *row_ptr, const double *H_on, const T *H,
-               const double *dH, const double *w, const ForcesWs &f, int bt_max, hipStream_t st)
+               const double *dH, const double *w, const ForcesWs &f, int bt_max, double *theta_on, hipStream_t st)
 {
     constexpr int NO = 5;
     const Layout lay = make_layout(p, map_workgroups(p.n_atoms, p.n_tiles));
@@ -844,7 +873,7 @@ int run_forces(const bop_plan &p, const char *mws, const int *row_ptr, const dou
     for (int first = 0; first < p.n_tiles; first += bt_max) {
         FBatch bt{first, std::min(bt_max, p.n_tiles - first)};
         k_finit<T, NO><<<bt.count, 256, 0, st>>>(bt, n, w, sizes, tiles, lay.tile_stride, row_ptr, xlev,
-                                                 f.xlev_rows, gbuf, f.g_rows, f.gpair);
+                                                 f.xlev_rows, gbuf, f.g_rows, f.gpair, theta_on);
         BOP_LAUNCHED();
         const int nb8 = (bt.count + 7) / 8;
         auto grid = [&](int lev) {
@@ -856,14 +885,14 @@ int run_forces(const bop_plan &p, const char *mws, const int *row_ptr, const dou
             const int nch = grid(l);
             k_fstep<T, NO, false><<<(unsigned)(nb8 * 8 * nch), FW, 0, st>>>(
                 bt, l, n, K, nch, p.chunk_rows, p.deg_max, p.rows_cap, row_ptr, H_on, H, dH, w, f.rev, sizes, tiles,
-                lay.tile_stride, xlev, f.xlev_rows, lo, gbuf, f.g_rows, f.accb, f.gpair);
+                lay.tile_stride, xlev, f.xlev_rows, lo, gbuf, f.g_rows, f.accb, f.gpair, f.aonb, nullptr);
             BOP_LAUNCHED();
         }
         for (int k = n - 1; k >= 0; --k) {
             const int nch = grid(k);
             k_fstep<T, NO, true><<<(unsigned)(nb8 * 8 * nch), FW, 0, st>>>(
                 bt, k, n, K, nch, p.chunk_rows, p.deg_max, p.rows_cap, row_ptr, H_on, H, dH, w, f.rev, sizes, tiles,
-                lay.tile_stride, xlev, f.xlev_rows, lo, gbuf, f.g_rows, f.accb, f.gpair);
+                lay.tile_stride, xlev, f.xlev_rows, lo, gbuf, f.g_rows, f.accb, f.gpair, f.aonb, theta_on);
             BOP_LAUNCHED();
         }
     }
@@ -929,8 +958,8 @@ extern "C" size_t bop_forces_workspace_size(const bop_plan *plan, long n_pairs, 
 
 extern "C" int bop_forces(const bop_plan *plan, const void *moments_ws, const int *row_ptr, const int *nbr_j,
                           const int *nbr_shift, long n_pairs, const double *H_on, const void *H_bond,
-                          const double *dH, const double *w, int batch_tiles, double *F, void *ws, size_t ws_bytes,
-                          hipStream_t stream)
+                          const double *dH, const double *w, int batch_tiles, double *F, double *theta_on,
+                          void *ws, size_t ws_bytes, hipStream_t stream)
 {
     BOP_REQUIRE(plan && n_pairs >= 0, BOP_E_ARG, "bop_forces: bad arguments");
     BOP_REQUIRE(plan->n_orb == 5, BOP_E_UNSUPPORTED, "bop_forces: d band (n_orb 5) only");
@@ -950,17 +979,43 @@ extern "C" int bop_forces(const bop_plan *plan, const void *moments_ws, const in
                 f.bytes, ws_bytes);
     const long ng = 3 * n_pairs;
     if (ng > 0) k_fill<<<(unsigned)((ng + 255) / 256), 256, 0, stream>>>(f.gpair, ng, 0.0);
+    if (theta_on)
+        k_fill<<<(unsigned)(((long)n * 5 + 255) / 256), 256, 0, stream>>>(theta_on, (long)n * 5, 0.0);
     if (n_pairs > 0)
         k_reverse<<<(unsigned)((n_pairs + 255) / 256), 256, 0, stream>>>(n, n_pairs, row_ptr, nbr_j, nbr_shift,
                                                                          f.rev);
     BOP_LAUNCHED();
     const int rc = plan->dtype == BOP_F64
                        ? run_forces<double>(*plan, (const char *)moments_ws, row_ptr, H_on, (const double *)H_bond,
-                                            dH, w, f, bt, stream)
+                                            dH, w, f, bt, theta_on, stream)
                        : run_forces<float>(*plan, (const char *)moments_ws, row_ptr, H_on, (const float *)H_bond, dH,
-                                           w, f, bt, stream);
+                                           w, f, bt, theta_on, stream);
     if (rc != BOP_OK) return rc;
     k_force_sum<<<(unsigned)((n + 255) / 256), 256, 0, stream>>>(n, row_ptr, f.rev, f.gpair, F);
+    BOP_LAUNCHED();
+    return BOP_OK;
+}
+
+// Eq. BOP_SCF summed over an atom's orbitals (one onsite shift per atom):
+// Delta_i = sum_a Theta~_(ia,ia) - N_i = dU/d(shift_i)
+__global__ void __launch_bounds__(256)
+k_scf_target(int n, int no, const double *__restrict__ theta_on, const double *__restrict__ N_atom,
+             double *__restrict__ delta)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0;
+    for (int a = 0; a < no; ++a) s += theta_on[(long)i * no + a];
+    delta[i] = s - N_atom[i];
+}
+
+extern "C" int bop_scf_target(int n_atoms, int n_orb, const double *theta_on, const double *N_atom, double *delta,
+                              hipStream_t stream)
+{
+    BOP_REQUIRE(n_atoms >= 0 && n_orb >= 1, BOP_E_ARG, "bop_scf_target: bad arguments");
+    if (n_atoms == 0) return BOP_OK;
+    BOP_REQUIRE(theta_on && N_atom && delta, BOP_E_ARG, "bop_scf_target: NULL array");
+    k_scf_target<<<(unsigned)((n_atoms + 255) / 256), 256, 0, stream>>>(n_atoms, n_orb, theta_on, N_atom, delta);
     BOP_LAUNCHED();
     return BOP_OK;
 }

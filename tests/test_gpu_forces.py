@@ -181,3 +181,106 @@ def test_forces_fullsize_fp32_vectors(bop, n_max, bound):
     e32 = np.abs(F32 - F).max()
     print(f"FP32 vectors vs FP64, 128,000 atoms, {n_max} moments: {e32:.3e} eV/A (max |F| {np.abs(F).max():.3f})")
     assert e32 <= bound * max(1.0, np.abs(F).max())
+
+
+def test_forces_batches_and_rejections(bop):
+    """The force passes over several tile batches (batch of 8 tiles: 11 tiles
+    of bcc 4^3 in two batches) give the same forces as one batch, to rounding
+    of the atomic sums; unsupported inputs are rejected with
+    BOP_E_UNSUPPORTED before anything runs: an s,p,d model, BF16 vectors, a
+    path radius, more than 20 moments."""
+    import torch
+    wl = W.bcc_small()
+    p = bop.EnergyPath(wl.pos, wl.cell, wl.species, wl.model, wl.n_max, wl.n_exp, "f64")
+    F1 = _np(p.forces(float(np.sum(wl.n_elec)))["F"])
+    F8 = _np(bop.forces(p.plan, p.mws, p.nl, p.H_on, p.H_bond, p.dH, p.w, batch_tiles=8))
+    assert p.plan.n_tiles > 8
+    assert np.abs(F8 - F1).max() < 1e-12
+    # BF16 plan
+    _, Hb = bop.build_H(wl.model, p.species, p.nl, dtype="bf16")
+    plan_b = bop.moments_plan(p.n, 5, wl.n_max, "bf16", p.nl)
+    mws_b = bop.moments_prepare(plan_b, p.nl)
+    with pytest.raises(bop.BopError) as e:
+        bop.forces(plan_b, mws_b, p.nl, p.H_on, Hb, p.dH, p.w)
+    assert e.value.code == bop.BOP_E_UNSUPPORTED
+    # a plan with a path radius
+    wl7 = W.bcc_large(reps=7)
+    p7 = bop.EnergyPath(wl7.pos, wl7.cell, wl7.species, wl7.model, 6, wl7.n_exp, "f64", r_max=5.0)
+    w7 = torch.zeros((p7.n * 5, 7), dtype=torch.float64, device="cuda")
+    dH7 = bop.bond_derivatives(wl7.model, p7.species, p7.nl)
+    with pytest.raises(bop.BopError) as e:
+        bop.forces(p7.plan, p7.mws, p7.nl, p7.H_on, p7.H_bond, dH7, w7)
+    assert e.value.code == bop.BOP_E_UNSUPPORTED
+    # s,p,d model: the block derivatives are d-d only
+    from test_gpu_parity import STRUCTS
+    pos, cell, spc, model, _ = STRUCTS["fcc_spd"]
+    sp = torch.as_tensor(spc, device="cuda")
+    nl = bop.build_neighbours(torch.as_tensor(pos, device="cuda"), cell, model["r_cut"])
+    with pytest.raises(bop.BopError) as e:
+        bop.bond_derivatives(model, sp, nl)
+    assert e.value.code == bop.BOP_E_UNSUPPORTED
+    # weights beyond 20 moments
+    mu = torch.ones((4, 22), dtype=torch.float64, device="cuda")
+    with pytest.raises(bop.BopError) as e:
+        bop.weights(mu, torch.zeros(4, dtype=torch.float64, device="cuda"),
+                    torch.zeros(1, dtype=torch.float64, device="cuda"), 21, 200)
+    assert e.value.code == bop.BOP_E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("case", ["bcc54_n8", "bcc54_n5", "bcc128_n9"])
+def test_onsite_theta_and_scf_target_match_oracle(bop, case):
+    """The onsite elements Theta~_(ia,ia) of the backward passes and the
+    per-atom target of Eq. BOP_SCF (sum_a Theta~_(ia,ia) - N_i) against the
+    oracle's dense Theta~ diagonal, within 1e-10 of max(1, max|Theta~|); the
+    same values from two tile batches (batch of 8 tiles) to rounding of the
+    atomic sums, and from FP32 vectors within 1e-5."""
+    import torch
+    wl = {"bcc54_n8": lambda: _bcc54(n_max=8), "bcc54_n5": lambda: _bcc54(n_max=5),
+          "bcc128_n9": W.bcc_small}[case]()
+    p = bop.EnergyPath(wl.pos, wl.cell, wl.species, wl.model, wl.n_max, wl.n_exp, "f64")
+    out = p.forces(float(np.sum(wl.n_elec)), scf_target=True)
+    th, delta = _np(out["theta_on"]), _np(out["delta"])
+    _, r, _ = O.forces(wl)
+    th_ref = r["theta_onsite"]
+    d_ref = th_ref.sum(axis=1) - r["N_atom"]
+    scale = max(1.0, np.abs(th_ref).max())
+    err = np.abs(th - th_ref).max()
+    print(f"{case}: max |theta - theta_ref| = {err:.3e} (max |theta| {np.abs(th_ref).max():.3f}), "
+          f"max |delta - delta_ref| = {np.abs(delta - d_ref).max():.3e}")
+    assert err <= 1e-10 * scale, err
+    assert np.abs(delta - d_ref).max() <= 1e-9 * scale
+    th8 = torch.empty_like(out["theta_on"])
+    bop.forces(p.plan, p.mws, p.nl, p.H_on, p.H_bond, p.dH, p.w, batch_tiles=8, theta_on=th8)
+    assert np.abs(_np(th8) - th).max() < 1e-12 * scale
+    H_on, H32 = bop.build_H(wl.model, p.species, p.nl, dtype="f32")
+    plan = bop.moments_plan(p.n, 5, wl.n_max, "f32", p.nl)
+    mws = bop.moments_prepare(plan, p.nl)
+    th32 = torch.empty_like(out["theta_on"])
+    bop.forces(plan, mws, p.nl, H_on, H32, p.dH, p.w, theta_on=th32)
+    assert np.abs(_np(th32) - th_ref).max() <= 1e-5 * scale
+
+
+def test_scf_target_fullsize_matches_energy_differences(bop):
+    """bcc 40^3, 128,000 atoms, 18 moments: Delta_i = sum_a Theta~_(ia,ia) -
+    N_i at two sampled atoms equals the central difference of the FP64 energy
+    path in that atom's onsite shift, the Fermi level following (h = 1e-3 eV;
+    rounding of U_total ~1e-10 eV / 2e-3 eV; bound 5e-5)."""
+    import torch
+    wl = W.bcc_large()
+    ne = float(np.sum(wl.n_elec))
+    p = bop.EnergyPath(wl.pos, wl.cell, wl.species, wl.model, wl.n_max, wl.n_exp, "f64")
+    out = p.forces(ne, scf_target=True)
+    delta = _np(out["delta"])
+    assert np.isfinite(delta).all()
+    h = 1e-3
+    rng = np.random.default_rng(37)
+    for k in rng.integers(wl.n_atoms, size=2):
+        u = []
+        for sgn in (1.0, -1.0):
+            s = torch.zeros(p.n, dtype=torch.float64, device="cuda")
+            s[int(k)] = sgn * h
+            p.rebuild(shift=s)
+            u.append(float(p.run(ne)["U_total"].item()))
+        fd = (u[0] - u[1]) / (2 * h)
+        print(f"atom {k}: delta {delta[k]:.8f}, central difference {fd:.8f}")
+        assert abs(delta[k] - fd) < 5e-5, (int(k), delta[k], fd)
