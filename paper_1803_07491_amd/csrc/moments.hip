@@ -1170,6 +1170,251 @@ k_step_bf16(Batch bt, int k, int K, int last, int keep, int fin, int nch, int ch
     }
 }
 
+// BF16 Lanczos form of the d band on MFMA, one fused pass per level (the
+// scheme of k_step with LANCZOS = 1).  Rows are packed without padding, two
+// orbitals per 32-bit word, 160 words (640 bytes) per row:
+//   W0[c] = (x_0, x_1), W1[c] = (x_2, x_3) of column c (64 words each),
+//   W2[c'] = (x_4 of column c', x_4 of column c' + 32), c' < 32.
+// A loaded (W0, W1) pair of a column is the B operand of
+// v_mfma_f32_16x16x16_bf16 as it stands.  Per row and 16-column block u, the
+// K dimension runs over (slot, b): four steps of four slots with b = 0..3
+// (lane group g takes slot 4q + g) and one step with b = 4 over slots 4g + i.
+// A = the blocks' rows (lane c < 5 of group g loads row c of its slot's
+// block, the rest are zero), D[a][16u + c] in lane (c, g) for a = 4g + r.
+// So a gathered row costs three 32-bit loads per column where FP32 costs
+// five, and the level's VMEM requests drop by about 40%; the products leave
+// the VALU.  Needs deg_max <= 16 (the five K steps cover 16 slots).
+constexpr int PK_ROW = 160;
+typedef short s16x4_t __attribute__((ext_vector_type(4)));
+
+__device__ inline s16x4_t words_to_s16x4(unsigned lo, unsigned hi)
+{
+    typedef unsigned u32x2_t __attribute__((ext_vector_type(2)));
+    return __builtin_bit_cast(s16x4_t, (u32x2_t){lo, hi});
+}
+__device__ inline float bf16_lo(unsigned w) { return __uint_as_float(w << 16); }
+__device__ inline float bf16_hi(unsigned w) { return __uint_as_float(w & 0xffff0000u); }
+// two values rounded to BF16 (nearest even) in one word: v_cvt_pk_bf16_f32
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+__device__ inline unsigned bf16_pack(float lo, float hi)
+{
+    return __builtin_bit_cast(unsigned, __builtin_convertvector((f32x2_t){lo, hi}, bf16x2_t));
+}
+
+template <int WGT>
+__global__ void __launch_bounds__(WGT)
+k_lstep16(Batch bt, int k, int K, int last, int keep, int nch, int chunk_rows, int deg_max, int rows_cap,
+          const int *__restrict__ row_ptr, const double *__restrict__ H_on, const unsigned short *__restrict__ H,
+          const int *__restrict__ sizes_, const char *tiles_base, size_t tile_stride, char *xbase,
+          size_t x_stride, double *__restrict__ part, const double *__restrict__ lc)
+{
+    constexpr int NW = WGT / 64, NO = 5, SW = 8;
+    __shared__ double s_red[3][NW][64];
+    __shared__ __align__(16) float s_d[NW][64 * 8];
+    const int xcd = blockIdx.x & 7, q = blockIdx.x >> 3;
+    const int t = (q / nch) * 8 + xcd, chunk = q % nch;
+    if (t >= bt.count) return;
+    const int tile = bt.first + t;
+    const int *sizes = sizes_ + tile * (MAXK + 2);
+    if (sizes[0] < 0) return;
+    const int nrow = last ? sizes[K] : sizes[k];
+    const int nct = tile_chunks(nrow, chunk_rows, NW);
+    if (chunk >= nct) return;
+    const int RS = nct * NW;
+    const int *sup = (const int *)(tiles_base + tile_stride * tile);
+    const int *rinfo = sup + rows_cap;
+    const int *lnb = rinfo + rows_cap;
+    const int src = last ? (K & 1) : ((k - 1) & 1);
+    const unsigned *Xp = (const unsigned *)(xbase + x_stride * (4 * (size_t)t + src));
+    unsigned *Xc = (unsigned *)(xbase + x_stride * (4 * (size_t)t + (k & 1)));
+    unsigned *Ra = (unsigned *)(xbase + x_stride * (4 * (size_t)t + 2 + ((k - 1) & 1)));
+    const unsigned *Rb = (const unsigned *)(xbase + x_stride * (4 * (size_t)t + 2 + (k & 1)));
+    const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    float *sD = &s_d[w][0];
+    // the lane's column (lane = column in the update): its coefficients, and
+    // its own onsite level E_col, by which its chain is shifted (H - E_col
+    // leaves the vectors unchanged, a_j comes back shifted), which keeps the
+    // BF16 rounding of the stored y' from entering H r_(j-1) with the weight
+    // of the onsite level
+    const double *lcol = lc + (size_t)t * LC_N * 64 + lane;
+    const float ls = (float)lcol[0], lbeta = (float)lcol[64], lcj = (float)lcol[128], lbp = (float)lcol[192],
+                linv = (float)lcol[256];
+    const int Bt = sizes[0];
+    const float ecol = lane < Bt * NO ? (float)H_on[(long)sup[lane / NO] * NO + lane % NO] : 0.f;
+    double so = 0.0, se = 0.0, sx = 0.0;
+    int l = chunk * NW + w;
+    int g_n = 0, info_n = 0, slots_n = 0, p0_n = 0;
+    if (l < nrow) {
+        g_n = __builtin_amdgcn_readfirstlane(sup[l]);
+        info_n = __builtin_amdgcn_readfirstlane(rinfo[l]);
+        slots_n = lane < deg_max ? lnb[(long)l * deg_max + lane] : 0;
+        p0_n = __builtin_amdgcn_readfirstlane(row_ptr[g_n]);
+    }
+    for (; l < nrow; l += RS) {
+        const int gatom = g_n, info = info_n, slots_all = slots_n, p0 = p0_n;
+        if (l + RS < nrow) {
+            g_n = __builtin_amdgcn_readfirstlane(sup[l + RS]);
+            info_n = __builtin_amdgcn_readfirstlane(rinfo[l + RS]);
+            slots_n = lane < deg_max ? lnb[(long)(l + RS) * deg_max + lane] : 0;
+            p0_n = __builtin_amdgcn_readfirstlane(row_ptr[g_n]);
+        }
+        const int L = info & 255, n1 = (info >> 8) & 255, n2 = (info >> 16) & 255, n3 = (info >> 24) & 255;
+        const bool has_prev = last || L <= k - 1;
+        const int nval = last ? n3 : (k - 1 >= L + 1 ? n3 : (k - 1 == L ? n2 : n1));
+        const int slots = lane < nval ? slots_all : 0;
+        // operands of the four b = 0..3 steps and the b = 4 step, all loads
+        // issued before the first product
+        s16x4_t A[4];
+        unsigned B0[4][4], B1[4][4];
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq) {
+            const int sl = 4 * qq + g;
+            const int pk = __shfl(slots, sl);
+            A[qq] = s16x4_t{0, 0, 0, 0};
+#pragma unroll
+            for (int u = 0; u < 4; ++u) B0[qq][u] = B1[qq][u] = 0u;
+            if (sl < nval) {
+                const unsigned *xr = Xp + (long)(pk >> 8) * PK_ROW;
+                if (c < NO) A[qq] = *(const s16x4_t *)(H + ((long)(p0 + (pk & 255)) * NO + c) * SW);
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    B0[qq][u] = xr[16 * u + c];
+                    B1[qq][u] = xr[64 + 16 * u + c];
+                }
+            }
+        }
+        unsigned short a4[4];
+        unsigned w2a[4], w2b[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int sl = 4 * g + i;
+            const int pk = __shfl(slots, sl);
+            a4[i] = 0;
+            w2a[i] = w2b[i] = 0u;
+            if (sl < nval) {
+                const unsigned *xr = Xp + (long)(pk >> 8) * PK_ROW + 128;
+                if (c < NO) a4[i] = H[((long)(p0 + (pk & 255)) * NO + c) * SW + 4];
+                w2a[i] = xr[c];
+                w2b[i] = xr[16 + c];
+            }
+        }
+        f32x4_t acc[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[u] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq) {
+            if (4 * qq >= nval) break;
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                acc[u] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A[qq], words_to_s16x4(B0[qq][u], B1[qq][u]),
+                                                                   acc[u], 0, 0, 0);
+        }
+        if (nval > 0) {
+            const s16x4_t A4 = words_to_s16x4((unsigned)a4[0] | ((unsigned)a4[1] << 16),
+                                              (unsigned)a4[2] | ((unsigned)a4[3] << 16));
+            // x_4 of columns c (low halves) and c + 32 (high halves) of W2[c],
+            // of columns 16 + c and 48 + c of W2[16 + c]
+            const unsigned lo_a01 = (w2a[0] & 0xffffu) | (w2a[1] << 16), lo_a23 = (w2a[2] & 0xffffu) | (w2a[3] << 16);
+            const unsigned hi_a01 = (w2a[0] >> 16) | (w2a[1] & 0xffff0000u),
+                           hi_a23 = (w2a[2] >> 16) | (w2a[3] & 0xffff0000u);
+            const unsigned lo_b01 = (w2b[0] & 0xffffu) | (w2b[1] << 16), lo_b23 = (w2b[2] & 0xffffu) | (w2b[3] << 16);
+            const unsigned hi_b01 = (w2b[0] >> 16) | (w2b[1] & 0xffff0000u),
+                           hi_b23 = (w2b[2] >> 16) | (w2b[3] & 0xffff0000u);
+            acc[0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A4, words_to_s16x4(lo_a01, lo_a23), acc[0], 0, 0, 0);
+            acc[1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A4, words_to_s16x4(lo_b01, lo_b23), acc[1], 0, 0, 0);
+            acc[2] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A4, words_to_s16x4(hi_a01, hi_a23), acc[2], 0, 0, 0);
+            acc[3] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A4, words_to_s16x4(hi_b01, hi_b23), acc[3], 0, 0, 0);
+        }
+        // D to the wave's LDS block as [column][8] (lane (c, g) holds a = 4g..4g+3
+        // of column 16u + c), then one column per lane for the update
+        __builtin_amdgcn_wave_barrier();
+        if (g < 2) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) *(f32x4_t *)&sD[(16 * u + c) * 8 + 4 * g] = acc[u];
+        }
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_s_waitcnt(0xc07f);          // the block's LDS writes are done
+        __builtin_amdgcn_wave_barrier();
+        const f32x4_t d03 = *(const f32x4_t *)&sD[lane * 8];
+        const float d4 = sD[lane * 8 + 4];
+        // the row's own y'_j, r_(j-1), r_(j-2) (zero outside their supports):
+        // H y'_j = D + (E - E_col) y'_j, H r_(j-1) = (y'_j + beta_(j-1) r_(j-2)) /
+        // s_(j-1), then r_j and y'_(j+1) as in the FP32 form, rounded to BF16
+        // when stored; the sums use the stored values
+        const bool h1 = L <= k - 2, h2 = L <= k - 3;
+        const long ro = (long)l * PK_ROW;
+        const int w2 = 128 + (lane & 31);
+        const unsigned x01 = has_prev ? Xp[ro + lane] : 0u, x23 = has_prev ? Xp[ro + 64 + lane] : 0u;
+        const unsigned x4w = has_prev ? Xp[ro + w2] : 0u;
+        const unsigned p01 = h1 ? Rb[ro + lane] : 0u, p23 = h1 ? Rb[ro + 64 + lane] : 0u;
+        const unsigned p4w = h1 ? Rb[ro + w2] : 0u;
+        const unsigned q01 = h2 ? Ra[ro + lane] : 0u, q23 = h2 ? Ra[ro + 64 + lane] : 0u;
+        const unsigned q4w = h2 ? Ra[ro + w2] : 0u;
+        const bool upper = lane >= 32;
+        const float xs[5] = {bf16_lo(x01), bf16_hi(x01), bf16_lo(x23), bf16_hi(x23),
+                             upper ? bf16_hi(x4w) : bf16_lo(x4w)};
+        const float r1[5] = {bf16_lo(p01), bf16_hi(p01), bf16_lo(p23), bf16_hi(p23),
+                             upper ? bf16_hi(p4w) : bf16_lo(p4w)};
+        const float r2[5] = {bf16_lo(q01), bf16_hi(q01), bf16_lo(q23), bf16_hi(q23),
+                             upper ? bf16_hi(q4w) : bf16_lo(q4w)};
+        const float dv[5] = {d03[0], d03[1], d03[2], d03[3], d4};
+        float rj[5], y[5];
+#pragma unroll
+        for (int a = 0; a < NO; ++a) {
+            const float hx = fmaf((float)H_on[(long)gatom * NO + a] - ecol, xs[a], dv[a]);
+            const float hrp = (xs[a] + lbp * r2[a]) * linv;
+            const float hr = hx - lcj * hrp;
+            rj[a] = xs[a] - lcj * r1[a];
+            y[a] = ls * hr - lbeta * r1[a];
+        }
+        // x_4 of column c' + 32 to lane c' for the shared W2 words
+        const float rj4u = __shfl_xor(rj[4], 32), y4u = __shfl_xor(y[4], 32);
+        const unsigned rw01 = bf16_pack(rj[0], rj[1]), rw23 = bf16_pack(rj[2], rj[3]);
+        const unsigned yw01 = bf16_pack(y[0], y[1]), yw23 = bf16_pack(y[2], y[3]);
+        const unsigned rw4 = upper ? bf16_pack(rj4u, rj[4]) : bf16_pack(rj[4], rj4u);
+        const unsigned yw4 = upper ? bf16_pack(y4u, y[4]) : bf16_pack(y[4], y4u);
+        const float rs[5] = {bf16_lo(rw01), bf16_hi(rw01), bf16_lo(rw23), bf16_hi(rw23),
+                             upper ? bf16_hi(rw4) : bf16_lo(rw4)};
+        const float ys[5] = {bf16_lo(yw01), bf16_hi(yw01), bf16_lo(yw23), bf16_hi(yw23),
+                             upper ? bf16_hi(yw4) : bf16_lo(yw4)};
+#pragma unroll
+        for (int a = 0; a < NO; ++a) {
+            so = fma((double)rs[a], (double)ys[a], so);
+            se = fma((double)ys[a], (double)ys[a], se);
+            sx = fma((double)rs[a], (double)rs[a], sx);
+        }
+        if (keep) {
+            __builtin_nontemporal_store(rw01, &Ra[ro + lane]);
+            __builtin_nontemporal_store(rw23, &Ra[ro + 64 + lane]);
+            __builtin_nontemporal_store(yw01, &Xc[ro + lane]);
+            __builtin_nontemporal_store(yw23, &Xc[ro + 64 + lane]);
+            if (!upper) {
+                __builtin_nontemporal_store(rw4, &Ra[ro + w2]);
+                __builtin_nontemporal_store(yw4, &Xc[ro + w2]);
+            }
+        }
+    }
+    s_red[0][w][lane] = so;
+    s_red[1][w][lane] = se;
+    s_red[2][w][lane] = sx;
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        double to = 0.0, te = 0.0, tx = 0.0;
+#pragma unroll
+        for (int q2 = 0; q2 < NW; ++q2) {
+            to += s_red[0][q2][threadIdx.x];
+            te += s_red[1][q2][threadIdx.x];
+            tx += s_red[2][q2][threadIdx.x];
+        }
+        double *pp = part + (((size_t)t * nch + chunk) * 3) * 64;
+        pp[threadIdx.x] = to;
+        pp[64 + threadIdx.x] = te;
+        pp[128 + threadIdx.x] = tx;
+    }
+}
+
 // dynamic LDS of a step launch that stages the rows' H blocks (one slice of
 // deg_max blocks per wavefront)
 static inline size_t h_lds_bytes(const bop_plan &p, int wgt, size_t elem)
@@ -1337,7 +1582,19 @@ __global__ void k_l0(Batch bt, int n_max, const int *__restrict__ sizes_, const 
         l[threadIdx.x] = threadIdx.x < Bt * NO ? 1.0 : 0.0;
         for (int q = 1; q < LC_N; ++q) l[q * 64 + threadIdx.x] = 0.0;
     }
-    if (bf16) {
+    if (bf16 == 2) {
+        // packed BF16 rows of the d band: words (x_0, x_1), (x_2, x_3) per
+        // column, then (x_4 of c', x_4 of c' + 32)
+        unsigned *X0 = (unsigned *)(xbase + x_stride * ((size_t)nbuf * t));
+        for (int e = threadIdx.x; e < Bt * PK_ROW; e += blockDim.x) {
+            const int l = e / PK_ROW, wd = e % PK_ROW;
+            int c0, a0, c1, a1;
+            if (wd < 128) { c0 = c1 = wd & 63; a0 = 2 * (wd >> 6); a1 = a0 + 1; }
+            else { c0 = wd - 128; c1 = c0 + 32; a0 = a1 = 4; }
+            const unsigned lo = c0 == l * NO + a0 ? 0x3f80u : 0u, hi = c1 == l * NO + a1 ? 0x3f80u : 0u;
+            X0[e] = lo | (hi << 16);
+        }
+    } else if (bf16) {
         constexpr int SW = NO <= 8 ? 8 : 16;
         unsigned short *X0 = (unsigned short *)(xbase + x_stride * ((size_t)nbuf * t));
         for (int e = threadIdx.x; e < Bt * 64 * SW; e += blockDim.x) {
@@ -1502,7 +1759,8 @@ __global__ void k_lreduce(Batch bt, int k, int K, int last, int which, int n_max
 __global__ void k_lreduce_fused(Batch bt, int k, int K, int last, int n_max, int no, int nch, int chunk_rows,
                                 int nw, double thr, const int *__restrict__ sizes_, const char *tiles_base,
                                 size_t tile_stride, const double *__restrict__ part, double *__restrict__ lc,
-                                double *__restrict__ a, double *__restrict__ b, int *__restrict__ flags)
+                                double *__restrict__ a, double *__restrict__ b, int *__restrict__ flags,
+                                const double *__restrict__ a_shift)
 {
     const int t = blockIdx.x;
     if (t >= bt.count) return;
@@ -1525,8 +1783,10 @@ __global__ void k_lreduce_fused(Batch bt, int k, int K, int last, int n_max, int
     const bool broke = fl & BOP_FLAG_BREAKDOWN;
     if (!isfinite(ry) || !isfinite(yy) || !isfinite(rr)) fl |= BOP_FLAG_NONFINITE;
     const double s = l[0];
-    const double av = broke ? a[gr * na + lev - 1] : s * ry;
-    a[gr * na + lev] = av;
+    // a_shift: the passes ran on H - a_shift[column] (the coefficients of the
+    // shifted chain; a_j gets the shift back)
+    const double av = broke ? 0.0 : s * ry;
+    a[gr * na + lev] = broke ? a[gr * na + lev - 1] : av + (a_shift ? a_shift[gr] : 0.0);
     if (!last && !broke) {
         const double bsq = yy - 2.0 * av * av + av * av * s * s * rr;
         const double var = lev == 0 ? bsq : b[gr * (nb + 1) + 1] * b[gr * (nb + 1) + 1];
@@ -1611,6 +1871,53 @@ int run_lanczos_bf16(const bop_plan &p, const int *row_ptr, const double *H_on, 
     return BOP_OK;
 }
 
+// BF16 Lanczos of the d band on MFMA (k_lstep16): one fused pass per level
+// as in the FP32 form, four packed vectors per tile, so a batch holds half
+// the plan's tiles in the same X buffers.
+int run_lanczos16(const bop_plan &p, const int *row_ptr, const double *H_on, const void *Hv, double *a, double *b,
+                  int *flags, char *ws, const Layout &lay, hipStream_t st)
+{
+    const int K = p.n_max / 2;
+    const int steps = K + (p.n_max & 1);
+    const int *sizes = (const int *)(ws + lay.sizes);
+    const char *tiles = ws + lay.tiles;
+    char *xb = ws + lay.x;
+    double *part = (double *)(ws + lay.part);
+    double *lc = (double *)(ws + lay.lc);
+    // breakdown threshold on b^2 relative to b_1^2, above the rounding level of BF16 vectors
+    const double thr = 1e-5;
+    const int lbt = p.batch_tiles >= 2 ? p.batch_tiles / 2 : 1;
+    for (int first = 0; first < p.n_tiles; first += lbt) {
+        Batch bt{first, min(lbt, p.n_tiles - first)};
+        k_l0<float, 5><<<bt.count, 256, 0, st>>>(bt, p.n_max, sizes, tiles, lay.tile_stride, xb, lay.x_stride, 4, lc,
+                                                 a, b, flags, 2);
+        BOP_LAUNCHED();
+        const int nb8 = (bt.count + 7) / 8;
+        for (int k = 1; k <= steps; ++k) {
+            const int last = k > K;
+            const int rows_k = last ? p.rows_k[K] : p.rows_k[k];
+            const int nch = (rows_k + p.chunk_rows - 1) / p.chunk_rows;
+            if (nch <= 0) continue;
+            const int keep = k < steps;
+            dim3 grid((unsigned)(nb8 * nch * 8));
+#define BOP_LSTEP16(W)                                                                                       \
+    k_lstep16<W><<<grid, W, 0, st>>>(bt, k, K, last, keep, nch, p.chunk_rows, p.deg_max, p.rows_cap, row_ptr,  \
+                                     H_on, (const unsigned short *)Hv, sizes, tiles, lay.tile_stride, xb,       \
+                                     lay.x_stride, part, lc)
+            if (p.block_threads == 256) BOP_LSTEP16(256);
+            else if (p.block_threads == 512) BOP_LSTEP16(512);
+            else BOP_LSTEP16(1024);
+#undef BOP_LSTEP16
+            BOP_LAUNCHED();
+            k_lreduce_fused<<<bt.count, 64, 0, st>>>(bt, k, K, last, p.n_max, 5, nch, p.chunk_rows,
+                                                     p.block_threads / 64, thr, sizes, tiles, lay.tile_stride, part,
+                                                     lc, a, b, flags, H_on);
+            BOP_LAUNCHED();
+        }
+    }
+    return BOP_OK;
+}
+
 // FP64 / FP32 (FP16 vector storage) Lanczos: one fused pass per level (k_step
 // with LANCZOS = 1, four vectors per tile, so a batch holds half the plan's
 // tiles in the same X buffers) and one column reduction.
@@ -1671,7 +1978,7 @@ int run_lanczos(const bop_plan &p, const int *row_ptr, const double *H_on, const
             BOP_LAUNCHED();
             k_lreduce_fused<<<bt.count, 64, 0, st>>>(bt, k, K, last, p.n_max, NO, nch, p.chunk_rows,
                                                      p.block_threads / 64, thr, sizes, tiles, lay.tile_stride, part,
-                                                     lc, a, b, flags);
+                                                     lc, a, b, flags, nullptr);
             BOP_LAUNCHED();
         }
     }
@@ -1901,6 +2208,10 @@ extern "C" int bop_lanczos(const bop_plan *plan, const int *row_ptr, const doubl
                 "bop_lanczos: NULL array");
     Layout lay = make_layout(*plan, map_workgroups(n, plan->n_tiles));
     char *w = (char *)ws;
+    // BF16 d band with at most 16 neighbours per row: the fused MFMA pass on
+    // packed rows; otherwise the two-pass form on padded rows
+    if (plan->dtype == BOP_BF16 && no == 5 && plan->deg_max <= 16)
+        return run_lanczos16(*plan, row_ptr, H_on, H_bond, a, b, flags, w, lay, stream);
     if (plan->dtype == BOP_BF16)
         return no == 5 ? run_lanczos_bf16<5>(*plan, row_ptr, H_on, H_bond, a, b, flags, w, lay, stream)
                        : run_lanczos_bf16<9>(*plan, row_ptr, H_on, H_bond, a, b, flags, w, lay, stream);
