@@ -1179,12 +1179,20 @@ k_step_bf16(Batch bt, int k, int K, int last, int keep, int fin, int nch, int ch
 // v_mfma_f32_16x16x16_bf16 as it stands.  Per row and 16-column block u, the
 // K dimension runs over (slot, b): four steps of four slots with b = 0..3
 // (lane group g takes slot 4q + g) and one step with b = 4 over slots 4g + i.
-// A = the blocks' rows (lane c < 5 of group g loads row c of its slot's
-// block, the rest are zero), D[a][16u + c] in lane (c, g) for a = 4g + r.
-// So a gathered row costs three 32-bit loads per column where FP32 costs
-// five, and the level's VMEM requests drop by about 40%; the products leave
-// the VALU.  Needs deg_max <= 16 (the five K steps cover 16 slots).
+// A = the blocks' rows (lane c < 5 of group g reads row c of its slot's
+// block from the wave's LDS copy of the row's blocks, the rest are zero),
+// D[a][16u + c] in lane (c, g) for a = 4g + r.  So a gathered row costs three
+// 32-bit loads per column where FP32 costs five, and the level's VMEM
+// requests drop by about 40%; the products leave the VALU.  Needs deg_max <=
+// 16 (the five K steps cover 16 slots).
 constexpr int PK_ROW = 160;
+// read-only arrays seen through the constant address space, so that loads at
+// wave-uniform addresses (a row's atom, layer word, pair range, onsite levels)
+// become scalar loads instead of vector loads that every lane repeats
+template <typename T> __device__ inline const __attribute__((address_space(4))) T *cst(const T *p)
+{
+    return (const __attribute__((address_space(4))) T *)p;
+}
 typedef short s16x4_t __attribute__((ext_vector_type(4)));
 
 __device__ inline s16x4_t words_to_s16x4(unsigned lo, unsigned hi)
@@ -1212,6 +1220,7 @@ k_lstep16(Batch bt, int k, int K, int last, int keep, int nch, int chunk_rows, i
     constexpr int NW = WGT / 64, NO = 5, SW = 8;
     __shared__ double s_red[3][NW][64];
     __shared__ __align__(16) float s_d[NW][64 * 8];
+    __shared__ __align__(16) unsigned short s_h[NW][16 * NO * SW];   // a row's blocks (<= 16 pairs)
     const int xcd = blockIdx.x & 7, q = blockIdx.x >> 3;
     const int t = (q / nch) * 8 + xcd, chunk = q % nch;
     if (t >= bt.count) return;
@@ -1233,6 +1242,7 @@ k_lstep16(Batch bt, int k, int K, int last, int keep, int nch, int chunk_rows, i
     const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     float *sD = &s_d[w][0];
+    unsigned short *sH = &s_h[w][0];
     // the lane's column (lane = column in the update): its coefficients, and
     // its own onsite level E_col, by which its chain is shifted (H - E_col
     // leaves the vectors unchanged, a_j comes back shifted), which keeps the
@@ -1245,39 +1255,55 @@ k_lstep16(Batch bt, int k, int K, int last, int keep, int nch, int chunk_rows, i
     const float ecol = lane < Bt * NO ? (float)H_on[(long)sup[lane / NO] * NO + lane % NO] : 0.f;
     double so = 0.0, se = 0.0, sx = 0.0;
     int l = chunk * NW + w;
-    int g_n = 0, info_n = 0, slots_n = 0, p0_n = 0;
+    int g_n = 0, info_n = 0, slots_n = 0, p0_n = 0, p1_n = 0;
+    // a row's blocks (pairs p0 .. p1, contiguous, 80 bytes each) reach the
+    // wave's LDS slice asynchronously (global_load_lds, 16 bytes per lane),
+    // issued one row ahead, so the A operands wait for no memory round trip
     if (l < nrow) {
-        g_n = __builtin_amdgcn_readfirstlane(sup[l]);
-        info_n = __builtin_amdgcn_readfirstlane(rinfo[l]);
+        g_n = cst(sup)[l];
+        info_n = cst(rinfo)[l];
         slots_n = lane < deg_max ? lnb[(long)l * deg_max + lane] : 0;
-        p0_n = __builtin_amdgcn_readfirstlane(row_ptr[g_n]);
+        p0_n = cst(row_ptr)[g_n];
+        p1_n = cst(row_ptr)[g_n + 1];
+        h_to_lds16((const float *)(H + (long)p0_n * NO * SW), (float *)sH, (p1_n - p0_n) * NO * SW / 2, lane);
     }
     for (; l < nrow; l += RS) {
-        const int gatom = g_n, info = info_n, slots_all = slots_n, p0 = p0_n;
+        const int gatom = g_n, info = info_n, slots_all = slots_n;
         if (l + RS < nrow) {
-            g_n = __builtin_amdgcn_readfirstlane(sup[l + RS]);
-            info_n = __builtin_amdgcn_readfirstlane(rinfo[l + RS]);
+            g_n = cst(sup)[l + RS];
+            info_n = cst(rinfo)[l + RS];
             slots_n = lane < deg_max ? lnb[(long)(l + RS) * deg_max + lane] : 0;
-            p0_n = __builtin_amdgcn_readfirstlane(row_ptr[g_n]);
+            p0_n = cst(row_ptr)[g_n];
+            p1_n = cst(row_ptr)[g_n + 1];
         }
         const int L = info & 255, n1 = (info >> 8) & 255, n2 = (info >> 16) & 255, n3 = (info >> 24) & 255;
         const bool has_prev = last || L <= k - 1;
         const int nval = last ? n3 : (k - 1 >= L + 1 ? n3 : (k - 1 == L ? n2 : n1));
         const int slots = lane < nval ? slots_all : 0;
-        // operands of the four b = 0..3 steps and the b = 4 step, all loads
-        // issued before the first product
-        s16x4_t A[4];
+        // the row's own y'_j, r_(j-1), r_(j-2) (zero outside their supports), one
+        // column per lane, issued with the gathers so that the update after the
+        // products waits for no further round trip
+        const bool h1 = L <= k - 2, h2 = L <= k - 3;
+        const long ro = (long)l * PK_ROW;
+        const int w2 = 128 + (lane & 31);
+        const unsigned x01 = has_prev ? Xp[ro + lane] : 0u, x23 = has_prev ? Xp[ro + 64 + lane] : 0u;
+        const unsigned x4w = has_prev ? Xp[ro + w2] : 0u;
+        const unsigned p01 = h1 ? Rb[ro + lane] : 0u, p23 = h1 ? Rb[ro + 64 + lane] : 0u;
+        const unsigned p4w = h1 ? Rb[ro + w2] : 0u;
+        const unsigned q01 = h2 ? Ra[ro + lane] : 0u, q23 = h2 ? Ra[ro + 64 + lane] : 0u;
+        const unsigned q4w = h2 ? Ra[ro + w2] : 0u;
+        // the B operands of the four b = 0..3 steps and the b = 4 step, all
+        // loads issued before the first product
+        int pkq[4], pki[4];
         unsigned B0[4][4], B1[4][4];
 #pragma unroll
         for (int qq = 0; qq < 4; ++qq) {
             const int sl = 4 * qq + g;
-            const int pk = __shfl(slots, sl);
-            A[qq] = s16x4_t{0, 0, 0, 0};
+            pkq[qq] = __shfl(slots, sl);
 #pragma unroll
             for (int u = 0; u < 4; ++u) B0[qq][u] = B1[qq][u] = 0u;
             if (sl < nval) {
-                const unsigned *xr = Xp + (long)(pk >> 8) * PK_ROW;
-                if (c < NO) A[qq] = *(const s16x4_t *)(H + ((long)(p0 + (pk & 255)) * NO + c) * SW);
+                const unsigned *xr = Xp + (long)(pkq[qq] >> 8) * PK_ROW;
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     B0[qq][u] = xr[16 * u + c];
@@ -1285,21 +1311,40 @@ k_lstep16(Batch bt, int k, int K, int last, int keep, int nch, int chunk_rows, i
                 }
             }
         }
-        unsigned short a4[4];
         unsigned w2a[4], w2b[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int sl = 4 * g + i;
-            const int pk = __shfl(slots, sl);
-            a4[i] = 0;
+            pki[i] = __shfl(slots, sl);
             w2a[i] = w2b[i] = 0u;
             if (sl < nval) {
-                const unsigned *xr = Xp + (long)(pk >> 8) * PK_ROW + 128;
-                if (c < NO) a4[i] = H[((long)(p0 + (pk & 255)) * NO + c) * SW + 4];
+                const unsigned *xr = Xp + (long)(pki[i] >> 8) * PK_ROW + 128;
                 w2a[i] = xr[c];
                 w2b[i] = xr[16 + c];
             }
         }
+        // this row's blocks have reached LDS (the copy was issued a row ahead):
+        // the A operands, lane c < 5 of group g takes row c of its slot's block
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_s_waitcnt(0);
+        __builtin_amdgcn_wave_barrier();
+        s16x4_t A[4];
+        unsigned short a4[4];
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq) {
+            A[qq] = s16x4_t{0, 0, 0, 0};
+            if (4 * qq + g < nval && c < NO) A[qq] = *(const s16x4_t *)(sH + ((pkq[qq] & 255) * NO + c) * SW);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            a4[i] = 0;
+            if (4 * g + i < nval && c < NO) a4[i] = sH[((pki[i] & 255) * NO + c) * SW + 4];
+        }
+        // the next row's blocks into the slice once these reads are done
+        __builtin_amdgcn_s_waitcnt(0xc07f);
+        __builtin_amdgcn_wave_barrier();
+        if (l + RS < nrow)
+            h_to_lds16((const float *)(H + (long)p0_n * NO * SW), (float *)sH, (p1_n - p0_n) * NO * SW / 2, lane);
         f32x4_t acc[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) acc[u] = f32x4_t{0.f, 0.f, 0.f, 0.f};
@@ -1339,19 +1384,9 @@ k_lstep16(Batch bt, int k, int K, int last, int keep, int nch, int chunk_rows, i
         __builtin_amdgcn_wave_barrier();
         const f32x4_t d03 = *(const f32x4_t *)&sD[lane * 8];
         const float d4 = sD[lane * 8 + 4];
-        // the row's own y'_j, r_(j-1), r_(j-2) (zero outside their supports):
         // H y'_j = D + (E - E_col) y'_j, H r_(j-1) = (y'_j + beta_(j-1) r_(j-2)) /
         // s_(j-1), then r_j and y'_(j+1) as in the FP32 form, rounded to BF16
         // when stored; the sums use the stored values
-        const bool h1 = L <= k - 2, h2 = L <= k - 3;
-        const long ro = (long)l * PK_ROW;
-        const int w2 = 128 + (lane & 31);
-        const unsigned x01 = has_prev ? Xp[ro + lane] : 0u, x23 = has_prev ? Xp[ro + 64 + lane] : 0u;
-        const unsigned x4w = has_prev ? Xp[ro + w2] : 0u;
-        const unsigned p01 = h1 ? Rb[ro + lane] : 0u, p23 = h1 ? Rb[ro + 64 + lane] : 0u;
-        const unsigned p4w = h1 ? Rb[ro + w2] : 0u;
-        const unsigned q01 = h2 ? Ra[ro + lane] : 0u, q23 = h2 ? Ra[ro + 64 + lane] : 0u;
-        const unsigned q4w = h2 ? Ra[ro + w2] : 0u;
         const bool upper = lane >= 32;
         const float xs[5] = {bf16_lo(x01), bf16_hi(x01), bf16_lo(x23), bf16_hi(x23),
                              upper ? bf16_hi(x4w) : bf16_lo(x4w)};
@@ -1363,7 +1398,7 @@ k_lstep16(Batch bt, int k, int K, int last, int keep, int nch, int chunk_rows, i
         float rj[5], y[5];
 #pragma unroll
         for (int a = 0; a < NO; ++a) {
-            const float hx = fmaf((float)H_on[(long)gatom * NO + a] - ecol, xs[a], dv[a]);
+            const float hx = fmaf((float)cst(H_on)[(long)gatom * NO + a] - ecol, xs[a], dv[a]);
             const float hrp = (xs[a] + lbp * r2[a]) * linv;
             const float hr = hx - lcj * hrp;
             rj[a] = xs[a] - lcj * r1[a];
