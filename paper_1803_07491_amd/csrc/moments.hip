@@ -663,6 +663,14 @@ __device__ inline void h_to_lds16(const float *src, float *dst, int n, int lane)
                                              (__attribute__((address_space(3))) void *)(dst + e), 16, 0, 0);
 }
 
+// read-only arrays seen through the constant address space, so that loads at
+// wave-uniform addresses (a row's atom, layer word, pair range, onsite levels)
+// become scalar loads instead of vector loads that every lane repeats
+template <typename T> __device__ inline const __attribute__((address_space(4))) T *cst(const T *p)
+{
+    return (const __attribute__((address_space(4))) T *)p;
+}
+
 // Floats of one wave's LDS slice of H blocks (deg_max blocks, whole 64-float
 // chunks so that the copy never writes past it).
 __host__ __device__ inline int h_slice(int deg_max, int nb) { return (deg_max * nb + 63) / 64 * 64; }
@@ -762,23 +770,23 @@ k_step(Batch bt, int k, int K, int last, int keep, int fin, int nch, int chunk_r
     int l = chunk * NW + w;
     int g_n = 0, info_n = 0, slots_n = 0, p0_n = 0, p1_n = 0, tm_n = -1;
     if (l < nrow) {
-        g_n = __builtin_amdgcn_readfirstlane(sup[l]);
-        info_n = __builtin_amdgcn_readfirstlane(rinfo[l]);
-        if constexpr (TR) tm_n = __builtin_amdgcn_readfirstlane(rmask[l]);
+        g_n = cst(sup)[l];
+        info_n = cst(rinfo)[l];
+        if constexpr (TR) tm_n = cst(rmask)[l];
         slots_n = lane < deg_max ? lnb[(long)l * deg_max + lane] : 0;
-        p0_n = row_ptr[g_n];
-        p1_n = row_ptr[g_n + 1];
+        p0_n = cst(row_ptr)[g_n];
+        p1_n = cst(row_ptr)[g_n + 1];
         if constexpr (!HS) h_copy((const float *)(H + (long)p0_n * NB), (float *)sH, (p1_n - p0_n) * NB);
     }
     for (; l < nrow; l += RS) {
         const int g = g_n, info = info_n, slots_all = slots_n, p0 = p0_n, deg = p1_n - p0_n, tm = tm_n;
         if (l + RS < nrow) {
-            g_n = __builtin_amdgcn_readfirstlane(sup[l + RS]);
-            info_n = __builtin_amdgcn_readfirstlane(rinfo[l + RS]);
-            if constexpr (TR) tm_n = __builtin_amdgcn_readfirstlane(rmask[l + RS]);
+            g_n = cst(sup)[l + RS];
+            info_n = cst(rinfo)[l + RS];
+            if constexpr (TR) tm_n = cst(rmask)[l + RS];
             slots_n = lane < deg_max ? lnb[(long)(l + RS) * deg_max + lane] : 0;
-            p0_n = row_ptr[g_n];
-            p1_n = row_ptr[g_n + 1];
+            p0_n = cst(row_ptr)[g_n];
+            p1_n = cst(row_ptr)[g_n + 1];
         }
         const int L = info & 255, n1 = (info >> 8) & 255, n2 = (info >> 16) & 255, n3 = (info >> 24) & 255;
         const bool has_prev = last || L <= k - 1;
@@ -797,7 +805,7 @@ k_step(Batch bt, int k, int K, int last, int keep, int fin, int nch, int chunk_r
 #pragma unroll
         for (int a = 0; a < NO; ++a) {
             xs[a] = has_prev ? (T)xrow[a * 64] : T(0);
-            acc[a] = from_f64<T>(H_on[(long)g * NO + a]) * xs[a];
+            acc[a] = from_f64<T>(cst(H_on)[(long)g * NO + a]) * xs[a];
         }
         // gather a group of G slots (slots past nval re-read this row, harmless,
         // and are masked in the product)
@@ -1186,13 +1194,6 @@ k_step_bf16(Batch bt, int k, int K, int last, int keep, int fin, int nch, int ch
 // requests drop by about 40%; the products leave the VALU.  Needs deg_max <=
 // 16 (the five K steps cover 16 slots).
 constexpr int PK_ROW = 160;
-// read-only arrays seen through the constant address space, so that loads at
-// wave-uniform addresses (a row's atom, layer word, pair range, onsite levels)
-// become scalar loads instead of vector loads that every lane repeats
-template <typename T> __device__ inline const __attribute__((address_space(4))) T *cst(const T *p)
-{
-    return (const __attribute__((address_space(4))) T *)p;
-}
 typedef short s16x4_t __attribute__((ext_vector_type(4)));
 
 __device__ inline s16x4_t words_to_s16x4(unsigned lo, unsigned hi)
