@@ -1178,17 +1178,18 @@ k_step_bf16(Batch bt, int k, int K, int last, int keep, int fin, int nch, int ch
     }
 }
 
-// BF16 Lanczos form of the d band on MFMA, one fused pass per level (the
-// scheme of k_step with LANCZOS = 1).  Rows are packed without padding, two
-// orbitals per 32-bit word, 160 words (640 bytes) per row:
+// BF16 (or FP16) Lanczos form of the d band on MFMA, one fused pass per
+// level (the scheme of k_step with LANCZOS = 1).  Rows are packed without
+// padding, two orbitals per 32-bit word, 160 words (640 bytes) per row:
 //   W0[c] = (x_0, x_1), W1[c] = (x_2, x_3) of column c (64 words each),
 //   W2[c'] = (x_4 of column c', x_4 of column c' + 32), c' < 32.
 // A loaded (W0, W1) pair of a column is the B operand of
-// v_mfma_f32_16x16x16_bf16 as it stands.  Per row and 16-column block u, the
+// v_mfma_f32_16x16x16_bf16 (or _f16) as it stands.  Per row and 16-column block u, the
 // K dimension runs over (slot, b): four steps of four slots with b = 0..3
 // (lane group g takes slot 4q + g) and one step with b = 4 over slots 4g + i.
 // A = the blocks' rows (lane c < 5 of group g reads row c of its slot's
-// block from the wave's LDS copy of the row's blocks, the rest are zero),
+// block from the wave's LDS copy of the row's blocks, the rest are zero;
+// the FP16 form reads the FP32 packed blocks and rounds them to FP16 there),
 // D[a][16u + c] in lane (c, g) for a = 4g + r.  So a gathered row costs three
 // 32-bit loads per column where FP32 costs five, and the level's VMEM
 // requests drop by about 40%; the products leave the VALU.  Needs deg_max <=
@@ -1201,27 +1202,58 @@ __device__ inline s16x4_t words_to_s16x4(unsigned lo, unsigned hi)
     typedef unsigned u32x2_t __attribute__((ext_vector_type(2)));
     return __builtin_bit_cast(s16x4_t, (u32x2_t){lo, hi});
 }
-__device__ inline float bf16_lo(unsigned w) { return __uint_as_float(w << 16); }
-__device__ inline float bf16_hi(unsigned w) { return __uint_as_float(w & 0xffff0000u); }
-// two values rounded to BF16 (nearest even) in one word: v_cvt_pk_bf16_f32
+// the two 16-bit formats of the packed rows: halves of a word to FP32, two
+// FP32 values rounded (nearest even) into a word (v_cvt_pk_bf16_f32,
+// v_cvt_pk_f16_f32), the 16x16x16 MFMA of the format, and 1.0
 typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x2_t __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x4_t __attribute__((ext_vector_type(4)));
 typedef float f32x2_t __attribute__((ext_vector_type(2)));
-__device__ inline unsigned bf16_pack(float lo, float hi)
-{
-    return __builtin_bit_cast(unsigned, __builtin_convertvector((f32x2_t){lo, hi}, bf16x2_t));
-}
+template <bool F16> struct Half16;
+template <> struct Half16<false> {
+    static __device__ float lo(unsigned w) { return __uint_as_float(w << 16); }
+    static __device__ float hi(unsigned w) { return __uint_as_float(w & 0xffff0000u); }
+    static __device__ unsigned pack(float a, float b)
+    {
+        return __builtin_bit_cast(unsigned, __builtin_convertvector((f32x2_t){a, b}, bf16x2_t));
+    }
+    static __device__ f32x4_t mfma(s16x4_t a, s16x4_t b, f32x4_t c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+    }
+    static constexpr unsigned one = 0x3f80u;
+};
+template <> struct Half16<true> {
+    static __device__ float lo(unsigned w) { return (float)__builtin_bit_cast(_Float16, (unsigned short)(w & 0xffffu)); }
+    static __device__ float hi(unsigned w) { return (float)__builtin_bit_cast(_Float16, (unsigned short)(w >> 16)); }
+    static __device__ unsigned pack(float a, float b)
+    {
+        return __builtin_bit_cast(unsigned, __builtin_convertvector((f32x2_t){a, b}, f16x2_t));
+    }
+    static __device__ f32x4_t mfma(s16x4_t a, s16x4_t b, f32x4_t c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x16f16(__builtin_bit_cast(f16x4_t, a), __builtin_bit_cast(f16x4_t, b), c,
+                                                     0, 0, 0);
+    }
+    static constexpr unsigned one = 0x3c00u;
+};
 
-template <int WGT>
+template <int WGT, bool F16>
 __global__ void __launch_bounds__(WGT)
 k_lstep16(Batch bt, int k, int K, int last, int keep, int nch, int chunk_rows, int deg_max, int rows_cap,
-          const int *__restrict__ row_ptr, const double *__restrict__ H_on, const unsigned short *__restrict__ H,
+          const int *__restrict__ row_ptr, const double *__restrict__ H_on, const void *__restrict__ Hv,
           const int *__restrict__ sizes_, const char *tiles_base, size_t tile_stride, char *xbase,
           size_t x_stride, double *__restrict__ part, const double *__restrict__ lc)
 {
     constexpr int NW = WGT / 64, NO = 5, SW = 8;
+    using HF = Half16<F16>;
+    // a pair's block as stored: BF16 rows padded to 8 ([5][8], 80 bytes), or
+    // FP32 packed symmetric (16 values, 64 bytes) for the FP16 vectors
+    constexpr int HB = F16 ? BOP_D_PACKED * 4 : NO * SW * 2;
+    const char *H = (const char *)Hv;
     __shared__ double s_red[3][NW][64];
     __shared__ __align__(16) float s_d[NW][64 * 8];
-    __shared__ __align__(16) unsigned short s_h[NW][16 * NO * SW];   // a row's blocks (<= 16 pairs)
+    __shared__ __align__(16) char s_h[NW][16 * HB];   // a row's blocks (<= 16 pairs)
     const int xcd = blockIdx.x & 7, q = blockIdx.x >> 3;
     const int t = (q / nch) * 8 + xcd, chunk = q % nch;
     if (t >= bt.count) return;
@@ -1243,7 +1275,7 @@ k_lstep16(Batch bt, int k, int K, int last, int keep, int nch, int chunk_rows, i
     const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     float *sD = &s_d[w][0];
-    unsigned short *sH = &s_h[w][0];
+    char *sH = &s_h[w][0];
     // the lane's column (lane = column in the update): its coefficients, and
     // its own onsite level E_col, by which its chain is shifted (H - E_col
     // leaves the vectors unchanged, a_j comes back shifted), which keeps the
@@ -1266,7 +1298,7 @@ k_lstep16(Batch bt, int k, int K, int last, int keep, int nch, int chunk_rows, i
         slots_n = lane < deg_max ? lnb[(long)l * deg_max + lane] : 0;
         p0_n = cst(row_ptr)[g_n];
         p1_n = cst(row_ptr)[g_n + 1];
-        h_to_lds16((const float *)(H + (long)p0_n * NO * SW), (float *)sH, (p1_n - p0_n) * NO * SW / 2, lane);
+        h_to_lds16((const float *)(H + (long)p0_n * HB), (float *)sH, (p1_n - p0_n) * HB / 4, lane);
     }
     for (; l < nrow; l += RS) {
         const int gatom = g_n, info = info_n, slots_all = slots_n;
@@ -1334,18 +1366,31 @@ k_lstep16(Batch bt, int k, int K, int last, int keep, int nch, int chunk_rows, i
 #pragma unroll
         for (int qq = 0; qq < 4; ++qq) {
             A[qq] = s16x4_t{0, 0, 0, 0};
-            if (4 * qq + g < nval && c < NO) A[qq] = *(const s16x4_t *)(sH + ((pkq[qq] & 255) * NO + c) * SW);
+            if (4 * qq + g < nval && c < NO) {
+                const char *hb = sH + (pkq[qq] & 255) * HB;
+                if constexpr (F16) {
+                    const float *h = (const float *)hb;
+                    A[qq] = words_to_s16x4(HF::pack(h[d_packed_index(c, 0)], h[d_packed_index(c, 1)]),
+                                           HF::pack(h[d_packed_index(c, 2)], h[d_packed_index(c, 3)]));
+                } else {
+                    A[qq] = *(const s16x4_t *)((const unsigned short *)hb + c * SW);
+                }
+            }
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             a4[i] = 0;
-            if (4 * g + i < nval && c < NO) a4[i] = sH[((pki[i] & 255) * NO + c) * SW + 4];
+            if (4 * g + i < nval && c < NO) {
+                const char *hb = sH + (pki[i] & 255) * HB;
+                if constexpr (F16) a4[i] = (unsigned short)(HF::pack(((const float *)hb)[d_packed_index(c, 4)], 0.f) & 0xffffu);
+                else a4[i] = ((const unsigned short *)hb)[c * SW + 4];
+            }
         }
         // the next row's blocks into the slice once these reads are done
         __builtin_amdgcn_s_waitcnt(0xc07f);
         __builtin_amdgcn_wave_barrier();
         if (l + RS < nrow)
-            h_to_lds16((const float *)(H + (long)p0_n * NO * SW), (float *)sH, (p1_n - p0_n) * NO * SW / 2, lane);
+            h_to_lds16((const float *)(H + (long)p0_n * HB), (float *)sH, (p1_n - p0_n) * HB / 4, lane);
         f32x4_t acc[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) acc[u] = f32x4_t{0.f, 0.f, 0.f, 0.f};
@@ -1354,8 +1399,7 @@ k_lstep16(Batch bt, int k, int K, int last, int keep, int nch, int chunk_rows, i
             if (4 * qq >= nval) break;
 #pragma unroll
             for (int u = 0; u < 4; ++u)
-                acc[u] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A[qq], words_to_s16x4(B0[qq][u], B1[qq][u]),
-                                                                   acc[u], 0, 0, 0);
+                acc[u] = HF::mfma(A[qq], words_to_s16x4(B0[qq][u], B1[qq][u]), acc[u]);
         }
         if (nval > 0) {
             const s16x4_t A4 = words_to_s16x4((unsigned)a4[0] | ((unsigned)a4[1] << 16),
@@ -1368,10 +1412,10 @@ k_lstep16(Batch bt, int k, int K, int last, int keep, int nch, int chunk_rows, i
             const unsigned lo_b01 = (w2b[0] & 0xffffu) | (w2b[1] << 16), lo_b23 = (w2b[2] & 0xffffu) | (w2b[3] << 16);
             const unsigned hi_b01 = (w2b[0] >> 16) | (w2b[1] & 0xffff0000u),
                            hi_b23 = (w2b[2] >> 16) | (w2b[3] & 0xffff0000u);
-            acc[0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A4, words_to_s16x4(lo_a01, lo_a23), acc[0], 0, 0, 0);
-            acc[1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A4, words_to_s16x4(lo_b01, lo_b23), acc[1], 0, 0, 0);
-            acc[2] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A4, words_to_s16x4(hi_a01, hi_a23), acc[2], 0, 0, 0);
-            acc[3] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A4, words_to_s16x4(hi_b01, hi_b23), acc[3], 0, 0, 0);
+            acc[0] = HF::mfma(A4, words_to_s16x4(lo_a01, lo_a23), acc[0]);
+            acc[1] = HF::mfma(A4, words_to_s16x4(lo_b01, lo_b23), acc[1]);
+            acc[2] = HF::mfma(A4, words_to_s16x4(hi_a01, hi_a23), acc[2]);
+            acc[3] = HF::mfma(A4, words_to_s16x4(hi_b01, hi_b23), acc[3]);
         }
         // D to the wave's LDS block as [column][8] (lane (c, g) holds a = 4g..4g+3
         // of column 16u + c), then one column per lane for the update
@@ -1389,12 +1433,12 @@ k_lstep16(Batch bt, int k, int K, int last, int keep, int nch, int chunk_rows, i
         // s_(j-1), then r_j and y'_(j+1) as in the FP32 form, rounded to BF16
         // when stored; the sums use the stored values
         const bool upper = lane >= 32;
-        const float xs[5] = {bf16_lo(x01), bf16_hi(x01), bf16_lo(x23), bf16_hi(x23),
-                             upper ? bf16_hi(x4w) : bf16_lo(x4w)};
-        const float r1[5] = {bf16_lo(p01), bf16_hi(p01), bf16_lo(p23), bf16_hi(p23),
-                             upper ? bf16_hi(p4w) : bf16_lo(p4w)};
-        const float r2[5] = {bf16_lo(q01), bf16_hi(q01), bf16_lo(q23), bf16_hi(q23),
-                             upper ? bf16_hi(q4w) : bf16_lo(q4w)};
+        const float xs[5] = {HF::lo(x01), HF::hi(x01), HF::lo(x23), HF::hi(x23),
+                             upper ? HF::hi(x4w) : HF::lo(x4w)};
+        const float r1[5] = {HF::lo(p01), HF::hi(p01), HF::lo(p23), HF::hi(p23),
+                             upper ? HF::hi(p4w) : HF::lo(p4w)};
+        const float r2[5] = {HF::lo(q01), HF::hi(q01), HF::lo(q23), HF::hi(q23),
+                             upper ? HF::hi(q4w) : HF::lo(q4w)};
         const float dv[5] = {d03[0], d03[1], d03[2], d03[3], d4};
         float rj[5], y[5];
 #pragma unroll
@@ -1407,14 +1451,14 @@ k_lstep16(Batch bt, int k, int K, int last, int keep, int nch, int chunk_rows, i
         }
         // x_4 of column c' + 32 to lane c' for the shared W2 words
         const float rj4u = __shfl_xor(rj[4], 32), y4u = __shfl_xor(y[4], 32);
-        const unsigned rw01 = bf16_pack(rj[0], rj[1]), rw23 = bf16_pack(rj[2], rj[3]);
-        const unsigned yw01 = bf16_pack(y[0], y[1]), yw23 = bf16_pack(y[2], y[3]);
-        const unsigned rw4 = upper ? bf16_pack(rj4u, rj[4]) : bf16_pack(rj[4], rj4u);
-        const unsigned yw4 = upper ? bf16_pack(y4u, y[4]) : bf16_pack(y[4], y4u);
-        const float rs[5] = {bf16_lo(rw01), bf16_hi(rw01), bf16_lo(rw23), bf16_hi(rw23),
-                             upper ? bf16_hi(rw4) : bf16_lo(rw4)};
-        const float ys[5] = {bf16_lo(yw01), bf16_hi(yw01), bf16_lo(yw23), bf16_hi(yw23),
-                             upper ? bf16_hi(yw4) : bf16_lo(yw4)};
+        const unsigned rw01 = HF::pack(rj[0], rj[1]), rw23 = HF::pack(rj[2], rj[3]);
+        const unsigned yw01 = HF::pack(y[0], y[1]), yw23 = HF::pack(y[2], y[3]);
+        const unsigned rw4 = upper ? HF::pack(rj4u, rj[4]) : HF::pack(rj[4], rj4u);
+        const unsigned yw4 = upper ? HF::pack(y4u, y[4]) : HF::pack(y[4], y4u);
+        const float rs[5] = {HF::lo(rw01), HF::hi(rw01), HF::lo(rw23), HF::hi(rw23),
+                             upper ? HF::hi(rw4) : HF::lo(rw4)};
+        const float ys[5] = {HF::lo(yw01), HF::hi(yw01), HF::lo(yw23), HF::hi(yw23),
+                             upper ? HF::hi(yw4) : HF::lo(yw4)};
 #pragma unroll
         for (int a = 0; a < NO; ++a) {
             so = fma((double)rs[a], (double)ys[a], so);
@@ -1618,16 +1662,17 @@ __global__ void k_l0(Batch bt, int n_max, const int *__restrict__ sizes_, const 
         l[threadIdx.x] = threadIdx.x < Bt * NO ? 1.0 : 0.0;
         for (int q = 1; q < LC_N; ++q) l[q * 64 + threadIdx.x] = 0.0;
     }
-    if (bf16 == 2) {
-        // packed BF16 rows of the d band: words (x_0, x_1), (x_2, x_3) per
-        // column, then (x_4 of c', x_4 of c' + 32)
+    if (bf16 >= 2) {
+        // packed 16-bit rows of the d band (2: BF16, 3: FP16): words (x_0, x_1),
+        // (x_2, x_3) per column, then (x_4 of c', x_4 of c' + 32)
+        const unsigned one = bf16 == 3 ? Half16<true>::one : Half16<false>::one;
         unsigned *X0 = (unsigned *)(xbase + x_stride * ((size_t)nbuf * t));
         for (int e = threadIdx.x; e < Bt * PK_ROW; e += blockDim.x) {
             const int l = e / PK_ROW, wd = e % PK_ROW;
             int c0, a0, c1, a1;
             if (wd < 128) { c0 = c1 = wd & 63; a0 = 2 * (wd >> 6); a1 = a0 + 1; }
             else { c0 = wd - 128; c1 = c0 + 32; a0 = a1 = 4; }
-            const unsigned lo = c0 == l * NO + a0 ? 0x3f80u : 0u, hi = c1 == l * NO + a1 ? 0x3f80u : 0u;
+            const unsigned lo = c0 == l * NO + a0 ? one : 0u, hi = c1 == l * NO + a1 ? one : 0u;
             X0[e] = lo | (hi << 16);
         }
     } else if (bf16) {
@@ -1910,6 +1955,7 @@ int run_lanczos_bf16(const bop_plan &p, const int *row_ptr, const double *H_on, 
 // BF16 Lanczos of the d band on MFMA (k_lstep16): one fused pass per level
 // as in the FP32 form, four packed vectors per tile, so a batch holds half
 // the plan's tiles in the same X buffers.
+template <bool F16>
 int run_lanczos16(const bop_plan &p, const int *row_ptr, const double *H_on, const void *Hv, double *a, double *b,
                   int *flags, char *ws, const Layout &lay, hipStream_t st)
 {
@@ -1920,13 +1966,13 @@ int run_lanczos16(const bop_plan &p, const int *row_ptr, const double *H_on, con
     char *xb = ws + lay.x;
     double *part = (double *)(ws + lay.part);
     double *lc = (double *)(ws + lay.lc);
-    // breakdown threshold on b^2 relative to b_1^2, above the rounding level of BF16 vectors
-    const double thr = 1e-5;
+    // breakdown threshold on b^2 relative to b_1^2, above the rounding level of the 16-bit vectors
+    const double thr = F16 ? 1e-7 : 1e-5;
     const int lbt = p.batch_tiles >= 2 ? p.batch_tiles / 2 : 1;
     for (int first = 0; first < p.n_tiles; first += lbt) {
         Batch bt{first, min(lbt, p.n_tiles - first)};
         k_l0<float, 5><<<bt.count, 256, 0, st>>>(bt, p.n_max, sizes, tiles, lay.tile_stride, xb, lay.x_stride, 4, lc,
-                                                 a, b, flags, 2);
+                                                 a, b, flags, F16 ? 3 : 2);
         BOP_LAUNCHED();
         const int nb8 = (bt.count + 7) / 8;
         for (int k = 1; k <= steps; ++k) {
@@ -1937,9 +1983,9 @@ int run_lanczos16(const bop_plan &p, const int *row_ptr, const double *H_on, con
             const int keep = k < steps;
             dim3 grid((unsigned)(nb8 * nch * 8));
 #define BOP_LSTEP16(W)                                                                                       \
-    k_lstep16<W><<<grid, W, 0, st>>>(bt, k, K, last, keep, nch, p.chunk_rows, p.deg_max, p.rows_cap, row_ptr,  \
-                                     H_on, (const unsigned short *)Hv, sizes, tiles, lay.tile_stride, xb,       \
-                                     lay.x_stride, part, lc)
+    k_lstep16<W, F16><<<grid, W, 0, st>>>(bt, k, K, last, keep, nch, p.chunk_rows, p.deg_max, p.rows_cap,      \
+                                          row_ptr, H_on, Hv, sizes, tiles, lay.tile_stride, xb, lay.x_stride, part, \
+                                          lc)
             if (p.block_threads == 256) BOP_LSTEP16(256);
             else if (p.block_threads == 512) BOP_LSTEP16(512);
             else BOP_LSTEP16(1024);
@@ -2244,10 +2290,12 @@ extern "C" int bop_lanczos(const bop_plan *plan, const int *row_ptr, const doubl
                 "bop_lanczos: NULL array");
     Layout lay = make_layout(*plan, map_workgroups(n, plan->n_tiles));
     char *w = (char *)ws;
-    // BF16 d band with at most 16 neighbours per row: the fused MFMA pass on
-    // packed rows; otherwise the two-pass form on padded rows
-    if (plan->dtype == BOP_BF16 && no == 5 && plan->deg_max <= 16)
-        return run_lanczos16(*plan, row_ptr, H_on, H_bond, a, b, flags, w, lay, stream);
+    // BF16 or FP16 vectors, d band, at most 16 neighbours per row: the fused
+    // MFMA pass on packed rows; otherwise BF16 takes the two-pass form on
+    // padded rows and FP16 the FP32 pass with FP16 storage
+    if ((plan->dtype == BOP_BF16 || plan->dtype == BOP_F16) && no == 5 && plan->deg_max <= 16)
+        return plan->dtype == BOP_BF16 ? run_lanczos16<false>(*plan, row_ptr, H_on, H_bond, a, b, flags, w, lay, stream)
+                                       : run_lanczos16<true>(*plan, row_ptr, H_on, H_bond, a, b, flags, w, lay, stream);
     if (plan->dtype == BOP_BF16)
         return no == 5 ? run_lanczos_bf16<5>(*plan, row_ptr, H_on, H_bond, a, b, flags, w, lay, stream)
                        : run_lanczos_bf16<9>(*plan, row_ptr, H_on, H_bond, a, b, flags, w, lay, stream);
