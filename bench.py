@@ -257,7 +257,7 @@ def main():
                    "batch_tiles": path.plan.batch_tiles, "chunk_rows": path.plan.chunk_rows},
         "roofline": {"bound": "mfma" if args.dtype == "bf16" else "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": traffic,
-                     "kernel": ("k_lstep16" if args.dtype == "bf16" and args.method == "lanczos" else "k_step")
+                     "kernel": ("k_lstep16" if args.dtype in ("bf16", "f16") and args.method == "lanczos" else "k_step")
                                + " (all H.X launches of one pass)", "kernel_ms": t_mom_ms,
                      "algorithmic_flops_per_launch": flops,
                      "flops_per_atom": float(fpa.mean()), "flops_per_atom_spread": float(np.ptp(fpa))},
