@@ -248,6 +248,24 @@ int bop_batch_concat(int n_structs, int n_atoms, const int *atom_off, const int 
                      const int *row_ptr_local, const int *nbr_j_local, const int *order_local,
                      int *row_ptr, int *nbr_j, int *order, hipStream_t stream);
 
+/* One call per batch step: bop_batch_concat, bop_moments_prepare and
+ * bop_moments in sequence on `stream`, with no synchronisation and no
+ * allocation, so that a serving loop can capture it in a HIP graph and
+ * replay it for new per-structure neighbour lists of the batch.  `plan` is
+ * made once (bop_moments_plan on a joined list of the batch; plan->n_atoms
+ * is the batch's atom count) and must still fit the new lists: tiles whose
+ * supports do not fit get NaN moments, as with bop_moments_prepare.  H_on
+ * [N][n_orb] and H_bond [P] are in the joined order (structure by
+ * structure, so each structure's blocks can be built from its own list).
+ * Arguments as bop_batch_concat and bop_moments; ws is the plan's
+ * workspace.  Errors: those of the three calls; BOP_E_UNSUPPORTED for a plan
+ * with a path radius. */
+int bop_moments_batched(const bop_plan *plan /*[host]*/, int n_structs, const int *atom_off,
+                        const int *pair_off, const int *row_ptr_local, const int *nbr_j_local,
+                        const int *order_local, int *row_ptr, int *nbr_j, int *order,
+                        const double *H_on, const void *H_bond, double *mu, void *ws,
+                        size_t ws_bytes, hipStream_t stream);
+
 /* =========================================================================
  * Recursion coefficients straight from the H.X products: the Lanczos chain
  * (Sec. "Density of states" of App. B, the tridiagonal Hamiltonian of the

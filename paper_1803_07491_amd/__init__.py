@@ -168,6 +168,7 @@ def load(path: str = LIB_PATH):
     lib.bop_forces_workspace_size.argtypes = [C.POINTER(Plan), C.c_long, C.c_int]
     lib.bop_forces.argtypes = [C.POINTER(Plan), P, P, P, P, C.c_long, P, P, P, P, C.c_int, P, P, P, C.c_size_t, P]
     lib.bop_scf_target.argtypes = [C.c_int, C.c_int, P, P, P, P]
+    lib.bop_moments_batched.argtypes = [C.POINTER(Plan), C.c_int, P, P, P, P, P, P, P, P, P, P, P, P, C.c_size_t, P]
     _lib = lib
     return lib
 

@@ -53,6 +53,7 @@ class BatchedMoments:
         _check(load().bop_batch_concat(self.n_structs, self.n, _ptr(d_atom_off), _ptr(d_pair_off), _ptr(row_ptr_local),
                                        _ptr(nbr_j_local), _ptr(order_local), _ptr(row_ptr), _ptr(nbr_j), _ptr(order),
                                        _stream()))
+        self.local = (d_atom_off, d_pair_off, row_ptr_local, nbr_j_local, order_local)
         self.nl = Neighbours(row_ptr, nbr_j, None, nbr_d, order, P)
         self.species = torch.as_tensor(np.concatenate(species), device=self.device)
         self.H_on, self.H_bond = build_H(model, self.species, self.nl, dtype=dtype)
@@ -77,6 +78,17 @@ class BatchedMoments:
         if self.method == "lanczos":
             return lanczos(self.plan, self.nl, self.H_on, self.H_bond, out=self.rec, ws=self.ws)
         return moments(self.plan, self.nl, self.H_on, self.H_bond, mu=self.mu, ws=self.ws)
+
+    def step(self):
+        """The whole batch step in one library call (``bop_moments_batched``):
+        join the per-structure lists, prepare the supports, moments."""
+        d_atom_off, d_pair_off, row_ptr_local, nbr_j_local, order_local = self.local
+        _check(load().bop_moments_batched(C.byref(self.plan), self.n_structs, _ptr(d_atom_off), _ptr(d_pair_off),
+                                          _ptr(row_ptr_local), _ptr(nbr_j_local), _ptr(order_local),
+                                          _ptr(self.nl.row_ptr), _ptr(self.nl.nbr_j), _ptr(self.nl.order),
+                                          _ptr(self.H_on), _ptr(self.H_bond), _ptr(self.mu), _ptr(self.ws),
+                                          self.ws.numel(), _stream()))
+        return self.mu
 
     def capture(self):
         """Record the launch sequence in a HIP graph (after one eager run on

@@ -70,3 +70,18 @@ extern "C" int bop_batch_concat(int n_structs, int n_atoms, const int *atom_off,
     }
     return BOP_OK;
 }
+
+extern "C" int bop_moments_batched(const bop_plan *plan, int n_structs, const int *atom_off, const int *pair_off,
+                                   const int *row_ptr_local, const int *nbr_j_local, const int *order_local,
+                                   int *row_ptr, int *nbr_j, int *order, const double *H_on, const void *H_bond,
+                                   double *mu, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    BOP_REQUIRE(plan, BOP_E_ARG, "bop_moments_batched: plan is NULL");
+    BOP_REQUIRE(plan->r_max == 0.0, BOP_E_UNSUPPORTED, "bop_moments_batched: no path radius");
+    int rc = bop_batch_concat(n_structs, plan->n_atoms, atom_off, pair_off, row_ptr_local, nbr_j_local, order_local,
+                              row_ptr, nbr_j, order, stream);
+    if (rc != BOP_OK) return rc;
+    rc = bop_moments_prepare(plan, row_ptr, nbr_j, order, nullptr, ws, ws_bytes, stream);
+    if (rc != BOP_OK) return rc;
+    return bop_moments(plan, row_ptr, H_on, H_bond, mu, ws, ws_bytes, stream);
+}

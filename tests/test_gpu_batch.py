@@ -43,6 +43,40 @@ def test_batched_equals_per_structure_and_oracle(bop):
             assert np.max(np.abs(mu_b - ref) / np.maximum(np.abs(ref), 1e-12 * np.abs(ref).max())) < 1e-10, s
 
 
+def test_moments_batched_one_call_and_its_graph(bop):
+    """bop_moments_batched (join, supports and moments in one enqueue-only
+    call) gives the moments of the separate calls bit for bit, and a graph
+    captured around it replays them, with the join and the supports redone
+    from cleared outputs at every replay."""
+    import torch
+    from paper_1803_07491_amd.batch import BatchedMoments
+    b = BatchedMoments(_batch(), _model(), 14, "f32")
+    b.run()
+    torch.cuda.synchronize()
+    eager = b.mu.clone()
+    b.mu.fill_(-7.0)
+    b.step()
+    torch.cuda.synchronize()
+    assert torch.equal(b.mu, eager)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        b.step()
+    torch.cuda.current_stream().wait_stream(s)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        b.step()
+    for r in range(3):
+        b.mu.fill_(-7.0)
+        b.nl.nbr_j.fill_(-1)
+        b.nl.row_ptr.fill_(0)
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(b.mu, eager), r
+        x = torch.randn(1 << 20, device="cuda")            # eager work between replays
+        float(x.sum())
+
+
 @pytest.mark.parametrize("method", ["moments", "lanczos"])
 def test_graph_replays_match_eager(bop, method):
     import torch
