@@ -84,6 +84,31 @@ def test_bcc_large_lanczos_fp32_per_atom(bop):
     assert eN < 1e-5 and eU < 1e-5, (eN, eU)
 
 
+# bcc 40^3, the 16-bit Lanczos forms on MFMA (packed rows, bench.py --dtype
+# bf16 / f16): per-atom N_i and U_i of 48 sampled atoms against the oracle at
+# the GPU's Fermi level.  Each level's coefficients take one rounding of the
+# stored vectors (unit roundoff u = 2^-9 BF16, 2^-11 FP16) times |H|, and the
+# per-atom energies move by about u relative: the bound is u (measured over
+# every atom against the FP64 path: BF16 U 9.4e-4, N 2.6e-4; FP16 U 1.3e-4,
+# N 3.8e-5).
+@pytest.mark.parametrize("dtype,u", [("bf16", 2.0 ** -9), ("f16", 2.0 ** -11)])
+def test_bcc_large_lanczos_16bit_per_atom(bop, dtype, u):
+    wl = W.bcc_large()
+    ne = float(np.sum(wl.n_elec))
+    p = bop.EnergyPath(wl.pos, wl.cell, wl.species, wl.model, wl.n_max, wl.n_exp, dtype, method="lanczos")
+    out = p.step(ne)
+    E_F = float(_np(out["E_F"])[0])
+    N = _np(out["N_atom"])
+    U = _np(out["U_atom"])
+    assert abs(N.sum() - ne) < 1e-8 * ne
+    sel = _sample(wl.n_atoms, 48, 107)
+    ref = O.energy_pipeline(wl, sel=sel, E_F=E_F)
+    eN = np.max(np.abs(N[sel] - ref["N_atom"]) / np.abs(ref["N_atom"]))
+    eU = np.max(np.abs(U[sel] - ref["U_atom"]) / np.abs(ref["U_atom"]))
+    print(f"{dtype} Lanczos per-atom relative error: N {eN:.3e}, U {eU:.3e} (bound {u:.2e})")
+    assert eN < u and eU < u, (eN, eU)
+
+
 # fcc A/B s,p,d alloy 30^3, 108,000 atoms, 20 moments: the FP32 Lanczos form
 # (the fastest form within 1 meV/atom) against the oracle's coefficients from
 # FP64 moments.  The FP32 rounding of the vectors (6e-8 times |H| of up to
