@@ -560,6 +560,19 @@ int bop_mlp_train_step(int batch, const int *idx, const float *x, const float *t
                        float *params, float *adam_m, float *adam_v, int step, float lr,
                        float *loss, float *grad, void *ws, size_t ws_bytes,
                        hipStream_t stream);
+/*  bop_mlp_backward    the training step's forward and backward passes
+ *                      only: loss[1] and grad[4673] (same layout as params)
+ *                      of the batch, params unchanged (bop_mlp_train_step
+ *                      with step 0).  Workspace from bop_mlp_train_workspace_size.
+ *  bop_mlp_adam        one Adam update (lr, beta1 0.9, beta2 0.999, eps 1e-8,
+ *                      bias correction with `step` >= 1) of params, adam_m,
+ *                      adam_v from a given grad[4673]: the update of
+ *                      bop_mlp_train_step split out. */
+int bop_mlp_backward(int batch, const int *idx, const float *x, const float *t,
+                     const float *params, float *loss, float *grad, void *ws, size_t ws_bytes,
+                     hipStream_t stream);
+int bop_mlp_adam(const float *grad, float *params, float *adam_m, float *adam_v, int step,
+                 float lr, hipStream_t stream);
 
 /* =========================================================================
  * Forces of the d-band bond energy (App. C.1-C.2: Eqs. dUdLambda, weights,

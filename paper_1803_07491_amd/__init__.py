@@ -157,6 +157,8 @@ def load(path: str = LIB_PATH):
     lib.bop_mlp_train_workspace_size.restype = C.c_size_t
     lib.bop_mlp_train_workspace_size.argtypes = [C.c_int]
     lib.bop_mlp_train_step.argtypes = [C.c_int, P, P, P, P, P, P, C.c_int, C.c_float, P, P, P, C.c_size_t, P]
+    lib.bop_mlp_backward.argtypes = [C.c_int, P, P, P, P, P, P, P, C.c_size_t, P]
+    lib.bop_mlp_adam.argtypes = [P, P, P, P, C.c_int, C.c_float, P]
     lib.bop_atom_average.argtypes = [C.c_int, C.c_int, C.c_int, P, P, P, P, P]
     lib.bop_energy_atom_averaged.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, P, P, P, P, P, P, C.c_double,
                                              C.c_int, P, P, P, P, P, P, P, C.c_size_t, P]
@@ -966,15 +968,22 @@ class MLP:
         self._wsb = 0
 
     def grad(self, x, t):
-        """Loss and gradient at the current parameters (no update)."""
+        """Loss and gradient at the current parameters, no update
+        (``bop_mlp_backward``)."""
         torch = _torch()
         B = x.shape[0]
         ws = _bytes(load().bop_mlp_train_workspace_size(B), x.device)
         g = torch.empty_like(self.params)
         loss = torch.zeros(1, dtype=torch.float32, device=x.device)
-        _check(load().bop_mlp_train_step(B, None, _ptr(x), _ptr(t), _ptr(self.params), None, None, 0, 0.0,
-                                         _ptr(loss), _ptr(g), _ptr(ws), ws.numel(), _stream()))
+        _check(load().bop_mlp_backward(B, None, _ptr(x), _ptr(t), _ptr(self.params), _ptr(loss), _ptr(g), _ptr(ws),
+                                       ws.numel(), _stream()))
         return loss, g
+
+    def adam(self, g, lr=1e-3):
+        """One Adam update of the parameters from a gradient (``bop_mlp_adam``)."""
+        self.t += 1
+        _check(load().bop_mlp_adam(_ptr(g), _ptr(self.params), _ptr(self.m), _ptr(self.v), self.t, float(lr),
+                                   _stream()))
 
     def train(self, x, t, epochs=50, batch=4096, lr=1e-3, seed=0, log_every=0):
         """Minibatch Adam over (x, t) device tensors; returns per-epoch mean loss."""

@@ -496,3 +496,23 @@ extern "C" int bop_mlp_train_step(int batch, const int *idx, const float *x, con
     BOP_LAUNCHED();
     return BOP_OK;
 }
+
+extern "C" int bop_mlp_backward(int batch, const int *idx, const float *x, const float *t, const float *params,
+                                float *loss, float *grad, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    BOP_REQUIRE(grad, BOP_E_ARG, "bop_mlp_backward: grad is NULL");
+    // the training step with no update: params are only read
+    return bop_mlp_train_step(batch, idx, x, t, const_cast<float *>(params), nullptr, nullptr, 0, 0.f, loss, grad, ws,
+                              ws_bytes, stream);
+}
+
+extern "C" int bop_mlp_adam(const float *grad, float *params, float *adam_m, float *adam_v, int step, float lr,
+                            hipStream_t stream)
+{
+    BOP_REQUIRE(grad && params && adam_m && adam_v, BOP_E_ARG, "bop_mlp_adam: NULL array");
+    BOP_REQUIRE(step >= 1, BOP_E_ARG, "bop_mlp_adam: step must be >= 1");
+    k_mlp_adam<<<(NPARAM + 255) / 256, 256, 0, stream>>>(1, 0, grad, nullptr, params, adam_m, adam_v, step, lr,
+                                                        nullptr, nullptr);
+    BOP_LAUNCHED();
+    return BOP_OK;
+}

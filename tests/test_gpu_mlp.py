@@ -59,6 +59,36 @@ def test_adam_step_matches_oracle(bop):
         assert np.max(np.abs(a - b)) < 2e-6
 
 
+def test_backward_then_adam_equals_training_step(bop):
+    """bop_mlp_backward + bop_mlp_adam (the step split in two) give the fused
+    training step's parameters bit for bit, over two steps; the split Adam
+    update matches the oracle's from the oracle's gradient."""
+    import torch
+    arrs, x, t, p, xd, td = _setup(bop, seed=2, B=640)
+    fused = bop.MLP()
+    fused.params = p.clone()
+    split = bop.MLP()
+    split.params = p.clone()
+    for _ in range(2):
+        fused.train(xd, td, epochs=1, batch=640, lr=1e-3, seed=0)
+        perm = torch.as_tensor(np.random.default_rng(0).permutation(640).astype(np.int64), device="cuda")
+        _, g = split.grad(xd[perm].contiguous(), td[perm].contiguous())
+        split.adam(g, lr=1e-3)
+    torch.cuda.synchronize()
+    assert torch.equal(fused.params, split.params)
+    one = bop.MLP()
+    one.params = p.clone()
+    perm = np.random.default_rng(0).permutation(640)
+    xs = x[perm].astype(np.float32).astype(np.float64)
+    ts = t[perm].astype(np.float32).astype(np.float64)
+    _, g_ref = O.mlp_loss_grad(arrs, xs, ts)
+    one.adam(bop.mlp_pack(g_ref), lr=1e-3)
+    zero = [np.zeros_like(a) for a in arrs]
+    new, _, _ = O.adam_step([a.astype(np.float32).astype(np.float64) for a in arrs], g_ref, zero, zero, 1)
+    for a, b in zip(bop.mlp_unpack(one.params), new):
+        assert np.max(np.abs(a - b)) < 2e-6
+
+
 def test_training_reduces_loss(bop):
     import torch
     rng = np.random.default_rng(3)
