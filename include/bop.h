@@ -173,10 +173,11 @@ int bop_build_H(const bop_model *model /*[host]*/, int n_atoms, const int *speci
 typedef struct bop_tuning {
     int tile_atoms;      /* atoms per tile; 0 = as many as fit one wavefront */
     int block_threads;   /* 256, 512 or 1024; 0 = default (512) */
-    int batch_tiles;     /* tiles whose X buffers are live at once; 0 = 24 GiB worth (at most a
+    int batch_tiles;     /* tiles whose X buffers are live at once; 0 = 48 GiB worth (at most a
                             quarter of the free device memory) */
     int chunk_rows;      /* support rows per workgroup and step (the rows are dealt to the
-                            workgroups of a tile in wave-sized groups, round robin); 0 = default (64) */
+                            workgroups of a tile in wave-sized groups, round robin); 0 = default
+                            (64; 128 for BF16 and FP16 d-band plans) */
     int plan_search;     /* support sizes in bop_moments_plan: 0 = automatic, 1 = visited bitmap in
                             LDS (up to 524,288 atoms), 2 = per-workgroup map in `scratch`; both
                             give the same plan */
