@@ -614,6 +614,32 @@ k_fstep(FBatch bt, int lev, int n, int K, int nch, int chunk_rows, int deg_max, 
         // most n - 1) to its last (lev = L)
         const bool first = BWD && lev == min(n - L, n - 1), last = BWD && lev == L;
         double *acc_row = acc_t + (size_t)l * deg_max * 3;
+        if (BWD && theta_on) {
+            // onsite elements Theta~_(ia,ia): X^lev[i a] G^(lev+1)[i a] summed
+            // over the columns, kept like the pair sums from the row's first
+            // to its last pass; formed before the slots, so that the row's own
+            // G^(lev+1) holds no registers across the slot loop
+#pragma unroll
+            for (int a = 0; a < NO; ++a) st[a * TSTRIDE + lane] = (double)xk[a] * (double)xs[a];
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_s_waitcnt(0xc07f);
+            __builtin_amdgcn_wave_barrier();
+            double v = 0.0;
+            if (vr < NO) {
+                const double *row = st + vr * TSTRIDE + 32 * hr;
+#pragma unroll 8
+                for (int c = 0; c < 32; ++c) v += row[c];
+            }
+            v += __shfl_xor(v, 32);
+            if (hr == 0 && vr < NO) {
+                double *ap = aon_t + (size_t)l * NO + vr;
+                if (first && last) unsafeAtomicAdd(&theta_on[(long)g * NO + vr], v);
+                else if (first) *ap = v;
+                else if (last) unsafeAtomicAdd(&theta_on[(long)g * NO + vr], *ap + v);
+                else *ap += v;
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
         for (int s0 = 0; s0 < nval; s0 += GS) {
             T xn[GS][NO];
 #pragma unroll
@@ -683,31 +709,6 @@ k_fstep(FBatch bt, int lev, int n, int K, int nch, int chunk_rows, int deg_max, 
                 }
                 __builtin_amdgcn_wave_barrier();
             }
-        }
-        if (BWD && theta_on) {
-            // onsite elements Theta~_(ia,ia): X^lev[i a] G^(lev+1)[i a] summed
-            // over the columns, kept like the pair sums from the row's first
-            // to its last pass
-#pragma unroll
-            for (int a = 0; a < NO; ++a) st[a * TSTRIDE + lane] = (double)xk[a] * (double)xs[a];
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_s_waitcnt(0xc07f);
-            __builtin_amdgcn_wave_barrier();
-            double v = 0.0;
-            if (vr < NO) {
-                const double *row = st + vr * TSTRIDE + 32 * hr;
-#pragma unroll 8
-                for (int c = 0; c < 32; ++c) v += row[c];
-            }
-            v += __shfl_xor(v, 32);
-            if (hr == 0 && vr < NO) {
-                double *ap = aon_t + (size_t)l * NO + vr;
-                if (first && last) unsafeAtomicAdd(&theta_on[(long)g * NO + vr], v);
-                else if (first) *ap = v;
-                else if (last) unsafeAtomicAdd(&theta_on[(long)g * NO + vr], *ap + v);
-                else *ap += v;
-            }
-            __builtin_amdgcn_wave_barrier();
         }
         if (BWD && first != last) {
             // slots whose operand is zero at this pass: start their sums at
