@@ -32,7 +32,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6, "bf16": 2500.0, "f16": 157.3}   # MI355X peaks: vector FP32 (incl. packed), FP64, dense BF16 MFMA
+# MI355X peaks: vector FP32 (incl. packed), FP64, dense BF16 and FP16 MFMA (the 16-bit H.X forms of the
+# d band run on MFMA)
+PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6, "bf16": 2500.0, "f16": 2500.0}
 PEAK_NONPACKED_F32 = 78.6                     # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
 PEAK_HBM_TBPS = 8.0
 
@@ -255,7 +257,8 @@ def main():
                    "method": args.method, "hx_dtype": args.dtype, "tail_dtype": "f64",
                    "tile_atoms": path.plan.tile_atoms, "block_threads": path.plan.block_threads,
                    "batch_tiles": path.plan.batch_tiles, "chunk_rows": path.plan.chunk_rows},
-        "roofline": {"bound": "mfma" if args.dtype == "bf16" else "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+        "roofline": {"bound": "mfma" if args.dtype in ("bf16", "f16") else "alu", "achieved": achieved, "peak": peak,
+                     "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": traffic,
                      "kernel": ("k_lstep16" if args.dtype in ("bf16", "f16") and args.method == "lanczos" else "k_step")
                                + " (all H.X launches of one pass)", "kernel_ms": t_mom_ms,
