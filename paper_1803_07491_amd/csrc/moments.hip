@@ -895,8 +895,11 @@ k_step(Batch bt, int k, int K, int last, int keep, int fin, int nch, int chunk_r
                 const T hr = acc[a] - lcj * hrp;                 // H r_j
                 const S rj = (S)(xs[a] - lcj * r1[a]);           // r_j
                 const S y = (S)(ls * hr - lbeta * r1[a]);        // y'_(j+1)
+                // r_j is zero on the newest layer (L = k, where y'_j and r_(j-1)
+                // are) and no later pass reads it there: stored on the older
+                // layers only
                 if (keep) {
-                    __builtin_nontemporal_store(rj, &ro[a * 64]);
+                    if (has_prev) __builtin_nontemporal_store(rj, &ro[a * 64]);
                     __builtin_nontemporal_store(y, &xo[a * 64]);
                 }
                 // sums of the vectors as stored
@@ -1470,13 +1473,16 @@ k_lstep16(Batch bt, int k, int K, int last, int keep, int nch, int chunk_rows, i
             se = fma((double)ys[a], (double)ys[a], se);
             sx = fma((double)rs[a], (double)rs[a], sx);
         }
+        // r_j only on the layers later passes read it (not the newest, where it is zero)
         if (keep) {
-            __builtin_nontemporal_store(rw01, &Ra[ro + lane]);
-            __builtin_nontemporal_store(rw23, &Ra[ro + 64 + lane]);
+            if (has_prev) {
+                __builtin_nontemporal_store(rw01, &Ra[ro + lane]);
+                __builtin_nontemporal_store(rw23, &Ra[ro + 64 + lane]);
+            }
             __builtin_nontemporal_store(yw01, &Xc[ro + lane]);
             __builtin_nontemporal_store(yw23, &Xc[ro + 64 + lane]);
             if (!upper) {
-                __builtin_nontemporal_store(rw4, &Ra[ro + w2]);
+                if (has_prev) __builtin_nontemporal_store(rw4, &Ra[ro + w2]);
                 __builtin_nontemporal_store(yw4, &Xc[ro + w2]);
             }
         }
