@@ -61,7 +61,8 @@ extern "C" {
 #define BOP_F64   0
 #define BOP_F32   1
 #define BOP_BF16  2
-#define BOP_F16   3   /* H.X vectors stored in FP16, FP32 H and arithmetic; Lanczos form only */
+#define BOP_F16   3   /* H.X vectors stored in FP16, FP32 blocks in memory; Lanczos form only
+                         (d band: products on FP16 MFMA; otherwise FP32 arithmetic) */
 
 /* ---- tight-binding model (host struct, passed by value to kernels) -------- */
 #define BOP_MAX_SPECIES 3
@@ -281,10 +282,16 @@ int bop_moments_batched(const bop_plan *plan /*[host]*/, int n_structs, const in
  * so FP32 and BF16 rounding shows up in a_n, b_n at about the unit roundoff
  * times |H|, where the moment route amplifies it (ill-conditioned Hankel
  * map).  Inner products and coefficients are FP64.
- * Breakdown: b_(k+1)^2 <= thr * b_1^2 (thr = 1e-14 FP64, 1e-10 FP32, 1e-5
- * BF16) sets that and later b to 0, repeats a, and flags BOP_FLAG_BREAKDOWN |
- * level << 8, as the moment route does.  Seeds of a failed tile get NaN
- * coefficients and BOP_FLAG_NONFINITE.
+ * Breakdown: b_(k+1)^2 <= thr * b_1^2 (thr = 1e-14 FP64, 1e-10 FP32, 1e-7
+ * FP16, 1e-5 BF16) sets that and later b to 0, repeats a, and flags
+ * BOP_FLAG_BREAKDOWN | level << 8, as the moment route does.  Seeds of a
+ * failed tile get NaN coefficients and BOP_FLAG_NONFINITE.
+ * 16-bit vectors: for the d band with at most 16 neighbours per atom, BF16
+ * and FP16 plans run the products on MFMA over packed rows (two orbitals per
+ * 32-bit word), with the blocks rounded to the vectors' format (FP16 plans
+ * keep FP32 blocks in memory and round them as they are read), each column's
+ * chain shifted by its own onsite level; otherwise BF16 takes a two-pass form
+ * on padded rows and FP16 stores FP16 vectors with FP32 products.
  *
  *  a [N*n_orb][n_a], b [N*n_orb][n_b+1] (b[.][0] = 0), flags [N*n_orb] out.
  *  Follow with bop_recursion(mu = NULL) for the terminator and bop_energy(mu
