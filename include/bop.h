@@ -178,7 +178,8 @@ typedef struct bop_tuning {
                             quarter of the free device memory) */
     int chunk_rows;      /* support rows per workgroup and step (the rows are dealt to the
                             workgroups of a tile in wave-sized groups, round robin); 0 = default
-                            (64; 128 for BF16 and FP16 d-band plans) */
+                            (64; 128 for BF16 and FP16 d-band plans).  The moment passes use it;
+                            the force passes deal their rows in chunks of 16 whatever it is */
     int plan_search;     /* support sizes in bop_moments_plan: 0 = automatic, 1 = visited bitmap in
                             LDS (up to 524,288 atoms), 2 = per-workgroup map in `scratch`; both
                             give the same plan */

@@ -57,6 +57,11 @@ namespace {
 
 constexpr int FW = 256;             // threads per block of the force passes
 constexpr int NWF = FW / 64;
+// Rows per chunk of the force passes, independent of the moment plan's: a
+// tile's chunks then fill about one XCD, so about one tile's rows are in
+// flight per XCD and its gathered FP64 rows stay in that XCD's L2, where
+// larger chunks put several tiles' windows in one L2.
+constexpr int F_CHUNK = 16;
 constexpr int WT = 256;             // threads per block of the weight kernels
 constexpr int F_MAXN = 20;          // largest n_max of the force path
 
@@ -879,20 +884,20 @@ int run_forces(const bop_plan &p, const char *mws, const int *row_ptr, const dou
         const int nb8 = (bt.count + 7) / 8;
         auto grid = [&](int lev) {
             const int h = std::min(std::min(lev, n - lev), K);
-            const int nch = (p.rows_k[h] + p.chunk_rows - 1) / p.chunk_rows;
+            const int nch = (p.rows_k[h] + F_CHUNK - 1) / F_CHUNK;
             return nch;
         };
         for (int l = 1; l < n; ++l) {
             const int nch = grid(l);
             k_fstep<T, NO, false><<<(unsigned)(nb8 * 8 * nch), FW, 0, st>>>(
-                bt, l, n, K, nch, p.chunk_rows, p.deg_max, p.rows_cap, row_ptr, H_on, H, dH, w, f.rev, sizes, tiles,
+                bt, l, n, K, nch, F_CHUNK, p.deg_max, p.rows_cap, row_ptr, H_on, H, dH, w, f.rev, sizes, tiles,
                 lay.tile_stride, xlev, f.xlev_rows, lo, gbuf, f.g_rows, f.accb, f.gpair, f.aonb, nullptr);
             BOP_LAUNCHED();
         }
         for (int k = n - 1; k >= 0; --k) {
             const int nch = grid(k);
             k_fstep<T, NO, true><<<(unsigned)(nb8 * 8 * nch), FW, 0, st>>>(
-                bt, k, n, K, nch, p.chunk_rows, p.deg_max, p.rows_cap, row_ptr, H_on, H, dH, w, f.rev, sizes, tiles,
+                bt, k, n, K, nch, F_CHUNK, p.deg_max, p.rows_cap, row_ptr, H_on, H, dH, w, f.rev, sizes, tiles,
                 lay.tile_stride, xlev, f.xlev_rows, lo, gbuf, f.g_rows, f.accb, f.gpair, f.aonb, theta_on);
             BOP_LAUNCHED();
         }
