@@ -539,8 +539,9 @@ __global__ void k_finit(FBatch bt, int n, const double *__restrict__ w, const in
 // A row's neighbour slots go in groups of GS: the group's rows of the operand
 // are gathered before any is used.  In the backward pass each lane's three
 // contraction values per slot go to the wave's LDS block [3 GS][65] and are
-// summed over the 64 columns by 48 lanes (two halves of 32 columns, then one
-// exchange), instead of a shuffle tree per value.
+// summed over the 64 columns by eight lanes per value, each adding every
+// eighth column, then three exchanges among the eight (a shuffle tree per
+// value, or a few lanes adding 32 columns each, cost more instructions).
 constexpr int GS = 2;                         // slots per gather group
 constexpr int TSTRIDE = 65;                   // LDS row of one value (64 columns + pad)
 
@@ -584,8 +585,8 @@ k_fstep(FBatch bt, int lev, int n, int K, int nch, int chunk_rows, int deg_max, 
     const int Bt = sizes[0];
     T wl = T(0);                       // the lane's column weight w_lev
     if (BWD && lev >= 1 && lane < Bt * NO) wl = (T)w[((long)sup[lane / NO] * NO + lane % NO) * (n + 1) + lev];
-    // reduction lanes: value vr of the group, half hr of the columns
-    const int vr = lane & 31, hr = lane >> 5;
+    // reduction lanes: value vg of the group, columns sg, sg + 8, ..., sg + 56
+    const int vg = lane >> 3, sg = lane & 7;
     // the next row's atom, layer word, slot list and first pair are fetched
     // while the current row computes
     int l = chunk * NWF + wv;
@@ -630,17 +631,19 @@ k_fstep(FBatch bt, int lev, int n, int K, int nch, int chunk_rows, int deg_max, 
             __builtin_amdgcn_s_waitcnt(0xc07f);
             __builtin_amdgcn_wave_barrier();
             double v = 0.0;
-            if (vr < NO) {
-                const double *row = st + vr * TSTRIDE + 32 * hr;
-#pragma unroll 8
-                for (int c = 0; c < 32; ++c) v += row[c];
+            if (vg < NO) {
+                const double *row = st + vg * TSTRIDE + sg;
+#pragma unroll
+                for (int c = 0; c < 8; ++c) v += row[8 * c];
             }
-            v += __shfl_xor(v, 32);
-            if (hr == 0 && vr < NO) {
-                double *ap = aon_t + (size_t)l * NO + vr;
-                if (first && last) unsafeAtomicAdd(&theta_on[(long)g * NO + vr], v);
+            v += __shfl_xor(v, 1);
+            v += __shfl_xor(v, 2);
+            v += __shfl_xor(v, 4);
+            if (sg == 0 && vg < NO) {
+                double *ap = aon_t + (size_t)l * NO + vg;
+                if (first && last) unsafeAtomicAdd(&theta_on[(long)g * NO + vg], v);
                 else if (first) *ap = v;
-                else if (last) unsafeAtomicAdd(&theta_on[(long)g * NO + vr], *ap + v);
+                else if (last) unsafeAtomicAdd(&theta_on[(long)g * NO + vg], *ap + v);
                 else *ap += v;
             }
             __builtin_amdgcn_wave_barrier();
@@ -695,14 +698,16 @@ k_fstep(FBatch bt, int lev, int n, int K, int nch, int chunk_rows, int deg_max, 
                 __builtin_amdgcn_wave_barrier();
                 const int ng = 3 * min(GS, nval - s0);
                 double v = 0.0;
-                if (vr < ng) {
-                    const double *row = st + vr * TSTRIDE + 32 * hr;
-#pragma unroll 8
-                    for (int c = 0; c < 32; ++c) v += row[c];
+                if (vg < ng) {
+                    const double *row = st + vg * TSTRIDE + sg;
+#pragma unroll
+                    for (int c = 0; c < 8; ++c) v += row[8 * c];
                 }
-                v += __shfl_xor(v, 32);
-                if (hr == 0 && vr < ng) {
-                    const int s = s0 + vr / 3, x = vr % 3;
+                v += __shfl_xor(v, 1);
+                v += __shfl_xor(v, 2);
+                v += __shfl_xor(v, 4);
+                if (sg == 0 && vg < ng) {
+                    const int s = s0 + vg / 3, x = vg % 3;
                     const long pp = (long)p0 + (lrow[s] & 255);
                     double *ap = acc_row + s * 3 + x;
                     if (rev[pp] > pp) {
