@@ -487,6 +487,11 @@ struct FBatch {
     int first, count;
 };
 
+// H and the derivative blocks are read at wave-uniform addresses through the
+// constant address space, so that their loads stay scalar loads also where the
+// kernel issues LDS-DMA loads (which the compiler takes as possible writes)
+template <typename T> using CT = const __attribute__((address_space(4))) T;
+
 // row offset of X^l in a tile's level store
 struct LevelOffsets {
     long off[F_MAXN + 1];
@@ -557,6 +562,7 @@ k_fstep(FBatch bt, int lev, int n, int K, int nch, int chunk_rows, int deg_max, 
     constexpr int NB = BOP_D_PACKED;
     constexpr int SR = NO * 64;
     __shared__ double s_t[BWD ? NWF : 1][BWD ? 3 * GS * TSTRIDE : 1];
+    __shared__ unsigned s_sink[sizeof(T) == 4 ? NWF : 1][64];   // LDS copies of the L2 touches, never read
     const int xcd = blockIdx.x & 7, q = blockIdx.x >> 3;
     const int t = (q / nch) * 8 + xcd, chunk = q % nch;
     if (t >= bt.count) return;
@@ -649,6 +655,21 @@ k_fstep(FBatch bt, int lev, int n, int K, int nch, int chunk_rows, int deg_max, 
             __builtin_amdgcn_wave_barrier();
         }
         for (int s0 = 0; s0 < nval; s0 += GS) {
+            if (sizeof(T) == 4) {
+                // FP32 vectors: the next group's H blocks (and derivative
+                // blocks) are fetched into L2 by an LDS-DMA load whose LDS copy
+                // is never read, so that their scalar loads find them there
+                // (with FP64 vectors this costs the backward pass an occupancy
+                // step and gains nothing)
+                const int u = lane >> 2, part = lane & 3;
+                const int sn = s0 + GS + u;
+                const int sw = __shfl(slots, sn < 64 ? sn : 0);
+                if (u < GS && sn < nval && (BWD || part == 0)) {
+                    const long pn = (long)p0 + (sw & 255);
+                    const void *a = part == 0 ? (const void *)(H + pn * NB) : (const void *)(dH + (pn * 3 + part - 1) * NB);
+                    __builtin_amdgcn_global_load_lds(a, (__attribute__((address_space(3))) void *)&s_sink[wv][0], 4, 0, 0);
+                }
+            }
             T xn[GS][NO];
 #pragma unroll
             for (int u = 0; u < GS; ++u) {
@@ -662,7 +683,7 @@ k_fstep(FBatch bt, int lev, int n, int K, int nch, int chunk_rows, int deg_max, 
             for (int u = 0; u < GS; ++u) {
                 if (s0 + u >= nval) break;
                 const long pp = (long)p0 + (__builtin_amdgcn_readlane(slots, s0 + u) & 255);
-                const T *h = H + pp * NB;
+                const CT<T> *h = (const CT<T> *)(H + pp * NB);
 #pragma unroll
                 for (int a = 0; a < NO; ++a)
 #pragma unroll
@@ -670,7 +691,7 @@ k_fstep(FBatch bt, int lev, int n, int K, int nch, int chunk_rows, int deg_max, 
                 // the contraction of the pair's canonical direction only (the
                 // one of lower index): g_reverse(p) = -g_p
                 if (BWD && __builtin_amdgcn_readfirstlane(rev[pp]) > pp) {
-                    const double *dh = dH + pp * 3 * NB;
+                    const CT<double> *dh = (const CT<double> *)(dH + pp * 3 * NB);
                     double t0 = 0.0, t1 = 0.0, t2 = 0.0;
 #pragma unroll
                     for (int a = 0; a < NO; ++a)
