@@ -532,14 +532,15 @@ def bench_scf(args, torch, P, W):
 def bench_precision(args, torch, P, W):
     """Precision form: fcc A/B alloy 30^3 (108,000 atoms), s,p,d blocks with
     exponential bond integrals, cutoff 4.2 A, 20 moments: FP64 / FP32 / BF16
-    H.X, moments and Lanczos forms, energy error against the FP64 path."""
+    H.X, moments and Lanczos forms, and Lanczos with FP16 vector storage;
+    energy error against the FP64 path."""
     import oracle as O
     wl = W.fcc_alloy_spd(reps=args.reps_spd)
     ne = float(np.sum(wl.n_elec))
     out = {}
     ref = None
     for method, dtype in (("moments", "f64"), ("moments", "f32"), ("moments", "bf16"),
-                          ("lanczos", "f64"), ("lanczos", "f32"), ("lanczos", "bf16")):
+                          ("lanczos", "f64"), ("lanczos", "f32"), ("lanczos", "bf16"), ("lanczos", "f16")):
         p = P.EnergyPath(wl.pos, wl.cell, wl.species, wl.model, wl.n_max, wl.n_exp, dtype, method=method)
         t_step, t_k, o = timed_steps(p, ne, args.steps, 1, torch)
         u = float(o["U_total"].item())
