@@ -171,8 +171,10 @@ __device__ inline int fb_of(int n_max) { return n_max / 2; }
 // branch decisions (breakdown, band edges, width floor, inside the band) are
 // taken on the values.  Writes dU, dN [R][n_max + 1] (column 0 untouched) and,
 // from the dir = 1 thread, n_r(E_F) of the row.
+// Two waves per SIMD: unbounded, the compiler takes all 256 VGPRs and runs
+// one; bounded to four it spills the chain.
 template <int LM>
-__global__ void __launch_bounds__(WT)
+__global__ void __launch_bounds__(WT) __attribute__((amdgpu_waves_per_eu(2, 8)))
 k_weights(int R, int n_max, int n_exp, const double *__restrict__ mu, const double *__restrict__ H_on,
           const double *__restrict__ E_F, double *__restrict__ dU, double *__restrict__ dN, double *__restrict__ Drow)
 {
@@ -314,9 +316,8 @@ k_weights(int R, int n_max, int n_exp, const double *__restrict__ mu, const doub
     D1 chi0 = dc<1>(0.0);
     D1 chi1 = 1.0 - phi / M_PI + s2 / (2.0 * M_PI);
     D1 N = dc<1>(0.0), U = dc<1>(0.0), Dd = dc<1>(0.0);
-    for (int mstep = 0; mstep <= n_exp; ++mstep) {
-        // this step's sigma_m: from the moments or from the chain
-        D1 sig = (mstep <= n_mom) ? gm[mstep <= n_mom ? mstep : 0] : z1[0];
+    // one term m of the sums, sigma_m given
+    auto term = [&](int mstep, const D1 &sig) {
         const D1 g = s_g[mstep] * sig;
         const D1 chi2 = (1.0 / M_PI) * (w3 * s_inv[mstep + 3] - w1 * s_inv[mstep + 1]);
         N = N + g * chi1;
@@ -329,19 +330,33 @@ k_weights(int R, int n_max, int n_exp, const double *__restrict__ mu, const doub
         w2 = w3;
         w3 = ns;
         c3 = nc;
-        if (mstep < n_exp && n_mom < n_exp) {
-            // the chain from sigma_0 = 1: after this step z1[0] = sigma_(m+1)
-            D1 zn[LM + 1];
+    };
+    // the chain from sigma_0 = 1 one step on: afterwards z1[0] = sigma_(m+1)
+    auto advance = [&]() {
+        // in place, level by level: lower holds the old z1[k - 1]
+        D1 lower = dc<1>(0.0);
 #pragma unroll
-            for (int k = 0; k <= LM; ++k) {
-                const D1 lower = (k > 0) ? z1[k > 0 ? k - 1 : 0] : dc<1>(0.0);
-                const D1 upper = (k < LM) ? z1[k < LM ? k + 1 : LM] : dc<1>(0.0);
-                const D1 full = 2.0 * (ah[k] * z1[k] + bh[k] * lower + bh[k + 1] * upper) - z0[k];
-                const D1 delay = 2.0 * (bh[k] * lower);
-                zn[k] = (k < L) ? full : ((k == L) ? delay : dc<1>(0.0));
-            }
+        for (int k = 0; k <= LM; ++k) {
+            const D1 cur = z1[k];
+            const D1 upper = (k < LM) ? z1[k < LM ? k + 1 : LM] : dc<1>(0.0);
+            const D1 full = 2.0 * (ah[k] * cur + bh[k] * lower + bh[k + 1] * upper) - z0[k];
+            const D1 delay = 2.0 * (bh[k] * lower);
+            z1[k] = (k < L) ? full : ((k == L) ? delay : dc<1>(0.0));
+            z0[k] = cur;
+            lower = cur;
+        }
+    };
+    // m <= n_mom: sigma_m from the moments (unrolled, so that gm is indexed
+    // at compile time and dies before the chain's arrays are live)
 #pragma unroll
-            for (int k = 0; k <= LM; ++k) { z0[k] = z1[k]; z1[k] = zn[k]; }
+    for (int q = 0; q <= F_MAXN; ++q)
+        if (q <= n_mom && q <= n_exp) term(q, n_mom > 0 ? gm[q] : dc<1>(1.0));
+    // m > n_mom: sigma_m from the chain, first advanced to sigma_(n_mom + 1)
+    if (n_mom < n_exp) {
+        for (int mstep = 0; mstep <= n_mom; ++mstep) advance();
+        for (int mstep = n_mom + 1; mstep <= n_exp; ++mstep) {
+            term(mstep, z1[0]);
+            if (mstep < n_exp) advance();
         }
     }
     U = bi * U + (ai - H_on[r]) * N;
@@ -954,7 +969,11 @@ extern "C" int bop_weights(int n_rows, int n_max, int n_exp, const double *mu, c
     BOP_REQUIRE(ws && ws_bytes >= ww.bytes, BOP_E_CAPACITY, "bop_weights: workspace of %zu bytes needed", ww.bytes);
     const long nt = (long)n_rows * n_max;
     const unsigned g = (unsigned)((nt + WT - 1) / WT);
-    k_weights<11><<<g, WT, 0, stream>>>(n_rows, n_max, n_exp, mu, H_on, E_F, w, ww.dN, ww.Drow);
+    // chain depth L = max(#a, #b) = (n_max + 1) / 2 levels below the delay level
+    if ((n_max + 1) / 2 <= 9)
+        k_weights<9><<<g, WT, 0, stream>>>(n_rows, n_max, n_exp, mu, H_on, E_F, w, ww.dN, ww.Drow);
+    else
+        k_weights<11><<<g, WT, 0, stream>>>(n_rows, n_max, n_exp, mu, H_on, E_F, w, ww.dN, ww.Drow);
     BOP_LAUNCHED();
     const unsigned rb = (unsigned)((n_rows + WT - 1) / WT);
     k_ebar_part<<<rb, WT, 0, stream>>>(n_rows, H_on, ww.Drow, ww.part);
