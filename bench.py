@@ -71,6 +71,86 @@ def algorithmic_flops_per_atom(row_ptr, nbr_j, n_orb, n_max, sample):
     return np.array(out)
 
 
+def algorithmic_flops_per_atom_radius(pos, cell, row_ptr, nbr_j, n_orb, n_max, sample, r_max):
+    """The same count with a maximum path radius: the supports and degrees are
+    those of the graph restricted to the atoms within r_max (minimum image) of
+    the column's atom, since a path leaving that ball is dropped."""
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import dijkstra
+    n = row_ptr.shape[0] - 1
+    inv = np.linalg.inv(cell)
+    i_of = np.repeat(np.arange(n), np.diff(row_ptr))
+    K = n_max // 2
+    out = []
+    for c in sample:
+        f = (pos - pos[c]) @ inv
+        f -= np.round(f)
+        inb = np.linalg.norm(f @ cell, axis=1) <= r_max
+        keep = inb[i_of] & inb[nbr_j]
+        A = sp.csr_matrix((np.ones(int(keep.sum())), (i_of[keep], nbr_j[keep])), shape=(n, n))
+        deg = np.asarray(A.sum(axis=1)).ravel()
+        d = dijkstra(A, indices=[c], unweighted=True, limit=K + 0.5)[0]
+        fl = 0.0
+        for k in range(1, K + 1):
+            s_ = d <= k - 1
+            fl += n_orb * (2 * n_orb * n_orb * deg[s_].sum() + 2 * n_orb * s_.sum())
+        if n_max % 2:
+            inK = d <= K
+            inner = A[inK][:, inK].sum()
+            fl += n_orb * (2 * n_orb * n_orb * inner + 2 * n_orb * inK.sum())
+        out.append(fl)
+    return np.array(out)
+
+
+def cpu_baseline_forces(W, reps=4):
+    """The oracle's force path on a small cell of the headline recipe (bcc
+    a = 3.16 A, sigma = 0.08 A, seed 2, the same model and moments): energy,
+    weights, Theta~ from dense matrix powers of the folded H, block
+    derivatives.  Dense in the cell, so its cost grows as N^3."""
+    import oracle as O
+    wl = W.bcc_large(reps=reps)
+    t = time.perf_counter()
+    O.forces(wl)
+    sec = time.perf_counter() - t
+    return {"value": wl.n_atoms / sec, "unit": "atoms/s", "cores": O.num_threads(), "kind": "oracle",
+            "sample": (f"energy and forces of a {wl.n_atoms}-atom cell (bcc {reps}^3, same lattice, displacements, "
+                       f"model and {wl.n_max} moments) by the oracle's dense path (its cost grows as N^3)"),
+            "seconds": round(sec, 2)}
+
+
+def cpu_baseline_scf(wl, kind, n_target, stoner=None, mix_m=0.8, traj_steps=0):
+    """The oracle's self-consistent cycle on a small cell: LCN with linear
+    mixing ("linear"), Broyden mixing ("broyden"), or collinear magnetism
+    from m = 1 ("magnetic"); with traj_steps > 0, that many seeded MD-like
+    steps, each started from the previous converged shifts (the metric is then
+    per step).  Also reported scaled to n_target atoms, assuming a cost linear
+    in the atoms (the oracle's per-atom moments) at the sample's iteration
+    count."""
+    import oracle as O
+    import workloads as W_
+    t = time.perf_counter()
+    if kind == "magnetic":
+        O.scf_mag(wl, stoner, np.ones(wl.n_atoms), mix=0.5, mix_m=mix_m, max_iter=800)
+        n_scf = 1
+    elif traj_steps:
+        shift = None
+        for pos in W_.md_trajectory(wl, traj_steps, step_sigma=0.02):
+            w = W_.Workload(wl.name, pos, wl.cell, wl.species, wl.model, wl.n_max, wl.n_exp, wl.n_elec, wl.meta)
+            fn = O.scf_broyden if kind == "broyden" else O.scf
+            shift, _, _ = fn(w, shift0=shift, tol=1e-4, max_iter=300)
+        n_scf = traj_steps
+    else:
+        (O.scf_broyden if kind == "broyden" else O.scf)(wl, tol=1e-4, max_iter=300)
+        n_scf = 1
+    sec = time.perf_counter() - t
+    return {"value": sec / n_scf, "unit": "s", "cores": O.num_threads(), "kind": "oracle",
+            "scaled_to_workload_s": sec / n_scf * n_target / wl.n_atoms,
+            "sample": (f"the oracle's {kind} cycle on a {wl.n_atoms}-atom cell of the same recipe"
+                       + (f", {traj_steps} warm-started MD-like steps" if traj_steps else "")
+                       + " (FP64, every atom's moments each iteration)"),
+            "seconds": round(sec, 2)}
+
+
 def kernel_source_hash(source="moments.hip"):
     """Hash of a kernel file's code: the source without // comments and
     blank lines, so that a change of comments keeps recorded counters valid."""
@@ -103,10 +183,11 @@ def per_atom_errors(out, ref):
     return {"N": eN, "U": eU}
 
 
-def cpu_baseline(wl, target_s=12.0):
+def cpu_baseline(wl, target_s=12.0, r_max=0.0):
     """The FP64 oracle on the host cores: full neighbour list and H, then
-    moments, recursion, expansion and energies (at a fixed Fermi level) for a
-    seeded sample of atoms sized to take about `target_s` seconds."""
+    moments (with a maximum path radius if r_max > 0), recursion, expansion
+    and energies (at a fixed Fermi level) for a seeded sample of atoms sized
+    to take about `target_s` seconds."""
     import oracle as O
     t0 = time.perf_counter()
     nl = O.neighbours(wl.pos, wl.cell, wl.model["r_cut"])
@@ -117,7 +198,7 @@ def cpu_baseline(wl, target_s=12.0):
     def run(m):
         sel = np.sort(rng.choice(wl.n_atoms, size=m, replace=False)).astype(np.int32)
         t = time.perf_counter()
-        mu = O.moments(nl, H_on, H_b, wl.n_max, sel)
+        mu = O.moments(nl, H_on, H_b, wl.n_max, sel, r_max=r_max)
         rows = mu.reshape(-1, wl.n_max + 1)
         rec = O.recursion(rows, wl.n_max)
         gs = O.dos_coeffs(rows, rec, wl.n_max, wl.n_exp)
@@ -134,7 +215,9 @@ def cpu_baseline(wl, target_s=12.0):
     t_tot = t_s + t_nlh * m / wl.n_atoms
     return {"value": m * wl.n_max / t_tot, "unit": "atom-moments/s", "cores": O.num_threads(),
             "kind": "oracle",
-            "sample": (f"{m} of {wl.n_atoms} atoms (seeded): FP64 moments, recursion, expansion and energies "
+            "sample": (f"{m} of {wl.n_atoms} atoms (seeded): FP64 moments"
+                       + (f" (paths within {r_max:g} A)" if r_max > 0 else "")
+                       + ", recursion, expansion and energies "
                        f"at a fixed Fermi level; full-cell neighbour list + H ({t_nlh:.2f} s) charged pro rata; "
                        f"Fermi bisection excluded (needs every atom)"),
             "seconds": round(t_s + t_nlh, 2)}
@@ -526,6 +609,9 @@ def bench_scf(args, torch, P, W):
                 "epochs": args.epochs, "val_rmse_eV": rmse, "train_seconds": t_train,
                 "data_seconds": t_data, "train_iterations_mean": float(np.mean(its))},
     }
+    if not args.no_cpu:
+        # the oracle's plain cycle from zero shifts on a small cell of the recipe
+        res["cpu_baseline"] = cpu_baseline_scf(W.bcc_alloy_scf(seed=5, reps=4), "linear", wl.n_atoms)
     print(json.dumps(res), flush=True)
 
 
@@ -619,6 +705,23 @@ def bench_radius(args, torch, P, W):
                                       "none tested is within 1 meV/atom of all paths; the widest)")),
                       "n_atoms": wl.n_atoms, "n_max": wl.n_max},
            "all_paths": {"ms_per_step": t0 * 1e3, "hx_ms": k0, "rows_cap": rows0}, "radii": forms}
+    # the chosen radius's H.X pass against the FP32 peak, on exact per-atom
+    # supports restricted to the radius
+    nlc = P.build_neighbours(torch.as_tensor(np.asarray(wl.pos, float), device="cuda"), wl.cell, wl.model["r_cut"])
+    rp, nj = nlc.row_ptr.cpu().numpy(), nlc.nbr_j.cpu().numpy()
+    r_b = float(best[0])
+    fpa = algorithmic_flops_per_atom_radius(np.asarray(wl.pos, float), wl.cell, rp, nj, 5,
+                                            wl.n_max, np.random.default_rng(7).choice(wl.n_atoms, 4, replace=False),
+                                            r_b)
+    flops = float(fpa.mean()) * wl.n_atoms
+    ach = flops / (best[1]["hx_ms"] * 1e-3) / 1e12
+    res["roofline"] = {"bound": "alu", "achieved": ach, "peak": PEAK_TFLOPS["f32"], "unit": "TFLOP/s",
+                       "frac": ach / PEAK_TFLOPS["f32"], "traffic": None,
+                       "kernel": f"k_step with a path radius of {best[0]} A (all H.X launches of one pass)",
+                       "kernel_ms": best[1]["hx_ms"], "algorithmic_flops_per_launch": flops,
+                       "flops_per_atom": float(fpa.mean())}
+    if not args.no_cpu:
+        res["cpu_baseline"] = cpu_baseline(wl, r_max=r_b)
     print(json.dumps(res), flush=True)
 
 
@@ -661,6 +764,8 @@ def bench_md(args, torch, P, W):
                       "n_atoms": wl.n_atoms, "n_max": wl.n_max},
            "mixers": res_m,
            "speedup_warm_vs_cold": res_m[best]["cold"]["total_s"] / res_m[best]["warm"]["total_s"]}
+    if not args.no_cpu:
+        res["cpu_baseline"] = cpu_baseline_scf(W.bcc_alloy_scf(reps=4), best, wl.n_atoms, traj_steps=3)
     print(json.dumps(res), flush=True)
 
 
@@ -716,6 +821,12 @@ def bench_magnetic(args, torch, P, W):
                                   f"from m=1 to max|q|,|dm|<1e-4",
                       "n_atoms": n, "n_max": 16},
            "forms": out}
+    if not args.no_cpu:
+        ps, cs = W_.cubic_lattice("bcc", 2.87, 4)
+        ps = W_.displace(ps, cs, 0.03, np.random.default_rng(9))
+        small = W_.Workload("magnetic_bcc", ps, cs, np.zeros(ps.shape[0], np.int32), model, 16, 200,
+                            np.full(ps.shape[0], 6.5))
+        res["cpu_baseline"] = cpu_baseline_scf(small, "magnetic", n, stoner=[0.8], mix_m=0.8)
     print(json.dumps(res), flush=True)
 
 
@@ -821,6 +932,8 @@ def bench_forces(args, torch, P, W):
     if res["roofline"]["traffic"]:
         res["roofline"]["achieved_hbm_TBps"] = res["roofline"]["traffic"] / (kms * 1e-3) / 1e12
         res["roofline"]["hbm_frac"] = res["roofline"]["achieved_hbm_TBps"] / PEAK_HBM_TBPS
+    if not args.no_cpu:
+        res["cpu_baseline"] = cpu_baseline_forces(W)
     log(f"forces: {t * 1e3:.1f} ms/step, force passes {kms:.1f} ms, {achieved:.2f} TFLOP/s")
     print(json.dumps(res), flush=True)
 
