@@ -244,6 +244,26 @@ def timed_steps(path, n_elec, steps, warmup, torch):
     return t, kms, out
 
 
+def hx_roofline(P, wl, dtype, method, torch):
+    """The H.X pass of one energy evaluation of the workload's cell, with the
+    dtype and form its cycle uses, against the compute peak on exact per-atom
+    supports (a cycle runs this pass once per iteration, per spin channel in
+    a collinear one)."""
+    p = P.EnergyPath(wl.pos, wl.cell, wl.species, wl.model, wl.n_max, wl.n_exp, dtype, method=method)
+    _, kms, _ = timed_steps(p, float(np.sum(wl.n_elec)), 2, 1, torch)
+    rp, nj = p.nl.row_ptr.cpu().numpy(), p.nl.nbr_j.cpu().numpy()
+    fpa = algorithmic_flops_per_atom(rp, nj, p.no, wl.n_max,
+                                     np.random.default_rng(7).choice(wl.n_atoms, 8, replace=False))
+    del p
+    torch.cuda.empty_cache()
+    flops = float(fpa.mean()) * wl.n_atoms
+    ach = flops / (kms * 1e-3) / 1e12
+    return {"bound": "alu", "achieved": ach, "peak": PEAK_TFLOPS[dtype], "unit": "TFLOP/s",
+            "frac": ach / PEAK_TFLOPS[dtype], "traffic": None,
+            "kernel": f"k_step ({method}, {dtype}): the H.X launches of one energy pass of the cell",
+            "kernel_ms": kms, "algorithmic_flops_per_launch": flops, "flops_per_atom": float(fpa.mean())}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -609,6 +629,8 @@ def bench_scf(args, torch, P, W):
                 "epochs": args.epochs, "val_rmse_eV": rmse, "train_seconds": t_train,
                 "data_seconds": t_data, "train_iterations_mean": float(np.mean(its))},
     }
+    res["roofline"] = hx_roofline(P, wl, "f32" if best is w32 else "f64", "lanczos" if best is w32 else "moments",
+                                  torch)
     if not args.no_cpu:
         # the oracle's plain cycle from zero shifts on a small cell of the recipe
         res["cpu_baseline"] = cpu_baseline_scf(W.bcc_alloy_scf(seed=5, reps=4), "linear", wl.n_atoms)
@@ -764,6 +786,7 @@ def bench_md(args, torch, P, W):
                       "n_atoms": wl.n_atoms, "n_max": wl.n_max},
            "mixers": res_m,
            "speedup_warm_vs_cold": res_m[best]["cold"]["total_s"] / res_m[best]["warm"]["total_s"]}
+    res["roofline"] = hx_roofline(P, wl, "f64", "moments", torch)
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline_scf(W.bcc_alloy_scf(reps=4), best, wl.n_atoms, traj_steps=3)
     print(json.dumps(res), flush=True)
@@ -821,6 +844,10 @@ def bench_magnetic(args, torch, P, W):
                                   f"from m=1 to max|q|,|dm|<1e-4",
                       "n_atoms": n, "n_max": 16},
            "forms": out}
+    # one spin channel's pass is the non-magnetic pass over the same cell
+    res["roofline"] = hx_roofline(P, W_.Workload("magnetic_bcc", pos, cell, spc, model, 16, 200, n0),
+                                  "f32" if best == "lanczos_f32" else "f64",
+                                  "lanczos" if best == "lanczos_f32" else "moments", torch)
     if not args.no_cpu:
         ps, cs = W_.cubic_lattice("bcc", 2.87, 4)
         ps = W_.displace(ps, cs, 0.03, np.random.default_rng(9))
