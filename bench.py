@@ -684,10 +684,21 @@ def bench_precision(args, torch, P, W):
                                f"fastest form within 1 meV/atom of FP64: {bname}",
                    "n_atoms": wl.n_atoms, "n_max": wl.n_max},
         "forms": out,
+        "roofline": None,
         "fp64_vs_oracle_sample": {"atoms": 64, "max_rel_err_moments": rel},
         "cpu_baseline": {"value": 64 * wl.n_max / t_o, "unit": "atom-moments/s", "cores": O.num_threads(),
                          "kind": "oracle", "sample": "64 seeded atoms, FP64 moments only"},
     }
+    # the chosen form's H.X pass against the peak of its dtype, exact supports
+    fpa = algorithmic_flops_per_atom(nl["row_ptr"], nl["nbr_j"], 9, wl.n_max,
+                                     np.random.default_rng(7).choice(wl.n_atoms, 4, replace=False))
+    flops = float(fpa.mean()) * wl.n_atoms
+    dt = bname.split("_")[1]
+    ach = flops / (best["hx_ms"] * 1e-3) / 1e12
+    res["roofline"] = {"bound": "mfma" if dt == "bf16" else "alu", "achieved": ach, "peak": PEAK_TFLOPS[dt],
+                       "unit": "TFLOP/s", "frac": ach / PEAK_TFLOPS[dt], "traffic": None,
+                       "kernel": f"H.X launches of one {bname} pass (9 orbitals)", "kernel_ms": best["hx_ms"],
+                       "algorithmic_flops_per_launch": flops, "flops_per_atom": float(fpa.mean())}
     print(json.dumps(res), flush=True)
 
 
