@@ -278,7 +278,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-f64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--workload", default="energy",
-                    choices=["energy", "batch", "scf", "precision", "radius", "md", "magnetic", "forces"],
+                    choices=["energy", "batch", "scf", "precision", "radius", "md", "magnetic", "forces",
+                             "terminators"],
                     help="energy: bcc 40^3 single energy (default); batch: 512 ragged structures; "
                          "scf: 250,000-atom alloy SCF with MLP warm start (and Broyden mixing); precision: s,p,d "
                          "alloy, 20 moments; radius: bcc 40^3 with maximum path radii; md: alloy SCF along a "
@@ -318,7 +319,8 @@ def main():
     P.load()
     if args.workload != "energy":
         {"batch": bench_batch, "scf": bench_scf, "precision": bench_precision, "radius": bench_radius,
-         "md": bench_md, "magnetic": bench_magnetic, "forces": bench_forces}[args.workload](args, torch, P, W)
+         "md": bench_md, "magnetic": bench_magnetic, "forces": bench_forces,
+         "terminators": bench_terminators}[args.workload](args, torch, P, W)
         return
     wl = W.bcc_large(reps=args.reps)
     n_elec = float(wl.n_elec.sum())
@@ -865,6 +867,92 @@ def bench_magnetic(args, torch, P, W):
         small = W_.Workload("magnetic_bcc", ps, cs, np.zeros(ps.shape[0], np.int32), model, 16, 200,
                             np.full(ps.shape[0], 6.5))
         res["cpu_baseline"] = cpu_baseline_scf(small, "magnetic", n, stoner=[0.8], mix_m=0.8)
+    print(json.dumps(res), flush=True)
+
+
+BW_OPTIONS = ("gershgorin", "lowest", "highest", "average", "average_highest", "minmax", "weighted")
+
+
+def bench_terminators(args, torch, P, W):
+    """Terminators and band-width estimates (App. B.5 options (i)-(v),
+    Gershgorin, the weighted-average terminator of App. B.1) on the headline
+    cell: the FP32 Lanczos coefficients once, then per option the tail
+    (a_inf, b_inf, expansion coefficients, Fermi level, energies), timed live;
+    energy differences to the Gershgorin estimate.  The tail is bound by the
+    Fermi passes, each of which reads every row's expansion coefficients."""
+    import oracle as O
+    wl = W.bcc_large(reps=args.reps)
+    ne = float(wl.n_elec.sum())
+    p = P.EnergyPath(wl.pos, wl.cell, wl.species, wl.model, wl.n_max, wl.n_exp, "f32", method="lanczos")
+    p.run(ne)
+    torch.cuda.synchronize()
+    # the tail ORs its conditions into the flags of the Lanczos pass, so each
+    # option starts from the pass's own flags
+    flags0 = p.rec["flags"].clone()
+    R = wl.n_atoms * p.no
+    forms = {}
+    u_ref = None
+    for mode in BW_OPTIONS:
+        p.bw = mode
+        p.rec["flags"].copy_(flags0)
+        out = p.run_tail(ne)
+        ts = []
+        for _ in range(args.steps):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            p.rec["flags"].copy_(flags0)
+            a.record()
+            out = p.run_tail(ne)
+            b.record()
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(b))
+        u = float(out["U_total"].item()) / wl.n_atoms
+        if u_ref is None:
+            u_ref = u
+        # an estimate that puts the band inside the chain's spectrum makes
+        # the chain's expansion diverge (flag 16); its energies mean nothing
+        div = int(((p.rec["flags"] & 16) != 0).sum().item())
+        forms[mode] = {"tail_ms": float(np.median(ts)), "U_eV_per_atom": u if div == 0 else None,
+                       "E_F": float(out["E_F"].cpu()[0]),
+                       "dU_vs_gershgorin_meV_per_atom": abs(u - u_ref) * 1e3 if div == 0 else None,
+                       "divergent_rows": div, "floor_rows": int(((p.rec["flags"] & 8) != 0).sum().item())}
+        log(f"{mode}: {forms[mode]}")
+    g = forms["gershgorin"]
+    e_f = g["E_F"]
+    n_pass = 16    # 64 halvings, four per pass
+    bytes_f = n_pass * R * (wl.n_exp + 1) * 8.0
+    res = {"metric": "orbital-tails/s", "value": R / (g["tail_ms"] * 1e-3), "unit": "orbital-tails/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": g["tail_ms"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": (f"bcc {args.reps}^3 ({wl.n_atoms} atoms, {R} orbital rows), 18 moments, "
+                                   f"FP32 Lanczos coefficients, FP64 tail per terminator option"),
+                      "n_atoms": wl.n_atoms, "n_max": wl.n_max, "n_exp": wl.n_exp},
+           "roofline": {"bound": "hbm", "achieved": bytes_f / (g["tail_ms"] * 1e-3) / 1e9, "peak": PEAK_HBM_TBPS * 1e3,
+                        "unit": "GB/s", "frac": bytes_f / (g["tail_ms"] * 1e-3) / 1e12 / PEAK_HBM_TBPS,
+                        "traffic": None, "kernel": "the tail (Gershgorin): its 16 Fermi passes' reads of the "
+                                                   "expansion coefficients over the whole tail's time",
+                        "kernel_ms": g["tail_ms"], "algorithmic_bytes_per_launch": bytes_f},
+           "options": forms}
+    del p
+    if not args.no_cpu:
+        # the oracle's tail per option on the moments of seeded atoms, at the
+        # GPU's Fermi level (a bisection needs every atom)
+        nl = O.neighbours(wl.pos, wl.cell, wl.model["r_cut"])
+        H_on, H_b = O.build_H(wl.model, wl.species, nl)
+        sel = np.sort(np.random.default_rng(123).choice(wl.n_atoms, 512, replace=False)).astype(np.int32)
+        rows = O.moments(nl, H_on, H_b, wl.n_max, sel).reshape(-1, wl.n_max + 1)
+        per = {}
+        for mode in BW_OPTIONS:
+            t = time.perf_counter()
+            rec = O.recursion(rows, wl.n_max, bw=mode)
+            gs = O.dos_coeffs(rows, rec, wl.n_max, wl.n_exp)
+            O.energy(gs, rec["a_inf"], rec["b_inf"], H_on[sel], e_f)
+            per[mode] = rows.shape[0] / (time.perf_counter() - t)
+        res["cpu_baseline"] = {"value": per["gershgorin"], "unit": "orbital-tails/s", "cores": O.num_threads(),
+                               "kind": "oracle", "per_option": per,
+                               "sample": (f"the {rows.shape[0]} orbital rows of 512 seeded atoms: recursion from "
+                                          f"the moments, terminator, expansion and energies at the GPU's Fermi "
+                                          f"level (the moments themselves not timed)")}
     print(json.dumps(res), flush=True)
 
 
