@@ -279,7 +279,7 @@ def main():
     ap.add_argument("--no-f64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--workload", default="energy",
                     choices=["energy", "batch", "scf", "precision", "radius", "md", "magnetic", "forces",
-                             "terminators"],
+                             "terminators", "mlp"],
                     help="energy: bcc 40^3 single energy (default); batch: 512 ragged structures; "
                          "scf: 250,000-atom alloy SCF with MLP warm start (and Broyden mixing); precision: s,p,d "
                          "alloy, 20 moments; radius: bcc 40^3 with maximum path radii; md: alloy SCF along a "
@@ -320,7 +320,7 @@ def main():
     if args.workload != "energy":
         {"batch": bench_batch, "scf": bench_scf, "precision": bench_precision, "radius": bench_radius,
          "md": bench_md, "magnetic": bench_magnetic, "forces": bench_forces,
-         "terminators": bench_terminators}[args.workload](args, torch, P, W)
+         "terminators": bench_terminators, "mlp": bench_mlp}[args.workload](args, torch, P, W)
         return
     wl = W.bcc_large(reps=args.reps)
     n_elec = float(wl.n_elec.sum())
@@ -867,6 +867,77 @@ def bench_magnetic(args, torch, P, W):
         small = W_.Workload("magnetic_bcc", ps, cs, np.zeros(ps.shape[0], np.int32), model, 16, 200,
                             np.full(ps.shape[0], 6.5))
         res["cpu_baseline"] = cpu_baseline_scf(small, "magnetic", n, stoner=[0.8], mix_m=0.8)
+    print(json.dumps(res), flush=True)
+
+
+def bench_mlp(args, torch, P, W):
+    """Warm-start network training: 6-64-64-1, minibatch Adam over 400,000
+    seeded feature rows (standard normal; smooth seeded targets of the shift
+    scale), batch 4,096; a step is one bop_mlp_train_step (row gather,
+    forward, backward, Adam).  Then forward passes over all rows.  The
+    roofline counts 2 (6*64 + 64*64 + 64) flops per row forward and three
+    times that per training row against the FP32 matrix peak."""
+    import oracle as O
+    rng = np.random.default_rng(3)
+    n, B, epochs = 400000, 4096, 10
+    x = rng.normal(size=(n, 6))
+    t = np.tanh(x @ rng.normal(size=6)) * 0.2
+    xd = torch.tensor(x, dtype=torch.float32, device="cuda")
+    td = torch.tensor(t, dtype=torch.float32, device="cuda")
+    m = P.MLP(seed=0)
+    m.train(xd, td, epochs=1, batch=B, lr=1e-3)          # warm-up epoch
+    torch.cuda.synchronize()
+    steps = epochs * (n // B)
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    a.record()
+    m.train(xd, td, epochs=epochs, batch=B, lr=1e-3)
+    b.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = a.elapsed_time(b) / steps
+    loss, _ = m.grad(xd, td)
+    y = P.mlp_forward(m.params, xd)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(10):
+        y = P.mlp_forward(m.params, xd)
+    b.record()
+    torch.cuda.synchronize()
+    ms_fwd = a.elapsed_time(b) / 10
+    f_row = 2.0 * (6 * 64 + 64 * 64 + 64)
+    ach = 3.0 * f_row * B / (ms_step * 1e-3) / 1e12
+    res = {"metric": "training rows/s", "value": B / (ms_step * 1e-3), "unit": "rows/s", "n_gpus": 1,
+           "steps": steps, "warmup": n // B, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": (f"6-64-64-1 tanh MLP, Adam (lr 1e-3), {n} seeded rows of 6 features, batch {B}, "
+                                   f"{epochs} epochs"), "rows": n, "batch": B},
+           "loss": float(loss.item()), "wall_s": wall, "forward_ms_all_rows": ms_fwd,
+           "forward_rows_per_s": n / (ms_fwd * 1e-3),
+           "roofline": {"bound": "mfma", "achieved": ach, "peak": PEAK_TFLOPS["f32"], "unit": "TFLOP/s",
+                        "frac": ach / PEAK_TFLOPS["f32"], "traffic": None,
+                        "kernel": "one training step (row gather, forward and backward tiles on MFMA, gradients, "
+                                  "Adam)", "kernel_ms": ms_step, "algorithmic_flops_per_launch": 3.0 * f_row * B}}
+    if not args.no_cpu:
+        # the oracle's NumPy step (forward, gradient, Adam) on the same rows
+        r2 = np.random.default_rng(0)
+        params = []
+        for shp in P.MLP_SHAPES:
+            lim = np.sqrt(6.0 / (shp[0] + shp[1])) if len(shp) == 2 else 0.0
+            params.append(r2.uniform(-lim, lim, size=shp) if len(shp) == 2 else np.zeros(shp))
+        mo = [np.zeros_like(q) for q in params]
+        vo = [np.zeros_like(q) for q in params]
+        k, tc = 0, time.perf_counter()
+        while time.perf_counter() - tc < 5.0:
+            idx = r2.integers(0, n, B)
+            _, g = O.mlp_loss_grad(params, x[idx], t[idx])
+            k += 1
+            params, mo, vo = O.adam_step(params, g, mo, vo, k)
+        sec = time.perf_counter() - tc
+        res["cpu_baseline"] = {"value": k * B / sec, "unit": "rows/s", "cores": O.num_threads(), "kind": "oracle",
+                               "sample": f"{k} training steps of batch {B} (NumPy forward, gradient and Adam)",
+                               "seconds": round(sec, 2)}
     print(json.dumps(res), flush=True)
 
 
