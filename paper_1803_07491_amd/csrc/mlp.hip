@@ -24,7 +24,7 @@ constexpr int OW1 = 0, OB1 = OW1 + NH * NX, OW2 = OB1 + NH, OB2 = OW2 + NH * NH,
               OB3 = OW3 + NH, NPARAM = OB3 + 1;
 static_assert(NPARAM == BOP_MLP_NPARAM, "parameter count");
 constexpr int MT = 256;           // threads per block
-constexpr int GRAD_BLOCKS = 32;   // row blocks of the gradient reduction
+constexpr int GRAD_BLOCKS = 64;   // row blocks of the gradient reduction (32: 74 us per 4,096-row step; 64: 57; 128: 73, Adam then summing more partials)
 
 __device__ inline void load_params(const float *__restrict__ p, float *s)
 {
@@ -148,20 +148,31 @@ k_mlp_grad(int B, const float *__restrict__ x, const float *__restrict__ H1, con
     }
 }
 
-// sum of the block partials (fixed order) and Adam (lr, 0.9, 0.999, 1e-8)
-__global__ void k_mlp_adam(int nblk, int nloss, const float *__restrict__ part, const float *__restrict__ loss_part,
-                           float *__restrict__ params, float *__restrict__ m, float *__restrict__ v, int step,
-                           float lr, float *__restrict__ grad_out, float *__restrict__ loss)
+// sum of the block partials and Adam (lr, 0.9, 0.999, 1e-8): 64 parameters
+// per workgroup, each summed by four threads over every fourth partial, the
+// four sums then added in a fixed order
+constexpr int AP = 64;                   // parameters per Adam workgroup
+
+__global__ void __launch_bounds__(4 * AP)
+k_mlp_adam(int nblk, int nloss, const float *__restrict__ part, const float *__restrict__ loss_part,
+           float *__restrict__ params, float *__restrict__ m, float *__restrict__ v, int step, float lr,
+           float *__restrict__ grad_out, float *__restrict__ loss)
 {
-    int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p == 0 && loss) {
+    __shared__ float s_g[4][AP];
+    const int pl = threadIdx.x % AP, grp = threadIdx.x / AP;
+    const int p = blockIdx.x * AP + pl;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && loss) {
         float l = 0.f;
         for (int b = 0; b < nloss; ++b) l += loss_part[b];
         loss[0] = l;
     }
-    if (p >= NPARAM) return;
-    float g = 0.f;
-    for (int b = 0; b < nblk; ++b) g += part[(size_t)b * NPARAM + p];
+    float gp = 0.f;
+    if (p < NPARAM)
+        for (int b = grp; b < nblk; b += 4) gp += part[(size_t)b * NPARAM + p];
+    s_g[grp][pl] = gp;
+    __syncthreads();
+    if (grp != 0 || p >= NPARAM) return;
+    const float g = ((s_g[0][pl] + s_g[1][pl]) + s_g[2][pl]) + s_g[3][pl];
     if (grad_out) grad_out[p] = g;
     if (step <= 0) return;
     const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
@@ -491,7 +502,7 @@ extern "C" int bop_mlp_train_step(int batch, const int *idx, const float *x, con
     k_mlp_grad<<<GRAD_BLOCKS, MT, 0, stream>>>(batch, xb, w.H1, w.H2, w.GZ1, w.GZ2, w.GY, w.part);
     k_mlp_grad_w2<<<GRAD_BLOCKS, MT, 0, stream>>>(batch, w.H1, w.GZ2, w.part);
     BOP_LAUNCHED();
-    k_mlp_adam<<<(NPARAM + 255) / 256, 256, 0, stream>>>(GRAD_BLOCKS, nfb, w.part, w.loss_part, params, adam_m,
+    k_mlp_adam<<<(NPARAM + AP - 1) / AP, 4 * AP, 0, stream>>>(GRAD_BLOCKS, nfb, w.part, w.loss_part, params, adam_m,
                                                         adam_v, step, lr, grad, loss);
     BOP_LAUNCHED();
     return BOP_OK;
@@ -511,7 +522,7 @@ extern "C" int bop_mlp_adam(const float *grad, float *params, float *adam_m, flo
 {
     BOP_REQUIRE(grad && params && adam_m && adam_v, BOP_E_ARG, "bop_mlp_adam: NULL array");
     BOP_REQUIRE(step >= 1, BOP_E_ARG, "bop_mlp_adam: step must be >= 1");
-    k_mlp_adam<<<(NPARAM + 255) / 256, 256, 0, stream>>>(1, 0, grad, nullptr, params, adam_m, adam_v, step, lr,
+    k_mlp_adam<<<(NPARAM + AP - 1) / AP, 4 * AP, 0, stream>>>(1, 0, grad, nullptr, params, adam_m, adam_v, step, lr,
                                                         nullptr, nullptr);
     BOP_LAUNCHED();
     return BOP_OK;
