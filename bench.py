@@ -763,7 +763,9 @@ def bench_radius(args, torch, P, W):
 def bench_md(args, torch, P, W):
     """Sec. III "Speed-ups" (ii): the alloy's charge-neutrality cycle along a
     seeded trajectory, each step started from the previous converged shifts
-    (warm) or from zero (cold); linear and Broyden mixing, FP64."""
+    (warm) or from zero (cold); linear and Broyden mixing, FP64; then the
+    better mixer's warm run with the FP32 Lanczos form, judged by the FP64
+    path's energy at its converged shifts."""
     wl = W.bcc_alloy_scf(reps=args.reps_md)
     traj = W.md_trajectory(wl, args.md_steps, step_sigma=0.02)
     res_m = {}
@@ -789,17 +791,42 @@ def bench_md(args, torch, P, W):
             del s
         res_m[mixer] = out
     best = min((m for m in res_m), key=lambda m: res_m[m]["warm"]["total_s"])
-    res = {"metric": "s per converged SCF", "value": res_m[best]["warm"]["total_s"] / args.md_steps, "unit": "s",
+    # the same warm run with the FP32 Lanczos form, judged by the FP64 path's
+    # energy at its converged shifts of the last step
+    s = P.SCFPath(wl.pos, wl.cell, wl.species, wl.model, wl.n_max, wl.n_elec, wl.n_exp, "f32", method="lanczos",
+                  mixer=best)
+    its, secs = [], []
+    for t, pos in enumerate(traj):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if t > 0:
+            s.set_positions(pos)
+        it, _ = s.run_scf(tol=1e-4, max_iter=300)
+        torch.cuda.synchronize()
+        its.append(it)
+        secs.append(time.perf_counter() - t0)
+    chk = P.EnergyPath(traj[-1], wl.cell, wl.species, wl.model, wl.n_max, wl.n_exp, "f64")
+    chk.H_on, _ = P.build_H(wl.model, chk.species, chk.nl, shift=s.shift, dtype="f64", H_on=chk.H_on,
+                            H_bond=chk.H_bond)
+    o = chk.run(float(np.sum(wl.n_elec)))
+    du = abs(float(o["U_total"].item()) / wl.n_atoms - res_m[best]["warm"]["U_last_eV_per_atom"]) * 1e3
+    del s, chk
+    w32 = {"iterations": its, "seconds": secs, "total_s": float(np.sum(secs)), "energy_err_meV_per_atom": du}
+    log(f"{best} warm FP32 Lanczos: {its} iterations, {w32['total_s']:.2f} s, {du:.2e} meV/atom")
+    use32 = w32["total_s"] < res_m[best]["warm"]["total_s"] and du <= 1.0
+    tot = w32["total_s"] if use32 else res_m[best]["warm"]["total_s"]
+    res = {"metric": "s per converged SCF", "value": tot / args.md_steps, "unit": "s",
            "n_gpus": 1, "steps": args.md_steps, "warmup": 0,
-           "ms_per_step": res_m[best]["warm"]["total_s"] / args.md_steps * 1e3, "higher_is_better": False,
-           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "ms_per_step": tot / args.md_steps * 1e3, "higher_is_better": False,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32" if use32 else "f64", "data": "synthetic",
            "config": {"workload": f"bcc A/B alloy {args.reps_md}^3 cells ({wl.n_atoms} atoms), 16 moments, LCN SCF "
                                   f"to max|q|<1e-4 along {args.md_steps} seeded MD-like steps (0.02 A per step), "
-                                  f"warm start from the previous step; {best} mixing",
+                                  f"warm start from the previous step; {best} mixing"
+                                  + ("; FP32 Lanczos form (FP64 tail)" if use32 else "; FP64"),
                       "n_atoms": wl.n_atoms, "n_max": wl.n_max},
-           "mixers": res_m,
+           "mixers": res_m, "warm_fp32_lanczos": w32,
            "speedup_warm_vs_cold": res_m[best]["cold"]["total_s"] / res_m[best]["warm"]["total_s"]}
-    res["roofline"] = hx_roofline(P, wl, "f64", "moments", torch)
+    res["roofline"] = hx_roofline(P, wl, "f32" if use32 else "f64", "lanczos" if use32 else "moments", torch)
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline_scf(W.bcc_alloy_scf(reps=4), best, wl.n_atoms, traj_steps=3)
     print(json.dumps(res), flush=True)
