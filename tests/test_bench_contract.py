@@ -53,3 +53,28 @@ def test_committed_bench_line_states_its_accuracy():
     r = j["roofline"]
     if r["traffic"]:
         assert abs(r["achieved_hbm_TBps"] - r["traffic"] / (r["kernel_ms"] * 1e-3) / 1e12) < 1e-9
+
+
+def test_radius_flop_count_reduces_to_the_unrestricted_one():
+    """The path-radius roofline's work count: with a radius beyond every
+    support it equals the unrestricted count atom by atom, and a radius below
+    the supports' extent removes work."""
+    sys.path.insert(0, ROOT)
+    import numpy as np
+    import bench
+    import oracle as O
+    import workloads as W
+    wl = W.bcc_large(reps=6)
+    nl = O.neighbours(wl.pos, wl.cell, wl.model["r_cut"])
+    smp = np.array([0, 7, 100])
+    full = bench.algorithmic_flops_per_atom(nl["row_ptr"], nl["nbr_j"], 5, wl.n_max, smp)
+    wide = bench.algorithmic_flops_per_atom_radius(wl.pos, wl.cell, nl["row_ptr"], nl["nbr_j"], 5, wl.n_max, smp,
+                                                   1e3)
+    small = bench.algorithmic_flops_per_atom_radius(wl.pos, wl.cell, nl["row_ptr"], nl["nbr_j"], 5, wl.n_max, smp,
+                                                    7.0)
+    np.testing.assert_array_equal(wide, full)
+    assert np.all(small < full) and np.all(small > 0)
+    # odd n_max adds the last product on the K-hop support; the same identity holds
+    f17 = bench.algorithmic_flops_per_atom(nl["row_ptr"], nl["nbr_j"], 5, 17, smp)
+    w17 = bench.algorithmic_flops_per_atom_radius(wl.pos, wl.cell, nl["row_ptr"], nl["nbr_j"], 5, 17, smp, 1e3)
+    np.testing.assert_array_equal(w17, f17)
