@@ -244,6 +244,30 @@ def timed_steps(path, n_elec, steps, warmup, torch):
     return t, kms, out
 
 
+def stage_times(path, n_elec, P, torch):
+    """One more step, after the timed ones, with HIP events between its
+    stages: a1 neighbour list, a2 H, the moment plan and supports, the H.X
+    passes, the tail (a4-a8).  The neighbour list and the plan read a count
+    back to the host, so their intervals include that round trip."""
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+    ev[0].record()
+    path.nl = P.build_neighbours(path.pos, path.cell, path.model["r_cut"], capacity=path.nl.n_pairs)
+    ev[1].record()
+    path.H_on, path.H_bond = P.build_H(path.model, path.species, path.nl, dtype=path.dtype, H_on=path.H_on,
+                                       H_bond=path.H_bond)
+    ev[2].record()
+    path.plan = P.moments_plan(path.n, path.no, path.n_max, path.dtype, path.nl, path.tuning, radius=path.radius)
+    path.mws = P.moments_prepare(path.plan, path.nl, ws=path.mws, radius=path.radius)
+    ev[3].record()
+    path.run_moments()
+    ev[4].record()
+    path.run_tail(n_elec)
+    ev[5].record()
+    torch.cuda.synchronize()
+    names = ("a1_neighbours", "a2_H", "plan_and_supports", "hx_passes", "tail_a4_a8")
+    return {k: ev[i].elapsed_time(ev[i + 1]) for i, k in enumerate(names)}
+
+
 def hx_roofline(P, wl, dtype, method, torch):
     """The H.X pass of one energy evaluation of the workload's cell, with the
     dtype and form its cycle uses, against the compute peak on exact per-atom
@@ -376,6 +400,10 @@ def main():
         res["roofline"]["hbm_frac"] = res["roofline"]["achieved_hbm_TBps"] / PEAK_HBM_TBPS
     if args.dtype == "f32":
         res["roofline"]["frac_nonpacked_fp32"] = achieved / PEAK_NONPACKED_F32
+    # where one step's time goes (one more step, outside the timed ones)
+    res["stages_ms"] = stage_times(path, n_elec, P, torch)
+    res["a1_a2_ms"] = res["stages_ms"]["a1_neighbours"] + res["stages_ms"]["a2_H"]
+    log(f"stages (ms): {res['stages_ms']}")
     if not args.no_f64 and (args.dtype != "f64" or args.method != "moments"):
         # the plain FP64 path (moments, FP64 recursion) as the reference
         p64 = P.EnergyPath(wl.pos, wl.cell, wl.species, wl.model, wl.n_max, wl.n_exp, "f64")
