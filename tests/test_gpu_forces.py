@@ -284,3 +284,39 @@ def test_scf_target_fullsize_matches_energy_differences(bop):
         fd = (u[0] - u[1]) / (2 * h)
         print(f"atom {k}: delta {delta[k]:.8f}, central difference {fd:.8f}")
         assert abs(delta[k] - fd) < 5e-5, (int(k), delta[k], fd)
+
+
+_FCC = {}
+
+
+def _fcc108():
+    """fcc a = 3.6 A, 3^3 cells (108 atoms), sigma = 0.05 A (seed 21), the
+    canonical d band with a 3.8 A cutoff (both first shells), 6 moments; the
+    oracle's forces computed once."""
+    if not _FCC:
+        rng = np.random.default_rng(21)
+        pos, cell = W.cubic_lattice("fcc", 3.6, 3)
+        pos = W.displace(pos, cell, 0.05, rng)
+        n = pos.shape[0]
+        wl = W.Workload("fcc108", pos, cell, np.zeros(n, np.int32), W.canonical_d_model(3.8), 6, 200,
+                        np.full(n, 6.5))
+        _FCC["wl"] = wl
+        _FCC["F"] = O.forces(wl)[0]
+    return _FCC["wl"], _FCC["F"]
+
+
+@pytest.mark.parametrize("dtype,bar", [("f64", 1e-10), ("f32", 1e-5)])
+def test_forces_fcc_eighteen_neighbours_match_oracle(bop, dtype, bar):
+    """fcc with the first two shells inside the cutoff (18 neighbours per
+    atom): rows with more slot groups than the bcc cells, and (FP32 vectors)
+    the L2 touches of the next group's blocks."""
+    wl, F_ref = _fcc108()
+    n = wl.n_atoms
+    p, _, F = _gpu_forces(bop, wl, dtype)
+    deg = np.diff(_np(p.nl.row_ptr))
+    assert deg.min() == deg.max() == 18
+    scale = max(1.0, np.abs(F_ref).max())
+    err = np.abs(F - F_ref).max()
+    print(f"fcc108 {dtype}: max |F - F_ref| = {err:.3e} eV/A (max |F| {np.abs(F_ref).max():.3f})")
+    assert err <= bar * scale, err
+    assert np.abs(F.sum(axis=0)).max() <= 1e-9 * max(1.0, np.abs(F).max() * n)
