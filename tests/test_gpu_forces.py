@@ -320,3 +320,30 @@ def test_forces_fcc_eighteen_neighbours_match_oracle(bop, dtype, bar):
     print(f"fcc108 {dtype}: max |F - F_ref| = {err:.3e} eV/A (max |F| {np.abs(F_ref).max():.3f})")
     assert err <= bar * scale, err
     assert np.abs(F.sum(axis=0)).max() <= 1e-9 * max(1.0, np.abs(F).max() * n)
+
+
+def test_weights_twenty_moments_from_the_oracle_moments(bop):
+    """The weights kernel's deeper chain (n_max 19-20) against the oracle's
+    weights from the same moments (the oracle's own), so that only the tail
+    differs: moments to recursion, band, expansion, N and U at E_F in dual
+    numbers against the complex step.  At 20 moments the map from moments is
+    ill-conditioned, so the bar is 1e-6 of each column's largest entry; a
+    wrong index in the chain would be an error of order one."""
+    import torch
+    wl = _bcc54(n_max=20)
+    ref = O.energy_pipeline(wl)
+    rows = ref["mu"].reshape(-1, 21)
+    H_on = ref["H_on"].reshape(-1)
+    mu = torch.as_tensor(np.ascontiguousarray(rows), dtype=torch.float64, device="cuda")
+    H = torch.as_tensor(np.ascontiguousarray(ref["H_on"]), dtype=torch.float64, device="cuda")
+    E_F = torch.tensor([ref["E_F"]], dtype=torch.float64, device="cuda")
+    w = _np(bop.weights(mu, H, E_F, 20, wl.n_exp))
+    w_ref, _, _ = O.weights(rows, 20, wl.n_exp, ref["E_F"], H_on)
+    assert np.all(w[:, 0] == 0.0)
+    worst = 0.0
+    for n in range(1, 21):
+        scale = np.abs(w_ref[:, n]).max()
+        err = np.abs(w[:, n] - w_ref[:, n]).max()
+        worst = max(worst, err / scale)
+        assert err <= 1e-6 * scale, (n, err, scale)
+    print(f"20 moments: largest column error {worst:.2e} of the column's largest entry")
